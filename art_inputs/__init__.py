@@ -1,0 +1,70 @@
+"""Seeded synthetic inputs and workload definitions shared by the oracle and
+the HIP path.
+
+This module holds no arithmetic of the method: only workload parameters and
+the random numbers the models draw (the magnetic-field phase of the thermal
+model, the turbulence of the gridded snapshot).  Both sides receive these as
+inputs.
+"""
+import numpy as np
+
+SGRA_MASS_MSUN = 4.0e6       # Sec. 3.1 semi-analytic model: M = 4e6 Msun, D = 7.78 kpc
+
+
+def thermal_params(seed=1, n0=2.0e6, theta0=100.0, beta_ref=10.0, r_ref=10.0,
+                   r_emit=50.0, ne_index=1.1, th_index=0.84, b_index=1.0):
+    """Model-parameter vector of the semi-analytic thermal plasma:
+    n_e = n0 r^-1.1, Theta_e = Theta0 r^-0.84, |B| ~ r^-1 with plasma beta
+    beta_ref at r_ref, field phase psi0 = 2 pi U(0,1) drawn from `seed`."""
+    rng = np.random.default_rng(seed)
+    psi0 = 2.0 * np.pi * rng.uniform()
+    mp = [0.0] * 16
+    mp[0], mp[1], mp[2], mp[3] = n0, theta0, beta_ref, r_ref
+    mp[4], mp[5] = psi0, r_emit
+    mp[6], mp[7], mp[8] = ne_index, th_index, b_index
+    return mp
+
+
+def toy_disk_params(r_in=2.0, h_over_r=0.3):
+    """j = r^-2 exp(-z^2 / (2 (h r)^2)) outside r_in, no absorption."""
+    mp = [0.0] * 16
+    mp[0], mp[1] = r_in, h_over_r
+    return mp
+
+
+def screen_ring_params(radius=5.0, width=0.35, diffuse=0.05, diffuse_scale=6.0):
+    """Closed-form screen intensity (refinement tests without ray tracing)."""
+    mp = [0.0] * 16
+    mp[0], mp[1], mp[2], mp[3] = radius, width, diffuse, diffuse_scale
+    return mp
+
+
+def screen_poly_params(c):
+    mp = [0.0] * 16
+    for i, v in enumerate(c):
+        mp[i] = float(v)
+    return mp
+
+
+def workload(name):
+    """Workload dictionaries.  Vertex-grid convention: a 'k^2 base' is k cells,
+    i.e. (k+1)^2 vertices, so 128^2 -> 1024^2 is 129^2 -> 1025^2."""
+    common = dict(r_cam=1000.0, r_out=1000.0, fov=40.0, eps=0.03, max_steps=100000,
+                  mass_msun=SGRA_MASS_MSUN)
+    if name == "toy_disk_64":
+        return dict(common, name=name, a=0.0, inc_deg=17.0, model="toy_disk",
+                    mp=toy_disk_params(), nstokes=1, nx0=64, ny0=64, levels=0,
+                    r_rel=-1.0, r_abs=-1.0, abs_norm="mean", freq_hz=230e9)
+    if name == "thermal_1025":
+        return dict(common, name=name, a=0.94, inc_deg=163.0, model="thermal",
+                    mp=thermal_params(seed=1), nstokes=4, nx0=129, ny0=129, levels=3,
+                    r_rel=0.01, r_abs=1e-3, abs_norm="max", freq_hz=230e9)
+    raise KeyError(name)
+
+
+def reduced(cfg, nx0, levels):
+    """Same physics on a smaller vertex grid (parity-test sizes)."""
+    c = dict(cfg)
+    c["nx0"] = c["ny0"] = nx0
+    c["levels"] = levels
+    return c

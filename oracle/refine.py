@@ -1,0 +1,199 @@
+"""Level-by-level adaptive refinement, written from the paper (test oracle).
+
+Test infrastructure only.  Follows Gelles et al. 2021:
+
+* Sec. 3.2 ("Adaptive Ray-Tracing by Recursive Subdivision"): trace an
+  n0x x n0y vertex grid, then refine by factors of two, (n) -> (2n-1) points
+  per axis, N times, giving n_x = 2^N (n0x - 1) + 1 (the grid-size equation).
+* Decision rule (Sec. 3.2, after Eqs. 3-4): a new point is ray traced iff the
+  estimated absolute error exceeds R_abs AND the estimated relative error
+  exceeds R_rel; otherwise it is interpolated.
+* Point categories 1-4 (Sec. 3.2, Fig. 2 list): already computed / between
+  two points above and below / between left and right / centre of four
+  corners.  Estimates use the level-n values only.
+* Linear branch of Eqs. 5-6 (and App. A.2): with the four corners and the
+  four continuations on the two diagonals,
+      eps_abs = |(I5+I6+I7+I8) - (I1+I2+I3+I4)| / (16 Ibar_int)
+      eps_rel = |(I5+I6+I7+I8) - (I1+I2+I3+I4)| / (4 (I1+I2+I3+I4)),
+  and the interpolated value is the corner mean (Eq. 14).  Categories 2-3 are
+  the one-axis simplification (App. A), read here as
+      eps_abs = |a+d-b-c| / (8 Ibar_int),  eps_rel = |a+d-b-c| / (4 |b+c|).
+* Ibar_int (Sec. 3.2, after Eq. 6): average of the level-0 interpolant, i.e.
+  the trapezoid-weighted mean of the base grid, fixed after the first pass.
+  Alternatively the level-0 maximum (a "1e-3 max I" tolerance).
+
+Readings where the paper is silent (App. A last paragraph: "appropriate
+modifications" at the edge): per axis, if one continuation point falls outside
+the image, the available one-sided second difference counts twice; if both
+fall outside, the axis is unavailable.  A centre point (category 4) with one
+diagonal unavailable uses twice the other diagonal's term; a point with no
+available axis is traced.  A NaN anywhere in the stencil traces.
+The decision is evaluated without division: trace iff
+|D| > (4 m R_abs) N_abs  and  |D| > (4 R_rel) |S|, m = 2 (1D) or 4 (2D).
+"""
+import numpy as np
+
+from .ray import screen_coords
+
+
+def grid_size(n0, levels):
+    """n = 2^N (n0 - 1) + 1 (Sec. 3.2)."""
+    return (1 << levels) * (n0 - 1) + 1
+
+
+def trapezoid_mean(I0):
+    """Mean of the bilinear interpolant of the base grid over the field of view
+    (trapezoid weights: 1/2 on edges, 1/4 in corners)."""
+    ny, nx = I0.shape
+    wx = np.ones(nx)
+    wx[0] = wx[-1] = 0.5
+    wy = np.ones(ny)
+    wy[0] = wy[-1] = 0.5
+    return float((wy[:, None] * wx[None, :] * I0).sum() / ((nx - 1) * (ny - 1)))
+
+
+def _axis_terms(lo_in, hi_in, lo_out, hi_out, has_lo, has_hi):
+    """Pair sum P = in_lo + in_hi and second-difference sum D for one axis.
+
+    D = (out_lo + out_hi) - P with both continuations present; twice the
+    available one-sided second difference if one is missing.  `inf` marks an
+    axis with both continuations outside the image (unavailable).
+    """
+    P = lo_in + hi_in
+    both = has_lo & has_hi
+    D = np.where(both, (lo_out + hi_out) - P, 0.0)
+    only_hi = ~has_lo & has_hi      # low continuation outside: use high side
+    D = np.where(only_hi, 2.0 * ((hi_out - 2.0 * hi_in) + lo_in), D)
+    only_lo = has_lo & ~has_hi
+    D = np.where(only_lo, 2.0 * ((lo_out - 2.0 * lo_in) + hi_in), D)
+    inf = ~has_lo & ~has_hi
+    return P, D, inf
+
+
+
+def level_stencil(img, nx0, ny0, l, s, nstokes):
+    """Stencil sums for every new point of level l+1 (Sec. 3.2 categories 2-4).
+
+    img holds the level-l values at multiples of 2s (final-grid units).
+    Returns the new points' level-(l+1) indices (p, q), the neighbour sums
+    S per Stokes plane, the second-difference sum D of Stokes I, the
+    no-available-axis flag and the neighbour count m.
+    """
+    nxl, nyl = grid_size(nx0, l + 1), grid_size(ny0, l + 1)
+    q, p = np.meshgrid(np.arange(nyl), np.arange(nxl), indexing="ij")
+    new = (p % 2 == 1) | (q % 2 == 1)
+    p, q = p[new], q[new]
+    cat2 = (p % 2 == 0) & (q % 2 == 1)   # between below/above (y axis)
+    cat3 = (p % 2 == 1) & (q % 2 == 0)   # between left/right (x axis)
+    cat4 = (p % 2 == 1) & (q % 2 == 1)   # centre of four corners
+
+    def val(pp, qq, st):
+        ok = (pp >= 0) & (pp < nxl) & (qq >= 0) & (qq < nyl)
+        pc = np.clip(pp, 0, nxl - 1) * s
+        qc = np.clip(qq, 0, nyl - 1) * s
+        return img[st, qc, pc], ok
+
+    npt = p.size
+    S_all = np.zeros((nstokes, npt))
+    D = np.zeros(npt)
+    inf = np.zeros(npt, dtype=bool)
+    m = np.where(cat4, 4.0, 2.0)
+    # categories 2 and 3: one axis (dx, dy) = (0, 1) or (1, 0)
+    for cat, (dx, dy) in ((cat2, (0, 1)), (cat3, (1, 0))):
+        pc, qc = p[cat], q[cat]
+        for st in range(nstokes):
+            lo_in, _ = val(pc - dx, qc - dy, st)
+            hi_in, _ = val(pc + dx, qc + dy, st)
+            S_all[st, cat] = lo_in + hi_in
+        lo_in, _ = val(pc - dx, qc - dy, 0)
+        hi_in, _ = val(pc + dx, qc + dy, 0)
+        lo_out, has_lo = val(pc - 3 * dx, qc - 3 * dy, 0)
+        hi_out, has_hi = val(pc + 3 * dx, qc + 3 * dy, 0)
+        _, Dc, infc = _axis_terms(lo_in, hi_in, lo_out, hi_out, has_lo, has_hi)
+        D[cat] = Dc
+        inf[cat] = infc
+    # category 4: diagonals x' (I1 -> I4, outer I5, I8), y' (I2 -> I3, outer I6, I7)
+    pc, qc = p[cat4], q[cat4]
+    for st in range(nstokes):
+        i1, _ = val(pc - 1, qc - 1, st)
+        i4, _ = val(pc + 1, qc + 1, st)
+        i2, _ = val(pc + 1, qc - 1, st)
+        i3, _ = val(pc - 1, qc + 1, st)
+        S_all[st, cat4] = (i1 + i4) + (i2 + i3)
+    i1, _ = val(pc - 1, qc - 1, 0)
+    i4, _ = val(pc + 1, qc + 1, 0)
+    i2, _ = val(pc + 1, qc - 1, 0)
+    i3, _ = val(pc - 1, qc + 1, 0)
+    i5, h5 = val(pc - 3, qc - 3, 0)
+    i8, h8 = val(pc + 3, qc + 3, 0)
+    i6, h6 = val(pc + 3, qc - 3, 0)
+    i7, h7 = val(pc - 3, qc + 3, 0)
+    _, Dx, infx = _axis_terms(i1, i4, i5, i8, h5, h8)
+    _, Dy, infy = _axis_terms(i2, i3, i6, i7, h6, h7)
+    D[cat4] = np.where(infx, 2.0 * Dy, np.where(infy, 2.0 * Dx, Dx + Dy))
+    inf[cat4] = infx & infy
+    return p, q, S_all, D, inf, m
+
+def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
+           nstokes=1, forced_level=None):
+    """Adaptive image by recursive subdivision.
+
+    ray_fn(x, y) -> (n, nstokes) array: traces screen points.
+    forced_level: optional final-grid int array; if given, a candidate at
+    level l+1 is traced iff forced_level == l+1 (mask-forced replay).
+
+    Returns dict(img=(nstokes, ny, nx), level=(ny, nx) int8 with -1 for
+    interpolated and l for traced at level l, n_abs, ibar, imax0, per-level
+    candidate and traced counts).
+    """
+    nx, ny = grid_size(nx0, levels), grid_size(ny0, levels)
+    img = np.full((nstokes, ny, nx), np.nan)
+    lev = np.full((ny, nx), -1, dtype=np.int8)
+    st0 = 1 << levels
+    jj, ii = np.meshgrid(np.arange(ny0) * st0, np.arange(nx0) * st0, indexing="ij")
+    x, y = screen_coords(fov, nx, ny, ii.ravel(), jj.ravel())
+    S0 = np.asarray(ray_fn(x, y)).reshape(-1, nstokes)
+    for s in range(nstokes):
+        img[s, jj, ii] = S0[:, s].reshape(ny0, nx0)
+    lev[jj, ii] = 0
+    I0 = img[0, jj, ii]
+    ibar = trapezoid_mean(I0)
+    imax0 = float(I0.max())
+    n_abs = ibar if abs_norm == "mean" else imax0
+    cand, traced = [nx0 * ny0], [nx0 * ny0]
+    for l in range(levels):
+        s = 1 << (levels - l - 1)          # spacing of the level-(l+1) grid
+        p, q, S_all, D, inf, m = level_stencil(img, nx0, ny0, l, s, nstokes)
+        npt = p.size
+        S = S_all[0]
+        thrA = (4.0 * m * r_abs) * n_abs
+        crel = 4.0 * r_rel
+        with np.errstate(invalid="ignore"):
+            dec = inf | np.isnan(D) | np.isnan(S) | (
+                (np.abs(D) > thrA) & (np.abs(D) > crel * np.abs(S)))
+        if forced_level is not None:
+            dec = forced_level[q * s, p * s] == l + 1
+        # interpolate everything first (level-l values only), then trace
+        for st in range(nstokes):
+            img[st, q * s, p * s] = S_all[st] * (1.0 / m)
+        tp, tq = p[dec] * s, q[dec] * s
+        if tp.size:
+            xs, ys = screen_coords(fov, nx, ny, tp, tq)
+            St = np.asarray(ray_fn(xs, ys)).reshape(-1, nstokes)
+            for st in range(nstokes):
+                img[st, tq, tp] = St[:, st]
+        lev[tq, tp] = l + 1
+        cand.append(int(npt))
+        traced.append(int(dec.sum()))
+    n_interp = int((lev < 0).sum())
+    return dict(img=img, level=lev, n_abs=n_abs, ibar=ibar, imax0=imax0,
+                candidates=cand, traced=traced, rays=int(sum(traced)),
+                interp_frac=n_interp / float(nx * ny), nx=nx, ny=ny)
+
+
+def uniform(ray_fn, fov, nx, ny, nstokes=1):
+    """Truth image: a ray through every vertex of the nx x ny grid."""
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    x, y = screen_coords(fov, nx, ny, ii.ravel(), jj.ravel())
+    S = np.asarray(ray_fn(x, y)).reshape(-1, nstokes)
+    return np.stack([S[:, s].reshape(ny, nx) for s in range(nstokes)])

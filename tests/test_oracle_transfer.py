@@ -1,0 +1,249 @@
+"""Pins of the oracle's radiative-transfer pieces.
+
+- Closed-form Lorentz exponential against scipy.linalg.expm (library routine)
+  over random and degenerate coefficient sets.
+- Constant-coefficient slabs: optically thin I = j L, thick I -> j/alpha,
+  pure Faraday rotation rotates (Q, U) by 2 ... rho_V L, and a general IQUV
+  slab converges (second order in the step) to the exact solution
+  integral_0^L expm(-K s) J ds computed by quadrature of expm.
+- Thermal synchrotron emissivity forms against direct numerical integration
+  of the textbook single-electron synchrotron spectrum over the
+  ultra-relativistic Maxwell-Juttner distribution.
+- Kirchhoff: absorption over emission equals 1/B_nu for I, Q, V.
+- Flow model: normalised, Keplerian at the equator outside the ISCO,
+  geodesic (E, L conserved) at the equator inside.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+from scipy import integrate, linalg, special
+
+from oracle import ray
+
+
+def K_matrix(aI, av, rv):
+    aQ, aU, aV = av
+    rQ, rU, rV = rv
+    return np.array([[aI, aQ, aU, aV],
+                     [aQ, aI, rV, -rU],
+                     [aU, -rV, aI, rQ],
+                     [aV, rU, -rQ, aI]])
+
+
+def lexp(aI, av, rv, x):
+    out = np.zeros(16)
+    ray.lib().or_lorentz_exp(aI, ray._dp(np.asarray(av, float)), ray._dp(np.asarray(rv, float)),
+                             x, ray._dp(out))
+    return out.reshape(4, 4)
+
+
+CASES = [
+    (1.0, [0.3, 0.1, -0.2], [2.0, -1.0, 0.5], 0.7),
+    (0.0, [0.0, 0.0, 0.0], [0.0, 0.0, 3.0], 1.3),          # pure rotation
+    (2.0, [1.5, 0.0, 0.0], [0.0, 0.0, 0.0], 0.9),          # pure boost
+    (1.0, [0.5, 0.0, 0.0], [0.5, 0.0, 0.0], 2.0),          # parallel
+    (1.0, [0.5, 0.0, 0.0], [0.0, 0.5, 0.0], 1.5),          # degenerate |a|=|r|, a.r=0
+    (1e-3, [1e-4, 2e-4, 0.0], [1e-5, 0.0, 3e-4], 0.2),     # tiny
+    (40.0, [20.0, 10.0, 5.0], [100.0, -30.0, 8.0], 0.8),   # thick, strongly rotating
+    (1.0, [0.2, 0.3, 0.1], [0.1, 0.1, 0.1], 1e-6),         # tiny step
+]
+
+
+@pytest.mark.parametrize("aI,av,rv,x", CASES)
+def test_lorentz_exp_matches_expm(aI, av, rv, x):
+    E = lexp(aI, av, rv, x)
+    R = linalg.expm(-K_matrix(aI, av, rv) * x)
+    assert np.abs(E - R).max() <= 1e-12 * max(1.0, np.abs(R).max()), np.abs(E - R).max()
+
+
+def test_lorentz_exp_random():
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        av = rng.normal(size=3) * 10 ** rng.uniform(-4, 1)
+        rv = rng.normal(size=3) * 10 ** rng.uniform(-4, 2)
+        aI = np.linalg.norm(av) * (1 + rng.uniform(0, 2))
+        x = 10 ** rng.uniform(-3, 0.5)
+        E = lexp(aI, av, rv, x)
+        R = linalg.expm(-K_matrix(aI, av, rv) * x)
+        assert np.abs(E - R).max() <= 1e-10 * max(1.0, np.abs(R).max())
+
+
+def slab(aI, av, rv, J, L, n):
+    S = np.zeros(4)
+    O = np.eye(4).ravel().copy()
+    h = L / n
+    for _ in range(n):
+        ray.lib().or_transfer_step4(ray._dp(S), ray._dp(O), aI, ray._dp(np.asarray(av, float)),
+                                    ray._dp(np.asarray(rv, float)), ray._dp(np.asarray(J, float)), h)
+    return S
+
+
+def exact_slab(aI, av, rv, J, L):
+    K = K_matrix(aI, av, rv)
+    f = lambda s: linalg.expm(-K * s) @ J
+    out = np.zeros(4)
+    for i in range(4):
+        out[i] = integrate.quad(lambda s: f(s)[i], 0, L, epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+    return out
+
+
+def test_thin_slab():
+    J = np.array([2.0, 0.0, 0.0, 0.0])
+    S = slab(0.0, [0, 0, 0], [0, 0, 0], J, 3.0, 7)
+    assert abs(S[0] - 6.0) < 1e-14
+
+
+def test_thick_slab_source_function():
+    J = np.array([2.0, 0.0, 0.0, 0.0])
+    S = slab(5.0, [0, 0, 0], [0, 0, 0], J, 30.0, 3)     # optically thick steps
+    assert abs(S[0] - 2.0 / 5.0) < 1e-14
+    S1 = slab(5.0, [0, 0, 0], [0, 0, 0], J, 0.3, 1)     # I = (j/a)(1 - e^-aL) exactly
+    assert abs(S1[0] - 0.4 * (1 - np.exp(-1.5))) < 1e-15
+
+
+def test_faraday_rotation_slab():
+    # Q emitted at the far end only: a thin emitting layer behind a rotating slab
+    rho = 0.7
+    S = np.zeros(4)
+    O = np.eye(4).ravel().copy()
+    L = 2.0
+    for _ in range(10):   # pure rotation slab first (camera side)
+        ray.lib().or_transfer_step4(ray._dp(S), ray._dp(O), 0.0, ray._dp(np.zeros(3)),
+                                    ray._dp(np.array([0.0, 0.0, rho])), ray._dp(np.zeros(4)), L / 10)
+    ray.lib().or_transfer_step4(ray._dp(S), ray._dp(O), 0.0, ray._dp(np.zeros(3)),
+                                ray._dp(np.zeros(3)), ray._dp(np.array([1.0, 1.0, 0.0, 0.0])), 1e-3)
+    # dQ/ds = -rho_V U, dU/ds = rho_V Q: (Q,U) rotate by angle rho_V L
+    ang = rho * L
+    assert abs(S[1] - 1e-3 * np.cos(ang)) < 1e-15
+    assert abs(S[2] - 1e-3 * np.sin(ang)) < 1e-15
+
+
+def test_general_slab_second_order():
+    aI, av, rv = 0.8, [0.3, -0.2, 0.1], [1.5, 0.4, -2.0]
+    J = np.array([1.0, 0.4, -0.2, 0.1])
+    L = 2.0
+    ex = exact_slab(aI, av, rv, J, L)
+    errs = [np.abs(slab(aI, av, rv, J, L, n) - ex).max() for n in (20, 40, 80)]
+    assert errs[-1] < 2e-4 * np.abs(ex).max()
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+# ---------------------------------------------------------------- emission
+E_CGS, ME, C = 4.80320471e-10, 9.1093837015e-28, 2.99792458e10
+H = 6.62607015e-27
+
+
+def F_sync(x):
+    """x * integral_x^inf K_{5/3}(t) dt (single-electron synchrotron spectrum)."""
+    return x * integrate.quad(lambda t: special.kv(5.0 / 3.0, t), x, np.inf, limit=200)[0]
+
+
+def G_sync(x):
+    return x * special.kv(2.0 / 3.0, x)
+
+
+def thermal_integral(xM, fn):
+    """(1/x_M) int_0^inf z^2 e^-z fn(x_M / z^2) dz: the ultra-relativistic
+    Maxwell-Juttner average of the single-electron spectrum."""
+    val = integrate.quad(lambda z: z * z * np.exp(-z) * fn(xM / (z * z)), 1e-8, 200.0,
+                         limit=400, epsrel=1e-10)[0]
+    return val / xM
+
+
+def coefs(ne, Th, B, nu, cth):
+    out = np.zeros(8)
+    ray.lib().or_thermal_coefs(ne, Th, B, nu, cth, ray._dp(out))
+    return out
+
+
+@pytest.mark.parametrize("xM", [1.0, 3.0, 10.0, 30.0, 100.0, 300.0])
+def test_emissivity_matches_textbook_integral(xM):
+    ne, Th, B, cth = 1e6, 20.0, 30.0, 0.4
+    sth = np.sqrt(1 - cth * cth)
+    nuB = E_CGS * B / (2 * np.pi * ME * C)
+    nu = xM * 3.0 * nuB * Th * Th * sth / 2.0
+    c = coefs(ne, Th, B, nu, cth)
+    pref = ne * E_CGS ** 2 * nu / (2 * np.sqrt(3) * C * Th * Th)
+    jI = pref * thermal_integral(xM, F_sync)
+    jQ = pref * thermal_integral(xM, G_sync)
+    # the published fitting forms are accurate to a few per cent in this range
+    assert abs(c[0] / jI - 1) < 0.05, (c[0], jI)
+    assert abs(-c[1] / jQ - 1) < 0.05, (c[1], jQ)
+
+
+def test_kirchhoff_and_polarised_fraction():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        ne = 10 ** rng.uniform(3, 8); Th = 10 ** rng.uniform(0, 2.5)
+        B = 10 ** rng.uniform(0, 3); nu = 10 ** rng.uniform(10, 12.5)
+        cth = rng.uniform(-1, 1)
+        c = coefs(ne, Th, B, nu, cth)
+        Bnu = 2 * H * nu ** 3 / C ** 2 / np.expm1(H * nu / (Th * ME * C * C))
+        for j, a in ((0, 3), (1, 4), (2, 5)):
+            assert abs(c[a] * Bnu - c[j]) <= 1e-12 * abs(c[j]) + 1e-300
+        assert c[0] >= 0 and np.hypot(c[1], c[2]) <= 0.99 * c[0] * (1 + 1e-12) + 1e-300
+        assert np.sign(c[2]) == np.sign(cth) or c[2] == 0
+        assert np.sign(c[7]) == np.sign(cth) or c[7] == 0
+
+
+def test_cold_plasma_limit_of_rotativities():
+    """Theta -> 0: rotativities tend to the textbook cold-plasma Faraday
+    rotation 2 n e^2 nu_B cos/(m c nu^2) and conversion n e^2 nu_B^2 sin^2/(m c nu^3)."""
+    ne, B, nu, cth = 1e5, 10.0, 2.3e11, 0.6
+    nuB = E_CGS * B / (2 * np.pi * ME * C)
+    wp2 = 4 * np.pi * ne * E_CGS ** 2 / ME
+    wB = 2 * np.pi * nuB
+    w = 2 * np.pi * nu
+    rV_cold = wp2 * wB * cth / (C * w * w)
+    rQ_cold = wp2 * wB * wB * (1 - cth * cth) / (2 * C * w ** 3)
+    c = coefs(ne, 1e-7, B, nu, cth)
+    assert abs(c[7] / rV_cold - 1) < 1e-5
+    assert abs(-c[6] / rQ_cold - 1) < 1e-5
+
+
+# ---------------------------------------------------------------- flow model
+def bl_cov(a, r, th):
+    Sig = r * r + a * a * np.cos(th) ** 2
+    Del = r * r - 2 * r + a * a
+    s2 = np.sin(th) ** 2
+    g = np.zeros((4, 4))
+    g[0, 0] = -(1 - 2 * r / Sig)
+    g[0, 3] = g[3, 0] = -2 * a * r * s2 / Sig
+    g[1, 1] = Sig / Del
+    g[2, 2] = Sig
+    g[3, 3] = (r * r + a * a + 2 * a * a * r * s2 / Sig) * s2
+    return g
+
+
+def flow(a, r, th):
+    u = np.zeros(4)
+    ray.lib().or_flow_u(a, r, th, ray._dp(u))
+    return u
+
+
+@pytest.mark.parametrize("a", [0.0, 0.5, 0.94, -0.94])
+def test_flow_normalised_keplerian_and_plunging(a):
+    risco = ray.lib().or_r_isco(a)
+    E = np.zeros(1); Lz = np.zeros(1)
+    ray.lib().or_circ_EL(a, risco, ray._dp(E), ray._dp(Lz))
+    if a == 0.0:
+        assert abs(risco - 6.0) < 1e-14 and abs(E[0] - np.sqrt(8.0 / 9.0)) < 1e-14
+    # ISCO = minimum of circular-orbit energy
+    Em, Ep = np.zeros(1), np.zeros(1)
+    ray.lib().or_circ_EL(a, risco * 0.999, ray._dp(Em), ray._dp(np.zeros(1)))
+    ray.lib().or_circ_EL(a, risco * 1.001, ray._dp(Ep), ray._dp(np.zeros(1)))
+    assert Em[0] > E[0] and Ep[0] > E[0]
+    rh = 1 + np.sqrt(1 - a * a)
+    for r in np.linspace(rh * 1.02, 40, 37):
+        for th in (0.2, 0.9, np.pi / 2, 2.5):
+            u = flow(a, r, th)
+            g = bl_cov(a, r, th)
+            assert abs(u @ g @ u + 1) < 1e-14 * (np.abs(u) @ np.abs(g) @ np.abs(u))
+            if th == np.pi / 2:
+                ucov = g @ u
+                if r >= risco:
+                    assert abs(u[3] / u[0] - 1 / (r ** 1.5 + a)) < 1e-12 and u[1] == 0
+                else:
+                    assert abs(-ucov[0] - E[0]) < 1e-10 and abs(ucov[3] - Lz[0]) < 1e-10
+                    assert u[1] < 0
