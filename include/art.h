@@ -1,0 +1,190 @@
+/*
+ * art.h -- C ABI of the adaptive black-hole ray tracer for MI355X (gfx950).
+ *
+ * Method: Gelles, Prather, Palumbo, Johnson, Wong & Georgiev (2021), "The Role
+ * of Adaptive Ray Tracing in Analyzing Black Hole Structure", arXiv:2103.07417.
+ *
+ * The library samples the screen intensity I(x) of a Kerr black hole by
+ * backward ray tracing (Sec. 3, opening paragraph) and builds the image by the
+ * level-by-level recursive subdivision of Sec. 3.2: an n0x x n0y vertex grid is
+ * traced, then each level doubles the resolution, (n) -> (2n - 1) points per
+ * axis, and a new point is traced only when both estimated interpolation
+ * errors exceed their tolerances (eps_abs > R_abs and eps_rel > R_rel,
+ * Eqs. 5-6 linear branch); otherwise it is linearly interpolated.  After N
+ * levels n_x = 2^N (n0x - 1) + 1.
+ *
+ * Conventions (all entry points):
+ *  - Units G = c = M = 1; screen coordinates (alpha, beta) are in M at the
+ *    hole's distance; x = -fov/2 + i fov/(nx-1), square cells, y centred.
+ *  - Buffers named *_dev are device pointers owned by the caller (the
+ *    library never frees them).  Images are planar FP64:
+ *    image[s][y][x], s = 0..nstokes-1 (I, Q, U, V).  The level map is int8
+ *    [y][x]: -1 interpolated, l >= 0 traced at refinement level l.  The
+ *    feature buffer is art_ray_feat[y][x] (only traced pixels are written).
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Work is enqueued asynchronously; a call that fills an art_stats
+ *    synchronises the stream before returning.
+ *  - Every call returns ART_OK (0) or a negative error code; the message of
+ *    the last failure on the calling thread is art_last_error().
+ *  - Scratch memory (trace lists, counters, partial sums) is owned by the
+ *    library, grown on demand and kept per device until art_release().
+ */
+#ifndef ART_H
+#define ART_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ART_OK        0
+#define ART_EINVAL   -1   /* invalid argument (|a| >= 1, n0 < 2, fov <= 0, ...) */
+#define ART_ENOMEM   -2   /* device allocation failed */
+#define ART_EDEVICE  -3   /* HIP runtime error */
+#define ART_ENUMERIC -4   /* a NaN reached the image (rays flagged in features) */
+
+/* emission models */
+#define ART_EMIS_TOY_DISK     1   /* j = r^-2 exp(-z^2/(2(h r)^2)), r > r_in, no absorption */
+#define ART_EMIS_THERMAL      2   /* power-law thermal plasma, polarised synchrotron */
+#define ART_EMIS_SCREEN_RING 10   /* closed-form screen intensity (no ray tracing) */
+#define ART_EMIS_SCREEN_POLY 11   /* quadratic screen intensity (no ray tracing) */
+
+/* absolute-error normalisation N_abs */
+#define ART_NORM_MEAN 0   /* Ibar_int: mean of the level-0 interpolant (Sec. 3.2) */
+#define ART_NORM_MAX  1   /* maximum of the level-0 image */
+
+/* per-ray status */
+#define ART_RAY_OK       0
+#define ART_RAY_CAPTURED 1
+#define ART_RAY_ESCAPED  2
+#define ART_RAY_STEPCAP  3
+#define ART_RAY_THICK    4
+#define ART_RAY_NAN      5
+
+/* transfer precision */
+#define ART_PREC_FP64  0  /* geodesic, coefficients and transfer in FP64 */
+#define ART_PREC_MIXED 1  /* FP64 geodesic, FP32 plasma/coefficients/transfer */
+
+typedef struct {
+    double a_spin;                 /* dimensionless spin, |a| < 1 */
+} art_spacetime;
+
+typedef struct {
+    double r_cam;                  /* camera radius [M], > horizon */
+    double inc_deg;                /* inclination [deg], 0 < inc < 180 */
+    double fov_M;                  /* screen width [M] at the hole's distance */
+    double r_out;                  /* escape radius [M] (<= 0: r_cam) */
+    int32_t nx0, ny0;              /* base vertex grid, >= 2 each */
+    int32_t levels;                /* refinement levels N, 0..20 */
+    int32_t pad;
+} art_camera;
+
+typedef struct {
+    int32_t kind;                  /* ART_EMIS_* */
+    int32_t pad;
+    double freq_hz;                /* observing frequency */
+    double mass_msun;              /* black-hole mass (sets the length unit GM/c^2) */
+    double params[16];             /* model constants, by kind:
+        TOY_DISK:    [0] r_in [M], [1] h/r
+        THERMAL:     [0] n0 [cm^-3], [1] Theta0, [2] plasma beta at r_ref,
+                     [3] r_ref [M], [4] field phase psi0 [rad], [5] outer
+                     emission radius [M], [6..8] power-law indices of n_e,
+                     Theta_e and |B| (n_e = n0 r^-[6], Theta_e = Theta0 r^-[7],
+                     |B| ~ r^-[8]; electron pressure n_e m c^2 Theta_e sets
+                     |B| at r_ref from beta)
+        SCREEN_RING: [0] radius, [1] width, [2] diffuse amplitude, [3] diffuse scale
+        SCREEN_POLY: I = [0] + [1] x + [2] y + [3] x^2 + [4] x y + [5] y^2  */
+} art_emission;
+
+typedef struct {
+    double r_rel;                  /* R_rel (Sec. 3.2); < 0 traces every point */
+    double r_abs;                  /* R_abs (Sec. 3.2) */
+    int32_t abs_norm;              /* ART_NORM_MEAN or ART_NORM_MAX */
+    int32_t pad;
+} art_refine;
+
+typedef struct {
+    int32_t nstokes;               /* 1 (I) or 4 (I, Q, U, V) */
+    int32_t precision;             /* ART_PREC_* */
+    int32_t max_steps;             /* geodesic step cap (> 0) */
+    int32_t pad;
+    double eps;                    /* step-rule accuracy, 0 < eps <= 0.5 */
+} art_transfer;
+
+typedef struct {
+    double* image_dev;             /* [nstokes][ny][nx] FP64, required */
+    int8_t* level_dev;             /* [ny][nx], required by art_render */
+    void* feat_dev;                /* art_ray_feat[ny][nx] or NULL */
+    int32_t nx, ny;                /* must equal the camera's final grid */
+} art_image;
+
+typedef struct {
+    float rmin;                    /* minimum Boyer-Lindquist radius reached */
+    int32_t ncross;                /* equatorial crossings (sign changes of cos theta) */
+    int32_t steps;                 /* geodesic steps taken */
+    int32_t status;                /* ART_RAY_* */
+} art_ray_feat;
+
+typedef struct {
+    int64_t rays_traced;           /* base + refined rays */
+    int64_t candidates[32];        /* per level: points examined (level 0: base) */
+    int64_t traced[32];            /* per level: points ray traced */
+    int64_t steps_total;           /* geodesic steps over all traced rays */
+    int64_t status_hist[8];        /* rays per ART_RAY_* status */
+    double interp_frac;            /* Sec. 4.1, Eq. 7 */
+    double ibar_int;               /* trapezoid mean of the level-0 image */
+    double imax0;                  /* maximum of the level-0 image */
+    double n_abs;                  /* normalisation used for eps_abs */
+    int64_t steps_emit;            /* steps that evaluated emission and transfer */
+    double t_trace_ms;             /* summed duration of the tracing kernels (HIP events) */
+    int32_t trace_launches;        /* number of tracing-kernel launches */
+    int32_t levels;
+} art_stats;
+
+/* Final grid size n = 2^N (n0 - 1) + 1 per axis (Sec. 3.2) and the image size
+ * in bytes for nstokes planes.  No device work. */
+int art_image_size(const art_camera* cam, int32_t nstokes,
+                   int32_t* nx, int32_t* ny, size_t* image_bytes);
+
+/* Adaptive render (Sec. 3.2): trace the base grid, then for each level
+ * estimate, interpolate, compact the points to trace (wavefront ballot) and
+ * trace them with the persistent work-queue kernel.  The level loop runs on
+ * the device without host synchronisation.  If st != NULL the stream is
+ * synchronised and the statistics are filled; then ART_ENUMERIC is returned
+ * if any traced ray produced a NaN. */
+int art_render(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+               const art_refine* rf, const art_transfer* tr, art_image* out,
+               art_stats* st, void* stream);
+
+/* Uniform render: one ray per vertex of the camera's final grid (the "truth"
+ * image of Sec. 4.1).  The level map, if given, is set to 0 everywhere. */
+int art_render_uniform(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                       const art_transfer* tr, art_image* out, art_stats* st, void* stream);
+
+/* Trace n arbitrary screen points (alpha_dev[i], beta_dev[i]) [M]; writes
+ * stokes_dev[i*nstokes + s] (FP64) and, if feat_dev != NULL, art_ray_feat[i].
+ * The camera's grid fields are ignored. */
+int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                     const art_transfer* tr, int64_t n, const double* alpha_dev,
+                     const double* beta_dev, double* stokes_dev, void* feat_dev,
+                     void* stream);
+
+/* Image metrics of Sec. 4.1 on n FP64 values (one Stokes plane), computed on
+ * the device with a deterministic two-pass reduction; synchronises:
+ *   flux error = |sum t - sum a| / |sum t|   (Eq. 8)
+ *   MSE        = sum (t - a)^2 / sum t^2     (Eq. 9)                      */
+int art_metrics(const double* truth_dev, const double* approx_dev, int64_t n,
+                double* flux_error, double* mse, void* stream);
+
+/* Last error message of the calling thread ("" if none). */
+const char* art_last_error(void);
+
+/* Free the library's scratch memory on every device (after synchronising). */
+int art_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ART_H */

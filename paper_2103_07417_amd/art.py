@@ -1,0 +1,245 @@
+"""Thin ctypes binding of libart.so (argument marshalling only).
+
+Every step of the render runs in the HIP kernels behind the C ABI declared in
+include/art.h; this module builds the parameter blocks, allocates the output
+tensors with PyTorch on the current CUDA (HIP) device and passes raw pointers
+and the current stream.  There is no CPU fallback: if the library is missing
+or no GPU is present, calls raise.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libart.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "art.h")
+
+EMIS = {"toy_disk": 1, "thermal": 2, "screen_ring": 10, "screen_poly": 11}
+NORM = {"mean": 0, "max": 1}
+PREC = {"fp64": 0, "mixed": 1}
+STATUS_NAMES = ("ok", "captured", "escaped", "step_cap", "thick", "nan")
+
+
+class ArtError(RuntimeError):
+    pass
+
+
+class Spacetime(ctypes.Structure):
+    _fields_ = [("a_spin", ctypes.c_double)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("r_cam", ctypes.c_double), ("inc_deg", ctypes.c_double),
+                ("fov_M", ctypes.c_double), ("r_out", ctypes.c_double),
+                ("nx0", ctypes.c_int32), ("ny0", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Emission(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("freq_hz", ctypes.c_double), ("mass_msun", ctypes.c_double),
+                ("params", ctypes.c_double * 16)]
+
+
+class Refine(ctypes.Structure):
+    _fields_ = [("r_rel", ctypes.c_double), ("r_abs", ctypes.c_double),
+                ("abs_norm", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Transfer(ctypes.Structure):
+    _fields_ = [("nstokes", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("eps", ctypes.c_double)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("image_dev", ctypes.c_void_p), ("level_dev", ctypes.c_void_p),
+                ("feat_dev", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rays_traced", ctypes.c_int64), ("candidates", ctypes.c_int64 * 32),
+                ("traced", ctypes.c_int64 * 32), ("steps_total", ctypes.c_int64),
+                ("status_hist", ctypes.c_int64 * 8), ("interp_frac", ctypes.c_double),
+                ("ibar_int", ctypes.c_double), ("imax0", ctypes.c_double),
+                ("n_abs", ctypes.c_double), ("steps_emit", ctypes.c_int64),
+                ("t_trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int32),
+                ("levels", ctypes.c_int32)]
+
+
+FEAT_DTYPE = np.dtype([("rmin", np.float32), ("ncross", np.int32),
+                       ("steps", np.int32), ("status", np.int32)])
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions declared in include/art.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(art_\w+)\s*\(", txt, re.M)))
+
+
+def lib():
+    """Load libart.so (raises ArtError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ArtError("libart.so not found at %s: run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        P = ctypes.POINTER
+        L.art_image_size.argtypes = [P(Camera), ctypes.c_int32, P(ctypes.c_int32),
+                                     P(ctypes.c_int32), P(ctypes.c_size_t)]
+        L.art_render.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine), P(Transfer),
+                                 P(Image), P(Stats), vp]
+        L.art_render_uniform.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Transfer),
+                                         P(Image), P(Stats), vp]
+        L.art_trace_points.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Transfer), i64,
+                                       vp, vp, vp, vp, vp]
+        L.art_metrics.argtypes = [vp, vp, i64, P(ctypes.c_double), P(ctypes.c_double), vp]
+        L.art_last_error.restype = ctypes.c_char_p
+        L.art_last_error.argtypes = []
+        L.art_release.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().art_last_error().decode()
+        raise ArtError("art error %d: %s" % (rc, msg))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise ArtError("no GPU available: the HIP path has no CPU fallback")
+    return torch
+
+
+def blocks(cfg):
+    """C parameter blocks from a workload dictionary."""
+    sp = Spacetime(float(cfg["a"]))
+    cam = Camera(float(cfg["r_cam"]), float(cfg["inc_deg"]), float(cfg["fov"]),
+                 float(cfg.get("r_out", cfg["r_cam"])), int(cfg.get("nx0", 2)),
+                 int(cfg.get("ny0", cfg.get("nx0", 2))), int(cfg.get("levels", 0)), 0)
+    em = Emission()
+    em.kind = EMIS[cfg["model"]]
+    em.freq_hz = float(cfg.get("freq_hz", 230e9))
+    em.mass_msun = float(cfg.get("mass_msun", 4.0e6))
+    mp = list(cfg.get("mp", []))
+    for i in range(16):
+        em.params[i] = float(mp[i]) if i < len(mp) else 0.0
+    rf = Refine(float(cfg.get("r_rel", -1.0)), float(cfg.get("r_abs", -1.0)),
+                NORM[cfg.get("abs_norm", "mean")], 0)
+    tr = Transfer(int(cfg.get("nstokes", 1)), PREC[cfg.get("precision", "fp64")],
+                  int(cfg.get("max_steps", 100000)), 0, float(cfg.get("eps", 0.03)))
+    return sp, cam, em, rf, tr
+
+
+def image_size(cfg):
+    _, cam, _, _, tr = blocks(cfg)
+    nx, ny, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(lib().art_image_size(ctypes.byref(cam), tr.nstokes, ctypes.byref(nx), ctypes.byref(ny),
+                                ctypes.byref(nb)))
+    return nx.value, ny.value
+
+
+def _stream(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def stats_dict(st):
+    L = st.levels
+    return dict(rays=int(st.rays_traced), traced=[int(st.traced[i]) for i in range(L + 1)],
+                candidates=[int(st.candidates[i]) for i in range(L + 1)],
+                steps=int(st.steps_total),
+                status={STATUS_NAMES[k]: int(st.status_hist[k]) for k in range(6)},
+                interp_frac=float(st.interp_frac), ibar=float(st.ibar_int),
+                imax0=float(st.imax0), n_abs=float(st.n_abs), levels=L,
+                steps_emit=int(st.steps_emit), t_trace_ms=float(st.t_trace_ms),
+                trace_launches=int(st.trace_launches))
+
+
+def alloc(cfg, feat=False):
+    """Output tensors for a render of cfg: image (nstokes, ny, nx) float64,
+    level map (ny, nx) int8, optional features (ny, nx, 4) int32 view."""
+    torch = _torch()
+    nx, ny = image_size(cfg)
+    ns = int(cfg.get("nstokes", 1))
+    img = torch.empty((ns, ny, nx), dtype=torch.float64, device="cuda")
+    lev = torch.empty((ny, nx), dtype=torch.int8, device="cuda")
+    ft = torch.empty((ny, nx, 4), dtype=torch.int32, device="cuda") if feat else None
+    return img, lev, ft
+
+
+def _image(img, lev, ft):
+    ny, nx = img.shape[1], img.shape[2]
+    return Image(img.data_ptr(), lev.data_ptr() if lev is not None else None,
+                 ft.data_ptr() if ft is not None else None, nx, ny)
+
+
+def render(cfg, out=None, feat=False, stats=True, stream=None):
+    """Adaptive render (Sec. 3.2).  Returns (image, level, feat, stats)."""
+    torch = _torch()
+    sp, cam, em, rf, tr = blocks(cfg)
+    img, lev, ft = out if out is not None else alloc(cfg, feat)
+    im = _image(img, lev, ft)
+    st = Stats()
+    rc = lib().art_render(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em), ctypes.byref(rf),
+                          ctypes.byref(tr), ctypes.byref(im),
+                          ctypes.byref(st) if stats else None, _stream(torch, stream))
+    _check(rc)
+    return img, lev, ft, (stats_dict(st) if stats else None)
+
+
+def render_uniform(cfg, out=None, feat=False, stats=True, stream=None):
+    """One ray per vertex of the final grid.  Returns (image, feat, stats)."""
+    torch = _torch()
+    sp, cam, em, rf, tr = blocks(cfg)
+    img, lev, ft = out if out is not None else alloc(cfg, feat)
+    im = _image(img, lev, ft)
+    st = Stats()
+    rc = lib().art_render_uniform(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em),
+                                  ctypes.byref(tr), ctypes.byref(im),
+                                  ctypes.byref(st) if stats else None, _stream(torch, stream))
+    _check(rc)
+    return img, ft, (stats_dict(st) if stats else None)
+
+
+def trace_points(cfg, alpha, beta, feat=True, stream=None):
+    """Trace arbitrary screen points.  alpha, beta: CUDA float64 tensors.
+    Returns (stokes (n, nstokes) float64, feat (n, 4) int32 or None)."""
+    torch = _torch()
+    sp, cam, em, rf, tr = blocks(cfg)
+    alpha = alpha.contiguous()
+    beta = beta.contiguous()
+    n = alpha.numel()
+    S = torch.empty((n, tr.nstokes), dtype=torch.float64, device=alpha.device)
+    ft = torch.empty((n, 4), dtype=torch.int32, device=alpha.device) if feat else None
+    rc = lib().art_trace_points(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em),
+                                ctypes.byref(tr), n, alpha.data_ptr(), beta.data_ptr(),
+                                S.data_ptr(), ft.data_ptr() if ft is not None else None,
+                                _stream(torch, stream))
+    _check(rc)
+    return S, ft
+
+
+def metrics(truth, approx, stream=None):
+    """(flux error, normalised MSE) of two same-shape FP64 CUDA tensors (Eqs. 8-9)."""
+    torch = _torch()
+    t = truth.contiguous()
+    a = approx.contiguous()
+    fe, mse = ctypes.c_double(), ctypes.c_double()
+    _check(lib().art_metrics(t.data_ptr(), a.data_ptr(), t.numel(), ctypes.byref(fe),
+                             ctypes.byref(mse), _stream(torch, stream)))
+    return fe.value, mse.value
+
+
+def feat_numpy(ft):
+    """Structured numpy view (rmin, ncross, steps, status) of a feature tensor."""
+    a = ft.cpu().contiguous().numpy()
+    return a.view(FEAT_DTYPE).reshape(a.shape[:-1])

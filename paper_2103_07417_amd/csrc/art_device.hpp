@@ -1,0 +1,500 @@
+// art_device.hpp -- per-ray device physics for the adaptive black-hole ray
+// tracer (gfx950).  One lane integrates one ray.
+//
+// The paper leaves everything per ray to an external GRRT code (Sec. 4.1,
+// "Models and Implementation"); only "trace a ray per sampled screen point and
+// return I (or I, Q, U, V)" is fixed (Sec. 3 opening paragraph; Sec. 6 last
+// paragraph).  The discretisation implemented here is this project's method:
+//   * Kerr spacetime (M = 1), spherical Kerr-Schild coordinates, Hamiltonian
+//     geodesic with conserved k_t, k_phi; state (r, th, ph, k_r, k_th); RK4;
+//     step h = eps clamp(r/20,1,4) / (|dr|/r + |dth| + |dph|), at most half the
+//     coordinate distance to the horizon when moving inward.
+//   * k = reversed photon momentum with k.u_cam = +1 (backward tracing).
+//   * Termination: r < 1.01 r_h, r > r_out outgoing, step cap, or the
+//     transmission of I below 1e-12.
+//   * Plasma, coefficients and the transfer update once per step at the
+//     arithmetic midpoint of the step's end states.
+//   * Polarised transfer by one-pass backward accumulation of the observer
+//     propagator O (S += O Delta, O <- O exp(-K h)), exp of the Lorentz-algebra
+//     part of K in closed form; emission propagated to its optical-depth
+//     weighted mean depth.
+//   * Polarisation frame from the Walker-Penrose constant of the camera's
+//     screen-up vector compared with that of the projected field.
+// Geometry runs in FP64; the plasma model, coefficients and transfer run in
+// the template type R (double, or float for the mixed-precision policy).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace art {
+
+enum : int { RAY_OK = 0, RAY_CAPTURED = 1, RAY_ESCAPED = 2, RAY_STEPCAP = 3,
+             RAY_THICK = 4, RAY_NAN = 5 };
+enum : int { MODEL_TOY = 1, MODEL_THERMAL = 2, MODEL_SCREEN_RING = 10, MODEL_SCREEN_POLY = 11 };
+
+// Kernel-side description of one render.  Filled on the host.
+struct Params {
+    double a, rh, rstop;
+    double r_cam, th_cam, r_out, eps;
+    double x0, y0, dx;             // screen coordinates of the final grid
+    int32_t nx, ny;
+    // ZAMO frame and BL metric at the camera
+    double c_al, c_om, c_er, c_eh, c_ep;
+    double c_gtt, c_gtp, c_grr, c_ghh, c_gpp, c_del;
+    // equatorial flow: ISCO radius, energy, angular momentum
+    double risco, Eis, Lis;
+    int32_t model, nstokes, max_steps, pad;
+    double freq, L_cm;
+    double mp[16];
+    double Bref, r_ref, psi_c, psi_s;   // thermal: |B| at r_ref, field phase
+};
+
+struct RayFeat { float rmin; int32_t ncross; int32_t steps; int32_t status; };
+
+// --------------------------------------------------------------- constants
+constexpr double kE  = 4.80320471e-10;     // electron charge [esu]
+constexpr double kMe = 9.1093837015e-28;   // electron mass [g]
+constexpr double kC  = 2.99792458e10;      // speed of light [cm/s]
+constexpr double kH  = 6.62607015e-27;     // Planck constant [erg s]
+constexpr double kPi = 3.14159265358979323846;
+
+// math wrappers resolving to the precision of R
+__device__ __forceinline__ double fexp(double x) { return ::exp(x); }
+__device__ __forceinline__ float  fexp(float x)  { return ::expf(x); }
+__device__ __forceinline__ double fexpm1(double x) { return ::expm1(x); }
+__device__ __forceinline__ float  fexpm1(float x)  { return ::expm1f(x); }
+__device__ __forceinline__ double fsqrt(double x) { return ::sqrt(x); }
+__device__ __forceinline__ float  fsqrt(float x)  { return ::sqrtf(x); }
+__device__ __forceinline__ double fcbrt(double x) { return ::cbrt(x); }
+__device__ __forceinline__ float  fcbrt(float x)  { return ::cbrtf(x); }
+__device__ __forceinline__ double flog1p(double x) { return ::log1p(x); }
+__device__ __forceinline__ float  flog1p(float x)  { return ::log1pf(x); }
+__device__ __forceinline__ double flog(double x) { return ::log(x); }
+__device__ __forceinline__ float  flog(float x)  { return ::logf(x); }
+__device__ __forceinline__ double fsin(double x) { return ::sin(x); }
+__device__ __forceinline__ float  fsin(float x)  { return ::sinf(x); }
+__device__ __forceinline__ double fabs_(double x) { return ::fabs(x); }
+__device__ __forceinline__ float  fabs_(float x)  { return ::fabsf(x); }
+
+// ------------------------------------------------------ geodesic right-hand side
+// Inverse Kerr-Schild metric: g^tt = -(1+2r/S), g^tr = 2r/S, g^rr = D/S,
+// g^rph = a/S, g^thth = 1/S, g^phph = 1/(S sin^2).  2H = -kt^2 + Qf/S with
+// Qf = -2r kt^2 + 4r kt kr + D kr^2 + 2a kr kph + kth^2 + kph^2/sin^2.
+// Returns cos(theta) of the evaluation point (used for crossing counts).
+__device__ __forceinline__ double geo_rhs(double a, double kt, double kph,
+                                          const double y[5], double dy[5])
+{
+    const double r = y[0], kr = y[3], kth = y[4];
+    double s, c;
+    ::sincos(y[1], &s, &c);
+    const double s2 = s * s;
+    const double Sig = r * r + a * a * c * c;
+    const double Del = r * r - 2.0 * r + a * a;
+    const double iS = 1.0 / Sig;
+    double Lph = 0.0, Lpo = 0.0, dQth = 0.0;
+    if (kph != 0.0) {
+        const double is2 = 1.0 / s2;
+        Lpo = kph * is2;
+        Lph = kph * Lpo;
+        dQth = -2.0 * Lph * c / s;
+    }
+    const double kt2 = kt * kt;
+    const double Qf = -2.0 * r * kt2 + 4.0 * r * kt * kr + Del * kr * kr
+                      + 2.0 * a * kr * kph + kth * kth + Lph;
+    const double dQr = -2.0 * kt2 + 4.0 * kt * kr + (2.0 * r - 2.0) * kr * kr;
+    const double dSth = -2.0 * a * a * c * s;
+    const double QiS2 = Qf * iS * iS;
+    dy[0] = (2.0 * r * kt + Del * kr + a * kph) * iS;
+    dy[1] = kth * iS;
+    dy[2] = (a * kr + Lpo) * iS;
+    dy[3] = -0.5 * (dQr * iS - 2.0 * r * QiS2);
+    dy[4] = -0.5 * (dQth * iS - dSth * QiS2);
+    return c;
+}
+
+// ------------------------------------------------------------ Walker-Penrose
+// kappa = (A1 - i A2)(r - i a cos th) with (BL contravariant components)
+//   A1 = (k^t f^r - k^r f^t) + a sin^2 (k^r f^ph - k^ph f^r)
+//   A2 = [(r^2+a^2)(k^ph f^th - k^th f^ph) - a (k^t f^th - k^th f^t)] sin
+__device__ __forceinline__ void walker_penrose(double a, double r, double s, double c,
+                                               const double k[4], const double f[4],
+                                               double& re, double& im)
+{
+    const double A1 = (k[0] * f[1] - k[1] * f[0]) + a * s * s * (k[1] * f[3] - k[3] * f[1]);
+    const double A2 = ((r * r + a * a) * (k[3] * f[2] - k[2] * f[3]) - a * (k[0] * f[2] - k[2] * f[0])) * s;
+    re = A1 * r - A2 * a * c;
+    im = -(A1 * a * c + A2 * r);
+}
+
+// --------------------------------------------------------------- ray start
+struct RayStart {
+    double y[5];
+    double kt, kph;
+    double k0r, k0i;      // Walker-Penrose constant of the polarisation reference
+};
+
+// Pinhole camera: backward direction d = (-r_cam e_r - beta e_th + alpha e_ph)/|.|
+// in the ZAMO frame at (r_cam, th_cam, 0); k = d - e_(t); reference = screen up
+// (-e_th) projected orthogonal to d.
+__device__ __forceinline__ void camera_start(const Params& P, double al, double be, RayStart& R)
+{
+    const double r = P.r_cam;
+    const double inrm = 1.0 / ::sqrt(r * r + al * al + be * be);
+    const double dr = -r * inrm, dh = -be * inrm, dp = al * inrm;
+    const double iual = 1.0 / P.c_al;
+    const double ku_t = -iual;
+    const double ku_r = dr * P.c_er;
+    const double ku_h = dh * P.c_eh;
+    const double ku_p = dp * P.c_ep - P.c_om * iual;
+    const double kt = P.c_gtt * ku_t + P.c_gtp * ku_p;
+    const double kr_bl = P.c_grr * ku_r;
+    const double kth = P.c_ghh * ku_h;
+    const double kph = P.c_gtp * ku_t + P.c_gpp * ku_p;
+    const double iD = 1.0 / P.c_del;
+    R.y[0] = r;
+    R.y[1] = P.th_cam;
+    R.y[2] = 0.0;
+    R.y[3] = kr_bl - (2.0 * r * iD) * kt - (P.a * iD) * kph;
+    R.y[4] = kth;
+    R.kt = kt;
+    R.kph = kph;
+    // polarisation reference: (0,-1,0) - (d.(0,-1,0)) d, normalised
+    double fr = dh * dr, fh = -1.0 + dh * dh, fp = dh * dp;
+    const double ifn = 1.0 / ::sqrt(fr * fr + fh * fh + fp * fp);
+    fr *= ifn; fh *= ifn; fp *= ifn;
+    const double kup[4] = { ku_t, ku_r, ku_h, ku_p };
+    const double fup[4] = { 0.0, fr * P.c_er, fh * P.c_eh, fp * P.c_ep };
+    double s, c;
+    ::sincos(P.th_cam, &s, &c);
+    walker_penrose(P.a, r, s, c, kup, fup, R.k0r, R.k0i);
+}
+
+// ------------------------------------------------------------- fluid model
+// ZAMO-frame 3-velocity of the equatorial flow at radius r (Keplerian
+// Omega = 1/(r^1.5 + a) outside the ISCO, the plunging geodesic with the ISCO
+// energy and angular momentum inside), applied at every theta.
+__device__ __forceinline__ void flow_v3(const Params& P, double r, double& vr, double& vp)
+{
+    const double a = P.a;
+    const double Del = r * r - 2.0 * r + a * a;
+    const double A = (r * r + a * a) * (r * r + a * a) - a * a * Del;
+    const double al = ::sqrt(r * r * Del / A);
+    const double om = 2.0 * a * r / A;
+    const double vpi = ::sqrt(A) / r;
+    if (r >= P.risco) {
+        const double Om = 1.0 / (r * ::sqrt(r) + a);
+        vp = vpi * (Om - om) / al;
+        vr = 0.0;
+    } else {
+        const double Gam = (P.Eis - om * P.Lis) / al;
+        vp = (P.Lis / vpi) / Gam;
+        const double q = 1.0 - 1.0 / (Gam * Gam) - vp * vp;
+        vr = -::sqrt(q > 0.0 ? q : 0.0);
+    }
+}
+
+// Everything the transfer needs at one point, per unit affine length.
+template <typename R>
+struct Coef {
+    R jI, jQ, jU, jV;     // emission (J)
+    R aI, aQ, aU, aV;     // absorption
+    R rQ, rU, rV;         // rotation
+};
+
+template <typename R>
+__device__ __forceinline__ void thermal_coefs(R ne, R Th, R B, R nu, R cth,
+                                              R& jI, R& jQ, R& jV, R& aI, R& aQ, R& aV,
+                                              R& rQ, R& rV)
+{
+    const R e2 = R(kE * kE);
+    const R sth2 = cth * cth < R(1) ? R(1) - cth * cth : R(0);
+    const R sth = fsqrt(sth2);
+    const R nuB = R(kE / (2.0 * kPi * kMe * kC)) * B;
+    const R lg = flog1p(R(2) * Th);
+    const R gV = lg / (R(2) * Th * Th + lg);
+    const R gQ = R(1) / (R(1) + R(2) * Th) + R(6) * Th;
+    const R imc = R(1.0 / (kMe * kC));
+    rV = R(2) * ne * e2 * nuB * cth * imc / (nu * nu) * gV;
+    rQ = -ne * e2 * nuB * nuB * sth2 * imc / (nu * nu * nu) * gQ;
+    jI = jQ = jV = aI = aQ = aV = R(0);
+    if (sth < R(1e-10)) return;
+    const R x = R(2) * nu / (R(3) * nuB * Th * Th * sth);
+    const R x13 = fcbrt(x);
+    const R xm13 = R(1) / x13, xm23 = xm13 * xm13;
+    const R ex = fexp(R(-1.8899) * x13);
+    const R II = R(2.5651) * (R(1) + R(1.92) * xm13 + R(0.9977) * xm23) * ex;
+    const R IQ = R(2.5651) * (R(1) + R(0.932) * xm13 + R(0.4998) * xm23) * ex;
+    const R IV = (R(1.8138) / x + R(3.423) * xm23 + R(0.02955) / fsqrt(x) + R(2.0377) * xm13) * ex;
+    const R pref = ne * e2 * nu / (R(2.0 * 1.7320508075688772 * kC) * Th * Th);
+    R jI_ = pref * II;
+    R jQ_ = pref * IQ;
+    R jV_ = pref * (R(4) * cth / (R(3) * Th * sth)) * IV;
+    const R P = fsqrt(jQ_ * jQ_ + jV_ * jV_);
+    if (P > R(0.99) * jI_) {
+        const R sc = R(0.99) * jI_ / P;
+        jQ_ *= sc; jV_ *= sc;
+    }
+    // 1/B_nu = expm1(q) c^2 / (2 h nu^3) with q = h nu / (Theta m c^2), written as
+    // (expm1(q)/q) / (2 Theta m nu^2) so that no factor leaves the FP32 range
+    const R q = R(kH / (kMe * kC * kC)) * nu / Th;
+    const R phq = q < R(1e-6) ? R(1) + R(0.5) * q : fexpm1(q) / q;
+    const R iBnu = phq / (R(2) * Th * (R(kMe) * nu) * nu);
+    jI = jI_; jQ = -jQ_; jV = jV_;
+    aI = jI_ * iBnu; aQ = -jQ_ * iBnu; aV = jV_ * iBnu;
+}
+
+// Plasma and coefficients at a midpoint.  Returns false where nothing emits.
+template <typename R, int MODEL>
+__device__ __forceinline__ bool plasma_point(const Params& P, double r, double th,
+                                             double kt, double kph, double kr_ks, double kth,
+                                             double k0r, double k0i, Coef<R>& C)
+{
+    const double a = P.a;
+    if (r <= P.rh * 1.0001) return false;
+    if constexpr (MODEL == MODEL_TOY) {
+        if (r <= P.mp[0]) return false;
+    } else {
+        if (r >= P.mp[5]) return false;
+    }
+    double s, c;
+    ::sincos(th, &s, &c);
+    const double s2 = s * s;
+    const double Sig = r * r + a * a * c * c;
+    const double Del = r * r - 2.0 * r + a * a;
+    const double A = (r * r + a * a) * (r * r + a * a) - a * a * Del * s2;
+    const double iD = 1.0 / Del;
+    const double kr_bl = kr_ks + (2.0 * r * iD) * kt + (a * iD) * kph;
+    // ZAMO frame at (r, th)
+    const double zal = ::sqrt(Sig * Del / A);
+    const double zom = 2.0 * a * r / A;
+    const double zer = ::sqrt(Del / Sig);
+    const double zep = 1.0 / (::sqrt(A / Sig) * s);
+    double vr, vp;
+    flow_v3(P, r, vr, vp);
+    const double Gam = 1.0 / ::sqrt(1.0 - vr * vr - vp * vp);
+    const double u0 = Gam / zal, u1 = Gam * vr * zer, u3 = Gam * (zom / zal + vp * zep);
+    const double ku = kt * u0 + kr_bl * u1 + kph * u3;
+    if constexpr (MODEL == MODEL_TOY) {
+        const double hr = P.mp[1];
+        const double j = ::exp(-c * c / (2.0 * hr * hr)) / (r * r);
+        C.jI = R(j / (ku * ku));
+        C.jQ = C.jU = C.jV = R(0);
+        C.aI = C.aQ = C.aU = C.aV = R(0);
+        C.rQ = C.rU = C.rV = R(0);
+        return true;
+    } else {
+    // thermal power-law plasma: scalars in R
+    const R lr = flog(R(r));
+    const R ne = R(P.mp[0]) * fexp(-R(P.mp[6]) * lr);
+    const R Th = R(P.mp[1]) * fexp(-R(P.mp[7]) * lr);
+    const R Bm = R(P.Bref) * fexp(-R(P.mp[8]) * (lr - flog(R(P.r_ref))));
+    // unit field direction: (cos psi e_ph + sin psi e_r) projected orthogonal to u
+    const double Bt_r = P.psi_s, Bt_p = P.psi_c;
+    const double Bdu = Gam * (vr * Bt_r + vp * Bt_p);
+    const double resc = 1.0 / ::sqrt(1.0 + Bdu * Bdu);
+    const double b0 = Bdu * u0 * resc;
+    const double b1 = (Bt_r * zer + Bdu * u1) * resc;
+    const double b3 = (Bt_p * zep + Bdu * u3) * resc;
+    const double kb = kt * b0 + kr_bl * b1 + kph * b3;
+    double cth = -kb / ku;
+    cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
+    // contravariant k (BL)
+    const double gitt = -A / (Sig * Del), gitp = -2.0 * a * r / (Sig * Del);
+    const double girr = Del / Sig, gihh = 1.0 / Sig, gipp = (Del - a * a * s2) / (Sig * Del * s2);
+    const double iku = 1.0 / ku;
+    const double kup[4] = { gitt * kt + gitp * kph, girr * kr_bl, gihh * kth, gitp * kt + gipp * kph };
+    // photon direction n = k/ku - u; b_perp = b - (b.n) n
+    const double n0 = kup[0] * iku - u0, n1 = kup[1] * iku - u1, n2 = kup[2] * iku, n3 = kup[3] * iku - u3;
+    const double gtt = -(1.0 - 2.0 * r / Sig), gtp = -2.0 * a * r * s2 / Sig;
+    const double grr = Sig / Del, ghh = Sig, gpp = (r * r + a * a + 2.0 * a * a * r * s2 / Sig) * s2;
+    const double bl0 = gtt * b0 + gtp * b3, bl1 = grr * b1, bl3 = gtp * b0 + gpp * b3;
+    const double bn = bl0 * n0 + bl1 * n1 + bl3 * n3;
+    const double bp[4] = { b0 - bn * n0, b1 - bn * n1, -bn * n2, b3 - bn * n3 };
+    double kbr, kbi;
+    walker_penrose(a, r, s, c, kup, bp, kbr, kbi);
+    const double zr = k0r * kbr + k0i * kbi;
+    const double zi = k0i * kbr - k0r * kbi;
+    const double zn = zr * zr + zi * zi;
+    double c2x = 1.0, s2x = 0.0;
+    if (zn > 0.0) {
+        const double izn = 1.0 / zn;
+        c2x = (zr * zr - zi * zi) * izn;
+        s2x = 2.0 * zr * zi * izn;
+    }
+    R jI, jQ, jV, aI, aQ, aV, rQ, rV;
+    thermal_coefs<R>(ne, Th, Bm, R(P.freq * ku), R(cth), jI, jQ, jV, aI, aQ, aV, rQ, rV);
+    const R fJ = R(P.L_cm * iku * iku), fK = R(P.L_cm * ku);
+    const R c2 = R(c2x), s2_ = R(s2x);
+    C.jI = fJ * jI; C.jQ = fJ * jQ * c2; C.jU = fJ * jQ * s2_; C.jV = fJ * jV;
+    C.aI = fK * aI; C.aQ = fK * aQ * c2; C.aU = fK * aQ * s2_; C.aV = fK * aV;
+    C.rQ = fK * rQ * c2; C.rU = fK * rQ * s2_; C.rV = fK * rV;
+    return true;
+    }
+}
+
+// ---------------------------------------------------------- transfer maths
+// e^-w sinh(u)/u, sin(v)/v, e^-w (sinh(u)/u - 1)/u^2, (1 - sin(v)/v)/v^2:
+// series below 1, closed forms above (no cancellation, no overflow for u <= w).
+template <typename R>
+__device__ __forceinline__ R shc_d(R u, R w)
+{
+    if (u < R(1)) {
+        const R u2 = u * u;
+        const R s = R(1) + u2 / R(6) * (R(1) + u2 / R(20) * (R(1) + u2 / R(42) * (R(1) + u2 / R(72) * (R(1) + u2 / R(110) * (R(1) + u2 / R(156))))));
+        return fexp(-w) * s;
+    }
+    return (fexp(u - w) - fexp(-u - w)) / (R(2) * u);
+}
+template <typename R>
+__device__ __forceinline__ R sinc_(R v)
+{
+    if (v < R(1)) {
+        const R v2 = v * v;
+        return R(1) - v2 / R(6) * (R(1) - v2 / R(20) * (R(1) - v2 / R(42) * (R(1) - v2 / R(72) * (R(1) - v2 / R(110) * (R(1) - v2 / R(156))))));
+    }
+    return fsin(v) / v;
+}
+template <typename R>
+__device__ __forceinline__ R gfun_d(R u, R w)
+{
+    if (u < R(1)) {
+        const R u2 = u * u;
+        const R s = R(1) / R(6) * (R(1) + u2 / R(20) * (R(1) + u2 / R(42) * (R(1) + u2 / R(72) * (R(1) + u2 / R(110) * (R(1) + u2 / R(156) * (R(1) + u2 / R(210)))))));
+        return fexp(-w) * s;
+    }
+    return (shc_d(u, w) - fexp(-w)) / (u * u);
+}
+template <typename R>
+__device__ __forceinline__ R hfun_(R v)
+{
+    if (v < R(1)) {
+        const R v2 = v * v;
+        return R(1) / R(6) * (R(1) - v2 / R(20) * (R(1) - v2 / R(42) * (R(1) - v2 / R(72) * (R(1) - v2 / R(110) * (R(1) - v2 / R(156) * (R(1) - v2 / R(210)))))));
+    }
+    return (R(1) - fsin(v) / v) / (v * v);
+}
+
+// Coefficients c0..c3 with exp(-aI x) exp(-A x) = c0 + c1 A + c2 A^2 + c3 A^3.
+// The eigenvalues of A are +-L1, +-i L2 (L1^2 - L2^2 = |a|^2 - |r|^2,
+// L1 L2 = a.r).
+template <typename R>
+__device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3], R x,
+                                               R& c0, R& c1, R& c2, R& c3)
+{
+    const R a2 = av[0] * av[0] + av[1] * av[1] + av[2] * av[2];
+    const R r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+    const R ad = av[0] * rv[0] + av[1] * rv[1] + av[2] * rv[2];
+    const R dl = a2 - r2;
+    const R D = fsqrt(dl * dl + R(4) * ad * ad);
+    R L1s = R(0.5) * (D + dl); L1s = L1s < R(0) ? R(0) : L1s;
+    R L2s = R(0.5) * (D - dl); L2s = L2s < R(0) ? R(0) : L2s;
+    const R L1 = fsqrt(L1s), L2 = fsqrt(L2s);
+    const R u = x * L1, v = x * L2, w = x * aI;
+    const R ew = fexp(-w);
+    const R ch = R(0.5) * (fexp(u - w) + fexp(-u - w));
+    if (D > R(0)) {
+        const R iD = R(1) / D;
+        const R shc = shc_d(u, w);
+        const R snc = sinc_(v);
+        const R sh2 = shc_d(R(0.5) * u, R(0.5) * w);
+        const R sn2 = sinc_(R(0.5) * v);
+        c2 = R(0.5) * x * x * (L1s * sh2 * sh2 + L2s * ew * sn2 * sn2) * iD;
+        c1 = -x * (L2s * shc + L1s * ew * snc) * iD;
+        c3 = -x * x * x * (L1s * gfun_d(u, w) + L2s * ew * hfun_(v)) * iD;
+    } else {
+        c2 = R(0.5) * x * x * ew;
+        c1 = -x * ew;
+        c3 = -x * x * x * ew / R(6);
+    }
+    c0 = ch - L1s * c2;
+}
+
+template <typename R>
+__device__ __forceinline__ R phi1_(R w)
+{
+    if (w < R(1e-4)) return R(1) - w / R(2) + w * w / R(6) - w * w * w / R(24);
+    return -fexpm1(-w) / w;
+}
+template <typename R>
+__device__ __forceinline__ R mean_depth_(R w)
+{
+    if (w < R(0.1)) { const R w2 = w * w; return R(0.5) - w / R(12) + w * w2 / R(720) - w * w2 * w2 / R(30240); }
+    return R(1) / w - R(1) / fexpm1(w);
+}
+
+// y = A x for A = [[0,aQ,aU,aV],[aQ,0,rV,-rU],[aU,-rV,0,rQ],[aV,rU,-rQ,0]]
+template <typename R>
+__device__ __forceinline__ void applyA(const Coef<R>& K, const R x[4], R y[4])
+{
+    y[0] = K.aQ * x[1] + K.aU * x[2] + K.aV * x[3];
+    y[1] = K.aQ * x[0] + K.rV * x[2] - K.rU * x[3];
+    y[2] = K.aU * x[0] - K.rV * x[1] + K.rQ * x[3];
+    y[3] = K.aV * x[0] + K.rU * x[1] - K.rQ * x[2];
+}
+// Y = X A (row vector times A, for each of the 4 rows of X)
+template <typename R>
+__device__ __forceinline__ void rowA(const Coef<R>& K, const R x[4], R y[4])
+{
+    y[0] = K.aQ * x[1] + K.aU * x[2] + K.aV * x[3];
+    y[1] = K.aQ * x[0] - K.rV * x[2] + K.rU * x[3];
+    y[2] = K.aU * x[0] + K.rV * x[1] - K.rQ * x[3];
+    y[3] = K.aV * x[0] - K.rU * x[1] + K.rQ * x[2];
+}
+
+// One constant-coefficient polarised step of affine length h:
+//   S += O * h phi1(aI h) exp(-A sbar) J,   O <- O exp(-aI h) exp(-A h).
+template <typename R, typename RS>
+__device__ __forceinline__ void transfer_step4(RS S[4], R O[16], const Coef<R>& K, R h)
+{
+    const R av[3] = { K.aQ, K.aU, K.aV };
+    const R rv[3] = { K.rQ, K.rU, K.rV };
+    const R w = K.aI * h;
+    const R sbar = h * mean_depth_(w);
+    R g0, g1, g2, g3;
+    lorentz_coeffs<R>(R(0), av, rv, sbar, g0, g1, g2, g3);
+    const R J[4] = { K.jI, K.jQ, K.jU, K.jV };
+    R AJ[4], A2J[4], A3J[4];
+    applyA(K, J, AJ);
+    applyA(K, AJ, A2J);
+    applyA(K, A2J, A3J);
+    const R sc = h * phi1_(w);
+    R d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] = sc * (g0 * J[i] + g1 * AJ[i] + g2 * A2J[i] + g3 * A3J[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        S[i] += RS(O[i * 4 + 0] * d[0] + O[i * 4 + 1] * d[1] + O[i * 4 + 2] * d[2] + O[i * 4 + 3] * d[3]);
+    R c0, c1, c2, c3;
+    lorentz_coeffs<R>(K.aI, av, rv, h, c0, c1, c2, c3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const R x[4] = { O[i * 4 + 0], O[i * 4 + 1], O[i * 4 + 2], O[i * 4 + 3] };
+        R xa[4], xa2[4], xa3[4];
+        rowA(K, x, xa);
+        rowA(K, xa, xa2);
+        rowA(K, xa2, xa3);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) O[i * 4 + j] = c0 * x[j] + c1 * xa[j] + c2 * xa2[j] + c3 * xa3[j];
+    }
+}
+
+// Closed-form screen intensities (refinement tests without ray tracing).
+__device__ __forceinline__ void screen_fn(const Params& P, double al, double be, double S[4])
+{
+    double I;
+    if (P.model == MODEL_SCREEN_RING) {
+        const double rho = ::sqrt(al * al + be * be);
+        const double d = (rho - P.mp[0]) / P.mp[1];
+        I = ::exp(-0.5 * d * d) * (1.0 + 0.5 * al / (rho + 1.0))
+            + P.mp[2] * ::exp(-rho * rho / (2.0 * P.mp[3] * P.mp[3]));
+    } else {
+        I = P.mp[0] + P.mp[1] * al + P.mp[2] * be + P.mp[3] * al * al + P.mp[4] * al * be
+            + P.mp[5] * be * be;
+    }
+    S[0] = I;
+    S[1] = 0.5 * I * ::cos(0.3 * al);
+    S[2] = 0.5 * I * ::sin(0.3 * be);
+    S[3] = 0.1 * I;
+}
+
+}  // namespace art

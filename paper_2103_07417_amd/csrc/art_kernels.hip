@@ -1,0 +1,538 @@
+// art_kernels.hip -- gfx950 kernels of the adaptive ray tracer.
+//
+//   k_trace      persistent work-queue tracer: one lane per ray, lanes refill
+//                from a global atomic cursor at wave-uniform points, so rays of
+//                very uneven step counts (photon-ring rays wind many times,
+//                Sec. 4.2 last paragraphs) keep every lane busy.
+//   k_estimate   one refinement level (Sec. 3.2): category from index parity,
+//                neighbour/continuation sums, the linear-branch estimates of
+//                Eqs. 5-6 evaluated without division, interpolation, and
+//                wavefront-ballot compaction of the points to trace.
+//   k_reduce_base  trapezoid mean and maximum of the level-0 image (Ibar_int,
+//                Sec. 3.2 after Eq. 6), one block, fixed summation order.
+//   k_metrics_*  flux error and normalised MSE (Sec. 4.1, Eqs. 8-9),
+//                deterministic two-pass reduction.
+#include "art_internal.hpp"
+
+namespace art {
+
+__device__ __forceinline__ unsigned lane_prefix(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// ---------------------------------------------------------------- fill kernels
+__global__ void k_fill_u32(uint32_t* p, long long n, uint32_t v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_f64(double* p, long long n, double v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_i8(int8_t* p, long long n, int8_t v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int fill_blocks(long long n)
+{
+    long long b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i8(int8_t* p, long long n, int8_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i8, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ base-grid list
+__global__ void k_base_list(uint32_t* list, uint32_t* count, int nx0, int ny0, int st0, int nx,
+                            int8_t* level)
+{
+    const int n = nx0 * ny0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int i = t % nx0, j = t / nx0;
+        const uint32_t pix = (uint32_t)(j * st0) * (uint32_t)nx + (uint32_t)(i * st0);
+        list[t] = pix;
+        if (level) level[pix] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = (uint32_t)n;
+}
+
+hipError_t launch_base_list(uint32_t* list, uint32_t* count, int nx0, int ny0, int st0, int nx,
+                            int8_t* level, hipStream_t s)
+{
+    const long long n = (long long)nx0 * ny0;
+    hipLaunchKernelGGL(k_base_list, dim3(fill_blocks(n)), dim3(256), 0, s, list, count, nx0, ny0,
+                       st0, nx, level);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- ray tracing
+template <typename R, int MODEL, int NS>
+struct RayState {
+    double y[5];
+    double kt, kph, k0r, k0i;
+    double cprev, rmin;
+    R S[NS];
+    R O[NS == 4 ? 16 : 1];
+    int ncross, nstep;
+    uint32_t item;
+};
+
+template <typename R, int MODEL, int NS>
+__device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>& st, double al, double be)
+{
+    RayStart rs;
+    camera_start(P, al, be, rs);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) st.y[i] = rs.y[i];
+    st.kt = rs.kt; st.kph = rs.kph; st.k0r = rs.k0r; st.k0i = rs.k0i;
+    st.cprev = ::cos(rs.y[1]);
+    st.rmin = rs.y[0];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) st.S[i] = R(0);
+    if constexpr (NS == 4) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) st.O[i] = (i % 5 == 0) ? R(1) : R(0);
+    } else {
+        st.O[0] = R(1);
+    }
+    st.ncross = 0;
+    st.nstep = 0;
+}
+
+// Advance one ray by one step.  Returns a RAY_* status (RAY_OK = continue).
+template <typename R, int MODEL, int NS>
+__device__ __forceinline__ int ray_step(const Params& P, RayState<R, MODEL, NS>& st, unsigned& emit)
+{
+    const double a = P.a;
+    double k1[5], acc[5], yt[5], kk[5];
+    const double c = geo_rhs(a, st.kt, st.kph, st.y, k1);
+    if (st.cprev * c < 0.0) st.ncross++;
+    st.cprev = c;
+    if (st.y[0] < st.rmin) st.rmin = st.y[0];
+    if (st.y[0] > P.r_out && k1[0] > 0.0) return RAY_ESCAPED;
+    if (st.y[0] < P.rstop) return RAY_CAPTURED;
+    if (st.nstep >= P.max_steps) return RAY_STEPCAP;
+    if (st.O[0] < R(1e-12)) return RAY_THICK;
+    if (!(st.y[0] == st.y[0]) || !(st.y[3] == st.y[3])) return RAY_NAN;
+    const double rate = ::fabs(k1[0]) / st.y[0] + ::fabs(k1[1]) + ::fabs(k1[2]);
+    double far = st.y[0] * (1.0 / 20.0);
+    far = far < 1.0 ? 1.0 : (far > 4.0 ? 4.0 : far);
+    double h = P.eps * far / rate;
+    if (k1[0] < 0.0) {
+        const double hh = 0.5 * (st.y[0] - P.rh) / (-k1[0]);
+        h = hh < h ? hh : h;
+    }
+    const double h2 = 0.5 * h;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h2 * k1[i]; acc[i] = k1[i]; }
+    geo_rhs(a, st.kt, st.kph, yt, kk);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h2 * kk[i]; acc[i] += 2.0 * kk[i]; }
+    geo_rhs(a, st.kt, st.kph, yt, kk);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h * kk[i]; acc[i] += 2.0 * kk[i]; }
+    geo_rhs(a, st.kt, st.kph, yt, kk);
+    const double h6 = h / 6.0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) yt[i] = st.y[i] + h6 * (acc[i] + kk[i]);
+    // transfer at the step midpoint
+    const double rm = 0.5 * (st.y[0] + yt[0]), thm = 0.5 * (st.y[1] + yt[1]);
+    const double krm = 0.5 * (st.y[3] + yt[3]), kthm = 0.5 * (st.y[4] + yt[4]);
+    Coef<R> C;
+    if (plasma_point<R, MODEL>(P, rm, thm, st.kt, st.kph, krm, kthm, st.k0r, st.k0i, C)) {
+        ++emit;
+        if constexpr (NS == 4) {
+            transfer_step4<R, R>(st.S, st.O, C, R(h));
+        } else {
+            const R w = C.aI * R(h);
+            st.S[0] += st.O[0] * R(h) * phi1_(w) * C.jI;
+            st.O[0] *= fexp(-w);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) st.y[i] = yt[i];
+    st.nstep++;
+    return RAY_OK;
+}
+
+template <typename R, int MODEL, int NS>
+__global__ __launch_bounds__(256) void k_trace(Params P, TraceJob J)
+{
+    const int lane = __lane_id();
+    const int nsout = P.nstokes;
+    RayState<R, MODEL, NS> st;
+    bool active = false, drained = false;
+    unsigned long long my_steps = 0;
+    unsigned my_emit = 0;
+    unsigned hist[6] = { 0, 0, 0, 0, 0, 0 };
+    const uint32_t cnt = *J.count;
+
+    for (;;) {
+        if (!drained) {
+            const unsigned long long need = __ballot(!active);
+            const int nidle = __popcll(need);
+            if (nidle >= J.refill && nidle > 0) {
+                const int leader = __ffsll((long long)need) - 1;
+                unsigned base = 0;
+                if (lane == leader) base = atomicAdd(J.cursor, (unsigned)nidle);
+                base = __shfl(base, leader);
+                if ((unsigned long long)base + (unsigned)nidle >= cnt) drained = true;
+                if (!active) {
+                    const unsigned my = base + lane_prefix(need);
+                    if (my < cnt) {
+                        double al, be;
+                        uint32_t item;
+                        if (J.src == SRC_POINTS) {
+                            item = my;
+                            al = J.alpha[my];
+                            be = J.beta[my];
+                        } else {
+                            item = (J.src == SRC_LIST) ? J.list[my] : my;
+                            const uint32_t i = item % (uint32_t)P.nx, j = item / (uint32_t)P.nx;
+                            al = P.x0 + (double)i * P.dx;
+                            be = P.y0 + (double)j * P.dx;
+                        }
+                        st.item = item;
+                        if (P.model >= MODEL_SCREEN_RING) {
+                            double S4[4];
+                            screen_fn(P, al, be, S4);
+                            if (J.src == SRC_POINTS) {
+                                for (int s = 0; s < nsout; ++s) J.out[(long long)item * nsout + s] = S4[s];
+                            } else {
+                                for (int s = 0; s < nsout; ++s) J.out[s * J.plane + item] = S4[s];
+                            }
+                            if (J.feat) {
+                                RayFeat f; f.rmin = (float)P.r_cam; f.ncross = 0; f.steps = 0; f.status = RAY_OK;
+                                J.feat[item] = f;
+                            }
+                            hist[RAY_OK]++;
+                        } else {
+                            ray_init<R, MODEL, NS>(P, st, al, be);
+                            active = true;
+                        }
+                    }
+                }
+            }
+        }
+        if (!__any(active)) {
+            if (drained) break;
+            continue;
+        }
+        if (active) {
+            const int status = ray_step<R, MODEL, NS>(P, st, my_emit);
+            if (status != RAY_OK) {
+                double Sd[4] = { 0.0, 0.0, 0.0, 0.0 };
+#pragma unroll
+                for (int s = 0; s < NS; ++s) Sd[s] = (double)st.S[s];
+                int stt = status;
+                if (!(Sd[0] == Sd[0])) stt = RAY_NAN;
+                if (J.src == SRC_POINTS) {
+                    for (int s = 0; s < nsout; ++s) J.out[(long long)st.item * nsout + s] = Sd[s];
+                } else {
+                    for (int s = 0; s < nsout; ++s) J.out[s * J.plane + st.item] = Sd[s];
+                }
+                if (J.feat) {
+                    RayFeat f;
+                    f.rmin = (float)st.rmin; f.ncross = st.ncross; f.steps = st.nstep; f.status = stt;
+                    J.feat[st.item] = f;
+                }
+                my_steps += (unsigned long long)st.nstep;
+                hist[stt]++;
+                active = false;
+            }
+        }
+    }
+    // wave-level statistics: one atomic per counter per wave
+    unsigned long long my_emit64 = my_emit;
+    for (int off = 32; off > 0; off >>= 1) my_steps += __shfl_xor(my_steps, off);
+    for (int off = 32; off > 0; off >>= 1) my_emit64 += __shfl_xor(my_emit64, off);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        for (int off = 32; off > 0; off >>= 1) hist[k] += __shfl_xor(hist[k], off);
+    if (lane == 0 && J.ctr) {
+        if (my_steps) atomicAdd(&J.ctr->steps, my_steps);
+        if (my_emit64) atomicAdd(&J.ctr->steps_emit, my_emit64);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (hist[k]) atomicAdd(&J.ctr->status[k], (unsigned long long)hist[k]);
+    }
+}
+
+template <typename R, int MODEL, int NS>
+static hipError_t launch_trace_t(const Params& P, const TraceJob& J, const LaunchCfg& L, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_trace<R, MODEL, NS>), dim3(L.trace_blocks), dim3(L.trace_threads), 0, s, P, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const Params& P, int precision, const TraceJob& J, const LaunchCfg& L,
+                        hipStream_t s)
+{
+    const bool pol = (P.nstokes == 4) && (P.model == MODEL_THERMAL);
+    const bool thermal = (P.model == MODEL_THERMAL);
+    if (precision == 0) {
+        if (thermal) return pol ? launch_trace_t<double, MODEL_THERMAL, 4>(P, J, L, s)
+                                : launch_trace_t<double, MODEL_THERMAL, 1>(P, J, L, s);
+        return launch_trace_t<double, MODEL_TOY, 1>(P, J, L, s);
+    }
+    if (thermal) return pol ? launch_trace_t<float, MODEL_THERMAL, 4>(P, J, L, s)
+                            : launch_trace_t<float, MODEL_THERMAL, 1>(P, J, L, s);
+    return launch_trace_t<float, MODEL_TOY, 1>(P, J, L, s);
+}
+
+int trace_occupancy_blocks(int precision, int model, int nstokes, int threads)
+{
+    int nb = 0;
+    const bool pol = (nstokes == 4) && (model == MODEL_THERMAL);
+    const bool thermal = (model == MODEL_THERMAL);
+    hipError_t e;
+    if (precision == 0) {
+        if (thermal && pol) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<double, MODEL_THERMAL, 4>, threads, 0);
+        else if (thermal) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<double, MODEL_THERMAL, 1>, threads, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<double, MODEL_TOY, 1>, threads, 0);
+    } else {
+        if (thermal && pol) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<float, MODEL_THERMAL, 4>, threads, 0);
+        else if (thermal) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<float, MODEL_THERMAL, 1>, threads, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<float, MODEL_TOY, 1>, threads, 0);
+    }
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+// ------------------------------------------------------ level-0 reduction
+__global__ __launch_bounds__(1024) void k_reduce_base(const double* img, int nx, int nx0, int ny0,
+                                                     int st0, int norm, Counters* ctr)
+{
+    __shared__ double ssum[1024];
+    __shared__ double smax[1024];
+    const int t = threadIdx.x;
+    double sum = 0.0, mx = -HUGE_VAL;
+    const int n = nx0 * ny0;
+    for (int k = t; k < n; k += 1024) {
+        const int i = k % nx0, j = k / nx0;
+        const double v = img[(long long)(j * st0) * nx + (long long)(i * st0)];
+        const double wx = (i == 0 || i == nx0 - 1) ? 0.5 : 1.0;
+        const double wy = (j == 0 || j == ny0 - 1) ? 0.5 : 1.0;
+        sum += (wy * wx) * v;
+        mx = v > mx ? v : mx;
+    }
+    ssum[t] = sum;
+    smax[t] = mx;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (t < off) {
+            ssum[t] += ssum[t + off];
+            smax[t] = smax[t + off] > smax[t] ? smax[t + off] : smax[t];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double ibar = ssum[0] / ((double)(nx0 - 1) * (double)(ny0 - 1));
+        ctr->scal[0] = ibar;
+        ctr->scal[1] = smax[0];
+        ctr->scal[2] = norm == 0 ? ibar : smax[0];
+    }
+}
+
+hipError_t launch_reduce_base(const double* img, int nx, int nx0, int ny0, int st0, int norm,
+                              Counters* ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_base, dim3(1), dim3(1024), 0, s, img, nx, nx0, ny0, st0, norm, ctr);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ refinement level
+// Per axis with in-points lo, hi and continuations at -3, +3 (level-(l+1)
+// units): D = (out_lo + out_hi) - (lo + hi); one continuation outside the
+// image: twice the one-sided second difference; both outside: unavailable.
+__device__ __forceinline__ bool axis_D(const double* I, long long nx, int s, int nxl, int nyl,
+                                       int p, int q, int dx, int dy, double lo, double hi, double& D)
+{
+    const int pl = p - 3 * dx, ql = q - 3 * dy, ph = p + 3 * dx, qh = q + 3 * dy;
+    const bool has_lo = pl >= 0 && pl < nxl && ql >= 0 && ql < nyl;
+    const bool has_hi = ph >= 0 && ph < nxl && qh >= 0 && qh < nyl;
+    const double olo = has_lo ? I[(long long)(ql * s) * nx + (long long)(pl * s)] : 0.0;
+    const double ohi = has_hi ? I[(long long)(qh * s) * nx + (long long)(ph * s)] : 0.0;
+    if (has_lo && has_hi) { D = (olo + ohi) - (lo + hi); return true; }
+    if (has_hi) { D = 2.0 * ((ohi - 2.0 * hi) + lo); return true; }
+    if (has_lo) { D = 2.0 * ((olo - 2.0 * lo) + hi); return true; }
+    D = 0.0;
+    return false;
+}
+
+__global__ __launch_bounds__(256) void k_estimate(double* img, int nstokes, long long plane, int nx,
+                                                  int nxl, int nyl, int s, int l, double r_rel,
+                                                  double r_abs, Counters* ctr, uint32_t* list,
+                                                  int8_t* level)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    const bool inside = p < nxl && q < nyl;
+    const bool isnew = inside && ((p & 1) | (q & 1));
+    bool trace = false;
+    long long pix = 0;
+    if (isnew) {
+        const double* I = img;
+        const long long NX = nx;
+        pix = (long long)(q * s) * NX + (long long)(p * s);
+        const bool c4 = (p & 1) && (q & 1);
+        double Ssum, D;
+        bool avail;
+        double m;
+        if (c4) {
+            const long long o1 = (long long)((q - 1) * s) * NX + (long long)((p - 1) * s);
+            const long long o4 = (long long)((q + 1) * s) * NX + (long long)((p + 1) * s);
+            const long long o2 = (long long)((q - 1) * s) * NX + (long long)((p + 1) * s);
+            const long long o3 = (long long)((q + 1) * s) * NX + (long long)((p - 1) * s);
+            const double i1 = I[o1], i4 = I[o4], i2 = I[o2], i3 = I[o3];
+            Ssum = (i1 + i4) + (i2 + i3);
+            // diagonal x': I1 (-1,-1) -> I4 (+1,+1), continuations I5, I8 at -+3;
+            // diagonal y': I2 (+1,-1) -> I3 (-1,+1), continuations I6 (+3,-3), I7 (-3,+3)
+            double Dx, Dy;
+            const bool ax = axis_D(I, NX, s, nxl, nyl, p, q, 1, 1, i1, i4, Dx);
+            const bool ay = axis_D(I, NX, s, nxl, nyl, p, q, -1, 1, i2, i3, Dy);
+            D = ax ? (ay ? Dx + Dy : 2.0 * Dx) : 2.0 * Dy;
+            avail = ax || ay;
+            m = 4.0;
+        } else {
+            const int dx = (p & 1) ? 1 : 0, dy = (p & 1) ? 0 : 1;
+            const long long olo = (long long)((q - dy) * s) * NX + (long long)((p - dx) * s);
+            const long long ohi = (long long)((q + dy) * s) * NX + (long long)((p + dx) * s);
+            const double lo = I[olo], hi = I[ohi];
+            Ssum = lo + hi;
+            avail = axis_D(I, NX, s, nxl, nyl, p, q, dx, dy, lo, hi, D);
+            m = 2.0;
+        }
+        const double nabs = ctr->scal[2];
+        const double thrA = (4.0 * m * r_abs) * nabs;
+        const double crel = 4.0 * r_rel;
+        const double aD = ::fabs(D);
+        trace = !avail || !(D == D) || !(Ssum == Ssum) || (aD > thrA && aD > crel * ::fabs(Ssum));
+        if (trace) {
+            level[pix] = (int8_t)(l + 1);
+        } else {
+            level[pix] = (int8_t)-1;
+            const double w = 1.0 / m;
+            for (int st = 0; st < nstokes; ++st) {
+                const double* Is = img + st * plane;
+                double S;
+                if (c4) {
+                    const long long o1 = (long long)((q - 1) * s) * NX + (long long)((p - 1) * s);
+                    const long long o4 = (long long)((q + 1) * s) * NX + (long long)((p + 1) * s);
+                    const long long o2 = (long long)((q - 1) * s) * NX + (long long)((p + 1) * s);
+                    const long long o3 = (long long)((q + 1) * s) * NX + (long long)((p - 1) * s);
+                    S = st == 0 ? Ssum : (Is[o1] + Is[o4]) + (Is[o2] + Is[o3]);
+                } else {
+                    const int dx = (p & 1) ? 1 : 0, dy = (p & 1) ? 0 : 1;
+                    const long long olo = (long long)((q - dy) * s) * NX + (long long)((p - dx) * s);
+                    const long long ohi = (long long)((q + dy) * s) * NX + (long long)((p + dx) * s);
+                    S = st == 0 ? Ssum : Is[olo] + Is[ohi];
+                }
+                img[st * plane + pix] = S * w;
+            }
+        }
+    }
+    // wavefront-ballot compaction of the points to trace
+    const unsigned long long mask = __ballot(trace);
+    if (mask) {
+        const int lane = __lane_id();
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned base = 0;
+        if (lane == leader) base = atomicAdd(&ctr->count[l + 1], (unsigned)__popcll(mask));
+        base = __shfl(base, leader);
+        if (trace) list[base + lane_prefix(mask)] = (uint32_t)pix;
+    }
+}
+
+hipError_t launch_estimate(double* img, int nstokes, long long plane, int nx, int nx0, int ny0,
+                           int levels, int l, double r_rel, double r_abs, Counters* ctr,
+                           uint32_t* list, int8_t* level, hipStream_t s)
+{
+    const int nxl = (1 << (l + 1)) * (nx0 - 1) + 1;
+    const int nyl = (1 << (l + 1)) * (ny0 - 1) + 1;
+    const int sp = 1 << (levels - l - 1);
+    dim3 grid((nxl + 255) / 256, nyl);
+    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, img, nstokes, plane, nx, nxl, nyl, sp, l,
+                       r_rel, r_abs, ctr, list, level);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- metrics
+// partial[b*4 + {0,1,2,3}] = sum t, sum a, sum (t-a)^2, sum t^2 over block b.
+__global__ __launch_bounds__(256) void k_metrics_partial(const double* t, const double* a, long long n,
+                                                         double* partial)
+{
+    __shared__ double sh[4][256];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const double x = t[i], y = a[i], d = x - y;
+        s0 += x; s1 += y; s2 += d * d; s3 += x * x;
+    }
+    const int k = threadIdx.x;
+    sh[0][k] = s0; sh[1][k] = s1; sh[2][k] = s2; sh[3][k] = s3;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (k < off) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sh[c][k] += sh[c][k + off];
+        }
+        __syncthreads();
+    }
+    if (k < 4) partial[blockIdx.x * 4 + k] = sh[k][0];
+}
+
+__global__ __launch_bounds__(256) void k_metrics_final(double* partial, int nb)
+{
+    __shared__ double sh[4][256];
+    const int k = threadIdx.x;
+    double s[4] = { 0.0, 0.0, 0.0, 0.0 };
+    for (int b = k; b < nb; b += 256)
+        for (int c = 0; c < 4; ++c) s[c] += partial[b * 4 + c];
+    for (int c = 0; c < 4; ++c) sh[c][k] = s[c];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (k < off)
+            for (int c = 0; c < 4; ++c) sh[c][k] += sh[c][k + off];
+        __syncthreads();
+    }
+    if (k < 4) partial[(long long)nb * 4 + k] = sh[k][0];
+}
+
+hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
+                          int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_metrics_partial, dim3(nblocks), dim3(256), 0, s, t, a, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(256), 0, s, partial, nblocks);
+    return hipGetLastError();
+}
+
+}  // namespace art
