@@ -59,7 +59,31 @@ def workload(name):
         return dict(common, name=name, a=0.94, inc_deg=163.0, model="thermal",
                     mp=thermal_params(seed=1), nstokes=4, nx0=129, ny0=129, levels=3,
                     r_rel=0.01, r_abs=1e-3, abs_norm="max", freq_hz=230e9)
+    if name == "thermal_1025_mixed":
+        return dict(workload("thermal_1025"), name=name, precision="mixed")
     raise KeyError(name)
+
+
+BATCH_SPINS = (0.0, 0.5, 0.94, -0.94)
+BATCH_INCS = (17.0, 60.0, 90.0, 163.0)
+BATCH_FREQS = (86e9, 230e9, 345e9, 690e9)
+
+
+def batch_workload(precision="mixed", base=129):
+    """64 thermal-plasma images: spin x inclination x frequency in
+    lexicographic order, image k refined 1 + (k mod 4) levels
+    (129^2 -> 257^2, 513^2, 1025^2, 2049^2)."""
+    cfgs = []
+    k = 0
+    for a in BATCH_SPINS:
+        for inc in BATCH_INCS:
+            for nu in BATCH_FREQS:
+                c = dict(workload("thermal_1025"), name="batch_%02d" % k, a=a, inc_deg=inc,
+                         freq_hz=nu, levels=1 + (k % 4), precision=precision,
+                         nx0=base, ny0=base)
+                cfgs.append(c)
+                k += 1
+    return cfgs
 
 
 def reduced(cfg, nx0, levels):

@@ -171,6 +171,68 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
                      const double* beta_dev, double* stokes_dev, void* feat_dev,
                      void* stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many images (different spin, inclination, frequency, tolerances and number
+ * of levels) rendered together: every level's new rays of every image go into
+ * one work queue of the persistent tracer, so long photon-ring rays of one
+ * image overlap with the work of the others.  All images of a batch use the
+ * same emission kind, nstokes and precision; at most 64 images. */
+typedef struct {
+    art_spacetime sp;
+    art_camera cam;
+    art_emission em;
+    art_refine rf;
+    art_transfer tr;
+} art_job;
+
+typedef struct art_batch art_batch;   /* opaque */
+
+/* Validate n jobs and their caller-owned output images (image_dev and
+ * level_dev required, nx/ny equal to each camera's final grid), allocate the
+ * batch's device scratch (trace list of sum nx*ny 8-byte items, counters,
+ * descriptors) and upload the descriptors.  Synchronises the null stream. */
+int art_batch_create(int32_t n, const art_job* jobs, const art_image* images, art_batch** out);
+
+/* Enqueue one adaptive render of every image of the batch on `stream`
+ * (asynchronous; the tracing launches are timed with HIP events). */
+int art_batch_render(art_batch* b, void* stream);
+
+/* Capture the batch's whole level loop (clears, base lists, tracing,
+ * reductions, estimators) into a hipGraph on a non-default `stream`; the
+ * graph contains kernel nodes only.  Replaces a previous capture. */
+int art_batch_capture(art_batch* b, void* stream);
+
+/* Replay the captured graph on `stream` (asynchronous). */
+int art_batch_launch(art_batch* b, void* stream);
+
+/* Statistics of image i of the last render or replay (i = -1: all images
+ * summed; ibar_int/imax0/n_abs then refer to image 0).  Synchronises. */
+int art_batch_stats(art_batch* b, int32_t i, art_stats* st, void* stream);
+
+/* Free the batch (after synchronising the device). */
+int art_batch_destroy(art_batch* b);
+
+/* ------------------------------------------------------- launch configuration
+ * Persistent-tracer launch shape: grid size, threads per block (64, 128 or
+ * 256) and the refill threshold (a wave claims new rays when at least this
+ * many of its lanes are idle).  Zero fields select the defaults (one block per
+ * CU per resident block of the kernel's occupancy, 256 threads, refill 1).
+ * art_set_launch applies to renders issued afterwards (process-wide). */
+typedef struct {
+    int32_t trace_blocks;
+    int32_t trace_threads;
+    int32_t refill;
+    int32_t pad;
+} art_launch;
+
+int art_set_launch(const art_launch* launch);
+int art_get_launch(int32_t precision, int32_t kind, int32_t nstokes, art_launch* launch);
+
+/* Launch shape of one batch (used by its next render or capture; a captured
+ * graph keeps the shape it was captured with). */
+int art_batch_set_launch(art_batch* b, const art_launch* launch);
+int art_batch_get_launch(const art_batch* b, art_launch* launch);
+
 /* Image metrics of Sec. 4.1 on n FP64 values (one Stokes plane), computed on
  * the device with a deterministic two-pass reduction; synchronises:
  *   flux error = |sum t - sum a| / |sum t|   (Eq. 8)

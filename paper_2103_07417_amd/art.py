@@ -69,6 +69,16 @@ class Stats(ctypes.Structure):
                 ("levels", ctypes.c_int32)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("sp", Spacetime), ("cam", Camera), ("em", Emission), ("rf", Refine),
+                ("tr", Transfer)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("trace_blocks", ctypes.c_int32), ("trace_threads", ctypes.c_int32),
+                ("refill", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 FEAT_DTYPE = np.dtype([("rmin", np.float32), ("ncross", np.int32),
                        ("steps", np.int32), ("status", np.int32)])
 
@@ -99,6 +109,16 @@ def lib():
         L.art_trace_points.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Transfer), i64,
                                        vp, vp, vp, vp, vp]
         L.art_metrics.argtypes = [vp, vp, i64, P(ctypes.c_double), P(ctypes.c_double), vp]
+        L.art_batch_create.argtypes = [ctypes.c_int32, P(Job), P(Image), P(vp)]
+        L.art_batch_render.argtypes = [vp, vp]
+        L.art_batch_capture.argtypes = [vp, vp]
+        L.art_batch_launch.argtypes = [vp, vp]
+        L.art_batch_stats.argtypes = [vp, ctypes.c_int32, P(Stats), vp]
+        L.art_batch_destroy.argtypes = [vp]
+        L.art_set_launch.argtypes = [P(Launch)]
+        L.art_batch_set_launch.argtypes = [vp, P(Launch)]
+        L.art_batch_get_launch.argtypes = [vp, P(Launch)]
+        L.art_get_launch.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(Launch)]
         L.art_last_error.restype = ctypes.c_char_p
         L.art_last_error.argtypes = []
         L.art_release.argtypes = []
@@ -243,3 +263,79 @@ def feat_numpy(ft):
     """Structured numpy view (rmin, ncross, steps, status) of a feature tensor."""
     a = ft.cpu().contiguous().numpy()
     return a.view(FEAT_DTYPE).reshape(a.shape[:-1])
+
+
+def set_launch(trace_blocks=0, trace_threads=0, refill=0):
+    """Persistent-tracer launch shape for later renders (0 = default)."""
+    _check(lib().art_set_launch(ctypes.byref(Launch(trace_blocks, trace_threads, refill, 0))))
+
+
+def get_launch(cfg):
+    _, _, em, _, tr = blocks(cfg)
+    L = Launch()
+    _check(lib().art_get_launch(tr.precision, em.kind, tr.nstokes, ctypes.byref(L)))
+    return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill)
+
+
+class Batch:
+    """Many adaptive images rendered together (one work queue per level).
+
+    cfgs: list of workload dictionaries (same model, nstokes, precision).
+    Outputs are allocated here: self.images[i] (nstokes, ny, nx) float64,
+    self.levels[i] (ny, nx) int8, self.feats[i] or None.
+    """
+
+    def __init__(self, cfgs, feat=False):
+        self._torch = _torch()
+        n = len(cfgs)
+        self.cfgs = list(cfgs)
+        jobs = (Job * n)()
+        ims = (Image * n)()
+        self.images, self.levels, self.feats = [], [], []
+        for i, c in enumerate(cfgs):
+            sp, cam, em, rf, tr = blocks(c)
+            jobs[i] = Job(sp, cam, em, rf, tr)
+            img, lev, ft = alloc(c, feat)
+            self.images.append(img)
+            self.levels.append(lev)
+            self.feats.append(ft)
+            ims[i] = _image(img, lev, ft)
+        self._torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(lib().art_batch_create(n, jobs, ims, ctypes.byref(h)))
+        self._h = h
+
+    def render(self, stream=None):
+        _check(lib().art_batch_render(self._h, _stream(self._torch, stream)))
+
+    def capture(self, stream):
+        """Capture the level loop into a hipGraph (stream must not be the default)."""
+        _check(lib().art_batch_capture(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def launch(self, stream):
+        _check(lib().art_batch_launch(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def stats(self, i=-1, stream=None):
+        st = Stats()
+        _check(lib().art_batch_stats(self._h, int(i), ctypes.byref(st), _stream(self._torch, stream)))
+        return stats_dict(st)
+
+    def set_launch(self, trace_blocks=0, trace_threads=0, refill=0):
+        _check(lib().art_batch_set_launch(self._h, ctypes.byref(Launch(trace_blocks, trace_threads,
+                                                                         refill, 0))))
+
+    def get_launch(self):
+        L = Launch()
+        _check(lib().art_batch_get_launch(self._h, ctypes.byref(L)))
+        return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().art_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

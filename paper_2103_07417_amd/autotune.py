@@ -1,0 +1,102 @@
+"""Launch-shape autotuner for the persistent tracer.
+
+Times a batch's adaptive render (HIP events on the render stream) over a small
+grid of launch shapes -- blocks per CU multiple, threads per block, refill
+threshold -- keeps the fastest, and caches the choice per (device, batch
+signature) in a JSON file.
+"""
+import hashlib
+import json
+import os
+import time
+
+from . import art
+
+CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
+                     "art", "autotune.json")
+
+
+def signature(cfgs):
+    keys = ("model", "nstokes", "precision", "nx0", "ny0", "levels", "a", "inc_deg", "freq_hz",
+            "r_rel", "r_abs", "eps")
+    blob = json.dumps([[c.get(k) for k in keys] for c in cfgs], sort_keys=True)
+    return hashlib.sha1(blob.encode()).hexdigest()[:16]
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def time_render(batch, torch, stream, reps):
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        with torch.cuda.stream(stream):
+            start.record(stream)
+            batch.render(stream)
+            stop.record(stream)
+        stop.synchronize()
+        best = min(best, start.elapsed_time(stop))
+    return best
+
+
+def autotune(batch, stream=None, reps=2, use_cache=True, log=None):
+    """Pick and apply the fastest launch shape for `batch`.  Returns a dict
+    with the chosen shape, its time and the full search table."""
+    import torch
+    stream = stream or torch.cuda.current_stream()
+    dev = torch.cuda.get_device_name(0)
+    key = dev + "/" + signature(batch.cfgs)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        c = cache[key]
+        batch.set_launch(c["trace_blocks"], c["trace_threads"], c["refill"])
+        return dict(c, cached=True)
+    default = batch.get_launch()
+    threads0 = default["trace_threads"]
+    per_cu = max(1, default["trace_blocks"] // max(1, torch.cuda.get_device_properties(0).multi_processor_count))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    table = []
+    t0 = time.perf_counter()
+    batch.render(stream)            # warm-up (code objects, caches)
+    stream.synchronize()
+    for threads in (64, 128, 256):
+        blocks_per_cu = max(1, per_cu * threads0 // threads)
+        for mult in (0.5, 1, 2, 4):
+            blocks = max(1, int(round(cus * blocks_per_cu * mult)))
+            for refill in (1, 16):
+                batch.set_launch(blocks, threads, refill)
+                ms = time_render(batch, torch, stream, reps)
+                table.append(dict(trace_blocks=blocks, trace_threads=threads, refill=refill, ms=ms))
+                if log:
+                    log("autotune blocks=%d threads=%d refill=%d: %.2f ms" % (blocks, threads, refill, ms))
+    best = min(table, key=lambda r: r["ms"])
+    batch.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"])
+    out = dict(trace_blocks=best["trace_blocks"], trace_threads=best["trace_threads"],
+               refill=best["refill"], ms=best["ms"], default=default,
+               default_ms=next((r["ms"] for r in table if r["trace_threads"] == threads0
+                                and r["trace_blocks"] == default["trace_blocks"]
+                                and r["refill"] == default["refill"]), None),
+               search_s=time.perf_counter() - t0)
+    if use_cache:
+        cache = _load()
+        cache[key] = {k: out[k] for k in ("trace_blocks", "trace_threads", "refill", "ms")}
+        _store(cache)
+    out["table"] = table
+    out["cached"] = False
+    return out

@@ -1,9 +1,12 @@
 // art_api.cpp -- C ABI of the adaptive ray tracer (see include/art.h).
 //
-// Host orchestration of one adaptive render (Sec. 3.2): base-grid trace,
-// Ibar_int / max reduction, then per level the estimator + compaction kernel
-// followed by the persistent tracer.  All counts stay on the device, so the
-// level loop needs no host synchronisation.
+// Host orchestration of adaptive renders (Sec. 3.2).  A render is a batch of
+// 1..64 images: base-grid lists for every image, one persistent tracing
+// launch for all base rays, the per-image Ibar_int / max reduction, then per
+// level one estimator + compaction launch over all images followed by one
+// tracing launch over every image's new rays.  All counts stay on the device,
+// so the level loop needs no host synchronisation and can be captured once in
+// a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -12,7 +15,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/art.h"
 #include "art_internal.hpp"
@@ -41,75 +46,6 @@ int fail(int code, const char* fmt, ...)
             return fail(ART_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
     } while (0)
 
-// Library-owned scratch, one per device, grown on demand.
-struct Workspace {
-    uint32_t* list = nullptr;
-    size_t list_cap = 0;
-    Counters* ctr = nullptr;
-    double* partial = nullptr;     // metrics: 1024 blocks x 4 + 4
-    int cus = 0;
-    hipEvent_t ev[2 * 34] = {};    // start/stop around each tracing launch
-    int nev = 0;                   // launches recorded in the current call
-};
-
-// Record an event pair around a tracing launch when timing is requested.
-struct TraceTimer {
-    Workspace* w;
-    hipStream_t s;
-    bool on;
-    hipError_t begin()
-    {
-        if (!on || w->nev >= 34) return hipSuccess;
-        if (!w->ev[2 * w->nev]) {
-            hipError_t e = hipEventCreate(&w->ev[2 * w->nev]);
-            if (e != hipSuccess) return e;
-            e = hipEventCreate(&w->ev[2 * w->nev + 1]);
-            if (e != hipSuccess) return e;
-        }
-        return hipEventRecord(w->ev[2 * w->nev], s);
-    }
-    hipError_t end()
-    {
-        if (!on || w->nev >= 34) return hipSuccess;
-        hipError_t e = hipEventRecord(w->ev[2 * w->nev + 1], s);
-        w->nev++;
-        return e;
-    }
-};
-
-constexpr int kMaxDev = 64;
-Workspace g_ws[kMaxDev];
-std::mutex g_mu;
-
-int get_ws(Workspace** out, size_t list_need)
-{
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    if (dev < 0 || dev >= kMaxDev) return fail(ART_EDEVICE, "device index %d out of range", dev);
-    std::lock_guard<std::mutex> lk(g_mu);
-    Workspace& w = g_ws[dev];
-    if (!w.ctr) {
-        if (hipMalloc(&w.ctr, sizeof(Counters)) != hipSuccess)
-            return fail(ART_ENOMEM, "hipMalloc(counters) failed");
-        if (hipMalloc(&w.partial, sizeof(double) * (1024 * 4 + 4)) != hipSuccess)
-            return fail(ART_ENOMEM, "hipMalloc(partials) failed");
-        HIP_TRY(hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev));
-    }
-    if (list_need > w.list_cap) {
-        if (w.list) {
-            HIP_TRY(hipDeviceSynchronize());
-            HIP_TRY(hipFree(w.list));
-            w.list = nullptr;
-            w.list_cap = 0;
-        }
-        if (hipMalloc(&w.list, list_need * sizeof(uint32_t)) != hipSuccess)
-            return fail(ART_ENOMEM, "hipMalloc(trace list, %zu entries) failed", list_need);
-        w.list_cap = list_need;
-    }
-    *out = &w;
-    return ART_OK;
-}
-
 long long grid_n(int n0, int levels) { return (1LL << levels) * (long long)(n0 - 1) + 1; }
 
 int env_int(const char* name, int dflt)
@@ -119,18 +55,38 @@ int env_int(const char* name, int dflt)
     return atoi(v);
 }
 
-LaunchCfg launch_cfg(const Workspace& w, int precision, int model, int nstokes)
-{
-    LaunchCfg L;
-    L.trace_threads = 256;
-    const int occ = trace_occupancy_blocks(precision, model, nstokes, L.trace_threads);
-    L.trace_blocks = env_int("ART_TRACE_BLOCKS", w.cus * occ);
-    if (L.trace_blocks < 1) L.trace_blocks = 1;
-    L.refill = env_int("ART_REFILL", 1);
-    if (L.refill < 1) L.refill = 1;
-    if (L.refill > 64) L.refill = 64;
-    return L;
-}
+art_launch g_launch = { 0, 0, 0, 0 };   // user override (0 = default)
+std::mutex g_mu;
+
+constexpr int kMaxEv = kMaxLevels + 2;
+
+}  // namespace
+
+// A batch: device descriptors, trace list, counters, timing events, graph.
+struct art_batch {
+    int dev = 0;
+    int n = 0;
+    int model = 0, nstokes = 1, precision = 0;
+    int lmax = 0;
+    int max_base = 0;
+    bool uniform = false;
+    std::vector<Params> hP;
+    std::vector<ImageDesc> hD;
+    Params* dP = nullptr;
+    ImageDesc* dD = nullptr;
+    unsigned long long* list = nullptr;
+    size_t list_cap = 0;
+    Counters* ctr = nullptr;
+    hipEvent_t ev[2 * kMaxEv] = {};
+    int nev = 0;
+    bool timing = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    LaunchCfg L{};
+    int cus = 0;
+};
+
+namespace {
 
 int validate(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
              const art_transfer* tr)
@@ -163,6 +119,20 @@ int validate(const art_spacetime* sp, const art_camera* cam, const art_emission*
     return ART_OK;
 }
 
+int grid_size(const art_camera* cam, int nstokes, int32_t* nx, int32_t* ny)
+{
+    if (!cam) return fail(ART_EINVAL, "camera is NULL");
+    if (cam->nx0 < 2 || cam->ny0 < 2) return fail(ART_EINVAL, "base grid must be at least 2x2");
+    if (cam->levels < 0 || cam->levels > 20) return fail(ART_EINVAL, "levels must be in 0..20");
+    if (nstokes != 1 && nstokes != 4) return fail(ART_EINVAL, "nstokes must be 1 or 4");
+    const long long X = grid_n(cam->nx0, cam->levels), Y = grid_n(cam->ny0, cam->levels);
+    if (X * Y >= (1LL << 32) || X > 65535LL * 256 || Y > 65535)
+        return fail(ART_EINVAL, "final grid %lldx%lld too large (< 2^32 pixels, <= 65535 rows)", X, Y);
+    *nx = (int32_t)X;
+    *ny = (int32_t)Y;
+    return ART_OK;
+}
+
 void circ_EL(double a, double r, double* E, double* L)
 {
     const double sr = std::sqrt(r), r34 = std::pow(r, 0.75);
@@ -179,7 +149,7 @@ double r_isco(double a)
     return 3.0 + z2 - sg * std::sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2));
 }
 
-// Fill the kernel parameter block (nx, ny = final grid; 0 for point tracing).
+// Kernel parameter block of one image (nx, ny = final grid; 0 for points).
 void make_params(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
                  const art_transfer* tr, int nx, int ny, Params& P)
 {
@@ -199,7 +169,6 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
         P.x0 = -0.5 * cam->fov_M;
         P.y0 = -0.5 * P.dx * (double)(ny - 1);
     }
-    // ZAMO frame and BL metric at the camera
     const double r = P.r_cam, th = P.th_cam;
     const double s = std::sin(th), c = std::cos(th);
     const double Sig = r * r + a * a * c * c, Del = r * r - 2.0 * r + a * a;
@@ -237,6 +206,25 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
     }
 }
 
+LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes)
+{
+    LaunchCfg L;
+    art_launch u;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        u = g_launch;
+    }
+    L.trace_threads = u.trace_threads > 0 ? u.trace_threads : env_int("ART_TRACE_THREADS", 256);
+    if (L.trace_threads != 64 && L.trace_threads != 128 && L.trace_threads != 256) L.trace_threads = 256;
+    const int occ = trace_occupancy_blocks(precision, model, nstokes, L.trace_threads);
+    L.trace_blocks = u.trace_blocks > 0 ? u.trace_blocks : env_int("ART_TRACE_BLOCKS", cus * occ);
+    if (L.trace_blocks < 1) L.trace_blocks = 1;
+    L.refill = u.refill > 0 ? u.refill : env_int("ART_REFILL", 1);
+    if (L.refill < 1) L.refill = 1;
+    if (L.refill > 64) L.refill = 64;
+    return L;
+}
+
 int check_image(const art_image* out, long long nx, long long ny, bool need_level)
 {
     if (!out || !out->image_dev) return fail(ART_EINVAL, "output image is NULL");
@@ -246,45 +234,255 @@ int check_image(const art_image* out, long long nx, long long ny, bool need_leve
     return ART_OK;
 }
 
-int finish_stats(Workspace* w, hipStream_t s, int levels, long long npix, bool adaptive, art_stats* st,
-                 int nx0 = 0, int ny0 = 0)
+void free_batch_mem(art_batch* b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    for (int k = 0; k < 2 * kMaxEv; ++k)
+        if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
+    for (int k = 0; k < 2 * kMaxEv; ++k) b->ev[k] = nullptr;
+    if (b->list) (void)hipFree(b->list);
+    if (b->ctr) (void)hipFree(b->ctr);
+    if (b->dP) (void)hipFree(b->dP);
+    if (b->dD) (void)hipFree(b->dD);
+    b->list = nullptr; b->ctr = nullptr; b->dP = nullptr; b->dD = nullptr;
+    b->list_cap = 0;
+}
+
+// Grow-only device buffers of a batch.
+int ensure_mem(art_batch* b, size_t list_need)
+{
+    if (!b->ctr) {
+        if (hipMalloc(&b->ctr, sizeof(Counters)) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(counters) failed");
+        if (hipMalloc(&b->dP, sizeof(Params) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(params) failed");
+        if (hipMalloc(&b->dD, sizeof(ImageDesc) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(descs) failed");
+        for (int k = 0; k < 2 * kMaxEv; ++k) HIP_TRY(hipEventCreate(&b->ev[k]));
+        HIP_TRY(hipGetDevice(&b->dev));
+        HIP_TRY(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev));
+    }
+    if (list_need > b->list_cap) {
+        if (b->list) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(b->list));
+            b->list = nullptr;
+            b->list_cap = 0;
+        }
+        if (hipMalloc(&b->list, list_need * sizeof(unsigned long long)) != hipSuccess)
+            return fail(ART_ENOMEM, "hipMalloc(trace list, %zu entries) failed", list_need);
+        b->list_cap = list_need;
+    }
+    return ART_OK;
+}
+
+// Validate jobs, fill host descriptors, grow buffers and upload descriptors.
+int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, bool uniform,
+            hipStream_t s)
+{
+    if (n < 1 || n > kMaxBatch) return fail(ART_EINVAL, "batch size %d outside 1..%d", n, kMaxBatch);
+    if (!jobs || !images) return fail(ART_EINVAL, "NULL jobs or images");
+    if (uniform && n != 1) return fail(ART_EINVAL, "uniform renders take one image");
+    b->n = n;
+    b->uniform = uniform;
+    b->hP.resize(n);
+    b->hD.resize(n);
+    b->lmax = 0;
+    b->max_base = 0;
+    size_t total = 0, base_total = 0;
+    for (int i = 0; i < n; ++i) {
+        const art_job& J = jobs[i];
+        int rc = validate(&J.sp, &J.cam, &J.em, &J.tr);
+        if (rc) return rc;
+        if (!uniform) {
+            if (J.rf.abs_norm != ART_NORM_MEAN && J.rf.abs_norm != ART_NORM_MAX)
+                return fail(ART_EINVAL, "image %d: unknown abs_norm %d", i, J.rf.abs_norm);
+            if (std::isnan(J.rf.r_rel) || std::isnan(J.rf.r_abs))
+                return fail(ART_EINVAL, "image %d: NaN tolerance", i);
+        }
+        if (i == 0) {
+            b->model = J.em.kind;
+            b->nstokes = J.tr.nstokes;
+            b->precision = J.tr.precision;
+        } else if (J.em.kind != b->model || J.tr.nstokes != b->nstokes || J.tr.precision != b->precision) {
+            return fail(ART_EINVAL, "image %d: a batch needs one emission kind, nstokes and precision", i);
+        }
+        int32_t nx, ny;
+        rc = grid_size(&J.cam, J.tr.nstokes, &nx, &ny);
+        if (rc) return rc;
+        rc = check_image(&images[i], nx, ny, !uniform);
+        if (rc) return rc;
+        make_params(&J.sp, &J.cam, &J.em, &J.tr, nx, ny, b->hP[i]);
+        ImageDesc& D = b->hD[i];
+        D.img = images[i].image_dev;
+        D.level = images[i].level_dev;
+        D.feat = (RayFeat*)images[i].feat_dev;
+        D.plane = (long long)nx * ny;
+        D.nx = nx; D.ny = ny;
+        D.nx0 = J.cam.nx0; D.ny0 = J.cam.ny0;
+        D.levels = uniform ? 0 : J.cam.levels;
+        D.nstokes = J.tr.nstokes;
+        D.abs_norm = J.rf.abs_norm;
+        D.r_rel = J.rf.r_rel;
+        D.r_abs = J.rf.r_abs;
+        D.base_off = (int32_t)base_total;   // base items of image i are contiguous in the list
+        base_total += (size_t)D.nx0 * (size_t)D.ny0;
+        if (!uniform) {
+            b->lmax = D.levels > b->lmax ? D.levels : b->lmax;
+            b->max_base = D.nx0 * D.ny0 > b->max_base ? D.nx0 * D.ny0 : b->max_base;
+        }
+        total += (size_t)D.plane;
+    }
+    if (total >= (1ULL << 31)) return fail(ART_EINVAL, "batch has %zu pixels (limit 2^31)", total);
+    int rc = ensure_mem(b, uniform ? 0 : total);
+    if (rc) return rc;
+    b->L = launch_cfg(b->cus, b->precision, b->model, b->nstokes);
+    HIP_TRY(hipMemcpyAsync(b->dP, b->hP.data(), sizeof(Params) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->dD, b->hD.data(), sizeof(ImageDesc) * n, hipMemcpyHostToDevice, s));
+    return ART_OK;
+}
+
+TraceJob base_job(const art_batch* b, int level)
+{
+    TraceJob J;
+    std::memset(&J, 0, sizeof(J));
+    J.src = SRC_LIST;
+    J.nimg = b->n;
+    J.params = b->dP;
+    J.desc = b->dD;
+    J.list = b->list;
+    J.count = &b->ctr->count[level];
+    J.cursor = &b->ctr->cursor[level];
+    J.ctr = b->ctr;
+    J.refill = b->L.refill;
+    return J;
+}
+
+hipError_t ev_begin(art_batch* b, hipStream_t s)
+{
+    if (!b->timing || b->nev >= kMaxEv) return hipSuccess;
+    return hipEventRecord(b->ev[2 * b->nev], s);
+}
+hipError_t ev_end(art_batch* b, hipStream_t s)
+{
+    if (!b->timing || b->nev >= kMaxEv) return hipSuccess;
+    hipError_t e = hipEventRecord(b->ev[2 * b->nev + 1], s);
+    b->nev++;
+    return e;
+}
+
+// Enqueue the whole adaptive level loop of a prepared batch.
+int enqueue_adaptive(art_batch* b, hipStream_t s)
+{
+    b->nev = 0;
+    HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
+    HIP_TRY(launch_base_list(b->dD, b->n, b->max_base, b->list, b->ctr, 0, s));
+    TraceJob J = base_job(b, 0);
+    HIP_TRY(ev_begin(b, s));
+    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+    HIP_TRY(ev_end(b, s));
+    HIP_TRY(launch_reduce_base(b->dD, b->n, b->ctr, s));
+    int nx0m = 0, ny0m = 0;
+    for (int i = 0; i < b->n; ++i) {
+        nx0m = b->hD[i].nx0 > nx0m ? b->hD[i].nx0 : nx0m;
+        ny0m = b->hD[i].ny0 > ny0m ? b->hD[i].ny0 : ny0m;
+    }
+    for (int l = 0; l < b->lmax; ++l) {
+        const int nxl = (int)grid_n(nx0m, l + 1), nyl = (int)grid_n(ny0m, l + 1);
+        HIP_TRY(launch_estimate(b->dD, b->n, nxl, nyl, l, b->ctr, b->list, s));
+        J = base_job(b, l + 1);
+        HIP_TRY(ev_begin(b, s));
+        HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+        HIP_TRY(ev_end(b, s));
+    }
+    return ART_OK;
+}
+
+int enqueue_uniform(art_batch* b, hipStream_t s)
+{
+    b->nev = 0;
+    const ImageDesc& D = b->hD[0];
+    HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
+    HIP_TRY(launch_fill_u32(&b->ctr->count[0], 1, (uint32_t)D.plane, s));
+    if (D.level) HIP_TRY(launch_fill_i8(D.level, D.plane, 0, s));
+    TraceJob J = base_job(b, 0);
+    J.list = nullptr;    // implicit list: item k = pixel k of image 0
+    HIP_TRY(ev_begin(b, s));
+    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+    HIP_TRY(ev_end(b, s));
+    return ART_OK;
+}
+
+// Statistics of image i (i < 0: whole batch).  Synchronises the stream.
+int batch_stats(art_batch* b, int i, art_stats* st, hipStream_t s)
 {
     Counters h;
-    HIP_TRY(hipMemcpyAsync(&h, w->ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h, b->ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::memset(st, 0, sizeof(*st));
-    st->levels = levels;
-    long long traced = 0;
-    for (int l = 0; l <= levels && l < 32; ++l) {
-        st->traced[l] = h.count[l];
-        traced += h.count[l];
+    long long npix = 0, traced = 0;
+    int lv = 0;
+    for (int k = 0; k < b->n; ++k) {
+        if (i >= 0 && k != i) continue;
+        const ImageDesc& D = b->hD[k];
+        npix += D.plane;
+        lv = D.levels > lv ? D.levels : lv;
+        for (int l = 0; l <= D.levels && l < 32; ++l) {
+            const long long t = b->uniform ? (long long)D.plane : (long long)h.img_traced[k][l];
+            st->traced[l] += t;
+            traced += t;
+            if (l == 0)
+                st->candidates[0] += b->uniform ? D.plane : (long long)D.nx0 * D.ny0;
+            else
+                st->candidates[l] += grid_n(D.nx0, l) * grid_n(D.ny0, l) -
+                                     grid_n(D.nx0, l - 1) * grid_n(D.ny0, l - 1);
+        }
     }
+    st->levels = lv;
     st->rays_traced = traced;
-    if (adaptive) {
-        st->candidates[0] = (int64_t)nx0 * ny0;
-        for (int l = 0; l < levels && l < 31; ++l)
-            st->candidates[l + 1] = grid_n(nx0, l + 1) * grid_n(ny0, l + 1) - grid_n(nx0, l) * grid_n(ny0, l);
-    } else {
-        st->candidates[0] = npix;
-    }
     st->steps_total = (int64_t)h.steps;
-    for (int k = 0; k < 8; ++k) st->status_hist[k] = (int64_t)h.status[k];
-    st->interp_frac = adaptive ? (double)(npix - traced) / (double)npix : 0.0;
     st->steps_emit = (int64_t)h.steps_emit;
+    for (int k = 0; k < 8; ++k) st->status_hist[k] = (int64_t)h.status[k];
+    st->interp_frac = b->uniform ? 0.0 : (double)(npix - traced) / (double)npix;
+    const int si = i >= 0 ? i : 0;
+    st->ibar_int = h.scal[si][0];
+    st->imax0 = h.scal[si][1];
+    st->n_abs = h.scal[si][2];
     double tms = 0.0;
-    for (int k = 0; k < w->nev; ++k) {
+    for (int k = 0; k < b->nev; ++k) {
         float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, w->ev[2 * k], w->ev[2 * k + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev[2 * k], b->ev[2 * k + 1]));
         tms += ms;
     }
     st->t_trace_ms = tms;
-    st->trace_launches = w->nev;
-    st->ibar_int = h.scal[0];
-    st->imax0 = h.scal[1];
-    st->n_abs = h.scal[2];
+    st->trace_launches = b->nev;
     if (h.status[RAY_NAN] > 0)
         return fail(ART_ENUMERIC, "%llu rays produced NaN", (unsigned long long)h.status[RAY_NAN]);
     return ART_OK;
+}
+
+// One reusable batch per device for the single-image entry points.
+art_batch g_single[64];
+std::mutex g_single_mu;
+
+art_batch* single_batch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    return &g_single[dev];
+}
+
+art_job make_job(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                 const art_refine* rf, const art_transfer* tr)
+{
+    art_job j;
+    std::memset(&j, 0, sizeof(j));
+    j.sp = *sp;
+    j.cam = *cam;
+    j.em = *em;
+    if (rf) j.rf = *rf;
+    j.tr = *tr;
+    return j;
 }
 
 }  // namespace
@@ -296,16 +494,12 @@ const char* art_last_error(void) { return g_err.c_str(); }
 int art_image_size(const art_camera* cam, int32_t nstokes, int32_t* nx, int32_t* ny,
                    size_t* image_bytes)
 {
-    if (!cam) return fail(ART_EINVAL, "camera is NULL");
-    if (cam->nx0 < 2 || cam->ny0 < 2) return fail(ART_EINVAL, "base grid must be at least 2x2");
-    if (cam->levels < 0 || cam->levels > 20) return fail(ART_EINVAL, "levels must be in 0..20");
-    if (nstokes != 1 && nstokes != 4) return fail(ART_EINVAL, "nstokes must be 1 or 4");
-    const long long X = grid_n(cam->nx0, cam->levels), Y = grid_n(cam->ny0, cam->levels);
-    if (X * Y >= (1LL << 32) || X > (1LL << 30) || Y > (1LL << 30))
-        return fail(ART_EINVAL, "final grid %lldx%lld exceeds 2^32 pixels", X, Y);
-    if (nx) *nx = (int32_t)X;
-    if (ny) *ny = (int32_t)Y;
-    if (image_bytes) *image_bytes = (size_t)(X * Y) * (size_t)nstokes * sizeof(double);
+    int32_t X, Y;
+    int rc = grid_size(cam, nstokes, &X, &Y);
+    if (rc) return rc;
+    if (nx) *nx = X;
+    if (ny) *ny = Y;
+    if (image_bytes) *image_bytes = (size_t)X * (size_t)Y * (size_t)nstokes * sizeof(double);
     return ART_OK;
 }
 
@@ -313,98 +507,36 @@ int art_render(const art_spacetime* sp, const art_camera* cam, const art_emissio
                const art_refine* rf, const art_transfer* tr, art_image* out, art_stats* st,
                void* stream)
 {
-    int rc = validate(sp, cam, em, tr);
-    if (rc) return rc;
-    if (!rf) return fail(ART_EINVAL, "refinement block is NULL");
-    if (rf->abs_norm != ART_NORM_MEAN && rf->abs_norm != ART_NORM_MAX)
-        return fail(ART_EINVAL, "unknown abs_norm %d", rf->abs_norm);
-    if (std::isnan(rf->r_rel) || std::isnan(rf->r_abs)) return fail(ART_EINVAL, "NaN tolerance");
-    int32_t nx, ny;
-    rc = art_image_size(cam, tr->nstokes, &nx, &ny, nullptr);
-    if (rc) return rc;
-    rc = check_image(out, nx, ny, true);
-    if (rc) return rc;
+    if (!sp || !cam || !em || !rf || !tr || !out) return fail(ART_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_single_mu);
+    art_batch* b = single_batch();
+    if (!b) return fail(ART_EDEVICE, "no current device");
     hipStream_t s = (hipStream_t)stream;
-    const long long npix = (long long)nx * ny;
-    Workspace* w = nullptr;
-    rc = get_ws(&w, (size_t)npix);
+    const art_job j = make_job(sp, cam, em, rf, tr);
+    int rc = prepare(b, 1, &j, out, false, s);
     if (rc) return rc;
-    Params P;
-    make_params(sp, cam, em, tr, nx, ny, P);
-    const LaunchCfg L = launch_cfg(*w, tr->precision, em->kind, tr->nstokes);
-    const int levels = cam->levels;
-    const int st0 = 1 << levels;
-
-    HIP_TRY(launch_fill_u32((uint32_t*)w->ctr, sizeof(Counters) / 4, 0u, s));
-    HIP_TRY(launch_base_list(w->list, &w->ctr->count[0], cam->nx0, cam->ny0, st0, nx,
-                             out->level_dev, s));
-    TraceJob J;
-    std::memset(&J, 0, sizeof(J));
-    J.src = SRC_LIST;
-    J.list = w->list;
-    J.out = out->image_dev;
-    J.plane = npix;
-    J.feat = (RayFeat*)out->feat_dev;
-    J.ctr = w->ctr;
-    J.refill = L.refill;
-    J.count = &w->ctr->count[0];
-    J.cursor = &w->ctr->cursor[0];
-    TraceTimer tt{w, s, st != nullptr};
-    w->nev = 0;
-    HIP_TRY(tt.begin());
-    HIP_TRY(launch_trace(P, tr->precision, J, L, s));
-    HIP_TRY(tt.end());
-    HIP_TRY(launch_reduce_base(out->image_dev, nx, cam->nx0, cam->ny0, st0, rf->abs_norm, w->ctr, s));
-    for (int l = 0; l < levels; ++l) {
-        HIP_TRY(launch_estimate(out->image_dev, tr->nstokes, npix, nx, cam->nx0, cam->ny0, levels, l,
-                                rf->r_rel, rf->r_abs, w->ctr, w->list, out->level_dev, s));
-        J.count = &w->ctr->count[l + 1];
-        J.cursor = &w->ctr->cursor[l + 1];
-        HIP_TRY(tt.begin());
-        HIP_TRY(launch_trace(P, tr->precision, J, L, s));
-        HIP_TRY(tt.end());
-    }
-    if (st) return finish_stats(w, s, levels, npix, true, st, cam->nx0, cam->ny0);
+    b->timing = st != nullptr;
+    rc = enqueue_adaptive(b, s);
+    if (rc) return rc;
+    if (st) return batch_stats(b, 0, st, s);
     return ART_OK;
 }
 
 int art_render_uniform(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
                        const art_transfer* tr, art_image* out, art_stats* st, void* stream)
 {
-    int rc = validate(sp, cam, em, tr);
-    if (rc) return rc;
-    int32_t nx, ny;
-    rc = art_image_size(cam, tr->nstokes, &nx, &ny, nullptr);
-    if (rc) return rc;
-    rc = check_image(out, nx, ny, false);
-    if (rc) return rc;
+    if (!sp || !cam || !em || !tr || !out) return fail(ART_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_single_mu);
+    art_batch* b = single_batch();
+    if (!b) return fail(ART_EDEVICE, "no current device");
     hipStream_t s = (hipStream_t)stream;
-    const long long npix = (long long)nx * ny;
-    Workspace* w = nullptr;
-    rc = get_ws(&w, 0);
+    const art_job j = make_job(sp, cam, em, nullptr, tr);
+    int rc = prepare(b, 1, &j, out, true, s);
     if (rc) return rc;
-    Params P;
-    make_params(sp, cam, em, tr, nx, ny, P);
-    const LaunchCfg L = launch_cfg(*w, tr->precision, em->kind, tr->nstokes);
-    HIP_TRY(launch_fill_u32((uint32_t*)w->ctr, sizeof(Counters) / 4, 0u, s));
-    HIP_TRY(launch_fill_u32(&w->ctr->count[0], 1, (uint32_t)npix, s));
-    if (out->level_dev) HIP_TRY(launch_fill_i8(out->level_dev, npix, 0, s));
-    TraceJob J;
-    std::memset(&J, 0, sizeof(J));
-    J.src = SRC_IDENTITY;
-    J.out = out->image_dev;
-    J.plane = npix;
-    J.feat = (RayFeat*)out->feat_dev;
-    J.ctr = w->ctr;
-    J.refill = L.refill;
-    J.count = &w->ctr->count[0];
-    J.cursor = &w->ctr->cursor[0];
-    TraceTimer tt{w, s, st != nullptr};
-    w->nev = 0;
-    HIP_TRY(tt.begin());
-    HIP_TRY(launch_trace(P, tr->precision, J, L, s));
-    HIP_TRY(tt.end());
-    if (st) return finish_stats(w, s, 0, npix, false, st);
+    b->timing = st != nullptr;
+    rc = enqueue_uniform(b, s);
+    if (rc) return rc;
+    if (st) return batch_stats(b, 0, st, s);
     return ART_OK;
 }
 
@@ -417,27 +549,145 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
     if (n < 0 || n >= (1LL << 32)) return fail(ART_EINVAL, "point count %lld out of range", (long long)n);
     if (n == 0) return ART_OK;
     if (!alpha_dev || !beta_dev || !stokes_dev) return fail(ART_EINVAL, "NULL point buffer");
+    std::lock_guard<std::mutex> lk(g_single_mu);
+    art_batch* b = single_batch();
+    if (!b) return fail(ART_EDEVICE, "no current device");
     hipStream_t s = (hipStream_t)stream;
-    Workspace* w = nullptr;
-    rc = get_ws(&w, 0);
+    rc = ensure_mem(b, 0);
     if (rc) return rc;
-    Params P;
-    make_params(sp, cam, em, tr, 0, 0, P);
-    const LaunchCfg L = launch_cfg(*w, tr->precision, em->kind, tr->nstokes);
-    HIP_TRY(launch_fill_u32((uint32_t*)w->ctr, sizeof(Counters) / 4, 0u, s));
-    HIP_TRY(launch_fill_u32(&w->ctr->count[0], 1, (uint32_t)n, s));
-    TraceJob J;
-    std::memset(&J, 0, sizeof(J));
+    b->n = 1;
+    b->hP.resize(1);
+    make_params(sp, cam, em, tr, 0, 0, b->hP[0]);
+    b->L = launch_cfg(b->cus, tr->precision, em->kind, tr->nstokes);
+    HIP_TRY(hipMemcpyAsync(b->dP, b->hP.data(), sizeof(Params), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
+    HIP_TRY(launch_fill_u32(&b->ctr->count[0], 1, (uint32_t)n, s));
+    TraceJob J = base_job(b, 0);
     J.src = SRC_POINTS;
+    J.list = nullptr;
     J.alpha = alpha_dev;
     J.beta = beta_dev;
     J.out = stokes_dev;
     J.feat = (RayFeat*)feat_dev;
-    J.ctr = w->ctr;
-    J.refill = L.refill;
-    J.count = &w->ctr->count[0];
-    J.cursor = &w->ctr->cursor[0];
-    HIP_TRY(launch_trace(P, tr->precision, J, L, s));
+    HIP_TRY(launch_trace(tr->precision, em->kind, tr->nstokes, J, b->L, s));
+    return ART_OK;
+}
+
+int art_batch_create(int32_t n, const art_job* jobs, const art_image* images, art_batch** out)
+{
+    if (!out) return fail(ART_EINVAL, "NULL output handle");
+    *out = nullptr;
+    art_batch* b = new (std::nothrow) art_batch();
+    if (!b) return fail(ART_ENOMEM, "out of host memory");
+    int rc = prepare(b, n, jobs, images, false, nullptr);
+    if (rc == ART_OK && hipStreamSynchronize(nullptr) != hipSuccess) rc = fail(ART_EDEVICE, "upload failed");
+    if (rc) {
+        free_batch_mem(b);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return ART_OK;
+}
+
+int art_batch_render(art_batch* b, void* stream)
+{
+    if (!b) return fail(ART_EINVAL, "NULL batch");
+    b->timing = true;
+    return enqueue_adaptive(b, (hipStream_t)stream);
+}
+
+int art_batch_capture(art_batch* b, void* stream)
+{
+    if (!b) return fail(ART_EINVAL, "NULL batch");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(ART_EINVAL, "graph capture needs a non-default stream");
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    b->timing = false;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_adaptive(b, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(ART_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    return ART_OK;
+}
+
+int art_batch_launch(art_batch* b, void* stream)
+{
+    if (!b) return fail(ART_EINVAL, "NULL batch");
+    if (!b->gexec) return fail(ART_EINVAL, "batch has no captured graph (call art_batch_capture)");
+    b->nev = 0;
+    HIP_TRY(hipGraphLaunch(b->gexec, (hipStream_t)stream));
+    return ART_OK;
+}
+
+int art_batch_stats(art_batch* b, int32_t i, art_stats* st, void* stream)
+{
+    if (!b || !st) return fail(ART_EINVAL, "NULL argument");
+    if (i >= b->n) return fail(ART_EINVAL, "image index %d outside batch of %d", i, b->n);
+    return batch_stats(b, i, st, (hipStream_t)stream);
+}
+
+int art_batch_destroy(art_batch* b)
+{
+    if (!b) return ART_OK;
+    (void)hipDeviceSynchronize();
+    free_batch_mem(b);
+    delete b;
+    return ART_OK;
+}
+
+int art_set_launch(const art_launch* L)
+{
+    if (!L) return fail(ART_EINVAL, "NULL launch configuration");
+    if (L->trace_threads != 0 && L->trace_threads != 64 && L->trace_threads != 128 && L->trace_threads != 256)
+        return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
+    if (L->trace_blocks < 0 || L->refill < 0 || L->refill > 64)
+        return fail(ART_EINVAL, "trace_blocks >= 0 and 0 <= refill <= 64 required");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_launch = *L;
+    return ART_OK;
+}
+
+int art_batch_set_launch(art_batch* b, const art_launch* L)
+{
+    if (!b || !L) return fail(ART_EINVAL, "NULL argument");
+    if (L->trace_threads != 0 && L->trace_threads != 64 && L->trace_threads != 128 && L->trace_threads != 256)
+        return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
+    if (L->trace_blocks < 0 || L->refill < 0 || L->refill > 64)
+        return fail(ART_EINVAL, "trace_blocks >= 0 and 0 <= refill <= 64 required");
+    const LaunchCfg d = launch_cfg(b->cus, b->precision, b->model, b->nstokes);
+    b->L.trace_threads = L->trace_threads ? L->trace_threads : d.trace_threads;
+    b->L.trace_blocks = L->trace_blocks ? L->trace_blocks : d.trace_blocks;
+    b->L.refill = L->refill ? L->refill : d.refill;
+    return ART_OK;
+}
+
+int art_batch_get_launch(const art_batch* b, art_launch* L)
+{
+    if (!b || !L) return fail(ART_EINVAL, "NULL argument");
+    L->trace_blocks = b->L.trace_blocks;
+    L->trace_threads = b->L.trace_threads;
+    L->refill = b->L.refill;
+    L->pad = 0;
+    return ART_OK;
+}
+
+int art_get_launch(int32_t precision, int32_t kind, int32_t nstokes, art_launch* L)
+{
+    if (!L) return fail(ART_EINVAL, "NULL launch configuration");
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const LaunchCfg c = launch_cfg(cus, precision, kind, nstokes);
+    L->trace_blocks = c.trace_blocks;
+    L->trace_threads = c.trace_threads;
+    L->refill = c.refill;
+    L->pad = 0;
     return ART_OK;
 }
 
@@ -447,13 +697,19 @@ int art_metrics(const double* truth_dev, const double* approx_dev, int64_t n, do
     if (!truth_dev || !approx_dev) return fail(ART_EINVAL, "NULL image");
     if (n <= 0) return fail(ART_EINVAL, "empty image");
     hipStream_t s = (hipStream_t)stream;
-    Workspace* w = nullptr;
-    int rc = get_ws(&w, 0);
-    if (rc) return rc;
+    static double* partial[64] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(ART_EDEVICE, "device index out of range");
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!partial[dev] && hipMalloc(&partial[dev], sizeof(double) * (1024 * 4 + 4)) != hipSuccess)
+            return fail(ART_ENOMEM, "hipMalloc(partials) failed");
+    }
     const int nb = 1024;
-    HIP_TRY(launch_metrics(truth_dev, approx_dev, n, w->partial, nb, s));
+    HIP_TRY(launch_metrics(truth_dev, approx_dev, n, partial[dev], nb, s));
     double h[4];
-    HIP_TRY(hipMemcpyAsync(h, w->partial + nb * 4, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h, partial[dev] + nb * 4, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (flux_error) *flux_error = std::fabs(h[0] - h[1]) / std::fabs(h[0]);
     if (mse) *mse = h[2] / h[3];
@@ -462,20 +718,15 @@ int art_metrics(const double* truth_dev, const double* approx_dev, int64_t n, do
 
 int art_release(void)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(g_single_mu);
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
-    for (int d = 0; d < kMaxDev; ++d) {
-        Workspace& w = g_ws[d];
-        if (!w.ctr && !w.list) continue;
+    for (int d = 0; d < 64; ++d) {
+        art_batch& b = g_single[d];
+        if (!b.ctr && !b.list) continue;
         HIP_TRY(hipSetDevice(d));
         HIP_TRY(hipDeviceSynchronize());
-        if (w.list) HIP_TRY(hipFree(w.list));
-        if (w.ctr) HIP_TRY(hipFree(w.ctr));
-        if (w.partial) HIP_TRY(hipFree(w.partial));
-        for (int k = 0; k < 2 * 34; ++k)
-            if (w.ev[k]) HIP_TRY(hipEventDestroy(w.ev[k]));
-        w = Workspace();
+        free_batch_mem(&b);
     }
     HIP_TRY(hipSetDevice(cur));
     return ART_OK;

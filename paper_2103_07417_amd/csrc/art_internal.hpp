@@ -1,4 +1,4 @@
-// art_internal.hpp -- host-side declarations shared by the kernels and the
+// art_internal.hpp -- host/kernel declarations shared by the kernels and the
 // C ABI implementation (not part of the public interface).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -8,50 +8,70 @@
 
 namespace art {
 
-// Device counters of one render, zeroed by a fill kernel at the start.
+constexpr int kMaxBatch = 64;     // images per launch (their Params are staged in LDS)
+constexpr int kMaxLevels = 21;
+
+// Device counters of one batch, zeroed by a fill kernel at the start.
 struct Counters {
-    uint32_t count[33];        // per level: points in the trace list
-    uint32_t cursor[33];       // per level: work-queue cursor
-    unsigned long long steps;  // geodesic steps
-    unsigned long long steps_emit;  // steps that evaluated the plasma/transfer
+    uint32_t count[kMaxLevels + 1];       // per level: work items in the trace list
+    uint32_t cursor[kMaxLevels + 1];      // per level: work-queue cursor
+    unsigned long long steps;             // geodesic steps
+    unsigned long long steps_emit;        // steps that evaluated the plasma/transfer
     unsigned long long status[8];
-    double scal[4];            // ibar_int, imax0, n_abs, spare
+    uint32_t img_traced[kMaxBatch][kMaxLevels + 1];   // per image and level
+    double scal[kMaxBatch][4];            // per image: ibar_int, imax0, n_abs, spare
 };
 
-enum TraceSrc : int { SRC_LIST = 0, SRC_IDENTITY = 1, SRC_POINTS = 2 };
+// Per-image description (device memory).
+struct ImageDesc {
+    double* img;          // [nstokes][ny][nx]
+    int8_t* level;        // [ny][nx]
+    RayFeat* feat;        // optional
+    long long plane;      // nx * ny
+    int32_t nx, ny, nx0, ny0, levels, nstokes, abs_norm, base_off;
+    double r_rel, r_abs;
+};
+
+enum TraceSrc : int { SRC_LIST = 0, SRC_POINTS = 1 };
+
+// Work item of the pixel queue: image index in the high 32 bits.
+__host__ __device__ inline unsigned long long make_item(uint32_t img, uint32_t pix)
+{
+    return ((unsigned long long)img << 32) | pix;
+}
 
 struct TraceJob {
-    int src;                   // TraceSrc
-    const uint32_t* list;      // SRC_LIST: pixel indices
-    const double* alpha;       // SRC_POINTS
+    int src;                      // TraceSrc
+    int nimg;                     // images in the batch (Params staged in LDS)
+    const Params* params;         // [nimg]
+    const ImageDesc* desc;        // [nimg] (pixel sources)
+    const unsigned long long* list;   // SRC_LIST: items
+    long long identity_n;         // > 0: the list is implicit, item = pixel of image 0
+    const double* alpha;          // SRC_POINTS
     const double* beta;
-    uint32_t* count;           // device count of work items
-    uint32_t* cursor;          // device queue cursor (zeroed)
-    double* out;               // image planes (pixel sources) or n x nstokes (points)
-    long long plane;           // stride between Stokes planes (pixel sources)
-    RayFeat* feat;             // optional
-    Counters* ctr;             // statistics (steps, status histogram)
-    int refill;                // refill when at least this many lanes idle
+    double* out;                  // SRC_POINTS: n x nstokes
+    RayFeat* feat;                // SRC_POINTS features (optional)
+    uint32_t* count;              // device count of work items
+    uint32_t* cursor;             // device queue cursor (zeroed)
+    Counters* ctr;                // statistics
+    int refill;                   // refill when at least this many lanes idle
 };
 
 struct LaunchCfg {
-    int trace_blocks;          // persistent grid size
-    int trace_threads;         // 64..1024, multiple of 64
-    int refill;                // refill threshold
+    int trace_blocks;             // persistent grid size
+    int trace_threads;            // 64, 128 or 256
+    int refill;                   // refill threshold (1..64)
 };
 
 hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
-hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 hipError_t launch_fill_i8(int8_t* p, long long n, int8_t v, hipStream_t s);
-hipError_t launch_base_list(uint32_t* list, uint32_t* count, int nx0, int ny0, int st0,
-                            int nx, int8_t* level, hipStream_t s);
-hipError_t launch_trace(const Params& P, int precision, const TraceJob& J, const LaunchCfg& L,
+hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsigned long long* list,
+                            Counters* ctr, int level_slot, hipStream_t s);
+hipError_t launch_trace(int precision, int model, int nstokes, const TraceJob& J, const LaunchCfg& L,
                         hipStream_t s);
-hipError_t launch_reduce_base(const double* img, int nx, int nx0, int ny0, int st0, int norm,
-                              Counters* ctr, hipStream_t s);
-hipError_t launch_estimate(double* img, int nstokes, long long plane, int nx, int nx0, int ny0,
-                           int levels, int l, double r_rel, double r_abs, Counters* ctr,
-                           uint32_t* list, int8_t* level, hipStream_t s);
+hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s);
+hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
+                           Counters* ctr, unsigned long long* list, hipStream_t s);
 hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
                           int nblocks, hipStream_t s);
 int trace_occupancy_blocks(int precision, int model, int nstokes, int threads);

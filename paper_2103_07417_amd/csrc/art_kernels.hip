@@ -29,12 +29,6 @@ __global__ void k_fill_u32(uint32_t* p, long long n, uint32_t v)
          i += (long long)gridDim.x * blockDim.x)
         p[i] = v;
 }
-__global__ void k_fill_f64(double* p, long long n, double v)
-{
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        p[i] = v;
-}
 __global__ void k_fill_i8(int8_t* p, long long n, int8_t v)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -56,12 +50,6 @@ hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s)
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
-hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_f64, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
-}
 hipError_t launch_fill_i8(int8_t* p, long long n, int8_t v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -70,25 +58,32 @@ hipError_t launch_fill_i8(int8_t* p, long long n, int8_t v, hipStream_t s)
 }
 
 // ------------------------------------------------------------ base-grid list
-__global__ void k_base_list(uint32_t* list, uint32_t* count, int nx0, int ny0, int st0, int nx,
-                            int8_t* level)
+// grid (x: base points, y: image).  Items of image i occupy
+// list[base_off_i, base_off_i + nx0_i ny0_i).
+__global__ void k_base_list(const ImageDesc* desc, unsigned long long* list, Counters* ctr, int slot)
 {
-    const int n = nx0 * ny0;
+    const int img = blockIdx.y;
+    const ImageDesc D = desc[img];
+    const int n = D.nx0 * D.ny0;
+    const int st0 = 1 << D.levels;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        const int i = t % nx0, j = t / nx0;
-        const uint32_t pix = (uint32_t)(j * st0) * (uint32_t)nx + (uint32_t)(i * st0);
-        list[t] = pix;
-        if (level) level[pix] = 0;
+        const int i = t % D.nx0, j = t / D.nx0;
+        const uint32_t pix = (uint32_t)(j * st0) * (uint32_t)D.nx + (uint32_t)(i * st0);
+        list[D.base_off + t] = make_item((uint32_t)img, pix);
+        if (D.level) D.level[pix] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *count = (uint32_t)n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&ctr->count[slot], (uint32_t)n);
+        ctr->img_traced[img][0] = (uint32_t)n;
+    }
 }
 
-hipError_t launch_base_list(uint32_t* list, uint32_t* count, int nx0, int ny0, int st0, int nx,
-                            int8_t* level, hipStream_t s)
+hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsigned long long* list,
+                            Counters* ctr, int slot, hipStream_t s)
 {
-    const long long n = (long long)nx0 * ny0;
-    hipLaunchKernelGGL(k_base_list, dim3(fill_blocks(n)), dim3(256), 0, s, list, count, nx0, ny0,
-                       st0, nx, level);
+    int bx = (max_base + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(k_base_list, dim3(bx, nimg), dim3(256), 0, s, desc, list, ctr, slot);
     return hipGetLastError();
 }
 
@@ -101,7 +96,8 @@ struct RayState {
     R S[NS];
     R O[NS == 4 ? 16 : 1];
     int ncross, nstep;
-    uint32_t item;
+    uint32_t pix;
+    int img;
 };
 
 template <typename R, int MODEL, int NS>
@@ -182,11 +178,23 @@ __device__ __forceinline__ int ray_step(const Params& P, RayState<R, MODEL, NS>&
     return RAY_OK;
 }
 
+// Persistent work-queue tracer.  Every wave loops: idle lanes are counted by
+// a ballot, one lane claims that many items with a single atomic, the items
+// are handed out by lane prefix; then every busy lane advances its ray by one
+// step.  The per-image parameter blocks are staged in LDS once per block.
 template <typename R, int MODEL, int NS>
-__global__ __launch_bounds__(256) void k_trace(Params P, TraceJob J)
+__global__ __launch_bounds__(256) void k_trace(TraceJob J)
 {
+    __shared__ Params sP[kMaxBatch];
+    {
+        static_assert(sizeof(Params) % 8 == 0, "Params must be a whole number of doubles");
+        const int nw = J.nimg * (int)(sizeof(Params) / 8);
+        const double* src = reinterpret_cast<const double*>(J.params);
+        double* dst = reinterpret_cast<double*>(sP);
+        for (int k = threadIdx.x; k < nw; k += blockDim.x) dst[k] = src[k];
+        __syncthreads();
+    }
     const int lane = __lane_id();
-    const int nsout = P.nstokes;
     RayState<R, MODEL, NS> st;
     bool active = false, drained = false;
     unsigned long long my_steps = 0;
@@ -207,35 +215,49 @@ __global__ __launch_bounds__(256) void k_trace(Params P, TraceJob J)
                 if (!active) {
                     const unsigned my = base + lane_prefix(need);
                     if (my < cnt) {
-                        double al, be;
-                        uint32_t item;
+                        double al = 0.0, be = 0.0;
+                        int img = 0;
+                        uint32_t pix = my;
+                        bool ok = true;
                         if (J.src == SRC_POINTS) {
-                            item = my;
                             al = J.alpha[my];
                             be = J.beta[my];
                         } else {
-                            item = (J.src == SRC_LIST) ? J.list[my] : my;
-                            const uint32_t i = item % (uint32_t)P.nx, j = item / (uint32_t)P.nx;
-                            al = P.x0 + (double)i * P.dx;
-                            be = P.y0 + (double)j * P.dx;
+                            if (J.list) {
+                                const unsigned long long it = J.list[my];
+                                img = (int)(it >> 32);
+                                pix = (uint32_t)it;
+                            }
+                            // a malformed item is dropped rather than written out of bounds
+                            ok = img < J.nimg && (long long)pix < J.desc[img].plane;
+                            if (ok) {
+                                const Params& Pi = sP[img];
+                                const uint32_t i = pix % (uint32_t)Pi.nx, j = pix / (uint32_t)Pi.nx;
+                                al = Pi.x0 + (double)i * Pi.dx;
+                                be = Pi.y0 + (double)j * Pi.dx;
+                            }
                         }
-                        st.item = item;
-                        if (P.model >= MODEL_SCREEN_RING) {
-                            double S4[4];
-                            screen_fn(P, al, be, S4);
-                            if (J.src == SRC_POINTS) {
-                                for (int s = 0; s < nsout; ++s) J.out[(long long)item * nsout + s] = S4[s];
-                            } else {
-                                for (int s = 0; s < nsout; ++s) J.out[s * J.plane + item] = S4[s];
-                            }
-                            if (J.feat) {
+                        if (ok) {
+                            st.img = img;
+                            st.pix = pix;
+                            const Params& P = sP[img];
+                            if (P.model >= MODEL_SCREEN_RING) {
+                                double S4[4];
+                                screen_fn(P, al, be, S4);
                                 RayFeat f; f.rmin = (float)P.r_cam; f.ncross = 0; f.steps = 0; f.status = RAY_OK;
-                                J.feat[item] = f;
+                                if (J.src == SRC_POINTS) {
+                                    for (int s = 0; s < P.nstokes; ++s) J.out[(long long)pix * P.nstokes + s] = S4[s];
+                                    if (J.feat) J.feat[pix] = f;
+                                } else {
+                                    const ImageDesc& D = J.desc[img];
+                                    for (int s = 0; s < D.nstokes; ++s) D.img[s * D.plane + pix] = S4[s];
+                                    if (D.feat) D.feat[pix] = f;
+                                }
+                                hist[RAY_OK]++;
+                            } else {
+                                ray_init<R, MODEL, NS>(P, st, al, be);
+                                active = true;
                             }
-                            hist[RAY_OK]++;
-                        } else {
-                            ray_init<R, MODEL, NS>(P, st, al, be);
-                            active = true;
                         }
                     }
                 }
@@ -246,6 +268,7 @@ __global__ __launch_bounds__(256) void k_trace(Params P, TraceJob J)
             continue;
         }
         if (active) {
+            const Params& P = sP[st.img];
             const int status = ray_step<R, MODEL, NS>(P, st, my_emit);
             if (status != RAY_OK) {
                 double Sd[4] = { 0.0, 0.0, 0.0, 0.0 };
@@ -253,15 +276,15 @@ __global__ __launch_bounds__(256) void k_trace(Params P, TraceJob J)
                 for (int s = 0; s < NS; ++s) Sd[s] = (double)st.S[s];
                 int stt = status;
                 if (!(Sd[0] == Sd[0])) stt = RAY_NAN;
+                RayFeat f;
+                f.rmin = (float)st.rmin; f.ncross = st.ncross; f.steps = st.nstep; f.status = stt;
                 if (J.src == SRC_POINTS) {
-                    for (int s = 0; s < nsout; ++s) J.out[(long long)st.item * nsout + s] = Sd[s];
+                    for (int s = 0; s < P.nstokes; ++s) J.out[(long long)st.pix * P.nstokes + s] = Sd[s];
+                    if (J.feat) J.feat[st.pix] = f;
                 } else {
-                    for (int s = 0; s < nsout; ++s) J.out[s * J.plane + st.item] = Sd[s];
-                }
-                if (J.feat) {
-                    RayFeat f;
-                    f.rmin = (float)st.rmin; f.ncross = st.ncross; f.steps = st.nstep; f.status = stt;
-                    J.feat[st.item] = f;
+                    const ImageDesc& D = J.desc[st.img];
+                    for (int s = 0; s < D.nstokes; ++s) D.img[s * D.plane + st.pix] = Sd[s];
+                    if (D.feat) D.feat[st.pix] = f;
                 }
                 my_steps += (unsigned long long)st.nstep;
                 hist[stt]++;
@@ -286,32 +309,32 @@ __global__ __launch_bounds__(256) void k_trace(Params P, TraceJob J)
 }
 
 template <typename R, int MODEL, int NS>
-static hipError_t launch_trace_t(const Params& P, const TraceJob& J, const LaunchCfg& L, hipStream_t s)
+static hipError_t launch_trace_t(const TraceJob& J, const LaunchCfg& L, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_trace<R, MODEL, NS>), dim3(L.trace_blocks), dim3(L.trace_threads), 0, s, P, J);
+    hipLaunchKernelGGL((k_trace<R, MODEL, NS>), dim3(L.trace_blocks), dim3(L.trace_threads), 0, s, J);
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const Params& P, int precision, const TraceJob& J, const LaunchCfg& L,
+hipError_t launch_trace(int precision, int model, int nstokes, const TraceJob& J, const LaunchCfg& L,
                         hipStream_t s)
 {
-    const bool pol = (P.nstokes == 4) && (P.model == MODEL_THERMAL);
-    const bool thermal = (P.model == MODEL_THERMAL);
+    const bool thermal = (model == MODEL_THERMAL);
+    const bool pol = (nstokes == 4) && thermal;
     if (precision == 0) {
-        if (thermal) return pol ? launch_trace_t<double, MODEL_THERMAL, 4>(P, J, L, s)
-                                : launch_trace_t<double, MODEL_THERMAL, 1>(P, J, L, s);
-        return launch_trace_t<double, MODEL_TOY, 1>(P, J, L, s);
+        if (thermal) return pol ? launch_trace_t<double, MODEL_THERMAL, 4>(J, L, s)
+                                : launch_trace_t<double, MODEL_THERMAL, 1>(J, L, s);
+        return launch_trace_t<double, MODEL_TOY, 1>(J, L, s);
     }
-    if (thermal) return pol ? launch_trace_t<float, MODEL_THERMAL, 4>(P, J, L, s)
-                            : launch_trace_t<float, MODEL_THERMAL, 1>(P, J, L, s);
-    return launch_trace_t<float, MODEL_TOY, 1>(P, J, L, s);
+    if (thermal) return pol ? launch_trace_t<float, MODEL_THERMAL, 4>(J, L, s)
+                            : launch_trace_t<float, MODEL_THERMAL, 1>(J, L, s);
+    return launch_trace_t<float, MODEL_TOY, 1>(J, L, s);
 }
 
 int trace_occupancy_blocks(int precision, int model, int nstokes, int threads)
 {
     int nb = 0;
-    const bool pol = (nstokes == 4) && (model == MODEL_THERMAL);
     const bool thermal = (model == MODEL_THERMAL);
+    const bool pol = (nstokes == 4) && thermal;
     hipError_t e;
     if (precision == 0) {
         if (thermal && pol) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<double, MODEL_THERMAL, 4>, threads, 0);
@@ -327,19 +350,22 @@ int trace_occupancy_blocks(int precision, int model, int nstokes, int threads)
 }
 
 // ------------------------------------------------------ level-0 reduction
-__global__ __launch_bounds__(1024) void k_reduce_base(const double* img, int nx, int nx0, int ny0,
-                                                     int st0, int norm, Counters* ctr)
+// One block per image: trapezoid-weighted mean and maximum of the base grid.
+__global__ __launch_bounds__(1024) void k_reduce_base(const ImageDesc* desc, Counters* ctr)
 {
     __shared__ double ssum[1024];
     __shared__ double smax[1024];
+    const int img = blockIdx.x;
+    const ImageDesc D = desc[img];
     const int t = threadIdx.x;
+    const int st0 = 1 << D.levels;
     double sum = 0.0, mx = -HUGE_VAL;
-    const int n = nx0 * ny0;
+    const int n = D.nx0 * D.ny0;
     for (int k = t; k < n; k += 1024) {
-        const int i = k % nx0, j = k / nx0;
-        const double v = img[(long long)(j * st0) * nx + (long long)(i * st0)];
-        const double wx = (i == 0 || i == nx0 - 1) ? 0.5 : 1.0;
-        const double wy = (j == 0 || j == ny0 - 1) ? 0.5 : 1.0;
+        const int i = k % D.nx0, j = k / D.nx0;
+        const double v = D.img[(long long)(j * st0) * D.nx + (long long)(i * st0)];
+        const double wx = (i == 0 || i == D.nx0 - 1) ? 0.5 : 1.0;
+        const double wy = (j == 0 || j == D.ny0 - 1) ? 0.5 : 1.0;
         sum += (wy * wx) * v;
         mx = v > mx ? v : mx;
     }
@@ -354,17 +380,16 @@ __global__ __launch_bounds__(1024) void k_reduce_base(const double* img, int nx,
         __syncthreads();
     }
     if (t == 0) {
-        const double ibar = ssum[0] / ((double)(nx0 - 1) * (double)(ny0 - 1));
-        ctr->scal[0] = ibar;
-        ctr->scal[1] = smax[0];
-        ctr->scal[2] = norm == 0 ? ibar : smax[0];
+        const double ibar = ssum[0] / ((double)(D.nx0 - 1) * (double)(D.ny0 - 1));
+        ctr->scal[img][0] = ibar;
+        ctr->scal[img][1] = smax[0];
+        ctr->scal[img][2] = D.abs_norm == 0 ? ibar : smax[0];
     }
 }
 
-hipError_t launch_reduce_base(const double* img, int nx, int nx0, int ny0, int st0, int norm,
-                              Counters* ctr, hipStream_t s)
+hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_base, dim3(1), dim3(1024), 0, s, img, nx, nx0, ny0, st0, norm, ctr);
+    hipLaunchKernelGGL(k_reduce_base, dim3(nimg), dim3(1024), 0, s, desc, ctr);
     return hipGetLastError();
 }
 
@@ -387,75 +412,74 @@ __device__ __forceinline__ bool axis_D(const double* I, long long nx, int s, int
     return false;
 }
 
-__global__ __launch_bounds__(256) void k_estimate(double* img, int nstokes, long long plane, int nx,
-                                                  int nxl, int nyl, int s, int l, double r_rel,
-                                                  double r_abs, Counters* ctr, uint32_t* list,
-                                                  int8_t* level)
+// grid (x: 256-wide strips of p, y: q, z: image).  One thread per point of the
+// level-(l+1) grid; new points are classified by index parity (categories 2-4).
+__global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
+                                                  unsigned long long* list)
 {
+    const int img = blockIdx.z;
+    const ImageDesc D = desc[img];
+    if (l >= D.levels) return;                     // uniform over the block
+    const int nxl = (1 << (l + 1)) * (D.nx0 - 1) + 1;
+    const int nyl = (1 << (l + 1)) * (D.ny0 - 1) + 1;
+    const int s = 1 << (D.levels - l - 1);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
-    const bool inside = p < nxl && q < nyl;
-    const bool isnew = inside && ((p & 1) | (q & 1));
+    const bool isnew = p < nxl && q < nyl && ((p & 1) | (q & 1));
     bool trace = false;
     long long pix = 0;
     if (isnew) {
-        const double* I = img;
-        const long long NX = nx;
+        const double* I = D.img;
+        const long long NX = D.nx;
         pix = (long long)(q * s) * NX + (long long)(p * s);
         const bool c4 = (p & 1) && (q & 1);
-        double Ssum, D;
+        double Ssum, D2;
         bool avail;
         double m;
+        long long o[4];
+        int nnb;
         if (c4) {
-            const long long o1 = (long long)((q - 1) * s) * NX + (long long)((p - 1) * s);
-            const long long o4 = (long long)((q + 1) * s) * NX + (long long)((p + 1) * s);
-            const long long o2 = (long long)((q - 1) * s) * NX + (long long)((p + 1) * s);
-            const long long o3 = (long long)((q + 1) * s) * NX + (long long)((p - 1) * s);
-            const double i1 = I[o1], i4 = I[o4], i2 = I[o2], i3 = I[o3];
-            Ssum = (i1 + i4) + (i2 + i3);
             // diagonal x': I1 (-1,-1) -> I4 (+1,+1), continuations I5, I8 at -+3;
             // diagonal y': I2 (+1,-1) -> I3 (-1,+1), continuations I6 (+3,-3), I7 (-3,+3)
+            o[0] = (long long)((q - 1) * s) * NX + (long long)((p - 1) * s);
+            o[1] = (long long)((q + 1) * s) * NX + (long long)((p + 1) * s);
+            o[2] = (long long)((q - 1) * s) * NX + (long long)((p + 1) * s);
+            o[3] = (long long)((q + 1) * s) * NX + (long long)((p - 1) * s);
+            nnb = 4;
+            const double i1 = I[o[0]], i4 = I[o[1]], i2 = I[o[2]], i3 = I[o[3]];
+            Ssum = (i1 + i4) + (i2 + i3);
             double Dx, Dy;
             const bool ax = axis_D(I, NX, s, nxl, nyl, p, q, 1, 1, i1, i4, Dx);
             const bool ay = axis_D(I, NX, s, nxl, nyl, p, q, -1, 1, i2, i3, Dy);
-            D = ax ? (ay ? Dx + Dy : 2.0 * Dx) : 2.0 * Dy;
+            D2 = ax ? (ay ? Dx + Dy : 2.0 * Dx) : 2.0 * Dy;
             avail = ax || ay;
             m = 4.0;
         } else {
             const int dx = (p & 1) ? 1 : 0, dy = (p & 1) ? 0 : 1;
-            const long long olo = (long long)((q - dy) * s) * NX + (long long)((p - dx) * s);
-            const long long ohi = (long long)((q + dy) * s) * NX + (long long)((p + dx) * s);
-            const double lo = I[olo], hi = I[ohi];
+            o[0] = (long long)((q - dy) * s) * NX + (long long)((p - dx) * s);
+            o[1] = (long long)((q + dy) * s) * NX + (long long)((p + dx) * s);
+            o[2] = o[3] = 0;
+            nnb = 2;
+            const double lo = I[o[0]], hi = I[o[1]];
             Ssum = lo + hi;
-            avail = axis_D(I, NX, s, nxl, nyl, p, q, dx, dy, lo, hi, D);
+            avail = axis_D(I, NX, s, nxl, nyl, p, q, dx, dy, lo, hi, D2);
             m = 2.0;
         }
-        const double nabs = ctr->scal[2];
-        const double thrA = (4.0 * m * r_abs) * nabs;
-        const double crel = 4.0 * r_rel;
-        const double aD = ::fabs(D);
-        trace = !avail || !(D == D) || !(Ssum == Ssum) || (aD > thrA && aD > crel * ::fabs(Ssum));
+        const double nabs = ctr->scal[img][2];
+        const double thrA = (4.0 * m * D.r_abs) * nabs;
+        const double crel = 4.0 * D.r_rel;
+        const double aD = ::fabs(D2);
+        trace = !avail || !(D2 == D2) || !(Ssum == Ssum) || (aD > thrA && aD > crel * ::fabs(Ssum));
         if (trace) {
-            level[pix] = (int8_t)(l + 1);
+            D.level[pix] = (int8_t)(l + 1);
         } else {
-            level[pix] = (int8_t)-1;
+            D.level[pix] = (int8_t)-1;
             const double w = 1.0 / m;
-            for (int st = 0; st < nstokes; ++st) {
-                const double* Is = img + st * plane;
-                double S;
-                if (c4) {
-                    const long long o1 = (long long)((q - 1) * s) * NX + (long long)((p - 1) * s);
-                    const long long o4 = (long long)((q + 1) * s) * NX + (long long)((p + 1) * s);
-                    const long long o2 = (long long)((q - 1) * s) * NX + (long long)((p + 1) * s);
-                    const long long o3 = (long long)((q + 1) * s) * NX + (long long)((p - 1) * s);
-                    S = st == 0 ? Ssum : (Is[o1] + Is[o4]) + (Is[o2] + Is[o3]);
-                } else {
-                    const int dx = (p & 1) ? 1 : 0, dy = (p & 1) ? 0 : 1;
-                    const long long olo = (long long)((q - dy) * s) * NX + (long long)((p - dx) * s);
-                    const long long ohi = (long long)((q + dy) * s) * NX + (long long)((p + dx) * s);
-                    S = st == 0 ? Ssum : Is[olo] + Is[ohi];
-                }
-                img[st * plane + pix] = S * w;
+            D.img[pix] = Ssum * w;
+            for (int st = 1; st < D.nstokes; ++st) {
+                const double* Is = I + st * D.plane;
+                const double S = nnb == 4 ? (Is[o[0]] + Is[o[1]]) + (Is[o[2]] + Is[o[3]]) : Is[o[0]] + Is[o[1]];
+                D.img[st * D.plane + pix] = S * w;
             }
         }
     }
@@ -464,23 +488,22 @@ __global__ __launch_bounds__(256) void k_estimate(double* img, int nstokes, long
     if (mask) {
         const int lane = __lane_id();
         const int leader = __ffsll((long long)mask) - 1;
+        const unsigned nset = (unsigned)__popcll(mask);
         unsigned base = 0;
-        if (lane == leader) base = atomicAdd(&ctr->count[l + 1], (unsigned)__popcll(mask));
+        if (lane == leader) {
+            base = atomicAdd(&ctr->count[l + 1], nset);
+            atomicAdd(&ctr->img_traced[img][l + 1], nset);
+        }
         base = __shfl(base, leader);
-        if (trace) list[base + lane_prefix(mask)] = (uint32_t)pix;
+        if (trace) list[base + lane_prefix(mask)] = make_item((uint32_t)img, (uint32_t)pix);
     }
 }
 
-hipError_t launch_estimate(double* img, int nstokes, long long plane, int nx, int nx0, int ny0,
-                           int levels, int l, double r_rel, double r_abs, Counters* ctr,
-                           uint32_t* list, int8_t* level, hipStream_t s)
+hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
+                           Counters* ctr, unsigned long long* list, hipStream_t s)
 {
-    const int nxl = (1 << (l + 1)) * (nx0 - 1) + 1;
-    const int nyl = (1 << (l + 1)) * (ny0 - 1) + 1;
-    const int sp = 1 << (levels - l - 1);
-    dim3 grid((nxl + 255) / 256, nyl);
-    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, img, nstokes, plane, nx, nxl, nyl, sp, l,
-                       r_rel, r_abs, ctr, list, level);
+    dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
+    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list);
     return hipGetLastError();
 }
 

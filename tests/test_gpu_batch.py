@@ -1,0 +1,96 @@
+"""GPU batches: many images through one work queue per level.
+
+A batched image must be bitwise equal to the same image rendered alone (the
+FP64 per-ray arithmetic does not depend on scheduling), a captured hipGraph
+must reproduce the eager render on every replay, and the launch shape
+(grid size, block size, refill threshold) must not change any result.
+"""
+import numpy as np
+import pytest
+
+import art_inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def art():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_07417_amd import art as a
+    a.lib()
+    return a
+
+
+def small_batch(precision="fp64"):
+    cfgs = []
+    for k, (a, inc, nu) in enumerate([(0.94, 163.0, 230e9), (0.0, 17.0, 86e9),
+                                      (-0.94, 60.0, 345e9), (0.5, 90.0, 690e9)]):
+        c = art_inputs.reduced(art_inputs.workload("thermal_1025"), 17, 1 + (k % 3))
+        c.update(a=a, inc_deg=inc, freq_hz=nu, precision=precision)
+        cfgs.append(c)
+    return cfgs
+
+
+def test_batch_equals_single(art):
+    print("CASE batch equals single", flush=True)
+    cfgs = small_batch()
+    B = art.Batch(cfgs)
+    B.render()
+    st = B.stats()
+    torch.cuda.synchronize()
+    total = 0
+    for i, c in enumerate(cfgs):
+        img, lev, _, s1 = art.render(c)
+        assert torch.equal(img, B.images[i]), i
+        assert torch.equal(lev, B.levels[i]), i
+        si = B.stats(i)
+        assert si["rays"] == s1["rays"] and si["traced"] == s1["traced"]
+        total += s1["rays"]
+    assert st["rays"] == total
+    B.close()
+
+
+def test_batch_graph_replays(art):
+    print("CASE batch graph replays", flush=True)
+    cfgs = small_batch("mixed")
+    B = art.Batch(cfgs)
+    B.render()
+    torch.cuda.synchronize()
+    ref = [im.clone() for im in B.images]
+    ref_lev = [lv.clone() for lv in B.levels]
+    s = torch.cuda.Stream()
+    B.capture(s)
+    for rep in range(3):
+        for im in B.images:
+            im.fill_(-1.0)                  # eager work between replays
+        torch.cuda.synchronize()
+        B.launch(s)
+        s.synchronize()
+        for i in range(len(cfgs)):
+            assert torch.equal(B.images[i], ref[i]), (rep, i)
+            assert torch.equal(B.levels[i], ref_lev[i]), (rep, i)
+    B.close()
+
+
+def test_launch_shape_does_not_change_results(art):
+    print("CASE launch shapes", flush=True)
+    cfg = art_inputs.reduced(art_inputs.workload("thermal_1025"), 17, 2)
+    ref, rlev, _, _ = art.render(cfg)
+    try:
+        for blocks, threads, refill in ((7, 64, 1), (300, 128, 8), (64, 256, 64)):
+            art.set_launch(blocks, threads, refill)
+            img, lev, _, _ = art.render(cfg)
+            assert torch.equal(img, ref) and torch.equal(lev, rlev), (blocks, threads, refill)
+    finally:
+        art.set_launch(0, 0, 0)
+
+
+def test_batch_rejects_mixed_kinds(art):
+    c1 = art_inputs.reduced(art_inputs.workload("thermal_1025"), 9, 1)
+    c2 = dict(c1, nstokes=1)
+    with pytest.raises(art.ArtError):
+        art.Batch([c1, c2])
+    with pytest.raises(art.ArtError):
+        art.Batch([c1] * 65)
