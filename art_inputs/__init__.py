@@ -59,6 +59,13 @@ def workload(name):
         return dict(common, name=name, a=0.94, inc_deg=163.0, model="thermal",
                     mp=thermal_params(seed=1), nstokes=4, nx0=129, ny0=129, levels=3,
                     r_rel=0.01, r_abs=1e-3, abs_norm="max", freq_hz=230e9)
+    if name == "grid_4097":
+        # gridded snapshot, paper's GRMHD tolerances (Sec. 4.1): R_rel = 1e-3, R_abs = 0.025
+        from . import mks
+        geo = mks.mks_snapshot_geometry()
+        return dict(common, name=name, a=0.94, inc_deg=163.0, model="grid",
+                    mp=mks.grid_params(geo), nstokes=4, nx0=257, ny0=257, levels=4,
+                    r_rel=1e-3, r_abs=0.025, abs_norm="mean", freq_hz=230e9, snapshot_seed=2)
     if name == "thermal_1025_mixed":
         return dict(workload("thermal_1025"), name=name, precision="mixed")
     raise KeyError(name)

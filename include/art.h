@@ -48,6 +48,7 @@ extern "C" {
 /* emission models */
 #define ART_EMIS_TOY_DISK     1   /* j = r^-2 exp(-z^2/(2(h r)^2)), r > r_in, no absorption */
 #define ART_EMIS_THERMAL      2   /* power-law thermal plasma, polarised synchrotron */
+#define ART_EMIS_GRID         3   /* gridded snapshot (MKS cells), polarised synchrotron */
 #define ART_EMIS_SCREEN_RING 10   /* closed-form screen intensity (no ray tracing) */
 #define ART_EMIS_SCREEN_POLY 11   /* quadratic screen intensity (no ray tracing) */
 
@@ -94,8 +95,19 @@ typedef struct {
                      Theta_e and |B| (n_e = n0 r^-[6], Theta_e = Theta0 r^-[7],
                      |B| ~ r^-[8]; electron pressure n_e m c^2 Theta_e sets
                      |B| at r_ref from beta)
+        GRID:        [0] n_e per code density [cm^-3], [1] R_high, [2] R_low,
+                     [3] adiabatic index, [4] sigma cut (no emission where
+                     |B|^2/rho exceeds it), [5] outer emission radius [M],
+                     [6] x1 = ln r of the first cell edge, [7] dx1,
+                     [8] h of theta = pi x2 + (1-h)/2 sin(2 pi x2), [9..11]
+                     n1, n2 (<= 256), n3; T_i/T_e = (R_high b^2 + R_low)/(1 + b^2)
+                     with b the plasma beta
         SCREEN_RING: [0] radius, [1] width, [2] diffuse amplitude, [3] diffuse scale
         SCREEN_POLY: I = [0] + [1] x + [2] y + [3] x^2 + [4] x y + [5] y^2  */
+    const float* grid_dev;         /* GRID: device array [n3][n2][n1][8] of cell-centre
+                                      rho, u, v_r, v_th, v_ph (ZAMO frame), B_r, B_th,
+                                      B_ph (ZAMO frame, code units); caller-owned */
+    int64_t grid_len;              /* GRID: number of floats, n1 n2 n3 8 */
 } art_emission;
 
 typedef struct {

@@ -42,6 +42,7 @@
 #define OR_C      2.99792458e10    /* speed of light [cm/s] */
 #define OR_H      6.62607015e-27   /* Planck [erg s] */
 #define OR_PI     3.14159265358979323846
+#define OR_MP     1.67262192369e-24 /* proton mass [g] */
 
 enum { OR_OK = 0, OR_CAPTURED = 1, OR_ESCAPED = 2, OR_STEPCAP = 3, OR_THICK = 4, OR_NAN = 5 };
 enum { OR_MODEL_TOYDISK = 1, OR_MODEL_THERMAL = 2, OR_MODEL_GRID = 3,
@@ -540,7 +541,101 @@ static void screen_fn(const or_params* p, double al, double be, double* S)
 /* ---------------------------------------------------------------- tracing */
 typedef struct { float rmin; int32_t ncross; int32_t steps; int32_t status; } ray_feat;
 
-static int plasma_point(const or_params* p, double r, double th, double kt, double kph,
+/* ------------------------------------------------------ gridded snapshot
+ * MKS cell centres: x1 = ln r at x1_0 + (i + 1/2) dx1, theta_j = theta(x2_j)
+ * with x2_j = (j + 1/2)/n2 and theta(x2) = pi x2 + (1-h)/2 sin(2 pi x2),
+ * phi_k = 2 pi (k + 1/2)/n3.  Fields are interpolated trilinearly in
+ * (x1, theta, phi) between cell centres: clamped in x1 and theta, periodic in
+ * phi.  A theta outside [0, pi] (pole passage) is reflected with phi + pi.   */
+static double mks_theta(double x2, double h)
+{
+    return OR_PI * x2 + 0.5 * (1.0 - h) * sin(2.0 * OR_PI * x2);
+}
+
+static void grid_sample(const or_params* p, double r, double th, double ph, double* out)
+{
+    int n1 = (int)p->mp[9], n2 = (int)p->mp[10], n3 = (int)p->mp[11];
+    double x1_0 = p->mp[6], dx1 = p->mp[7], h = p->mp[8];
+    double tw = fmod(th, 2.0 * OR_PI);
+    if (tw < 0.0) tw += 2.0 * OR_PI;
+    if (tw > OR_PI) { tw = 2.0 * OR_PI - tw; ph += OR_PI; }
+    double pw = ph - 2.0 * OR_PI * floor(ph / (2.0 * OR_PI));
+    /* x1 */
+    double f1 = (log(r) - x1_0) / dx1 - 0.5;
+    int i1 = (int)floor(f1);
+    double t1 = f1 - i1;
+    if (i1 < 0) { i1 = 0; t1 = 0.0; }
+    if (i1 > n1 - 2) { i1 = n1 - 2; t1 = 1.0; }
+    /* theta by bisection over the cell-centre angles */
+    int j;
+    double t2;
+    double th0 = mks_theta(0.5 / n2, h), thn = mks_theta((n2 - 0.5) / n2, h);
+    if (tw <= th0) { j = 0; t2 = 0.0; }
+    else if (tw >= thn) { j = n2 - 2; t2 = 1.0; }
+    else {
+        int lo = 0, hi = n2 - 1;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) / 2;
+            if (mks_theta((mid + 0.5) / n2, h) <= tw) lo = mid; else hi = mid;
+        }
+        j = lo;
+        double ta = mks_theta((j + 0.5) / n2, h), tb = mks_theta((j + 1.5) / n2, h);
+        t2 = (tw - ta) / (tb - ta);
+    }
+    /* phi, periodic */
+    double f3 = pw * n3 / (2.0 * OR_PI) - 0.5;
+    double fl3 = floor(f3);
+    double t3 = f3 - fl3;
+    int k0 = ((int)fl3 % n3 + n3) % n3, k1 = (k0 + 1) % n3;
+    for (int q = 0; q < 8; ++q) out[q] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        int di = c & 1, dj = (c >> 1) & 1, dk = (c >> 2) & 1;
+        double w = (di ? t1 : 1.0 - t1) * (dj ? t2 : 1.0 - t2) * (dk ? t3 : 1.0 - t3);
+        size_t idx = (((size_t)(dk ? k1 : k0) * n2 + (size_t)(j + dj)) * n1 + (size_t)(i1 + di)) * 8;
+        for (int q = 0; q < 8; ++q) out[q] += w * (double)p->grid[idx + q];
+    }
+}
+
+void or_grid_sample(const or_params* p, double r, double th, double ph, double* out8)
+{
+    grid_sample(p, r, th, ph, out8);
+}
+
+/* Electron density, temperature and field strength of the gridded model:
+ * p = (gamma-1) u, plasma beta b = p / (|B|^2/2), T_i/T_e = (R_high b^2 +
+ * R_low)/(1 + b^2), Theta_e = (m_p/m_e) (p/rho) / (1 + T_i/T_e),
+ * n_e = rho n_unit, |B|_G = |B| c sqrt(4 pi n_unit m_p); nothing emits where
+ * |B|^2/rho exceeds the sigma cut.  Returns 0 where nothing emits.        */
+static int grid_plasma(const or_params* p, double r, double th, double ph, double* f,
+                       double* ne, double* Th, double* Bmag)
+{
+    grid_sample(p, r, th, ph, f);
+    double rho = f[0], uu = f[1];
+    if (!(rho > 0.0)) return 0;
+    double gam = p->mp[3];
+    double pg = (gam - 1.0) * uu;
+    double b2 = f[5] * f[5] + f[6] * f[6] + f[7] * f[7];
+    if (b2 / rho > p->mp[4]) return 0;
+    double bet = b2 > 0.0 ? pg / (0.5 * b2) : 1e30;
+    double bet2 = bet * bet;
+    double tratio = (p->mp[1] * bet2 + p->mp[2]) / (1.0 + bet2);
+    *Th = (OR_MP / OR_ME) * pg / rho / (1.0 + tratio);
+    if (!(*Th > 0.0)) return 0;
+    double n_unit = p->mp[0];
+    *ne = rho * n_unit;
+    *Bmag = sqrt(b2) * OR_C * sqrt(4.0 * OR_PI * n_unit * OR_MP);
+    if (!(*Bmag > 0.0)) return 0;
+    return 1;
+}
+
+int or_grid_plasma(const or_params* p, double r, double th, double ph, double* out3)
+{
+    double f[8];
+    int ok = grid_plasma(p, r, th, ph, f, &out3[0], &out3[1], &out3[2]);
+    return ok;
+}
+
+static int plasma_point(const or_params* p, double r, double th, double ph, double kt, double kph,
                         double kr_ks, double kth, const cplx* kap0, double rh,
                         double risco, double Eis, double Lis,
                         double* J, double* aI, double* av, double* rv)
@@ -570,68 +665,86 @@ static int plasma_point(const or_params* p, double r, double th, double kt, doub
         J[0] = j / (ku * ku);
         return 1;
     }
+    double ne, Th, Bmag;          /* n_e [cm^-3], Theta_e, |B| [G] */
+    double v3[3], B3[3];          /* ZAMO-frame velocity and field (r, th, ph) */
     if (p->model == OR_MODEL_THERMAL) {
         if (r >= p->mp[5]) return 0;
-        flow_u(a, r, th, risco, Eis, Lis, u, &Gam, &vr, &vp, &z);
-        double ku = kcov[0] * u[0] + kcov[1] * u[1] + kcov[2] * u[2] + kcov[3] * u[3];
+        double vr_, vp_;
+        flow_v3(a, r, risco, Eis, Lis, &vr_, &vp_);
         double n0 = p->mp[0], Th0 = p->mp[1], beta_ref = p->mp[2], r_ref = p->mp[3];
         double psi = p->mp[4];
         double ine = p->mp[6], ith = p->mp[7], ib = p->mp[8];
-        double ne = n0 * pow(r, -ine);
-        double Th = Th0 * pow(r, -ith);
+        ne = n0 * pow(r, -ine);
+        Th = Th0 * pow(r, -ith);
         double ne_ref = n0 * pow(r_ref, -ine), Th_ref = Th0 * pow(r_ref, -ith);
         double Bref = sqrt(8.0 * OR_PI * ne_ref * OR_ME * OR_C * OR_C * Th_ref / beta_ref);
-        double Bmag = Bref * pow(r / r_ref, -ib);
-        /* field: |B|(cos psi e_ph + sin psi e_r) in the ZAMO frame, projected
-         * orthogonal to u and rescaled to |B|.  Tetrad components:           */
-        double Bt_r = Bmag * sin(psi), Bt_p = Bmag * cos(psi);
-        double Bdotu = Gam * (vr * Bt_r + vp * Bt_p);
-        double resc = Bmag / sqrt(Bmag * Bmag + Bdotu * Bdotu);
-        double Bup[4];
-        Bup[0] = 0.0;
-        Bup[1] = Bt_r * z.er;
-        Bup[2] = 0.0;
-        Bup[3] = Bt_p * z.ep;
-        double b[4];
-        for (int m = 0; m < 4; ++m) b[m] = (Bup[m] + Bdotu * u[m]) * resc;
-        double kb = kcov[0] * b[0] + kcov[1] * b[1] + kcov[2] * b[2] + kcov[3] * b[3];
-        double nu = p->freq * ku;
-        double cth = -kb / (ku * Bmag);
-        if (cth > 1.0) cth = 1.0;
-        if (cth < -1.0) cth = -1.0;
-        coefs c; thermal_coefs(ne, Th, Bmag, nu, cth, &c);
-        /* polarisation angle: project b orthogonal to the photon direction */
-        double n[4];
-        for (int m = 0; m < 4; ++m) n[m] = kup[m] / ku - u[m];
-        /* b.n with n spatial in the fluid frame: use covariant metric */
-        double bl[4];
-        bl[0] = g.tt * b[0] + g.tp * b[3];
-        bl[1] = g.rr * b[1];
-        bl[2] = g.hh * b[2];
-        bl[3] = g.tp * b[0] + g.pp * b[3];
-        double bn = bl[0] * n[0] + bl[1] * n[1] + bl[2] * n[2] + bl[3] * n[3];
-        double bp[4];
-        for (int m = 0; m < 4; ++m) bp[m] = b[m] - bn * n[m];
-        cplx kb_ = walker_penrose(a, r, th, kup, bp);
-        /* z = kappa0 * conj(kappa_B) */
-        double zr = kap0->re * kb_.re + kap0->im * kb_.im;
-        double zi = kap0->im * kb_.re - kap0->re * kb_.im;
-        double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
-        double zn = zr * zr + zi * zi;
-        double c2x = 1.0, s2x = 0.0;
-        if (zn > 0.0) { c2x = z2r / zn; s2x = z2i / zn; }
-        double L = p->L_cm;
-        double fJ = L / (ku * ku), fK = L * ku;
-        J[0] = fJ * c.jI;
-        J[1] = fJ * c.jQ * c2x;
-        J[2] = fJ * c.jQ * s2x;
-        J[3] = fJ * c.jV;
-        *aI = fK * c.aI;
-        av[0] = fK * c.aQ * c2x; av[1] = fK * c.aQ * s2x; av[2] = fK * c.aV;
-        rv[0] = fK * c.rQ * c2x; rv[1] = fK * c.rQ * s2x; rv[2] = fK * c.rV;
-        return 1;
+        Bmag = Bref * pow(r / r_ref, -ib);
+        /* field |B|(cos psi e_ph + sin psi e_r) in the ZAMO frame */
+        v3[0] = vr_; v3[1] = 0.0; v3[2] = vp_;
+        B3[0] = sin(psi); B3[1] = 0.0; B3[2] = cos(psi);
+    } else if (p->model == OR_MODEL_GRID) {
+        if (r >= p->mp[5]) return 0;
+        double f[8];
+        if (!grid_plasma(p, r, th, ph, f, &ne, &Th, &Bmag)) return 0;
+        v3[0] = f[2]; v3[1] = f[3]; v3[2] = f[4];
+        B3[0] = f[5]; B3[1] = f[6]; B3[2] = f[7];
+    } else {
+        return 0;
     }
-    return 0;
+    /* common tail: fluid 4-velocity and unit comoving field direction from
+     * their ZAMO-frame components; polarisation angle; coefficients */
+    zamo_frame(a, r, th, &z);
+    double vv = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2];
+    Gam = 1.0 / sqrt(1.0 - vv);
+    u[0] = Gam / z.al;
+    u[1] = Gam * v3[0] * z.er;
+    u[2] = Gam * v3[1] * z.eh;
+    u[3] = Gam * (z.om / z.al + v3[2] * z.ep);
+    double ku = kcov[0] * u[0] + kcov[1] * u[1] + kcov[2] * u[2] + kcov[3] * u[3];
+    double Bn = sqrt(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]);
+    double Bt[3] = { B3[0] / Bn, B3[1] / Bn, B3[2] / Bn };
+    double Bdotu = Gam * (v3[0] * Bt[0] + v3[1] * Bt[1] + v3[2] * Bt[2]);
+    double resc = 1.0 / sqrt(1.0 + Bdotu * Bdotu);
+    double b[4];
+    b[0] = (Bdotu * u[0]) * resc;
+    b[1] = (Bt[0] * z.er + Bdotu * u[1]) * resc;
+    b[2] = (Bt[1] * z.eh + Bdotu * u[2]) * resc;
+    b[3] = (Bt[2] * z.ep + Bdotu * u[3]) * resc;
+    double kb = kcov[0] * b[0] + kcov[1] * b[1] + kcov[2] * b[2] + kcov[3] * b[3];
+    double nu = p->freq * ku;
+    double cth = -kb / ku;
+    if (cth > 1.0) cth = 1.0;
+    if (cth < -1.0) cth = -1.0;
+    coefs c; thermal_coefs(ne, Th, Bmag, nu, cth, &c);
+    /* polarisation angle: project b orthogonal to the photon direction */
+    double n[4];
+    for (int m = 0; m < 4; ++m) n[m] = kup[m] / ku - u[m];
+    double bl[4];
+    bl[0] = g.tt * b[0] + g.tp * b[3];
+    bl[1] = g.rr * b[1];
+    bl[2] = g.hh * b[2];
+    bl[3] = g.tp * b[0] + g.pp * b[3];
+    double bn = bl[0] * n[0] + bl[1] * n[1] + bl[2] * n[2] + bl[3] * n[3];
+    double bp[4];
+    for (int m = 0; m < 4; ++m) bp[m] = b[m] - bn * n[m];
+    cplx kb_ = walker_penrose(a, r, th, kup, bp);
+    /* z = kappa0 * conj(kappa_B) */
+    double zr = kap0->re * kb_.re + kap0->im * kb_.im;
+    double zi = kap0->im * kb_.re - kap0->re * kb_.im;
+    double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
+    double zn = zr * zr + zi * zi;
+    double c2x = 1.0, s2x = 0.0;
+    if (zn > 0.0) { c2x = z2r / zn; s2x = z2i / zn; }
+    double L = p->L_cm;
+    double fJ = L / (ku * ku), fK = L * ku;
+    J[0] = fJ * c.jI;
+    J[1] = fJ * c.jQ * c2x;
+    J[2] = fJ * c.jQ * s2x;
+    J[3] = fJ * c.jV;
+    *aI = fK * c.aI;
+    av[0] = fK * c.aQ * c2x; av[1] = fK * c.aQ * s2x; av[2] = fK * c.aV;
+    rv[0] = fK * c.rQ * c2x; rv[1] = fK * c.rQ * s2x; rv[2] = fK * c.rV;
+    return 1;
 }
 
 static void trace_one(const or_params* p, double al, double be, double* S, ray_feat* ft,
@@ -682,10 +795,10 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
         geo_rhs(a, kt, kph, yt, k4);
         for (int i = 0; i < 5; ++i) yn[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
         /* transfer over the step at the midpoint */
-        double rm = 0.5 * (y[0] + yn[0]), thm = 0.5 * (y[1] + yn[1]);
+        double rm = 0.5 * (y[0] + yn[0]), thm = 0.5 * (y[1] + yn[1]), phm = 0.5 * (y[2] + yn[2]);
         double krm = 0.5 * (y[3] + yn[3]), kthm = 0.5 * (y[4] + yn[4]);
         double J[4], aI, av[3], rv[3];
-        if (plasma_point(p, rm, thm, kt, kph, krm, kthm, &kap0, rh, risco, Eis, Lis, J, &aI, av, rv)) {
+        if (plasma_point(p, rm, thm, phm, kt, kph, krm, kthm, &kap0, rh, risco, Eis, Lis, J, &aI, av, rv)) {
             if (pol) {
                 transfer_step4(S, O, aI, av, rv, J, h);
             } else {

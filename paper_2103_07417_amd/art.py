@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libart.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "art.h")
 
-EMIS = {"toy_disk": 1, "thermal": 2, "screen_ring": 10, "screen_poly": 11}
+EMIS = {"toy_disk": 1, "thermal": 2, "grid": 3, "screen_ring": 10, "screen_poly": 11}
 NORM = {"mean": 0, "max": 1}
 PREC = {"fp64": 0, "mixed": 1}
 STATUS_NAMES = ("ok", "captured", "escaped", "step_cap", "thick", "nan")
@@ -40,7 +40,8 @@ class Camera(ctypes.Structure):
 class Emission(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("freq_hz", ctypes.c_double), ("mass_msun", ctypes.c_double),
-                ("params", ctypes.c_double * 16)]
+                ("params", ctypes.c_double * 16),
+                ("grid_dev", ctypes.c_void_p), ("grid_len", ctypes.c_int64)]
 
 
 class Refine(ctypes.Structure):
@@ -152,6 +153,10 @@ def blocks(cfg):
     mp = list(cfg.get("mp", []))
     for i in range(16):
         em.params[i] = float(mp[i]) if i < len(mp) else 0.0
+    g = cfg.get("grid_dev")
+    if g is not None:
+        em.grid_dev = g.data_ptr()
+        em.grid_len = g.numel()
     rf = Refine(float(cfg.get("r_rel", -1.0)), float(cfg.get("r_abs", -1.0)),
                 NORM[cfg.get("abs_norm", "mean")], 0)
     tr = Transfer(int(cfg.get("nstokes", 1)), PREC[cfg.get("precision", "fp64")],

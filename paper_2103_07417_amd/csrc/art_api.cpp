@@ -77,6 +77,8 @@ struct art_batch {
     unsigned long long* list = nullptr;
     size_t list_cap = 0;
     Counters* ctr = nullptr;
+    double* dTh = nullptr;         // gridded model: theta table of the batch's snapshot
+    double hTh[kMaxThetaCells] = {};
     hipEvent_t ev[2 * kMaxEv] = {};
     int nev = 0;
     bool timing = false;
@@ -105,9 +107,24 @@ int validate(const art_spacetime* sp, const art_camera* cam, const art_emission*
     if (!(tr->eps > 0.0 && tr->eps <= 0.5)) return fail(ART_EINVAL, "eps must be in (0, 0.5]");
     if (tr->max_steps <= 0) return fail(ART_EINVAL, "max_steps must be > 0");
     const int k = em->kind;
-    if (k != ART_EMIS_TOY_DISK && k != ART_EMIS_THERMAL && k != ART_EMIS_SCREEN_RING &&
-        k != ART_EMIS_SCREEN_POLY)
+    if (k != ART_EMIS_TOY_DISK && k != ART_EMIS_THERMAL && k != ART_EMIS_GRID &&
+        k != ART_EMIS_SCREEN_RING && k != ART_EMIS_SCREEN_POLY)
         return fail(ART_EINVAL, "unknown emission kind %d", k);
+    if (k == ART_EMIS_GRID) {
+        const double* mp = em->params;
+        const long long n1 = (long long)mp[9], n2 = (long long)mp[10], n3 = (long long)mp[11];
+        if (!em->grid_dev) return fail(ART_EINVAL, "gridded model needs grid_dev");
+        if (n1 < 2 || n2 < 2 || n3 < 1 || n2 > kMaxThetaCells || (double)n1 != mp[9] ||
+            (double)n2 != mp[10] || (double)n3 != mp[11])
+            return fail(ART_EINVAL, "grid dimensions must be integers, n1, n2 >= 2, n3 >= 1, n2 <= %d",
+                        kMaxThetaCells);
+        if (em->grid_len != n1 * n2 * n3 * 8)
+            return fail(ART_EINVAL, "grid_len %lld != n1 n2 n3 8 = %lld", (long long)em->grid_len,
+                        n1 * n2 * n3 * 8);
+        if (!(mp[0] > 0.0 && mp[3] > 1.0 && mp[7] > 0.0 && mp[8] >= 0.0 && mp[8] <= 1.0))
+            return fail(ART_EINVAL, "gridded model needs n_unit > 0, gamma > 1, dx1 > 0, 0 <= h <= 1");
+        if (((uintptr_t)em->grid_dev) % 16 != 0) return fail(ART_EINVAL, "grid_dev must be 16-byte aligned");
+    }
     if (k == ART_EMIS_THERMAL && !(em->freq_hz > 0.0 && em->mass_msun > 0.0))
         return fail(ART_EINVAL, "thermal model needs freq_hz > 0 and mass_msun > 0");
     if (k == ART_EMIS_THERMAL && !(em->params[1] > 0.0 && em->params[2] > 0.0 && em->params[3] > 0.0))
@@ -204,6 +221,23 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
         P.psi_c = std::cos(em->params[4]);
         P.psi_s = std::sin(em->params[4]);
     }
+    if (em->kind == ART_EMIS_GRID) {
+        const double mp_g = 1.67262192369e-24;
+        P.grid = em->grid_dev;
+        P.g_n1 = (int32_t)em->params[9];
+        P.g_n2 = (int32_t)em->params[10];
+        P.g_n3 = (int32_t)em->params[11];
+        P.B_unit = C * std::sqrt(4.0 * M_PI * em->params[0] * mp_g);
+    }
+}
+
+// Cell-centre angles theta(x2_j) = pi x2 + (1-h)/2 sin(2 pi x2), x2_j = (j + 1/2)/n2.
+void theta_table(double h, int n2, double* out)
+{
+    for (int j = 0; j < n2; ++j) {
+        const double x2 = (j + 0.5) / n2;
+        out[j] = M_PI * x2 + 0.5 * (1.0 - h) * std::sin(2.0 * M_PI * x2);
+    }
 }
 
 LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes)
@@ -247,7 +281,8 @@ void free_batch_mem(art_batch* b)
     if (b->ctr) (void)hipFree(b->ctr);
     if (b->dP) (void)hipFree(b->dP);
     if (b->dD) (void)hipFree(b->dD);
-    b->list = nullptr; b->ctr = nullptr; b->dP = nullptr; b->dD = nullptr;
+    if (b->dTh) (void)hipFree(b->dTh);
+    b->list = nullptr; b->ctr = nullptr; b->dP = nullptr; b->dD = nullptr; b->dTh = nullptr;
     b->list_cap = 0;
 }
 
@@ -258,6 +293,7 @@ int ensure_mem(art_batch* b, size_t list_need)
         if (hipMalloc(&b->ctr, sizeof(Counters)) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(counters) failed");
         if (hipMalloc(&b->dP, sizeof(Params) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(params) failed");
         if (hipMalloc(&b->dD, sizeof(ImageDesc) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(descs) failed");
+        if (hipMalloc(&b->dTh, sizeof(double) * kMaxThetaCells) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(theta table) failed");
         for (int k = 0; k < 2 * kMaxEv; ++k) HIP_TRY(hipEventCreate(&b->ev[k]));
         HIP_TRY(hipGetDevice(&b->dev));
         HIP_TRY(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev));
@@ -306,6 +342,10 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
             b->precision = J.tr.precision;
         } else if (J.em.kind != b->model || J.tr.nstokes != b->nstokes || J.tr.precision != b->precision) {
             return fail(ART_EINVAL, "image %d: a batch needs one emission kind, nstokes and precision", i);
+        } else if (J.em.kind == ART_EMIS_GRID &&
+                   (J.em.grid_dev != jobs[0].em.grid_dev || J.em.params[8] != jobs[0].em.params[8] ||
+                    J.em.params[10] != jobs[0].em.params[10])) {
+            return fail(ART_EINVAL, "image %d: all images of a batch must share one snapshot", i);
         }
         int32_t nx, ny;
         rc = grid_size(&J.cam, J.tr.nstokes, &nx, &ny);
@@ -337,6 +377,12 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
     int rc = ensure_mem(b, uniform ? 0 : total);
     if (rc) return rc;
     b->L = launch_cfg(b->cus, b->precision, b->model, b->nstokes);
+    if (b->model == ART_EMIS_GRID) {
+        const int n2 = (int)jobs[0].em.params[10];
+        theta_table(jobs[0].em.params[8], n2, b->hTh);
+        HIP_TRY(hipMemcpyAsync(b->dTh, b->hTh, sizeof(double) * n2, hipMemcpyHostToDevice, s));
+        for (int i = 0; i < n; ++i) b->hP[i].theta_tab = b->dTh;
+    }
     HIP_TRY(hipMemcpyAsync(b->dP, b->hP.data(), sizeof(Params) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(b->dD, b->hD.data(), sizeof(ImageDesc) * n, hipMemcpyHostToDevice, s));
     return ART_OK;
@@ -559,6 +605,12 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
     b->hP.resize(1);
     make_params(sp, cam, em, tr, 0, 0, b->hP[0]);
     b->L = launch_cfg(b->cus, tr->precision, em->kind, tr->nstokes);
+    if (em->kind == ART_EMIS_GRID) {
+        const int n2 = (int)em->params[10];
+        theta_table(em->params[8], n2, b->hTh);
+        HIP_TRY(hipMemcpyAsync(b->dTh, b->hTh, sizeof(double) * n2, hipMemcpyHostToDevice, s));
+        b->hP[0].theta_tab = b->dTh;
+    }
     HIP_TRY(hipMemcpyAsync(b->dP, b->hP.data(), sizeof(Params), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
     HIP_TRY(launch_fill_u32(&b->ctr->count[0], 1, (uint32_t)n, s));

@@ -30,7 +30,7 @@ namespace art {
 
 enum : int { RAY_OK = 0, RAY_CAPTURED = 1, RAY_ESCAPED = 2, RAY_STEPCAP = 3,
              RAY_THICK = 4, RAY_NAN = 5 };
-enum : int { MODEL_TOY = 1, MODEL_THERMAL = 2, MODEL_SCREEN_RING = 10, MODEL_SCREEN_POLY = 11 };
+enum : int { MODEL_TOY = 1, MODEL_THERMAL = 2, MODEL_GRID = 3, MODEL_SCREEN_RING = 10, MODEL_SCREEN_POLY = 11 };
 
 // Kernel-side description of one render.  Filled on the host.
 struct Params {
@@ -47,7 +47,13 @@ struct Params {
     double freq, L_cm;
     double mp[16];
     double Bref, r_ref, psi_c, psi_s;   // thermal: |B| at r_ref, field phase
+    const float* grid;             // gridded model: [n3][n2][n1][8] cell-centre fields
+    const double* theta_tab;       // gridded model: theta of the n2 cell centres
+    double B_unit;                 // gridded model: Gauss per code field unit
+    int32_t g_n1, g_n2, g_n3, pad2;
 };
+
+constexpr int kMaxThetaCells = 256;
 
 struct RayFeat { float rmin; int32_t ncross; int32_t steps; int32_t status; };
 
@@ -57,6 +63,7 @@ constexpr double kMe = 9.1093837015e-28;   // electron mass [g]
 constexpr double kC  = 2.99792458e10;      // speed of light [cm/s]
 constexpr double kH  = 6.62607015e-27;     // Planck constant [erg s]
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kMp = 1.67262192369e-24;   // proton mass [g]
 
 // math wrappers resolving to the precision of R
 __device__ __forceinline__ double fexp(double x) { return ::exp(x); }
@@ -243,11 +250,60 @@ __device__ __forceinline__ void thermal_coefs(R ne, R Th, R B, R nu, R cth,
     aI = jI_ * iBnu; aQ = -jQ_ * iBnu; aV = jV_ * iBnu;
 }
 
+// Gridded snapshot: trilinear interpolation in (x1 = ln r, theta, phi) between
+// cell centres, clamped in x1 and theta, periodic in phi; theta outside
+// [0, pi] is reflected with phi + pi.  The cell-centre angles come from the
+// LDS table `tht` (bisection).  Fields are FP32 [n3][n2][n1][8].
+template <typename R>
+__device__ __forceinline__ void grid_sample(const Params& P, const double* tht, double r, double th,
+                                            double ph, R f[8])
+{
+    const int n1 = P.g_n1, n2 = P.g_n2, n3 = P.g_n3;
+    double tw = ::fmod(th, 2.0 * kPi);
+    if (tw < 0.0) tw += 2.0 * kPi;
+    if (tw > kPi) { tw = 2.0 * kPi - tw; ph += kPi; }
+    const double pw = ph - 2.0 * kPi * ::floor(ph * (1.0 / (2.0 * kPi)));
+    const double f1 = (::log(r) - P.mp[6]) / P.mp[7] - 0.5;
+    int i1 = (int)::floor(f1);
+    double t1 = f1 - (double)i1;
+    if (i1 < 0) { i1 = 0; t1 = 0.0; }
+    if (i1 > n1 - 2) { i1 = n1 - 2; t1 = 1.0; }
+    int j;
+    double t2;
+    if (tw <= tht[0]) { j = 0; t2 = 0.0; }
+    else if (tw >= tht[n2 - 1]) { j = n2 - 2; t2 = 1.0; }
+    else {
+        int lo = 0, hi = n2 - 1;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tht[mid] <= tw) lo = mid; else hi = mid;
+        }
+        j = lo;
+        t2 = (tw - tht[j]) / (tht[j + 1] - tht[j]);
+    }
+    const double f3 = pw * (double)n3 / (2.0 * kPi) - 0.5;
+    const double fl3 = ::floor(f3);
+    const double t3 = f3 - fl3;
+    const int k0 = (((int)fl3 % n3) + n3) % n3, k1 = (k0 + 1) % n3;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = R(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int di = c & 1, dj = (c >> 1) & 1, dk = (c >> 2) & 1;
+        const R w = R((di ? t1 : 1.0 - t1) * (dj ? t2 : 1.0 - t2) * (dk ? t3 : 1.0 - t3));
+        const size_t idx = (((size_t)(dk ? k1 : k0) * n2 + (size_t)(j + dj)) * n1 + (size_t)(i1 + di)) * 8;
+        const float4 lo = *reinterpret_cast<const float4*>(P.grid + idx);
+        const float4 hi = *reinterpret_cast<const float4*>(P.grid + idx + 4);
+        f[0] += w * R(lo.x); f[1] += w * R(lo.y); f[2] += w * R(lo.z); f[3] += w * R(lo.w);
+        f[4] += w * R(hi.x); f[5] += w * R(hi.y); f[6] += w * R(hi.z); f[7] += w * R(hi.w);
+    }
+}
+
 // Plasma and coefficients at a midpoint.  Returns false where nothing emits.
 template <typename R, int MODEL>
-__device__ __forceinline__ bool plasma_point(const Params& P, double r, double th,
-                                             double kt, double kph, double kr_ks, double kth,
-                                             double k0r, double k0i, Coef<R>& C)
+__device__ __forceinline__ bool plasma_point(const Params& P, const double* tht, double r, double th,
+                                             double ph, double kt, double kph, double kr_ks,
+                                             double kth, double k0r, double k0i, Coef<R>& C)
 {
     const double a = P.a;
     if (r <= P.rh * 1.0001) return false;
@@ -268,13 +324,14 @@ __device__ __forceinline__ bool plasma_point(const Params& P, double r, double t
     const double zal = ::sqrt(Sig * Del / A);
     const double zom = 2.0 * a * r / A;
     const double zer = ::sqrt(Del / Sig);
+    const double zeh = 1.0 / ::sqrt(Sig);
     const double zep = 1.0 / (::sqrt(A / Sig) * s);
-    double vr, vp;
-    flow_v3(P, r, vr, vp);
-    const double Gam = 1.0 / ::sqrt(1.0 - vr * vr - vp * vp);
-    const double u0 = Gam / zal, u1 = Gam * vr * zer, u3 = Gam * (zom / zal + vp * zep);
-    const double ku = kt * u0 + kr_bl * u1 + kph * u3;
     if constexpr (MODEL == MODEL_TOY) {
+        double vr, vp;
+        flow_v3(P, r, vr, vp);
+        const double Gam = 1.0 / ::sqrt(1.0 - vr * vr - vp * vp);
+        const double u0 = Gam / zal, u1 = Gam * vr * zer, u3 = Gam * (zom / zal + vp * zep);
+        const double ku = kt * u0 + kr_bl * u1 + kph * u3;
         const double hr = P.mp[1];
         const double j = ::exp(-c * c / (2.0 * hr * hr)) / (r * r);
         C.jI = R(j / (ku * ku));
@@ -283,52 +340,86 @@ __device__ __forceinline__ bool plasma_point(const Params& P, double r, double t
         C.rQ = C.rU = C.rV = R(0);
         return true;
     } else {
-    // thermal power-law plasma: scalars in R
-    const R lr = flog(R(r));
-    const R ne = R(P.mp[0]) * fexp(-R(P.mp[6]) * lr);
-    const R Th = R(P.mp[1]) * fexp(-R(P.mp[7]) * lr);
-    const R Bm = R(P.Bref) * fexp(-R(P.mp[8]) * (lr - flog(R(P.r_ref))));
-    // unit field direction: (cos psi e_ph + sin psi e_r) projected orthogonal to u
-    const double Bt_r = P.psi_s, Bt_p = P.psi_c;
-    const double Bdu = Gam * (vr * Bt_r + vp * Bt_p);
-    const double resc = 1.0 / ::sqrt(1.0 + Bdu * Bdu);
-    const double b0 = Bdu * u0 * resc;
-    const double b1 = (Bt_r * zer + Bdu * u1) * resc;
-    const double b3 = (Bt_p * zep + Bdu * u3) * resc;
-    const double kb = kt * b0 + kr_bl * b1 + kph * b3;
-    double cth = -kb / ku;
-    cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
-    // contravariant k (BL)
-    const double gitt = -A / (Sig * Del), gitp = -2.0 * a * r / (Sig * Del);
-    const double girr = Del / Sig, gihh = 1.0 / Sig, gipp = (Del - a * a * s2) / (Sig * Del * s2);
-    const double iku = 1.0 / ku;
-    const double kup[4] = { gitt * kt + gitp * kph, girr * kr_bl, gihh * kth, gitp * kt + gipp * kph };
-    // photon direction n = k/ku - u; b_perp = b - (b.n) n
-    const double n0 = kup[0] * iku - u0, n1 = kup[1] * iku - u1, n2 = kup[2] * iku, n3 = kup[3] * iku - u3;
-    const double gtt = -(1.0 - 2.0 * r / Sig), gtp = -2.0 * a * r * s2 / Sig;
-    const double grr = Sig / Del, ghh = Sig, gpp = (r * r + a * a + 2.0 * a * a * r * s2 / Sig) * s2;
-    const double bl0 = gtt * b0 + gtp * b3, bl1 = grr * b1, bl3 = gtp * b0 + gpp * b3;
-    const double bn = bl0 * n0 + bl1 * n1 + bl3 * n3;
-    const double bp[4] = { b0 - bn * n0, b1 - bn * n1, -bn * n2, b3 - bn * n3 };
-    double kbr, kbi;
-    walker_penrose(a, r, s, c, kup, bp, kbr, kbi);
-    const double zr = k0r * kbr + k0i * kbi;
-    const double zi = k0i * kbr - k0r * kbi;
-    const double zn = zr * zr + zi * zi;
-    double c2x = 1.0, s2x = 0.0;
-    if (zn > 0.0) {
-        const double izn = 1.0 / zn;
-        c2x = (zr * zr - zi * zi) * izn;
-        s2x = 2.0 * zr * zi * izn;
-    }
-    R jI, jQ, jV, aI, aQ, aV, rQ, rV;
-    thermal_coefs<R>(ne, Th, Bm, R(P.freq * ku), R(cth), jI, jQ, jV, aI, aQ, aV, rQ, rV);
-    const R fJ = R(P.L_cm * iku * iku), fK = R(P.L_cm * ku);
-    const R c2 = R(c2x), s2_ = R(s2x);
-    C.jI = fJ * jI; C.jQ = fJ * jQ * c2; C.jU = fJ * jQ * s2_; C.jV = fJ * jV;
-    C.aI = fK * aI; C.aQ = fK * aQ * c2; C.aU = fK * aQ * s2_; C.aV = fK * aV;
-    C.rQ = fK * rQ * c2; C.rU = fK * rQ * s2_; C.rV = fK * rV;
-    return true;
+        R ne, Th, Bm;
+        double v3[3], B3[3];
+        if constexpr (MODEL == MODEL_THERMAL) {
+            // power-law plasma: scalars in R
+            const R lr = flog(R(r));
+            ne = R(P.mp[0]) * fexp(-R(P.mp[6]) * lr);
+            Th = R(P.mp[1]) * fexp(-R(P.mp[7]) * lr);
+            Bm = R(P.Bref) * fexp(-R(P.mp[8]) * (lr - flog(R(P.r_ref))));
+            double vr, vp;
+            flow_v3(P, r, vr, vp);
+            v3[0] = vr; v3[1] = 0.0; v3[2] = vp;
+            B3[0] = P.psi_s; B3[1] = 0.0; B3[2] = P.psi_c;
+        } else {
+            R f[8];
+            grid_sample<R>(P, tht, r, th, ph, f);
+            const R rho = f[0];
+            if (!(rho > R(0))) return false;
+            const R pg = (R(P.mp[3]) - R(1)) * f[1];
+            const R b2 = f[5] * f[5] + f[6] * f[6] + f[7] * f[7];
+            if (b2 / rho > R(P.mp[4])) return false;           // sigma cut
+            const R bet = b2 > R(0) ? pg / (R(0.5) * b2) : R(1e30);
+            const R bet2 = bet * bet;
+            const R tratio = (R(P.mp[1]) * bet2 + R(P.mp[2])) / (R(1) + bet2);
+            Th = R(kMp / kMe) * pg / rho / (R(1) + tratio);
+            if (!(Th > R(0))) return false;
+            ne = rho * R(P.mp[0]);
+            Bm = fsqrt(b2) * R(P.B_unit);
+            if (!(Bm > R(0))) return false;
+            v3[0] = (double)f[2]; v3[1] = (double)f[3]; v3[2] = (double)f[4];
+            B3[0] = (double)f[5]; B3[1] = (double)f[6]; B3[2] = (double)f[7];
+        }
+        // fluid 4-velocity and unit comoving field direction from ZAMO components
+        const double vv = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2];
+        const double Gam = 1.0 / ::sqrt(1.0 - vv);
+        const double u0 = Gam / zal, u1 = Gam * v3[0] * zer, u2 = Gam * v3[1] * zeh;
+        const double u3 = Gam * (zom / zal + v3[2] * zep);
+        const double ku = kt * u0 + kr_bl * u1 + kth * u2 + kph * u3;
+        const double iBn = 1.0 / ::sqrt(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]);
+        const double Bt0 = B3[0] * iBn, Bt1 = B3[1] * iBn, Bt2 = B3[2] * iBn;
+        const double Bdu = Gam * (v3[0] * Bt0 + v3[1] * Bt1 + v3[2] * Bt2);
+        const double resc = 1.0 / ::sqrt(1.0 + Bdu * Bdu);
+        const double b0 = Bdu * u0 * resc;
+        const double b1 = (Bt0 * zer + Bdu * u1) * resc;
+        const double b2_ = (Bt1 * zeh + Bdu * u2) * resc;
+        const double b3 = (Bt2 * zep + Bdu * u3) * resc;
+        const double kb = kt * b0 + kr_bl * b1 + kth * b2_ + kph * b3;
+        double cth = -kb / ku;
+        cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
+        // contravariant k (BL)
+        const double gitt = -A / (Sig * Del), gitp = -2.0 * a * r / (Sig * Del);
+        const double girr = Del / Sig, gihh = 1.0 / Sig, gipp = (Del - a * a * s2) / (Sig * Del * s2);
+        const double iku = 1.0 / ku;
+        const double kup[4] = { gitt * kt + gitp * kph, girr * kr_bl, gihh * kth, gitp * kt + gipp * kph };
+        // photon direction n = k/ku - u; b_perp = b - (b.n) n
+        const double n0 = kup[0] * iku - u0, n1 = kup[1] * iku - u1, n2 = kup[2] * iku - u2;
+        const double n3 = kup[3] * iku - u3;
+        const double gtt = -(1.0 - 2.0 * r / Sig), gtp = -2.0 * a * r * s2 / Sig;
+        const double grr = Sig / Del, ghh = Sig, gpp = (r * r + a * a + 2.0 * a * a * r * s2 / Sig) * s2;
+        const double bl0 = gtt * b0 + gtp * b3, bl1 = grr * b1, bl2 = ghh * b2_, bl3 = gtp * b0 + gpp * b3;
+        const double bn = bl0 * n0 + bl1 * n1 + bl2 * n2 + bl3 * n3;
+        const double bp[4] = { b0 - bn * n0, b1 - bn * n1, b2_ - bn * n2, b3 - bn * n3 };
+        double kbr, kbi;
+        walker_penrose(a, r, s, c, kup, bp, kbr, kbi);
+        const double zr = k0r * kbr + k0i * kbi;
+        const double zi = k0i * kbr - k0r * kbi;
+        const double zn = zr * zr + zi * zi;
+        double c2x = 1.0, s2x = 0.0;
+        if (zn > 0.0) {
+            const double izn = 1.0 / zn;
+            c2x = (zr * zr - zi * zi) * izn;
+            s2x = 2.0 * zr * zi * izn;
+        }
+        R jI, jQ, jV, aI, aQ, aV, rQ, rV;
+        thermal_coefs<R>(ne, Th, Bm, R(P.freq * ku), R(cth), jI, jQ, jV, aI, aQ, aV, rQ, rV);
+        const R fJ = R(P.L_cm * iku * iku), fK = R(P.L_cm * ku);
+        const R c2 = R(c2x), s2r = R(s2x);
+        C.jI = fJ * jI; C.jQ = fJ * jQ * c2; C.jU = fJ * jQ * s2r; C.jV = fJ * jV;
+        C.aI = fK * aI; C.aQ = fK * aQ * c2; C.aU = fK * aQ * s2r; C.aV = fK * aV;
+        C.rQ = fK * rQ * c2; C.rU = fK * rQ * s2r; C.rV = fK * rV;
+        return true;
     }
 }
 

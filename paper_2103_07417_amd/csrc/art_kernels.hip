@@ -124,7 +124,8 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>
 
 // Advance one ray by one step.  Returns a RAY_* status (RAY_OK = continue).
 template <typename R, int MODEL, int NS>
-__device__ __forceinline__ int ray_step(const Params& P, RayState<R, MODEL, NS>& st, unsigned& emit)
+__device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayState<R, MODEL, NS>& st,
+                                        unsigned& emit)
 {
     const double a = P.a;
     double k1[5], acc[5], yt[5], kk[5];
@@ -160,9 +161,10 @@ __device__ __forceinline__ int ray_step(const Params& P, RayState<R, MODEL, NS>&
     for (int i = 0; i < 5; ++i) yt[i] = st.y[i] + h6 * (acc[i] + kk[i]);
     // transfer at the step midpoint
     const double rm = 0.5 * (st.y[0] + yt[0]), thm = 0.5 * (st.y[1] + yt[1]);
+    const double phm = 0.5 * (st.y[2] + yt[2]);
     const double krm = 0.5 * (st.y[3] + yt[3]), kthm = 0.5 * (st.y[4] + yt[4]);
     Coef<R> C;
-    if (plasma_point<R, MODEL>(P, rm, thm, st.kt, st.kph, krm, kthm, st.k0r, st.k0i, C)) {
+    if (plasma_point<R, MODEL>(P, tht, rm, thm, phm, st.kt, st.kph, krm, kthm, st.k0r, st.k0i, C)) {
         ++emit;
         if constexpr (NS == 4) {
             transfer_step4<R, R>(st.S, st.O, C, R(h));
@@ -192,8 +194,15 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
         const double* src = reinterpret_cast<const double*>(J.params);
         double* dst = reinterpret_cast<double*>(sP);
         for (int k = threadIdx.x; k < nw; k += blockDim.x) dst[k] = src[k];
-        __syncthreads();
     }
+    // gridded model: cell-centre angles of the snapshot shared by the batch
+    __shared__ double sTh[MODEL == MODEL_GRID ? kMaxThetaCells : 1];
+    if constexpr (MODEL == MODEL_GRID) {
+        const double* tab = J.params[0].theta_tab;
+        const int n2 = J.params[0].g_n2;
+        for (int k = threadIdx.x; k < n2; k += blockDim.x) sTh[k] = tab[k];
+    }
+    __syncthreads();
     const int lane = __lane_id();
     RayState<R, MODEL, NS> st;
     bool active = false, drained = false;
@@ -269,7 +278,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
         }
         if (active) {
             const Params& P = sP[st.img];
-            const int status = ray_step<R, MODEL, NS>(P, st, my_emit);
+            const int status = ray_step<R, MODEL, NS>(P, sTh, st, my_emit);
             if (status != RAY_OK) {
                 double Sd[4] = { 0.0, 0.0, 0.0, 0.0 };
 #pragma unroll
@@ -308,43 +317,37 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
     }
 }
 
-template <typename R, int MODEL, int NS>
-static hipError_t launch_trace_t(const TraceJob& J, const LaunchCfg& L, hipStream_t s)
+// Kernel instantiation for (precision, model, nstokes): the screen test
+// functions run through the toy-disk instantiation (they never integrate).
+template <typename F>
+static hipError_t dispatch(int precision, int model, int nstokes, F&& f)
 {
-    hipLaunchKernelGGL((k_trace<R, MODEL, NS>), dim3(L.trace_blocks), dim3(L.trace_threads), 0, s, J);
-    return hipGetLastError();
+    const bool pol = nstokes == 4;
+    if (precision == 0) {
+        if (model == MODEL_THERMAL) return pol ? f((k_trace<double, MODEL_THERMAL, 4>)) : f((k_trace<double, MODEL_THERMAL, 1>));
+        if (model == MODEL_GRID) return pol ? f((k_trace<double, MODEL_GRID, 4>)) : f((k_trace<double, MODEL_GRID, 1>));
+        return f((k_trace<double, MODEL_TOY, 1>));
+    }
+    if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4>)) : f((k_trace<float, MODEL_THERMAL, 1>));
+    if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4>)) : f((k_trace<float, MODEL_GRID, 1>));
+    return f((k_trace<float, MODEL_TOY, 1>));
 }
 
 hipError_t launch_trace(int precision, int model, int nstokes, const TraceJob& J, const LaunchCfg& L,
                         hipStream_t s)
 {
-    const bool thermal = (model == MODEL_THERMAL);
-    const bool pol = (nstokes == 4) && thermal;
-    if (precision == 0) {
-        if (thermal) return pol ? launch_trace_t<double, MODEL_THERMAL, 4>(J, L, s)
-                                : launch_trace_t<double, MODEL_THERMAL, 1>(J, L, s);
-        return launch_trace_t<double, MODEL_TOY, 1>(J, L, s);
-    }
-    if (thermal) return pol ? launch_trace_t<float, MODEL_THERMAL, 4>(J, L, s)
-                            : launch_trace_t<float, MODEL_THERMAL, 1>(J, L, s);
-    return launch_trace_t<float, MODEL_TOY, 1>(J, L, s);
+    return dispatch(precision, model, nstokes, [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(L.trace_blocks), dim3(L.trace_threads), 0, s, J);
+        return hipGetLastError();
+    });
 }
 
 int trace_occupancy_blocks(int precision, int model, int nstokes, int threads)
 {
     int nb = 0;
-    const bool thermal = (model == MODEL_THERMAL);
-    const bool pol = (nstokes == 4) && thermal;
-    hipError_t e;
-    if (precision == 0) {
-        if (thermal && pol) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<double, MODEL_THERMAL, 4>, threads, 0);
-        else if (thermal) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<double, MODEL_THERMAL, 1>, threads, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<double, MODEL_TOY, 1>, threads, 0);
-    } else {
-        if (thermal && pol) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<float, MODEL_THERMAL, 4>, threads, 0);
-        else if (thermal) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<float, MODEL_THERMAL, 1>, threads, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<float, MODEL_TOY, 1>, threads, 0);
-    }
+    hipError_t e = dispatch(precision, model, nstokes, [&](auto kern) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, 0);
+    });
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }

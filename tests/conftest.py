@@ -17,3 +17,7 @@ def pytest_configure(config):
 def oracle_lib():
     from oracle import ray
     return ray.lib()
+
+TESTS = os.path.dirname(os.path.abspath(__file__))
+if TESTS not in sys.path:
+    sys.path.insert(0, TESTS)

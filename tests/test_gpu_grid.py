@@ -1,0 +1,65 @@
+"""GPU parity of the gridded-snapshot model (MKS 288 x 128 x 128 FP32 fields)."""
+import numpy as np
+import pytest
+
+import art_inputs
+from art_inputs import mks
+from gpu_helpers import check_adaptive, rel_l2
+from oracle import ray as oray
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def art():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_07417_amd import art as a
+    a.lib()
+    return a
+
+
+@pytest.fixture(scope="module")
+def snap():
+    grid, geo = mks.mks_snapshot(seed=2)
+    return grid, torch.from_numpy(grid).cuda()
+
+
+def cfg_grid(snap, **kw):
+    c = dict(art_inputs.workload("grid_4097"), grid_dev=snap[1])
+    c.update(kw)
+    return c
+
+
+@pytest.mark.parametrize("nst", [4, 1])
+def test_grid_points_fp64(art, snap, nst):
+    print("CASE grid points", nst, flush=True)
+    cfg = cfg_grid(snap, nstokes=nst)
+    rng = np.random.default_rng(8)
+    al = rng.uniform(-20, 20, 640)
+    be = rng.uniform(-20, 20, 640)
+    S, ft = art.trace_points(cfg, torch.tensor(al, device="cuda"), torch.tensor(be, device="cuda"))
+    g = S.cpu().numpy()
+    c, cf = oray.trace(cfg, al, be, grid=snap[0])
+    for s in range(nst):
+        assert rel_l2(g[:, s], c[:, s]) <= 1e-6, (s, rel_l2(g[:, s], c[:, s]))
+    gf = art.feat_numpy(ft)
+    assert np.mean(gf["status"] == cf["status"]) > 0.99
+
+
+def test_grid_adaptive_fp64(art, snap):
+    print("CASE grid adaptive", flush=True)
+    cfg = cfg_grid(snap, nx0=17, ny0=17, levels=2)
+    g, gl, st, o = check_adaptive(art, cfg, 1e-6, grid=snap[0])
+    assert st["status"]["nan"] == 0 and 0.3 < st["interp_frac"] < 0.99
+
+
+def test_grid_mixed_precision(art, snap):
+    print("CASE grid mixed", flush=True)
+    cfg = cfg_grid(snap, nx0=33, ny0=33, levels=1)
+    g64, _, _ = art.render_uniform(cfg)
+    g32, _, _ = art.render_uniform(dict(cfg, precision="mixed"))
+    for s in range(4):
+        fe, mse = art.metrics(g64[s], g32[s])
+        assert mse <= 1e-3, (s, mse)
