@@ -83,27 +83,60 @@ __device__ __forceinline__ float  fsin(float x)  { return ::sinf(x); }
 __device__ __forceinline__ double fabs_(double x) { return ::fabs(x); }
 __device__ __forceinline__ float  fabs_(float x)  { return ::fabsf(x); }
 
+// Reciprocals: hardware estimate refined by Newton steps (two in FP64, one in
+// FP32) -- within an ulp or two of the correctly rounded quotient, at a third
+// of the cost of an IEEE division sequence.
+__device__ __forceinline__ double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = ::fma(::fma(-x, r, 1.0), r, r);
+    r = ::fma(::fma(-x, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ float frcp(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    return ::fmaf(::fmaf(-x, r, 1.0f), r, r);
+}
+
+// sin and cos of theta + d from sin, cos of theta for a small increment d
+// (|d| <= 0.25: Taylor series to d^13, then the angle-addition formulas).
+__device__ __forceinline__ void rotate_sc(double s0, double c0, double d, double& s, double& c)
+{
+    if (::fabs(d) > 0.25) {
+        double sd, cd;
+        ::sincos(d, &sd, &cd);
+        s = s0 * cd + c0 * sd;
+        c = c0 * cd - s0 * sd;
+        return;
+    }
+    const double d2 = d * d;
+    const double sd = d * (1.0 - d2 * (1.0 / 6.0) * (1.0 - d2 * (1.0 / 20.0) * (1.0 - d2 * (1.0 / 42.0) * (1.0 - d2 * (1.0 / 72.0) * (1.0 - d2 * (1.0 / 110.0) * (1.0 - d2 * (1.0 / 156.0)))))));
+    const double cm = d2 * (1.0 / 2.0) * (1.0 - d2 * (1.0 / 12.0) * (1.0 - d2 * (1.0 / 30.0) * (1.0 - d2 * (1.0 / 56.0) * (1.0 - d2 * (1.0 / 90.0) * (1.0 - d2 * (1.0 / 132.0))))));
+    // cos d = 1 - cm; keep the small correction separate for accuracy
+    s = s0 + (c0 * sd - s0 * cm);
+    c = c0 - (s0 * sd + c0 * cm);
+}
+
 // ------------------------------------------------------ geodesic right-hand side
 // Inverse Kerr-Schild metric: g^tt = -(1+2r/S), g^tr = 2r/S, g^rr = D/S,
 // g^rph = a/S, g^thth = 1/S, g^phph = 1/(S sin^2).  2H = -kt^2 + Qf/S with
 // Qf = -2r kt^2 + 4r kt kr + D kr^2 + 2a kr kph + kth^2 + kph^2/sin^2.
-// Returns cos(theta) of the evaluation point (used for crossing counts).
-__device__ __forceinline__ double geo_rhs(double a, double kt, double kph,
-                                          const double y[5], double dy[5])
+// (s, c) = (sin, cos) of the evaluation point's theta, supplied by the caller.
+__device__ __forceinline__ void geo_rhs(double a, double kt, double kph, const double y[5],
+                                        double s, double c, double dy[5])
 {
     const double r = y[0], kr = y[3], kth = y[4];
-    double s, c;
-    ::sincos(y[1], &s, &c);
     const double s2 = s * s;
     const double Sig = r * r + a * a * c * c;
     const double Del = r * r - 2.0 * r + a * a;
-    const double iS = 1.0 / Sig;
+    const double iS = frcp(Sig);
     double Lph = 0.0, Lpo = 0.0, dQth = 0.0;
     if (kph != 0.0) {
-        const double is2 = 1.0 / s2;
+        const double is2 = frcp(s2);
         Lpo = kph * is2;
         Lph = kph * Lpo;
-        dQth = -2.0 * Lph * c / s;
+        dQth = -2.0 * Lph * c * (s * is2);
     }
     const double kt2 = kt * kt;
     const double Qf = -2.0 * r * kt2 + 4.0 * r * kt * kr + Del * kr * kr
@@ -116,7 +149,6 @@ __device__ __forceinline__ double geo_rhs(double a, double kt, double kph,
     dy[2] = (a * kr + Lpo) * iS;
     dy[3] = -0.5 * (dQr * iS - 2.0 * r * QiS2);
     dy[4] = -0.5 * (dQth * iS - dSth * QiS2);
-    return c;
 }
 
 // ------------------------------------------------------------ Walker-Penrose
@@ -185,17 +217,22 @@ __device__ __forceinline__ void flow_v3(const Params& P, double r, double& vr, d
     const double a = P.a;
     const double Del = r * r - 2.0 * r + a * a;
     const double A = (r * r + a * a) * (r * r + a * a) - a * a * Del;
-    const double al = ::sqrt(r * r * Del / A);
-    const double om = 2.0 * a * r / A;
-    const double vpi = ::sqrt(A) / r;
+    const double iA = frcp(A);
+    const double al = ::sqrt(r * r * Del * iA);
+    const double ial = frcp(al);
+    const double om = 2.0 * a * r * iA;
+    const double sA = ::sqrt(A);
+    const double ir = frcp(r);
+    const double vpi = sA * ir;
     if (r >= P.risco) {
-        const double Om = 1.0 / (r * ::sqrt(r) + a);
-        vp = vpi * (Om - om) / al;
+        const double Om = frcp(r * ::sqrt(r) + a);
+        vp = vpi * (Om - om) * ial;
         vr = 0.0;
     } else {
-        const double Gam = (P.Eis - om * P.Lis) / al;
-        vp = (P.Lis / vpi) / Gam;
-        const double q = 1.0 - 1.0 / (Gam * Gam) - vp * vp;
+        const double Gam = (P.Eis - om * P.Lis) * ial;
+        vp = (P.Lis * r * frcp(sA)) * frcp(Gam);
+        const double iG = frcp(Gam);
+        const double q = 1.0 - iG * iG - vp * vp;
         vr = -::sqrt(q > 0.0 ? q : 0.0);
     }
 }
@@ -217,35 +254,39 @@ __device__ __forceinline__ void thermal_coefs(R ne, R Th, R B, R nu, R cth,
     const R sth2 = cth * cth < R(1) ? R(1) - cth * cth : R(0);
     const R sth = fsqrt(sth2);
     const R nuB = R(kE / (2.0 * kPi * kMe * kC)) * B;
+    const R iTh = frcp(Th);
+    const R inu = frcp(nu);
     const R lg = flog1p(R(2) * Th);
-    const R gV = lg / (R(2) * Th * Th + lg);
-    const R gQ = R(1) / (R(1) + R(2) * Th) + R(6) * Th;
+    const R gV = lg * frcp(R(2) * Th * Th + lg);
+    const R gQ = frcp(R(1) + R(2) * Th) + R(6) * Th;
     const R imc = R(1.0 / (kMe * kC));
-    rV = R(2) * ne * e2 * nuB * cth * imc / (nu * nu) * gV;
-    rQ = -ne * e2 * nuB * nuB * sth2 * imc / (nu * nu * nu) * gQ;
+    const R nee = ne * e2;
+    rV = R(2) * nee * nuB * cth * imc * (inu * inu) * gV;
+    rQ = -nee * nuB * nuB * sth2 * imc * (inu * inu * inu) * gQ;
     jI = jQ = jV = aI = aQ = aV = R(0);
     if (sth < R(1e-10)) return;
-    const R x = R(2) * nu / (R(3) * nuB * Th * Th * sth);
+    const R x = R(2) * nu * frcp(R(3) * nuB * Th * Th * sth);
     const R x13 = fcbrt(x);
-    const R xm13 = R(1) / x13, xm23 = xm13 * xm13;
+    const R xm13 = frcp(x13), xm23 = xm13 * xm13;
     const R ex = fexp(R(-1.8899) * x13);
     const R II = R(2.5651) * (R(1) + R(1.92) * xm13 + R(0.9977) * xm23) * ex;
     const R IQ = R(2.5651) * (R(1) + R(0.932) * xm13 + R(0.4998) * xm23) * ex;
-    const R IV = (R(1.8138) / x + R(3.423) * xm23 + R(0.02955) / fsqrt(x) + R(2.0377) * xm13) * ex;
-    const R pref = ne * e2 * nu / (R(2.0 * 1.7320508075688772 * kC) * Th * Th);
+    const R IV = (R(1.8138) * (xm13 * xm23) + R(3.423) * xm23 + R(0.02955) * frcp(fsqrt(x))
+                  + R(2.0377) * xm13) * ex;
+    const R pref = nee * nu * (iTh * iTh) * R(1.0 / (2.0 * 1.7320508075688772 * kC));
     R jI_ = pref * II;
     R jQ_ = pref * IQ;
-    R jV_ = pref * (R(4) * cth / (R(3) * Th * sth)) * IV;
+    R jV_ = pref * (R(4) * cth * frcp(R(3) * Th * sth)) * IV;
     const R P = fsqrt(jQ_ * jQ_ + jV_ * jV_);
     if (P > R(0.99) * jI_) {
-        const R sc = R(0.99) * jI_ / P;
+        const R sc = R(0.99) * jI_ * frcp(P);
         jQ_ *= sc; jV_ *= sc;
     }
     // 1/B_nu = expm1(q) c^2 / (2 h nu^3) with q = h nu / (Theta m c^2), written as
     // (expm1(q)/q) / (2 Theta m nu^2) so that no factor leaves the FP32 range
-    const R q = R(kH / (kMe * kC * kC)) * nu / Th;
-    const R phq = q < R(1e-6) ? R(1) + R(0.5) * q : fexpm1(q) / q;
-    const R iBnu = phq / (R(2) * Th * (R(kMe) * nu) * nu);
+    const R q = R(kH / (kMe * kC * kC)) * nu * iTh;
+    const R phq = q < R(1e-6) ? R(1) + R(0.5) * q : fexpm1(q) * frcp(q);
+    const R iBnu = phq * frcp(R(2) * Th * (R(kMe) * nu) * nu);
     jI = jI_; jQ = -jQ_; jV = jV_;
     aI = jI_ * iBnu; aQ = -jQ_ * iBnu; aV = jV_ * iBnu;
 }
@@ -263,7 +304,7 @@ __device__ __forceinline__ void grid_sample(const Params& P, const double* tht, 
     if (tw < 0.0) tw += 2.0 * kPi;
     if (tw > kPi) { tw = 2.0 * kPi - tw; ph += kPi; }
     const double pw = ph - 2.0 * kPi * ::floor(ph * (1.0 / (2.0 * kPi)));
-    const double f1 = (::log(r) - P.mp[6]) / P.mp[7] - 0.5;
+    const double f1 = (::log(r) - P.mp[6]) * frcp(P.mp[7]) - 0.5;
     int i1 = (int)::floor(f1);
     double t1 = f1 - (double)i1;
     if (i1 < 0) { i1 = 0; t1 = 0.0; }
@@ -279,9 +320,9 @@ __device__ __forceinline__ void grid_sample(const Params& P, const double* tht, 
             if (tht[mid] <= tw) lo = mid; else hi = mid;
         }
         j = lo;
-        t2 = (tw - tht[j]) / (tht[j + 1] - tht[j]);
+        t2 = (tw - tht[j]) * frcp(tht[j + 1] - tht[j]);
     }
-    const double f3 = pw * (double)n3 / (2.0 * kPi) - 0.5;
+    const double f3 = pw * (double)n3 * (1.0 / (2.0 * kPi)) - 0.5;
     const double fl3 = ::floor(f3);
     const double t3 = f3 - fl3;
     const int k0 = (((int)fl3 % n3) + n3) % n3, k1 = (k0 + 1) % n3;
@@ -300,10 +341,12 @@ __device__ __forceinline__ void grid_sample(const Params& P, const double* tht, 
 }
 
 // Plasma and coefficients at a midpoint.  Returns false where nothing emits.
+// (s, c) = (sin, cos) of th, supplied by the caller.
 template <typename R, int MODEL>
 __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht, double r, double th,
-                                             double ph, double kt, double kph, double kr_ks,
-                                             double kth, double k0r, double k0i, Coef<R>& C)
+                                             double s, double c, double ph, double kt, double kph,
+                                             double kr_ks, double kth, double k0r, double k0i,
+                                             Coef<R>& C)
 {
     const double a = P.a;
     if (r <= P.rh * 1.0001) return false;
@@ -312,29 +355,32 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
     } else {
         if (r >= P.mp[5]) return false;
     }
-    double s, c;
-    ::sincos(th, &s, &c);
     const double s2 = s * s;
     const double Sig = r * r + a * a * c * c;
     const double Del = r * r - 2.0 * r + a * a;
     const double A = (r * r + a * a) * (r * r + a * a) - a * a * Del * s2;
-    const double iD = 1.0 / Del;
+    const double iD = frcp(Del);
+    const double iS = frcp(Sig);
+    const double iA = frcp(A);
+    const double is = frcp(s);
     const double kr_bl = kr_ks + (2.0 * r * iD) * kt + (a * iD) * kph;
     // ZAMO frame at (r, th)
-    const double zal = ::sqrt(Sig * Del / A);
-    const double zom = 2.0 * a * r / A;
-    const double zer = ::sqrt(Del / Sig);
-    const double zeh = 1.0 / ::sqrt(Sig);
-    const double zep = 1.0 / (::sqrt(A / Sig) * s);
+    const double zal = ::sqrt(Sig * Del * iA);
+    const double izal = frcp(zal);
+    const double zom = 2.0 * a * r * iA;
+    const double zer = ::sqrt(Del * iS);
+    const double zeh = ::sqrt(iS);
+    const double zep = ::sqrt(Sig * iA) * is;
     if constexpr (MODEL == MODEL_TOY) {
         double vr, vp;
         flow_v3(P, r, vr, vp);
-        const double Gam = 1.0 / ::sqrt(1.0 - vr * vr - vp * vp);
-        const double u0 = Gam / zal, u1 = Gam * vr * zer, u3 = Gam * (zom / zal + vp * zep);
+        const double Gam = frcp(::sqrt(1.0 - vr * vr - vp * vp));
+        const double u0 = Gam * izal, u1 = Gam * vr * zer, u3 = Gam * (zom * izal + vp * zep);
         const double ku = kt * u0 + kr_bl * u1 + kph * u3;
         const double hr = P.mp[1];
-        const double j = ::exp(-c * c / (2.0 * hr * hr)) / (r * r);
-        C.jI = R(j / (ku * ku));
+        const double iku = frcp(ku);
+        const double j = ::exp(-c * c * frcp(2.0 * hr * hr)) * frcp(r * r);
+        C.jI = R(j * iku * iku);
         C.jQ = C.jU = C.jV = R(0);
         C.aI = C.aQ = C.aU = C.aV = R(0);
         C.rQ = C.rU = C.rV = R(0);
@@ -359,11 +405,11 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
             if (!(rho > R(0))) return false;
             const R pg = (R(P.mp[3]) - R(1)) * f[1];
             const R b2 = f[5] * f[5] + f[6] * f[6] + f[7] * f[7];
-            if (b2 / rho > R(P.mp[4])) return false;           // sigma cut
-            const R bet = b2 > R(0) ? pg / (R(0.5) * b2) : R(1e30);
+            if (b2 > R(P.mp[4]) * rho) return false;           // sigma cut
+            const R bet = b2 > R(0) ? pg * frcp(R(0.5) * b2) : R(1e30);
             const R bet2 = bet * bet;
-            const R tratio = (R(P.mp[1]) * bet2 + R(P.mp[2])) / (R(1) + bet2);
-            Th = R(kMp / kMe) * pg / rho / (R(1) + tratio);
+            const R tratio = (R(P.mp[1]) * bet2 + R(P.mp[2])) * frcp(R(1) + bet2);
+            Th = R(kMp / kMe) * pg * frcp(rho) * frcp(R(1) + tratio);
             if (!(Th > R(0))) return false;
             ne = rho * R(P.mp[0]);
             Bm = fsqrt(b2) * R(P.B_unit);
@@ -373,31 +419,32 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
         }
         // fluid 4-velocity and unit comoving field direction from ZAMO components
         const double vv = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2];
-        const double Gam = 1.0 / ::sqrt(1.0 - vv);
-        const double u0 = Gam / zal, u1 = Gam * v3[0] * zer, u2 = Gam * v3[1] * zeh;
-        const double u3 = Gam * (zom / zal + v3[2] * zep);
+        const double Gam = frcp(::sqrt(1.0 - vv));
+        const double u0 = Gam * izal, u1 = Gam * v3[0] * zer, u2 = Gam * v3[1] * zeh;
+        const double u3 = Gam * (zom * izal + v3[2] * zep);
         const double ku = kt * u0 + kr_bl * u1 + kth * u2 + kph * u3;
-        const double iBn = 1.0 / ::sqrt(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]);
+        const double iBn = frcp(::sqrt(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]));
         const double Bt0 = B3[0] * iBn, Bt1 = B3[1] * iBn, Bt2 = B3[2] * iBn;
         const double Bdu = Gam * (v3[0] * Bt0 + v3[1] * Bt1 + v3[2] * Bt2);
-        const double resc = 1.0 / ::sqrt(1.0 + Bdu * Bdu);
+        const double resc = frcp(::sqrt(1.0 + Bdu * Bdu));
         const double b0 = Bdu * u0 * resc;
         const double b1 = (Bt0 * zer + Bdu * u1) * resc;
         const double b2_ = (Bt1 * zeh + Bdu * u2) * resc;
         const double b3 = (Bt2 * zep + Bdu * u3) * resc;
         const double kb = kt * b0 + kr_bl * b1 + kth * b2_ + kph * b3;
-        double cth = -kb / ku;
+        const double iku = frcp(ku);
+        double cth = -kb * iku;
         cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
         // contravariant k (BL)
-        const double gitt = -A / (Sig * Del), gitp = -2.0 * a * r / (Sig * Del);
-        const double girr = Del / Sig, gihh = 1.0 / Sig, gipp = (Del - a * a * s2) / (Sig * Del * s2);
-        const double iku = 1.0 / ku;
+        const double iSD = iS * iD;
+        const double gitt = -A * iSD, gitp = -2.0 * a * r * iSD;
+        const double girr = Del * iS, gihh = iS, gipp = (Del - a * a * s2) * iSD * (is * is);
         const double kup[4] = { gitt * kt + gitp * kph, girr * kr_bl, gihh * kth, gitp * kt + gipp * kph };
         // photon direction n = k/ku - u; b_perp = b - (b.n) n
         const double n0 = kup[0] * iku - u0, n1 = kup[1] * iku - u1, n2 = kup[2] * iku - u2;
         const double n3 = kup[3] * iku - u3;
-        const double gtt = -(1.0 - 2.0 * r / Sig), gtp = -2.0 * a * r * s2 / Sig;
-        const double grr = Sig / Del, ghh = Sig, gpp = (r * r + a * a + 2.0 * a * a * r * s2 / Sig) * s2;
+        const double gtt = -(1.0 - 2.0 * r * iS), gtp = -2.0 * a * r * s2 * iS;
+        const double grr = Sig * iD, ghh = Sig, gpp = (r * r + a * a + 2.0 * a * a * r * s2 * iS) * s2;
         const double bl0 = gtt * b0 + gtp * b3, bl1 = grr * b1, bl2 = ghh * b2_, bl3 = gtp * b0 + gpp * b3;
         const double bn = bl0 * n0 + bl1 * n1 + bl2 * n2 + bl3 * n3;
         const double bp[4] = { b0 - bn * n0, b1 - bn * n1, b2_ - bn * n2, b3 - bn * n3 };
@@ -408,7 +455,7 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
         const double zn = zr * zr + zi * zi;
         double c2x = 1.0, s2x = 0.0;
         if (zn > 0.0) {
-            const double izn = 1.0 / zn;
+            const double izn = frcp(zn);
             c2x = (zr * zr - zi * zi) * izn;
             s2x = 2.0 * zr * zi * izn;
         }
@@ -424,50 +471,40 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
 }
 
 // ---------------------------------------------------------- transfer maths
-// e^-w sinh(u)/u, sin(v)/v, e^-w (sinh(u)/u - 1)/u^2, (1 - sin(v)/v)/v^2:
-// series below 1, closed forms above (no cancellation, no overflow for u <= w).
+// Polynomial parts (u, v < 1) of sinh(u)/u, sin(v)/v, (sinh(u)/u - 1)/u^2 and
+// (1 - sin(v)/v)/v^2.
 template <typename R>
-__device__ __forceinline__ R shc_d(R u, R w)
+__device__ __forceinline__ R shc_poly(R u2)
 {
-    if (u < R(1)) {
-        const R u2 = u * u;
-        const R s = R(1) + u2 / R(6) * (R(1) + u2 / R(20) * (R(1) + u2 / R(42) * (R(1) + u2 / R(72) * (R(1) + u2 / R(110) * (R(1) + u2 / R(156))))));
-        return fexp(-w) * s;
-    }
-    return (fexp(u - w) - fexp(-u - w)) / (R(2) * u);
+    return R(1) + u2 * R(1.0 * (1.0 / 6.0)) * (R(1) + u2 * R(1.0 * (1.0 / 20.0)) * (R(1) + u2 * R(1.0 * (1.0 / 42.0)) * (R(1) + u2 * R(1.0 * (1.0 / 72.0)) * (R(1) + u2 * R(1.0 * (1.0 / 110.0)) * (R(1) + u2 * R(1.0 * (1.0 / 156.0)))))));
 }
 template <typename R>
-__device__ __forceinline__ R sinc_(R v)
+__device__ __forceinline__ R sinc_poly(R v2)
 {
-    if (v < R(1)) {
-        const R v2 = v * v;
-        return R(1) - v2 / R(6) * (R(1) - v2 / R(20) * (R(1) - v2 / R(42) * (R(1) - v2 / R(72) * (R(1) - v2 / R(110) * (R(1) - v2 / R(156))))));
-    }
-    return fsin(v) / v;
+    return R(1) - v2 * R(1.0 * (1.0 / 6.0)) * (R(1) - v2 * R(1.0 * (1.0 / 20.0)) * (R(1) - v2 * R(1.0 * (1.0 / 42.0)) * (R(1) - v2 * R(1.0 * (1.0 / 72.0)) * (R(1) - v2 * R(1.0 * (1.0 / 110.0)) * (R(1) - v2 * R(1.0 * (1.0 / 156.0)))))));
 }
 template <typename R>
-__device__ __forceinline__ R gfun_d(R u, R w)
+__device__ __forceinline__ R g_poly(R u2)
 {
-    if (u < R(1)) {
-        const R u2 = u * u;
-        const R s = R(1) / R(6) * (R(1) + u2 / R(20) * (R(1) + u2 / R(42) * (R(1) + u2 / R(72) * (R(1) + u2 / R(110) * (R(1) + u2 / R(156) * (R(1) + u2 / R(210)))))));
-        return fexp(-w) * s;
-    }
-    return (shc_d(u, w) - fexp(-w)) / (u * u);
+    return R(1) * R(1.0 * (1.0 / 6.0)) * (R(1) + u2 * R(1.0 * (1.0 / 20.0)) * (R(1) + u2 * R(1.0 * (1.0 / 42.0)) * (R(1) + u2 * R(1.0 * (1.0 / 72.0)) * (R(1) + u2 * R(1.0 * (1.0 / 110.0)) * (R(1) + u2 * R(1.0 * (1.0 / 156.0)) * (R(1) + u2 * R(1.0 * (1.0 / 210.0))))))));
 }
 template <typename R>
-__device__ __forceinline__ R hfun_(R v)
+__device__ __forceinline__ R h_poly(R v2)
 {
-    if (v < R(1)) {
-        const R v2 = v * v;
-        return R(1) / R(6) * (R(1) - v2 / R(20) * (R(1) - v2 / R(42) * (R(1) - v2 / R(72) * (R(1) - v2 / R(110) * (R(1) - v2 / R(156) * (R(1) - v2 / R(210)))))));
-    }
-    return (R(1) - fsin(v) / v) / (v * v);
+    return R(1) * R(1.0 * (1.0 / 6.0)) * (R(1) - v2 * R(1.0 * (1.0 / 20.0)) * (R(1) - v2 * R(1.0 * (1.0 / 42.0)) * (R(1) - v2 * R(1.0 * (1.0 / 72.0)) * (R(1) - v2 * R(1.0 * (1.0 / 110.0)) * (R(1) - v2 * R(1.0 * (1.0 / 156.0)) * (R(1) - v2 * R(1.0 * (1.0 / 210.0))))))));
 }
+__device__ __forceinline__ void fsincos(double x, double* s, double* c) { ::sincos(x, s, c); }
+__device__ __forceinline__ void fsincos(float x, float* s, float* c) { ::sincosf(x, s, c); }
 
 // Coefficients c0..c3 with exp(-aI x) exp(-A x) = c0 + c1 A + c2 A^2 + c3 A^3.
 // The eigenvalues of A are +-L1, +-i L2 (L1^2 - L2^2 = |a|^2 - |r|^2,
-// L1 L2 = a.r).
+// L1 L2 = a.r); with u = x L1, v = x L2, w = x aI (u <= w for physical
+// coefficients):
+//   c2 = x^2/2 (L1^2 e^-w shc(u/2)^2 + L2^2 e^-w sinc(v/2)^2) / D
+//   c1 = -x (L2^2 e^-w shc(u) + L1^2 e^-w sinc(v)) / D
+//   c3 = -x^3 (L1^2 e^-w g(u) + L2^2 e^-w h(v)) / D,   c0 = e^-w cosh u - L1^2 c2,
+// D = L1^2 + L2^2.  Exponentials: e^-w and e^u (square roots give the half
+// arguments); sin/cos of v/2 give sin v and the half-argument sinc.
 template <typename R>
 __device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3], R x,
                                                R& c0, R& c1, R& c2, R& c3)
@@ -482,20 +519,57 @@ __device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3
     const R L1 = fsqrt(L1s), L2 = fsqrt(L2s);
     const R u = x * L1, v = x * L2, w = x * aI;
     const R ew = fexp(-w);
-    const R ch = R(0.5) * (fexp(u - w) + fexp(-u - w));
+    const R ew2 = fsqrt(ew);                 // e^-w/2
+    // hyperbolic parts, damped by e^-w
+    R ch, shc, sh2, gu;
+    const R u2 = u * u;
+    if (u < R(1)) {
+        const R p2 = shc_poly(R(0.25) * u2);   // sinh(u/2)/(u/2)
+        ch = ew * (R(1) + R(0.5) * u2 * p2 * p2);   // cosh u = 1 + 2 sinh^2(u/2)
+        shc = ew * shc_poly(u2);
+        sh2 = ew2 * p2;
+        gu = ew * g_poly(u2);
+    } else {
+        R ep, em;                              // e^(u-w), e^(-u-w)
+        if (u < R(60)) {
+            const R eu = fexp(u);
+            ep = eu * ew;
+            em = ew * frcp(eu);
+        } else {
+            ep = fexp(u - w);
+            em = fexp(-u - w);
+        }
+        ch = R(0.5) * (ep + em);
+        const R iu = frcp(u);
+        shc = R(0.5) * (ep - em) * iu;
+        sh2 = (fsqrt(ep) - fsqrt(em)) * iu;
+        gu = (shc - ew) * (iu * iu);
+    }
+    // trigonometric parts
+    R snc, sn2, hv;
+    const R v2 = v * v;
+    if (v < R(1)) {
+        snc = sinc_poly(v2);
+        sn2 = sinc_poly(R(0.25) * v2);
+        hv = h_poly(v2);
+    } else {
+        R sh, chh;
+        fsincos(R(0.5) * v, &sh, &chh);
+        const R iv = frcp(v);
+        const R sv = R(2) * sh * chh;
+        snc = sv * iv;
+        sn2 = R(2) * sh * iv;
+        hv = (R(1) - snc) * (iv * iv);
+    }
     if (D > R(0)) {
-        const R iD = R(1) / D;
-        const R shc = shc_d(u, w);
-        const R snc = sinc_(v);
-        const R sh2 = shc_d(R(0.5) * u, R(0.5) * w);
-        const R sn2 = sinc_(R(0.5) * v);
+        const R iD = frcp(D);
         c2 = R(0.5) * x * x * (L1s * sh2 * sh2 + L2s * ew * sn2 * sn2) * iD;
         c1 = -x * (L2s * shc + L1s * ew * snc) * iD;
-        c3 = -x * x * x * (L1s * gfun_d(u, w) + L2s * ew * hfun_(v)) * iD;
+        c3 = -x * x * x * (L1s * gu + L2s * ew * hv) * iD;
     } else {
         c2 = R(0.5) * x * x * ew;
         c1 = -x * ew;
-        c3 = -x * x * x * ew / R(6);
+        c3 = -x * x * x * ew * R(1.0 * (1.0 / 6.0));
     }
     c0 = ch - L1s * c2;
 }
@@ -503,14 +577,14 @@ __device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3
 template <typename R>
 __device__ __forceinline__ R phi1_(R w)
 {
-    if (w < R(1e-4)) return R(1) - w / R(2) + w * w / R(6) - w * w * w / R(24);
-    return -fexpm1(-w) / w;
+    if (w < R(1e-4)) return R(1) - w * R(1.0 * (1.0 / 2.0)) + w * w * R(1.0 * (1.0 / 6.0)) - w * w * w * R(1.0 * (1.0 / 24.0));
+    return -fexpm1(-w) * frcp(w);
 }
 template <typename R>
 __device__ __forceinline__ R mean_depth_(R w)
 {
-    if (w < R(0.1)) { const R w2 = w * w; return R(0.5) - w / R(12) + w * w2 / R(720) - w * w2 * w2 / R(30240); }
-    return R(1) / w - R(1) / fexpm1(w);
+    if (w < R(0.1)) { const R w2 = w * w; return R(0.5) - w * R(1.0 * (1.0 / 12.0)) + w * w2 * R(1.0 * (1.0 / 720.0)) - w * w2 * w2 * R(1.0 * (1.0 / 30240.0)); }
+    return frcp(w) - frcp(fexpm1(w));
 }
 
 // y = A x for A = [[0,aQ,aU,aV],[aQ,0,rV,-rU],[aU,-rV,0,rQ],[aV,rU,-rQ,0]]

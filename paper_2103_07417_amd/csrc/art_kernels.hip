@@ -123,48 +123,57 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>
 }
 
 // Advance one ray by one step.  Returns a RAY_* status (RAY_OK = continue).
+// sin/cos of theta are evaluated once per step; the RK stages and the
+// midpoint rotate them by their (small) theta increments.
 template <typename R, int MODEL, int NS>
 __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayState<R, MODEL, NS>& st,
                                         unsigned& emit)
 {
     const double a = P.a;
     double k1[5], acc[5], yt[5], kk[5];
-    const double c = geo_rhs(a, st.kt, st.kph, st.y, k1);
-    if (st.cprev * c < 0.0) st.ncross++;
-    st.cprev = c;
+    double s0, c0;
+    ::sincos(st.y[1], &s0, &c0);
+    geo_rhs(a, st.kt, st.kph, st.y, s0, c0, k1);
+    if (st.cprev * c0 < 0.0) st.ncross++;
+    st.cprev = c0;
     if (st.y[0] < st.rmin) st.rmin = st.y[0];
     if (st.y[0] > P.r_out && k1[0] > 0.0) return RAY_ESCAPED;
     if (st.y[0] < P.rstop) return RAY_CAPTURED;
     if (st.nstep >= P.max_steps) return RAY_STEPCAP;
     if (st.O[0] < R(1e-12)) return RAY_THICK;
     if (!(st.y[0] == st.y[0]) || !(st.y[3] == st.y[3])) return RAY_NAN;
-    const double rate = ::fabs(k1[0]) / st.y[0] + ::fabs(k1[1]) + ::fabs(k1[2]);
+    const double rate = ::fabs(k1[0]) * frcp(st.y[0]) + ::fabs(k1[1]) + ::fabs(k1[2]);
     double far = st.y[0] * (1.0 / 20.0);
     far = far < 1.0 ? 1.0 : (far > 4.0 ? 4.0 : far);
-    double h = P.eps * far / rate;
+    double h = P.eps * far * frcp(rate);
     if (k1[0] < 0.0) {
-        const double hh = 0.5 * (st.y[0] - P.rh) / (-k1[0]);
+        const double hh = 0.5 * (st.y[0] - P.rh) * frcp(-k1[0]);
         h = hh < h ? hh : h;
     }
     const double h2 = 0.5 * h;
+    double s, c;
 #pragma unroll
     for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h2 * k1[i]; acc[i] = k1[i]; }
-    geo_rhs(a, st.kt, st.kph, yt, kk);
+    rotate_sc(s0, c0, h2 * k1[1], s, c);
+    geo_rhs(a, st.kt, st.kph, yt, s, c, kk);
 #pragma unroll
     for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h2 * kk[i]; acc[i] += 2.0 * kk[i]; }
-    geo_rhs(a, st.kt, st.kph, yt, kk);
+    rotate_sc(s0, c0, h2 * kk[1], s, c);
+    geo_rhs(a, st.kt, st.kph, yt, s, c, kk);
 #pragma unroll
     for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h * kk[i]; acc[i] += 2.0 * kk[i]; }
-    geo_rhs(a, st.kt, st.kph, yt, kk);
-    const double h6 = h / 6.0;
+    rotate_sc(s0, c0, h * kk[1], s, c);
+    geo_rhs(a, st.kt, st.kph, yt, s, c, kk);
+    const double h6 = h * (1.0 / 6.0);
 #pragma unroll
     for (int i = 0; i < 5; ++i) yt[i] = st.y[i] + h6 * (acc[i] + kk[i]);
     // transfer at the step midpoint
     const double rm = 0.5 * (st.y[0] + yt[0]), thm = 0.5 * (st.y[1] + yt[1]);
     const double phm = 0.5 * (st.y[2] + yt[2]);
     const double krm = 0.5 * (st.y[3] + yt[3]), kthm = 0.5 * (st.y[4] + yt[4]);
+    rotate_sc(s0, c0, 0.5 * (yt[1] - st.y[1]), s, c);
     Coef<R> C;
-    if (plasma_point<R, MODEL>(P, tht, rm, thm, phm, st.kt, st.kph, krm, kthm, st.k0r, st.k0i, C)) {
+    if (plasma_point<R, MODEL>(P, tht, rm, thm, s, c, phm, st.kt, st.kph, krm, kthm, st.k0r, st.k0i, C)) {
         ++emit;
         if constexpr (NS == 4) {
             transfer_step4<R, R>(st.S, st.O, C, R(h));
