@@ -20,7 +20,9 @@
  *    library never frees them).  Images are planar FP64:
  *    image[s][y][x], s = 0..nstokes-1 (I, Q, U, V).  The level map is int8
  *    [y][x]: -1 interpolated, l >= 0 traced at refinement level l.  The
- *    feature buffer is art_ray_feat[y][x] (only traced pixels are written).
+ *    feature buffer is art_ray_feat[y][x]: traced pixels get their ray's
+ *    values; an interpolated pixel gets the smallest r_min and the largest
+ *    n_cross of the points it is interpolated from, steps = 0.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *    Work is enqueued asynchronously; a call that fills an art_stats
  *    synchronises the stream before returning.
@@ -153,6 +155,12 @@ typedef struct {
     double t_trace_ms;             /* summed duration of the tracing kernels (HIP events) */
     int32_t trace_launches;        /* number of tracing-kernel launches */
     int32_t levels;
+    int64_t learned[5];            /* learned renders (else 0): [0] proposed points the
+                                      criterion would not trace, [1] criterion-flagged
+                                      points the network suppressed, [2] points the
+                                      criterion traced as fallback after a look-ahead
+                                      pass, [3] criterion-flagged points left
+                                      interpolated (fallback off), [4] look-ahead rays */
 } art_stats;
 
 /* Final grid size n = 2^N (n0 - 1) + 1 per axis (Sec. 3.2) and the image size
@@ -244,6 +252,100 @@ int art_get_launch(int32_t precision, int32_t kind, int32_t nstokes, art_launch*
  * graph keeps the shape it was captured with). */
 int art_batch_set_launch(art_batch* b, const art_launch* launch);
 int art_batch_get_launch(const art_batch* b, art_launch* launch);
+
+/* ----------------------------------------------- learned refinement proposal
+ * A small convolutional network (4 layers of 3x3 convolutions, channels
+ * 3 -> 32 -> 32 -> 32 -> 15, ReLU between layers; 23,727 FP32 master
+ * parameters, BF16 MFMA arithmetic with FP32 accumulation) reads the level-l
+ * vertex grid of an adaptive render and predicts, for each level-l vertex,
+ * whether each of the 15 new points of its cell (3 at level l+1, 12 at level
+ * l+2) is traced by the refinement criterion of Sec. 3.2.  It is trained on
+ * level maps of plain renders.  In a learned render the network looks ahead:
+ * level-(l+2) points it proposes are traced in the same pass as level l+1, and
+ * the criterion of Eqs. 5-6 stays the judge (every point it flags is counted)
+ * and the fallback (flagged points the look-ahead missed are traced).
+ *
+ * Tensors (device, caller-owned):
+ *   features  x[B][3][H][W] FP32: ln(max(I,0)/N_abs + 1e-4), min(r_min, 20)/10,
+ *             min(n_cross, 4)/4 at the level-l vertices (H = 2^l (n0y-1) + 1,
+ *             W = 2^l (n0x-1) + 1)
+ *   logits    z[B][15][H][W] FP32
+ *   labels, valid  [B][15][H][W] uint8 (valid = the point exists)
+ * Output k of vertex (i, j): k = 0..2 the level-(l+1) points (2i+1, 2j),
+ * (2i, 2j+1), (2i+1, 2j+1); k = 3..14 the level-(l+2) points (4i+dx, 4j+dy)
+ * with (dx, dy) in row-major order over the 4x4 block, both even excluded.
+ * Parameter order: W0, b0, W1, b1, W2, b2, W3, b3, W[l] as [c_out][c_in][3][3].
+ * The forward/gradient/training calls of one network share its workspace:
+ * issue them on one stream at a time. */
+typedef struct art_cnn art_cnn;       /* opaque */
+
+/* Number of FP32 parameters (23,727). */
+int art_cnn_num_params(void);
+
+/* Create a network with seeded He-normal weights and zero biases. */
+int art_cnn_create(uint64_t seed, art_cnn** out);
+int art_cnn_destroy(art_cnn* net);
+
+/* Copy n FP32 parameters from / to host memory; set also resets the Adam
+ * state.  Both synchronise the device. */
+int art_cnn_set_params(art_cnn* net, const float* host, int64_t n);
+int art_cnn_get_params(art_cnn* net, float* host, int64_t n);
+
+/* Logits of B feature grids (B H W <= 2^28).  Asynchronous on `stream`. */
+int art_cnn_forward(art_cnn* net, const float* x_dev, int32_t B, int32_t H, int32_t W,
+                    float* logits_dev, void* stream);
+
+/* Loss L = mean over valid outputs of the positive-weighted binary cross-
+ * entropy -[w y ln s(z) + (1-y) ln(1-s(z))], and its gradient w.r.t. every
+ * parameter (copied to grad_host[num_params] if non-NULL; the loss to
+ * *loss_out if non-NULL).  Synchronises when either output is requested. */
+int art_cnn_gradients(art_cnn* net, const float* x_dev, const uint8_t* labels_dev,
+                      const uint8_t* valid_dev, int32_t B, int32_t H, int32_t W,
+                      float pos_weight, float* grad_host, float* loss_out, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * gradient of the loss above; the loss before the step goes to *loss_out if
+ * non-NULL (then synchronises). */
+int art_cnn_train_step(art_cnn* net, const float* x_dev, const uint8_t* labels_dev,
+                       const uint8_t* valid_dev, int32_t B, int32_t H, int32_t W, float lr,
+                       float pos_weight, float* loss_out, void* stream);
+
+/* Features of level `level` of one rendered image (image plane 0 and the
+ * art_ray_feat buffer, NULL = zeros for r_min and n_cross) into x_dev[3][H][W]. */
+int art_cnn_features(const double* image_dev, const void* feat_dev, int32_t nx, int32_t ny,
+                     int32_t nx0, int32_t ny0, int32_t levels, int32_t level, double n_abs,
+                     float* x_dev, void* stream);
+
+/* Training labels of level `level` (< levels) from a plain render's level map:
+ * label = 1 if the point was traced at its own level. */
+int art_cnn_labels(const int8_t* level_dev, int32_t nx, int32_t ny, int32_t nx0, int32_t ny0,
+                   int32_t levels, int32_t level, uint8_t* labels_dev, uint8_t* valid_dev,
+                   void* stream);
+
+typedef struct {
+    float z_propose;               /* logit above which a point is traced without waiting
+                                      for the criterion */
+    float z_suppress;              /* logit below which a flagged point is interpolated
+                                      (-INFINITY: never) */
+    int32_t fallback;              /* 1: after a look-ahead pass the criterion traces the
+                                      points it flags that were not traced; 0: it only
+                                      counts them (art_stats.learned[3]) */
+    int32_t all_levels;            /* 0: the network runs only at levels l with l + 2 <= N
+                                      (look-ahead); 1: also at l = N - 1 */
+} art_learned;
+
+/* Switch a batch to learned renders with `net` (NULL: back to plain).  All
+ * images need the same base grid and level count, and feature buffers
+ * (art_image.feat_dev).  Allocates the batch's own network workspace; later
+ * art_batch_render / art_batch_capture use the network (a captured graph
+ * reads the parameters at replay, so training in between is seen).  `net`
+ * must outlive the batch's use of it. */
+int art_batch_set_learned(art_batch* b, art_cnn* net, const art_learned* opt);
+
+/* Single-image learned render (like art_render, plus the network). */
+int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                       const art_refine* rf, const art_transfer* tr, art_cnn* net,
+                       const art_learned* opt, art_image* out, art_stats* st, void* stream);
 
 /* Image metrics of Sec. 4.1 on n FP64 values (one Stokes plane), computed on
  * the device with a deterministic two-pass reduction; synchronises:

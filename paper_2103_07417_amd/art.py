@@ -67,7 +67,12 @@ class Stats(ctypes.Structure):
                 ("ibar_int", ctypes.c_double), ("imax0", ctypes.c_double),
                 ("n_abs", ctypes.c_double), ("steps_emit", ctypes.c_int64),
                 ("t_trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int32),
-                ("levels", ctypes.c_int32)]
+                ("levels", ctypes.c_int32), ("learned", ctypes.c_int64 * 5)]
+
+
+class Learned(ctypes.Structure):
+    _fields_ = [("z_propose", ctypes.c_float), ("z_suppress", ctypes.c_float),
+                ("fallback", ctypes.c_int32), ("all_levels", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -120,6 +125,20 @@ def lib():
         L.art_batch_set_launch.argtypes = [vp, P(Launch)]
         L.art_batch_get_launch.argtypes = [vp, P(Launch)]
         L.art_get_launch.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(Launch)]
+        f32, u64, i32 = ctypes.c_float, ctypes.c_uint64, ctypes.c_int32
+        L.art_cnn_num_params.argtypes = []
+        L.art_cnn_create.argtypes = [u64, P(vp)]
+        L.art_cnn_destroy.argtypes = [vp]
+        L.art_cnn_set_params.argtypes = [vp, vp, i64]
+        L.art_cnn_get_params.argtypes = [vp, vp, i64]
+        L.art_cnn_forward.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+        L.art_cnn_gradients.argtypes = [vp, vp, vp, vp, i32, i32, i32, f32, vp, P(f32), vp]
+        L.art_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, f32, f32, P(f32), vp]
+        L.art_cnn_features.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, ctypes.c_double, vp, vp]
+        L.art_cnn_labels.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp, vp]
+        L.art_batch_set_learned.argtypes = [vp, vp, P(Learned)]
+        L.art_render_learned.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine),
+                                         P(Transfer), vp, P(Learned), P(Image), P(Stats), vp]
         L.art_last_error.restype = ctypes.c_char_p
         L.art_last_error.argtypes = []
         L.art_release.argtypes = []
@@ -186,7 +205,10 @@ def stats_dict(st):
                 interp_frac=float(st.interp_frac), ibar=float(st.ibar_int),
                 imax0=float(st.imax0), n_abs=float(st.n_abs), levels=L,
                 steps_emit=int(st.steps_emit), t_trace_ms=float(st.t_trace_ms),
-                trace_launches=int(st.trace_launches))
+                trace_launches=int(st.trace_launches),
+                learned=dict(proposed_extra=int(st.learned[0]), suppressed=int(st.learned[1]),
+                             fallback=int(st.learned[2]), missed=int(st.learned[3]),
+                             lookahead=int(st.learned[4])))
 
 
 def alloc(cfg, feat=False):
@@ -233,6 +255,27 @@ def render_uniform(cfg, out=None, feat=False, stats=True, stream=None):
                                   ctypes.byref(st) if stats else None, _stream(torch, stream))
     _check(rc)
     return img, ft, (stats_dict(st) if stats else None)
+
+
+def learned_opts(z_propose=2.0, z_suppress=float("-inf"), fallback=True, all_levels=False):
+    return Learned(float(z_propose), float(z_suppress), 1 if fallback else 0, 1 if all_levels else 0)
+
+
+def render_learned(cfg, net, out=None, stats=True, stream=None, **opts):
+    """Learned adaptive render (network look-ahead, criterion as judge and
+    fallback).  Returns (image, level, feat, stats)."""
+    torch = _torch()
+    sp, cam, em, rf, tr = blocks(cfg)
+    img, lev, ft = out if out is not None else alloc(cfg, True)
+    im = _image(img, lev, ft)
+    st = Stats()
+    lo = learned_opts(**opts)
+    rc = lib().art_render_learned(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em),
+                                  ctypes.byref(rf), ctypes.byref(tr), net.handle, ctypes.byref(lo),
+                                  ctypes.byref(im), ctypes.byref(st) if stats else None,
+                                  _stream(torch, stream))
+    _check(rc)
+    return img, lev, ft, (stats_dict(st) if stats else None)
 
 
 def trace_points(cfg, alpha, beta, feat=True, stream=None):
@@ -334,6 +377,14 @@ class Batch:
         _check(lib().art_batch_get_launch(self._h, ctypes.byref(L)))
         return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill)
 
+    def set_learned(self, net, **opts):
+        """Use the network `net` (a Cnn, or None for plain renders) in later
+        renders and captures of this batch."""
+        lo = learned_opts(**opts)
+        self._net = net                      # keep the network alive while used
+        _check(lib().art_batch_set_learned(self._h, net.handle if net is not None else None,
+                                           ctypes.byref(lo)))
+
     def close(self):
         if getattr(self, "_h", None):
             lib().art_batch_destroy(self._h)
@@ -344,3 +395,101 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Cnn:
+    """Learned refinement proposal network (BF16 MFMA forward and backward on
+    the GPU, FP32 master weights, Adam).  Parameter order: W0, b0, ..., W3, b3
+    with W[l] as [c_out][c_in][3][3]."""
+
+    N_OUT = 15
+
+    def __init__(self, seed=4):
+        self._torch = _torch()
+        h = ctypes.c_void_p()
+        _check(lib().art_cnn_create(int(seed), ctypes.byref(h)))
+        self.handle = h
+        self.n_params = int(lib().art_cnn_num_params())
+
+    def set_params(self, vec):
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        _check(lib().art_cnn_set_params(self.handle, v.ctypes.data, v.size))
+
+    def get_params(self):
+        v = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().art_cnn_get_params(self.handle, v.ctypes.data, v.size))
+        return v
+
+    def forward(self, x, stream=None):
+        """x: CUDA float32 (B, 3, H, W) -> logits (B, 15, H, W)."""
+        torch = self._torch
+        x = x.contiguous()
+        B, C, H, W = x.shape
+        assert C == 3 and x.dtype == torch.float32
+        z = torch.empty((B, self.N_OUT, H, W), dtype=torch.float32, device=x.device)
+        _check(lib().art_cnn_forward(self.handle, x.data_ptr(), B, H, W, z.data_ptr(),
+                                     _stream(torch, stream)))
+        return z
+
+    def gradients(self, x, labels, valid, pos_weight=1.0, stream=None):
+        """(loss, flat gradient) of the batch; labels/valid CUDA uint8 (B, 15, H, W)."""
+        torch = self._torch
+        x, labels, valid = x.contiguous(), labels.contiguous(), valid.contiguous()
+        B, _, H, W = x.shape
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(lib().art_cnn_gradients(self.handle, x.data_ptr(), labels.data_ptr(),
+                                       valid.data_ptr(), B, H, W, float(pos_weight), g.ctypes.data,
+                                       ctypes.byref(loss), _stream(torch, stream)))
+        return float(loss.value), g
+
+    def train_step(self, x, labels, valid, lr=1e-3, pos_weight=1.0, want_loss=True, stream=None):
+        torch = self._torch
+        x, labels, valid = x.contiguous(), labels.contiguous(), valid.contiguous()
+        B, _, H, W = x.shape
+        loss = ctypes.c_float()
+        _check(lib().art_cnn_train_step(self.handle, x.data_ptr(), labels.data_ptr(),
+                                        valid.data_ptr(), B, H, W, float(lr), float(pos_weight),
+                                        ctypes.byref(loss) if want_loss else None,
+                                        _stream(torch, stream)))
+        return float(loss.value) if want_loss else None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().art_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cnn_level_shape(cfg, level):
+    return ((1 << level) * (int(cfg["ny0"]) - 1) + 1, (1 << level) * (int(cfg["nx0"]) - 1) + 1)
+
+
+def cnn_features(cfg, img, ft, level, n_abs, stream=None):
+    """Network input (1, 3, H, W) float32 of level `level` of a rendered image."""
+    torch = _torch()
+    H, W = cnn_level_shape(cfg, level)
+    x = torch.empty((1, 3, H, W), dtype=torch.float32, device=img.device)
+    ny, nx = img.shape[1], img.shape[2]
+    _check(lib().art_cnn_features(img.data_ptr(), ft.data_ptr() if ft is not None else None, nx, ny,
+                                  int(cfg["nx0"]), int(cfg["ny0"]), int(cfg["levels"]), int(level),
+                                  float(n_abs), x.data_ptr(), _stream(torch, stream)))
+    return x
+
+
+def cnn_labels(cfg, lev, level, stream=None):
+    """Training labels and valid mask (1, 15, H, W) uint8 from a plain render's level map."""
+    torch = _torch()
+    H, W = cnn_level_shape(cfg, level)
+    lab = torch.empty((1, 15, H, W), dtype=torch.uint8, device=lev.device)
+    val = torch.empty((1, 15, H, W), dtype=torch.uint8, device=lev.device)
+    ny, nx = lev.shape
+    _check(lib().art_cnn_labels(lev.data_ptr(), nx, ny, int(cfg["nx0"]), int(cfg["ny0"]),
+                                int(cfg["levels"]), int(level), lab.data_ptr(), val.data_ptr(),
+                                _stream(torch, stream)))
+    return lab, val

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/art.h"
+#include "art_cnn.hpp"
 #include "art_internal.hpp"
 
 using namespace art;
@@ -38,6 +39,23 @@ int fail(int code, const char* fmt, ...)
     g_err = buf;
     return code;
 }
+
+}  // namespace
+
+namespace art {
+int api_fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+}  // namespace art
+
+namespace {
 
 #define HIP_TRY(expr)                                                                    \
     do {                                                                                 \
@@ -86,6 +104,9 @@ struct art_batch {
     hipGraphExec_t gexec = nullptr;
     LaunchCfg L{};
     int cus = 0;
+    art_cnn* net = nullptr;        // learned renders when set
+    art_learned lopt{};
+    CnnWork ws;                    // the batch's own network workspace
 };
 
 namespace {
@@ -282,6 +303,8 @@ void free_batch_mem(art_batch* b)
     if (b->dP) (void)hipFree(b->dP);
     if (b->dD) (void)hipFree(b->dD);
     if (b->dTh) (void)hipFree(b->dTh);
+    cnn_work_free(&b->ws);
+    b->net = nullptr;
     b->list = nullptr; b->ctr = nullptr; b->dP = nullptr; b->dD = nullptr; b->dTh = nullptr;
     b->list_cap = 0;
 }
@@ -444,6 +467,101 @@ int enqueue_adaptive(art_batch* b, hipStream_t s)
     return ART_OK;
 }
 
+// Learned level loop: where the network can look two levels ahead it runs
+// on the level-l grid of every image, its level-(l+2) proposals are traced in
+// pass l+1 together with the level-(l+1) points (proposed or flagged by the
+// criterion and not suppressed), and the criterion then judges level l+2 and
+// traces what the look-ahead missed (fallback) or only counts it.
+int enqueue_learned(art_batch* b, hipStream_t s)
+{
+    b->nev = 0;
+    const ImageDesc& D0 = b->hD[0];
+    const int N = D0.levels;
+    HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
+    HIP_TRY(launch_base_list(b->dD, b->n, b->max_base, b->list, b->ctr, 0, s));
+    TraceJob J = base_job(b, 0);
+    HIP_TRY(ev_begin(b, s));
+    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+    HIP_TRY(ev_end(b, s));
+    HIP_TRY(launch_reduce_base(b->dD, b->n, b->ctr, s));
+    const art_learned& o = b->lopt;
+    int l = 0;
+    while (l < N) {
+        const bool net_here = l + 2 <= N || (o.all_levels && l + 1 <= N);
+        const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
+        if (!net_here) {
+            HIP_TRY(launch_estimate(b->dD, b->n, nxl, nyl, l, b->ctr, b->list, s));
+            J = base_job(b, l + 1);
+            HIP_TRY(ev_begin(b, s));
+            HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+            HIP_TRY(ev_end(b, s));
+            l += 1;
+            continue;
+        }
+        const int W = (int)grid_n(D0.nx0, l), H = (int)grid_n(D0.ny0, l);
+        HIP_TRY(cnn_features_batch(b->dD, b->ctr, b->n, l, H, W, b->ws.xf, s));
+        HIP_TRY(cnn_net_forward(&b->net->net, &b->ws, b->ws.xf, b->n, H, W, b->ws.logits, s));
+        HIP_TRY(cnn_propose(b->ws.logits, b->dD, b->n, l, H, W, o.z_propose, o.z_suppress, b->list, b->ctr, s));
+        HIP_TRY(launch_estimate(b->dD, b->n, nxl, nyl, l, b->ctr, b->list, s, 1, 1));
+        J = base_job(b, l + 1);
+        HIP_TRY(ev_begin(b, s));
+        HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+        HIP_TRY(ev_end(b, s));
+        if (l + 2 <= N) {
+            const int nx2 = (int)grid_n(D0.nx0, l + 2), ny2 = (int)grid_n(D0.ny0, l + 2);
+            HIP_TRY(launch_estimate(b->dD, b->n, nx2, ny2, l + 1, b->ctr, b->list, s, 2, o.fallback ? 1 : 0));
+            if (o.fallback) {
+                J = base_job(b, l + 2);
+                HIP_TRY(ev_begin(b, s));
+                HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+                HIP_TRY(ev_end(b, s));
+            }
+            l += 2;
+        } else {
+            l += 1;
+        }
+    }
+    return ART_OK;
+}
+
+int enqueue_render(art_batch* b, hipStream_t s)
+{
+    return b->net ? enqueue_learned(b, s) : enqueue_adaptive(b, s);
+}
+
+// Check that a prepared batch can run learned renders and size its workspace.
+int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
+{
+    if (!net) {
+        b->net = nullptr;
+        return ART_OK;
+    }
+    if (!opt) return fail(ART_EINVAL, "NULL learned-render options");
+    if (std::isnan(opt->z_propose) || std::isnan(opt->z_suppress) || !(opt->z_suppress <= opt->z_propose))
+        return fail(ART_EINVAL, "need z_suppress <= z_propose (no NaN)");
+    if (b->uniform) return fail(ART_EINVAL, "uniform renders have no refinement");
+    const ImageDesc& D0 = b->hD[0];
+    for (int i = 0; i < b->n; ++i) {
+        const ImageDesc& D = b->hD[i];
+        if (D.nx0 != D0.nx0 || D.ny0 != D0.ny0 || D.levels != D0.levels)
+            return fail(ART_EINVAL, "learned renders need one base grid and level count for the whole batch");
+        if (!D.feat) return fail(ART_EINVAL, "image %d: learned renders need a feature buffer", i);
+    }
+    // largest level the network runs at
+    int lmax = -1;
+    for (int l = 0; l < D0.levels; ++l)
+        if (l + 2 <= D0.levels || (opt->all_levels && l + 1 <= D0.levels)) lmax = l;
+    if (lmax >= 0) {
+        const long long P = (long long)b->n * grid_n(D0.nx0, lmax) * grid_n(D0.ny0, lmax);
+        if (P > (1LL << 28)) return fail(ART_EINVAL, "network grid of %lld positions too large", P);
+        int rc = cnn_work_reserve(&b->ws, P);
+        if (rc) return rc;
+    }
+    b->net = net;
+    b->lopt = *opt;
+    return ART_OK;
+}
+
 int enqueue_uniform(art_batch* b, hipStream_t s)
 {
     b->nev = 0;
@@ -502,6 +620,10 @@ int batch_stats(art_batch* b, int i, art_stats* st, hipStream_t s)
     }
     st->t_trace_ms = tms;
     st->trace_launches = b->nev;
+    for (int k = 0; k < b->n; ++k) {
+        if (i >= 0 && k != i) continue;
+        for (int j = 0; j < 5; ++j) st->learned[j] += (int64_t)h.judge[k][j];
+    }
     if (h.status[RAY_NAN] > 0)
         return fail(ART_ENUMERIC, "%llu rays produced NaN", (unsigned long long)h.status[RAY_NAN]);
     return ART_OK;
@@ -562,7 +684,30 @@ int art_render(const art_spacetime* sp, const art_camera* cam, const art_emissio
     int rc = prepare(b, 1, &j, out, false, s);
     if (rc) return rc;
     b->timing = st != nullptr;
+    b->net = nullptr;
     rc = enqueue_adaptive(b, s);
+    if (rc) return rc;
+    if (st) return batch_stats(b, 0, st, s);
+    return ART_OK;
+}
+
+int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                       const art_refine* rf, const art_transfer* tr, art_cnn* net, const art_learned* opt,
+                       art_image* out, art_stats* st, void* stream)
+{
+    if (!sp || !cam || !em || !rf || !tr || !out || !net || !opt) return fail(ART_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_single_mu);
+    art_batch* b = single_batch();
+    if (!b) return fail(ART_EDEVICE, "no current device");
+    hipStream_t s = (hipStream_t)stream;
+    const art_job j = make_job(sp, cam, em, rf, tr);
+    int rc = prepare(b, 1, &j, out, false, s);
+    if (rc) return rc;
+    rc = setup_learned(b, net, opt);
+    if (rc) return rc;
+    b->timing = st != nullptr;
+    rc = enqueue_learned(b, s);
+    b->net = nullptr;             // the single-image batch keeps no network
     if (rc) return rc;
     if (st) return batch_stats(b, 0, st, s);
     return ART_OK;
@@ -646,7 +791,7 @@ int art_batch_render(art_batch* b, void* stream)
 {
     if (!b) return fail(ART_EINVAL, "NULL batch");
     b->timing = true;
-    return enqueue_adaptive(b, (hipStream_t)stream);
+    return enqueue_render(b, (hipStream_t)stream);
 }
 
 int art_batch_capture(art_batch* b, void* stream)
@@ -658,7 +803,7 @@ int art_batch_capture(art_batch* b, void* stream)
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     b->timing = false;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_adaptive(b, s);
+    int rc = enqueue_render(b, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -675,6 +820,12 @@ int art_batch_launch(art_batch* b, void* stream)
     b->nev = 0;
     HIP_TRY(hipGraphLaunch(b->gexec, (hipStream_t)stream));
     return ART_OK;
+}
+
+int art_batch_set_learned(art_batch* b, art_cnn* net, const art_learned* opt)
+{
+    if (!b) return fail(ART_EINVAL, "NULL batch");
+    return setup_learned(b, net, opt);
 }
 
 int art_batch_stats(art_batch* b, int32_t i, art_stats* st, void* stream)

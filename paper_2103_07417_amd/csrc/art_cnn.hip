@@ -1,0 +1,575 @@
+// art_cnn.hip -- learned refinement proposal: a 4-layer 3x3 convolutional
+// network (channels 3 -> 32 -> 32 -> 32 -> 15) run and trained with BF16 MFMA
+// (v_mfma_f32_32x32x8_bf16) and FP32 accumulation on gfx950.
+//
+// The network sees the level-l vertex grid of an adaptive render (log
+// intensity, minimum radius, equatorial crossings) and predicts, for every
+// level-l vertex, whether the 3 points it owns at level l+1 and the 12 at
+// level l+2 will be ray traced.  The refinement criterion of Sec. 3.2
+// (Eqs. 5-6) stays the judge and the fallback.
+//
+// Layouts.  Activations are NHWC in BF16 with the channel count padded to a
+// multiple of 8 (input 3 -> 8, hidden 32, output gradient 15 -> 16), so a
+// lane's 4 consecutive reduction elements are one 8-byte load.  The GEMM
+// depth is ordered tap-major, k = (dy * 3 + dx) * C_pad + c, so one 8-wide
+// MFMA step reads 8 channels of one shifted position.  Logits are FP32 NCHW
+// ([b][15][H][W]) like labels.  Master weights stay FP32 in the order
+// W[c_out][c_in][3][3] and are packed into BF16 GEMM matrices after each
+// update.
+//
+// Convolution = implicit GEMM D[position][c_out] = sum_k A[position][k]
+// B[k][c_out]: one wave per 32 positions of one row x 32 output channels.
+// Weight gradients are the GEMM dW[c_out][k] = sum_position dZ A, reduced
+// over position chunks in a fixed order (deterministic).  Input gradients are
+// the forward convolution of dZ with the flipped, transposed weights.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "art_cnn.hpp"
+
+namespace art {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);          // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ------------------------------------------------------------------ forward
+// in [B][H][W][cin_pad] bf16; Wm [32][Kp] bf16 (row = output channel, k
+// tap-major); bias [co].  Output by mode (see art_cnn.hpp); bf16 outputs are
+// NHWC with 32 channels, FP32 logits NCHW with co channels.
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ in, int cin_pad, int B, int H,
+                                                  int W, const uint16_t* __restrict__ Wm, int Kp,
+                                                  const float* __restrict__ bias, int co, int mode,
+                                                  void* __restrict__ out, const uint16_t* __restrict__ mask)
+{
+    const int lane = threadIdx.x & 63;
+    const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tiles_x = (W + 31) >> 5;
+    const long long row = wave / tiles_x;                 // b * H + y
+    if (row >= (long long)B * H) return;                  // uniform per wave
+    const int b = (int)(row / H), y = (int)(row - (long long)b * H);
+    const int x0 = (int)(wave - row * tiles_x) << 5;
+    const int m = lane & 31, kb = lane >> 5;
+    const int x = x0 + m;
+    const long long HW = (long long)H * W;
+    const uint16_t* inb = in + (long long)b * HW * cin_pad;
+    floatx16 acc;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+    for (int r = 0; r < 9; ++r) {
+        const int yy = y + r / 3 - 1, xx = x + (r % 3) - 1;
+        const bool inside = x < W && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const long long so = inside ? ((long long)yy * W + xx) * cin_pad : 0;
+        for (int c8 = 0; c8 < cin_pad; c8 += 8) {
+            bf16x4 a = { 0, 0, 0, 0 };
+            if (inside) a = *(const bf16x4*)(inb + so + c8 + 4 * kb);
+            const bf16x4 bw = *(const bf16x4*)(Wm + (long long)m * Kp + r * cin_pad + c8 + 4 * kb);
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bw, acc, 0, 0, 0);
+        }
+    }
+    // D[row][col]: col = lane % 32 (output channel), row = 8 (j/4) + 4 (lane/32) + j%4
+    const int oc = m;
+    if (mode == 1 && oc >= co) return;
+    const float bb = (mode == 2 || oc >= co) ? 0.0f : bias[oc];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int xo = x0 + 8 * (j >> 2) + 4 * kb + (j & 3);
+        if (xo >= W) continue;
+        const long long pos = (long long)y * W + xo;
+        const float v = acc[j] + bb;
+        if (mode == 0) {
+            ((uint16_t*)out)[((long long)b * HW + pos) * 32 + oc] = f2bf(v > 0.0f ? v : 0.0f);
+        } else if (mode == 1) {
+            ((float*)out)[((long long)b * co + oc) * HW + pos] = v;
+        } else {
+            const long long o = ((long long)b * HW + pos) * 32 + oc;
+            ((uint16_t*)out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? v : 0.0f);
+        }
+    }
+}
+
+hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, const uint16_t* Wm, int Kp,
+                        const float* bias, int co, int mode, void* out, const uint16_t* mask,
+                        hipStream_t s)
+{
+    const long long waves = (long long)B * H * ((W + 31) / 32);
+    const long long blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL(k_conv_fwd, dim3((unsigned)blocks), dim3(256), 0, s, in, cin_pad, B, H, W, Wm, Kp, bias,
+                       co, mode, out, mask);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- weight gradients
+// Positions are split into nchunks chunks of clen (a multiple of 8); one wave
+// per (chunk, 32-wide tile of k = c * 9 + tap in master order) writes
+// part[chunk][ktile][32 c_out][32 k].  A operand = dZ (rows = output
+// channel), B operand = im2col(in) (columns = k); reduction over positions.
+__global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in, int ci, int cin_pad, int B,
+                                                 int H, int W, const uint16_t* __restrict__ dZ, int co,
+                                                 int cout_pad, float* __restrict__ part, int nchunks,
+                                                 long long clen)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int K = ci * 9;
+    const int ktiles = (K + 31) >> 5;
+    const int chunk = wave / ktiles;
+    if (chunk >= nchunks) return;
+    const int kt = wave - chunk * ktiles;
+    const int m = lane & 31, kb = lane >> 5;
+    const long long HW = (long long)H * W;
+    const long long P = (long long)B * HW;
+    const long long p0 = (long long)chunk * clen;
+    const long long p1 = p0 + clen < P ? p0 + clen : P;
+    floatx16 acc;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+    const int k = kt * 32 + m;                       // this lane's B column
+    int c = 0, dy = 0, dx = 0;
+    if (k < K) { c = k / 9; const int r = k - 9 * c; dy = r / 3 - 1; dx = (r % 3) - 1; }
+    for (long long ps = p0; ps < p1; ps += 8) {
+        bf16x4 a, bv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const long long p = ps + 4 * kb + t;
+            short av = 0, bw = 0;
+            if (p < p1) {
+                if (m < co) av = (short)dZ[p * cout_pad + m];
+                if (k < K) {
+                    const long long bi = p / HW;
+                    const long long q = p - bi * HW;
+                    const int y = (int)(q / W), x = (int)(q - (long long)y * W);
+                    const int yy = y + dy, xx = x + dx;
+                    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                        bw = (short)in[(bi * HW + (long long)yy * W + xx) * cin_pad + c];
+                }
+            }
+            a[t] = av;
+            bv[t] = bw;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+    }
+    float* Pp = part + ((long long)chunk * ktiles + kt) * 1024;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = 8 * (j >> 2) + 4 * kb + (j & 3);      // output channel
+        Pp[row * 32 + m] = acc[j];
+    }
+}
+
+// dW[co][k] (FP32, k < K) = sum over chunks in order.
+__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, int nchunks, int ktiles,
+                                                   int co, int K, float* __restrict__ dW)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= co * K) return;
+    const int o = idx / K, k = idx - o * K;
+    const int kt = k >> 5, kk = k & 31;
+    float s = 0.0f;
+    for (int ch = 0; ch < nchunks; ++ch) s += part[((long long)ch * ktiles + kt) * 1024 + o * 32 + kk];
+    dW[idx] = s;
+}
+
+// db[o] = sum over positions of dZ[p][o] (one block per output channel).
+__global__ __launch_bounds__(256) void k_db(const uint16_t* __restrict__ dZ, long long P, int cout_pad,
+                                            float* __restrict__ db)
+{
+    __shared__ float sh[256];
+    const int o = blockIdx.x;
+    float s = 0.0f;
+    for (long long p = threadIdx.x; p < P; p += 256) s += bf2f(dZ[p * cout_pad + o]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[o] = sh[0];
+}
+
+namespace {
+void dw_split(long long P, int& nchunks, long long& clen)
+{
+    clen = (P + 127) / 128;
+    clen = (clen + 7) / 8 * 8;
+    if (clen < 64) clen = 64;
+    nchunks = (int)((P + clen - 1) / clen);
+}
+}  // namespace
+
+long long cnn_dw_part_floats(long long positions, int ci)
+{
+    int nchunks;
+    long long clen;
+    dw_split(positions, nchunks, clen);
+    return (long long)nchunks * ((ci * 9 + 31) / 32) * 1024;
+}
+
+hipError_t cnn_conv_dw(const uint16_t* in, int ci, int cin_pad, int B, int H, int W, const uint16_t* dZ, int co,
+                       int cout_pad, float* part, float* dW, float* db, hipStream_t s)
+{
+    const long long P = (long long)B * H * W;
+    int nchunks;
+    long long clen;
+    dw_split(P, nchunks, clen);
+    const int K = ci * 9;
+    const int ktiles = (K + 31) / 32;
+    const long long waves = (long long)nchunks * ktiles;
+    hipLaunchKernelGGL(k_conv_dw, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, in, ci, cin_pad, B, H, W,
+                       dZ, co, cout_pad, part, nchunks, clen);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dw_reduce, dim3((co * K + 255) / 256), dim3(256), 0, s, part, nchunks, ktiles, co,
+                       K, dW);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_db, dim3(co), dim3(256), 0, s, dZ, P, cout_pad, db);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- weights
+// Pack FP32 master weights W[co][ci][3][3] into the forward matrix
+// Wf[32][9 * cin_pad] (row o, k = tap * cin_pad + c) and the input-gradient
+// matrix Wb[32][9 * cout_pad] (row c, k = tap' * cout_pad + o holding the
+// flipped kernel W[o][c][2 - dy'][2 - dx']), both BF16, zero padded.
+__global__ void k_pack(const float* __restrict__ Wt, int ci, int co, int cin_pad, int cout_pad,
+                       uint16_t* __restrict__ Wf, uint16_t* __restrict__ Wb)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Kp = 9 * cin_pad, Kpb = 9 * cout_pad;
+    if (idx < 32 * Kp) {
+        const int o = idx / Kp, k = idx - o * Kp;
+        const int tap = k / cin_pad, c = k - tap * cin_pad;
+        float v = 0.0f;
+        if (o < co && c < ci) v = Wt[(o * ci + c) * 9 + tap];
+        Wf[idx] = f2bf(v);
+    }
+    if (Wb && idx < 32 * Kpb) {
+        const int c = idx / Kpb, k = idx - c * Kpb;
+        const int tap = k / cout_pad, o = k - tap * cout_pad;
+        float v = 0.0f;
+        if (c < ci && o < co) v = Wt[(o * ci + c) * 9 + (8 - tap)];   // (2-dy)*3 + (2-dx) = 8 - tap
+        Wb[idx] = f2bf(v);
+    }
+}
+
+hipError_t cnn_pack(const float* Wt, int ci, int co, int cin_pad, int cout_pad, uint16_t* Wf, uint16_t* Wb,
+                    hipStream_t s)
+{
+    const int n = 32 * 9 * (cin_pad > cout_pad ? cin_pad : cout_pad);
+    hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, Wt, ci, co, cin_pad, cout_pad, Wf, Wb);
+    return hipGetLastError();
+}
+
+// Adam update of FP32 parameters p with gradients g (bias-corrected).
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+hipError_t cnn_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                    float eps, int t, hipStream_t s)
+{
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)t)));
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- loss
+__global__ __launch_bounds__(256) void k_count_valid(const uint8_t* __restrict__ valid, long long n,
+                                                     float* __restrict__ inv_out)
+{
+    __shared__ unsigned long long sh[256];
+    unsigned long long c = 0;
+    for (long long i = threadIdx.x; i < n; i += 256) c += valid[i] ? 1ull : 0ull;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *inv_out = 1.0f / (float)(sh[0] > 0 ? sh[0] : 1ull);
+}
+
+hipError_t cnn_count_valid(const uint8_t* valid, long long n, float* inv_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_valid, dim3(1), dim3(256), 0, s, valid, n, inv_out);
+    return hipGetLastError();
+}
+
+// Positive-weighted BCE on logits over valid points.  Logits, labels and the
+// valid mask are NCHW [b][15][HW]; the loss gradient
+// dZ = (w y (s - 1) + (1 - y) s) valid / n_valid is written NHWC [b][HW][16]
+// (channel 15 = 0); per-block partial losses go to part.
+__global__ __launch_bounds__(256) void k_bce(const float* __restrict__ z, const uint8_t* __restrict__ y,
+                                             const uint8_t* __restrict__ valid, long long HW, long long n16,
+                                             float pos_w, const float* __restrict__ inv_dev,
+                                             uint16_t* __restrict__ dz, float* __restrict__ part)
+{
+    __shared__ float sh[256];
+    const float inv_nvalid = *inv_dev;
+    float s = 0.0f;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n16; i += (long long)gridDim.x * 256) {
+        const int k = (int)(i & 15);
+        const long long P = i >> 4;
+        float g = 0.0f;
+        if (k < kCnnOut) {
+            const long long b = P / HW, p = P - b * HW;
+            const long long idx = (b * kCnnOut + k) * HW + p;
+            if (valid[idx]) {
+                const float zi = z[idx];
+                const float yi = y[idx] ? 1.0f : 0.0f;
+                // log sigmoid(z) and log(1 - sigmoid(z)) without overflow
+                const float l1p = log1pf(expf(-fabsf(zi)));
+                const float lsp = -(fmaxf(-zi, 0.0f) + l1p);
+                const float lsn = -(fmaxf(zi, 0.0f) + l1p);
+                s += -(pos_w * yi * lsp + (1.0f - yi) * lsn);
+                const float sg = 1.0f / (1.0f + expf(-zi));
+                g = (pos_w * yi * (sg - 1.0f) + (1.0f - yi) * sg) * inv_nvalid;
+            }
+        }
+        dz[i] = f2bf(g);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] * inv_nvalid;
+}
+
+hipError_t cnn_bce(const float* z, const uint8_t* y, const uint8_t* valid, long long B, long long HW,
+                   float pos_w, const float* inv_dev, uint16_t* dz, float* part, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bce, dim3(nblocks), dim3(256), 0, s, z, y, valid, HW, B * HW * 16, pos_w, inv_dev, dz,
+                       part);
+    return hipGetLastError();
+}
+
+// FP32 NCHW [b][3][HW] -> BF16 NHWC [b][HW][8] (channels 3..7 zero).
+__global__ void k_input_bf16(const float* __restrict__ x, long long HW, long long n8, uint16_t* __restrict__ y)
+{
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n8; i += (long long)gridDim.x * 256) {
+        const int c = (int)(i & 7);
+        const long long P = i >> 3;
+        float v = 0.0f;
+        if (c < kCnnIn) {
+            const long long b = P / HW, p = P - b * HW;
+            v = x[(b * kCnnIn + c) * HW + p];
+        }
+        y[i] = f2bf(v);
+    }
+}
+
+hipError_t cnn_input_bf16(const float* x, long long B, long long HW, uint16_t* y, hipStream_t s)
+{
+    const long long n8 = B * HW * 8;
+    long long b = (n8 + 255) / 256;
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_input_bf16, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, x, HW, n8, y);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- features and labels
+// Level-l vertex (i, j) of an image stored at final resolution (stride s):
+// c0 = ln(max(I, 0) / N_abs + 1e-4), c1 = min(r_min, 20) / 10,
+// c2 = min(n_cross, 4) / 4.
+__device__ __forceinline__ void feature_at(const double* img, const RayFeat* feat, long long pix, double nabs,
+                                           float& c0, float& c1, float& c2)
+{
+    const double I = img[pix];
+    c0 = (float)::log((I > 0.0 ? I : 0.0) / nabs + 1e-4);
+    c1 = 0.0f;
+    c2 = 0.0f;
+    if (feat) {
+        const RayFeat f = feat[pix];
+        c1 = fminf(f.rmin, 20.0f) * 0.1f;
+        c2 = (float)(f.ncross < 4 ? f.ncross : 4) * 0.25f;
+    }
+}
+
+__global__ void k_cnn_features(const double* __restrict__ img, const RayFeat* __restrict__ feat, long long nx,
+                               int s, int H, int W, double nabs, float* __restrict__ x)
+{
+    const long long HW = (long long)H * W;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= HW) return;
+    const int j = (int)(t / W), i = (int)(t - (long long)j * W);
+    float c0, c1, c2;
+    feature_at(img, feat, (long long)j * s * nx + (long long)i * s, nabs, c0, c1, c2);
+    x[t] = c0;
+    x[HW + t] = c1;
+    x[2 * HW + t] = c2;
+}
+
+hipError_t cnn_features(const double* img, const RayFeat* feat, long long nx, int s, int H, int W, double nabs,
+                        float* x, hipStream_t st)
+{
+    const long long HW = (long long)H * W;
+    hipLaunchKernelGGL(k_cnn_features, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, st, img, feat, nx, s,
+                       H, W, nabs, x);
+    return hipGetLastError();
+}
+
+// Batched form: grid.y = image; N_abs = the image's level-0 normalisation.
+__global__ void k_cnn_features_batch(const ImageDesc* __restrict__ desc, const Counters* __restrict__ ctr,
+                                     int l, int H, int W, float* __restrict__ x)
+{
+    const int b = blockIdx.y;
+    const long long HW = (long long)H * W;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= HW) return;
+    const ImageDesc& D = desc[b];
+    const int s = 1 << (D.levels - l);
+    const int j = (int)(t / W), i = (int)(t - (long long)j * W);
+    float c0, c1, c2;
+    feature_at(D.img, D.feat, (long long)j * s * D.nx + (long long)i * s, ctr->scal[b][2], c0, c1, c2);
+    float* xb = x + (long long)b * kCnnIn * HW;
+    xb[t] = c0;
+    xb[HW + t] = c1;
+    xb[2 * HW + t] = c2;
+}
+
+hipError_t cnn_features_batch(const ImageDesc* desc, const Counters* ctr, int nimg, int l, int H, int W,
+                              float* x, hipStream_t st)
+{
+    const long long HW = (long long)H * W;
+    hipLaunchKernelGGL(k_cnn_features_batch, dim3((unsigned)((HW + 255) / 256), nimg), dim3(256), 0, st, desc, ctr,
+                       l, H, W, x);
+    return hipGetLastError();
+}
+
+// Offsets (dx, dy) of the points a level-l vertex owns: 3 at level l+1 (in
+// level-(l+1) units), then 12 at level l+2 (in level-(l+2) units); together
+// the new points of the vertex's cell (right and lower edges included).
+__constant__ int kOwnDx[kCnnOut] = { 1, 0, 1, 1, 3, 0, 1, 2, 3, 1, 3, 0, 1, 2, 3 };
+__constant__ int kOwnDy[kCnnOut] = { 0, 1, 1, 0, 0, 1, 1, 1, 1, 2, 2, 3, 3, 3, 3 };
+
+__device__ __forceinline__ bool owned_point(int k, int i, int j, int l, int N, int nx0, int ny0, long long nx,
+                                            long long& pix, int& lev)
+{
+    const int up = k < 3 ? 1 : 2;
+    lev = l + up;
+    if (lev > N) return false;
+    const int p = (i << up) + kOwnDx[k], q = (j << up) + kOwnDy[k];
+    const int nxl = (1 << lev) * (nx0 - 1) + 1, nyl = (1 << lev) * (ny0 - 1) + 1;
+    if (p >= nxl || q >= nyl) return false;
+    const int sL = 1 << (N - lev);
+    pix = (long long)q * sL * nx + (long long)p * sL;
+    return true;
+}
+
+// Labels of a plain render's level map: lab[k][j][i] = 1 if the point was
+// traced at its level; val = 1 if the point exists.
+__global__ void k_cnn_labels(const int8_t* __restrict__ level, long long nx, int nx0, int ny0, int N, int l,
+                             uint8_t* __restrict__ lab, uint8_t* __restrict__ val)
+{
+    const int W = (1 << l) * (nx0 - 1) + 1, H = (1 << l) * (ny0 - 1) + 1;
+    const long long HW = (long long)H * W;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= HW) return;
+    const int j = (int)(t / W), i = (int)(t - (long long)j * W);
+    for (int k = 0; k < kCnnOut; ++k) {
+        long long pix = 0;
+        int lev;
+        const bool ok = owned_point(k, i, j, l, N, nx0, ny0, nx, pix, lev);
+        val[k * HW + t] = ok ? 1 : 0;
+        lab[k * HW + t] = ok && level[pix] == lev ? 1 : 0;
+    }
+}
+
+hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N, int l, uint8_t* lab,
+                      uint8_t* val, hipStream_t s)
+{
+    const int W = (1 << l) * (nx0 - 1) + 1, H = (1 << l) * (ny0 - 1) + 1;
+    const long long HW = (long long)H * W;
+    hipLaunchKernelGGL(k_cnn_labels, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, level, nx, nx0, ny0,
+                       N, l, lab, val);
+    return hipGetLastError();
+}
+
+// Proposals: one thread per (vertex, output) of image blockIdx.y.  Level-(l+2)
+// proposals are compacted with a wave ballot into the trace list of pass l+1.
+__global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ logits,
+                                                     const ImageDesc* __restrict__ desc, int l, int H, int W,
+                                                     float z_hi, float z_lo,
+                                                     unsigned long long* __restrict__ list,
+                                                     Counters* __restrict__ ctr)
+{
+    const int b = blockIdx.y;
+    const ImageDesc& D = desc[b];
+    const long long HW = (long long)H * W;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    bool app = false;
+    long long pix = 0;
+    if (t < HW * kCnnOut) {
+        const int k = (int)(t / HW);
+        const long long v = t - (long long)k * HW;
+        const int j = (int)(v / W), i = (int)(v - (long long)j * W);
+        int lev;
+        if (owned_point(k, i, j, l, D.levels, D.nx0, D.ny0, D.nx, pix, lev)) {
+            const float z = logits[(long long)b * kCnnOut * HW + t];
+            if (z > z_hi) {
+                if (k < 3) {
+                    D.level[pix] = kMarkPropose;
+                } else {
+                    D.level[pix] = (int8_t)lev;
+                    app = true;
+                }
+            } else if (z < z_lo) {
+                D.level[pix] = kMarkSuppress;
+            } else {
+                D.level[pix] = kMarkUnset;      // undecided: the criterion decides
+            }
+        }
+    }
+    const unsigned long long mask = __ballot(app);
+    if (mask) {
+        const int lane = __lane_id();
+        const int leader = __ffsll((long long)mask) - 1;
+        const unsigned n = (unsigned)__popcll(mask);
+        unsigned base = 0;
+        if (lane == leader) {
+            base = atomicAdd(&ctr->count[l + 1], n);
+            atomicAdd(&ctr->img_traced[b][l + 1], n);
+            atomicAdd(&ctr->judge[b][4], (unsigned long long)n);
+        }
+        base = __shfl(base, leader);
+        if (app) {
+            const unsigned off = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            list[base + off] = make_item((uint32_t)b, (uint32_t)pix);
+        }
+    }
+}
+
+hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int l, int H, int W, float z_hi,
+                       float z_lo, unsigned long long* list, Counters* ctr, hipStream_t s)
+{
+    const long long n = (long long)H * W * kCnnOut;
+    hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((n + 255) / 256), nimg), dim3(256), 0, s, logits, desc, l, H,
+                       W, z_hi, z_lo, list, ctr);
+    return hipGetLastError();
+}
+
+}  // namespace art

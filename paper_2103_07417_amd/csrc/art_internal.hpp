@@ -20,6 +20,12 @@ struct Counters {
     unsigned long long status[8];
     uint32_t img_traced[kMaxBatch][kMaxLevels + 1];   // per image and level
     double scal[kMaxBatch][4];            // per image: ibar_int, imax0, n_abs, spare
+    // learned proposals, per image: [0] proposed points the criterion would
+    // not trace, [1] criterion-flagged points the network rejected, [2] points
+    // traced by the criterion as fallback after a look-ahead pass, [3]
+    // criterion-flagged points left interpolated (judge-only mode), [4]
+    // look-ahead proposals
+    unsigned long long judge[kMaxBatch][8];
 };
 
 // Per-image description (device memory).
@@ -70,8 +76,14 @@ hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsig
 hipError_t launch_trace(int precision, int model, int nstokes, const TraceJob& J, const LaunchCfg& L,
                         hipStream_t s);
 hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s);
+// mode 0: plain criterion.  mode 1: learned, level l -> l+1 (points marked
+// proposed are traced, points marked suppressed are interpolated, the
+// criterion decides the rest).  mode 2: learned, after a look-ahead pass
+// (points already traced are kept, suppressed points are interpolated, the
+// criterion decides the rest and its points are traced only if `fallback`).
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
-                           Counters* ctr, unsigned long long* list, hipStream_t s);
+                           Counters* ctr, unsigned long long* list, hipStream_t s, int mode = 0,
+                           int fallback = 1);
 hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
                           int nblocks, hipStream_t s);
 int trace_occupancy_blocks(int precision, int model, int nstokes, int threads);

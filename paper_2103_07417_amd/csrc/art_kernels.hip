@@ -13,6 +13,7 @@
 //   k_metrics_*  flux error and normalised MSE (Sec. 4.1, Eqs. 8-9),
 //                deterministic two-pass reduction.
 #include "art_internal.hpp"
+#include "art_cnn.hpp"
 
 namespace art {
 
@@ -427,7 +428,7 @@ __device__ __forceinline__ bool axis_D(const double* I, long long nx, int s, int
 // grid (x: 256-wide strips of p, y: q, z: image).  One thread per point of the
 // level-(l+1) grid; new points are classified by index parity (categories 2-4).
 __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
-                                                  unsigned long long* list)
+                                                  unsigned long long* list, int mode, int fallback)
 {
     const int img = blockIdx.z;
     const ImageDesc D = desc[img];
@@ -439,6 +440,7 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
     const int q = blockIdx.y;
     const bool isnew = p < nxl && q < nyl && ((p & 1) | (q & 1));
     bool trace = false;
+    bool jd[4] = { false, false, false, false };
     long long pix = 0;
     if (isnew) {
         const double* I = D.img;
@@ -481,10 +483,30 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
         const double thrA = (4.0 * m * D.r_abs) * nabs;
         const double crel = 4.0 * D.r_rel;
         const double aD = ::fabs(D2);
-        trace = !avail || !(D2 == D2) || !(Ssum == Ssum) || (aD > thrA && aD > crel * ::fabs(Ssum));
+        const bool crit = !avail || !(D2 == D2) || !(Ssum == Ssum) || (aD > thrA && aD > crel * ::fabs(Ssum));
+        bool keep = false;               // point already traced by a look-ahead pass
+        if (mode == 0) {
+            trace = crit;
+        } else {
+            const int8_t mk = D.level[pix];
+            const bool sup = mk == kMarkSuppress;
+            if (mode == 1) {
+                const bool prop = mk == kMarkPropose;
+                trace = prop || (crit && !sup);
+                jd[0] = prop && !crit;
+                jd[1] = crit && sup;
+            } else {
+                keep = mk == (int8_t)(l + 1);
+                const bool want = crit && !sup && !keep;
+                trace = want && fallback;
+                jd[1] = crit && sup && !keep;
+                jd[2] = want && fallback;
+                jd[3] = want && !fallback;
+            }
+        }
         if (trace) {
             D.level[pix] = (int8_t)(l + 1);
-        } else {
+        } else if (!keep) {
             D.level[pix] = (int8_t)-1;
             const double w = 1.0 / m;
             D.img[pix] = Ssum * w;
@@ -493,6 +515,28 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
                 const double S = nnb == 4 ? (Is[o[0]] + Is[o[1]]) + (Is[o[2]] + Is[o[3]]) : Is[o[0]] + Is[o[1]];
                 D.img[st * D.plane + pix] = S * w;
             }
+            if (D.feat) {
+                // interpolated points inherit the smallest radius and the largest
+                // crossing count of their neighbours
+                RayFeat f = D.feat[o[0]];
+                for (int q2 = 1; q2 < nnb; ++q2) {
+                    const RayFeat g = D.feat[o[q2]];
+                    f.rmin = g.rmin < f.rmin ? g.rmin : f.rmin;
+                    f.ncross = g.ncross > f.ncross ? g.ncross : f.ncross;
+                }
+                f.steps = 0;
+                f.status = RAY_OK;
+                D.feat[pix] = f;
+            }
+        }
+    }
+    if (mode != 0) {
+        // judge counters: one atomic per wave and counter
+        const int lane = __lane_id();
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) {
+            const unsigned long long mk = __ballot(jd[q2]);
+            if (mk && lane == __ffsll((long long)mk) - 1) atomicAdd(&ctr->judge[img][q2], (unsigned long long)__popcll(mk));
         }
     }
     // wavefront-ballot compaction of the points to trace
@@ -512,10 +556,10 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
 }
 
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
-                           Counters* ctr, unsigned long long* list, hipStream_t s)
+                           Counters* ctr, unsigned long long* list, hipStream_t s, int mode, int fallback)
 {
     dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
-    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list);
+    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, mode, fallback);
     return hipGetLastError();
 }
 
