@@ -93,6 +93,40 @@ def batch_workload(precision="mixed", base=129):
     return cfgs
 
 
+def batch_workload_1025(precision="mixed"):
+    """64 images of the thermal_1025 kind (base 129^2, 3 levels -> 1025^2):
+    spin x inclination x frequency in lexicographic order, one level count
+    for the whole batch (the learned form's batch)."""
+    cfgs = []
+    k = 0
+    for a in BATCH_SPINS:
+        for inc in BATCH_INCS:
+            for nu in BATCH_FREQS:
+                cfgs.append(dict(workload("thermal_1025"), name="b1025_%02d" % k, a=a, inc_deg=inc,
+                                 freq_hz=nu, precision=precision))
+                k += 1
+    return cfgs
+
+
+TRAIN_SPINS = (0.3, 0.7, -0.5, 0.99)
+TRAIN_INCS = (30.0, 75.0, 120.0, 150.0)
+
+
+def training_workload(precision="mixed", nx0=129, levels=3):
+    """Training images of the learned proposal: thermal plasma at spins and
+    inclinations disjoint from the benchmark batch, 230 GHz, plasma field
+    phases from seeds 11.., same grid as the images it will refine."""
+    cfgs = []
+    k = 0
+    for a in TRAIN_SPINS:
+        for inc in TRAIN_INCS:
+            cfgs.append(dict(workload("thermal_1025"), name="train_%02d" % k, a=a, inc_deg=inc,
+                             mp=thermal_params(seed=11 + k), precision=precision, nx0=nx0,
+                             ny0=nx0, levels=levels))
+            k += 1
+    return cfgs
+
+
 def reduced(cfg, nx0, levels):
     """Same physics on a smaller vertex grid (parity-test sizes)."""
     c = dict(cfg)

@@ -1,19 +1,25 @@
 """Benchmark: adaptive black-hole image rendering on one MI355X.
 
-One step = one full adaptive render (Sec. 3.2) of the thermal-plasma workload:
-Kerr a = 0.94, inclination 163 deg, polarised I,Q,U,V transfer at 230 GHz,
-base 129^2 vertices refined 3 levels to 1025^2 with R_rel = 0.01 and
-R_abs = 1e-3 x (max of the level-0 image).  Every step runs the whole hot path:
-base-grid tracing, the level-0 reduction, and per level the estimator /
-interpolation / ballot compaction kernel and the persistent tracing kernel.
-Inputs (camera, plasma parameters) are resident before the timed region.
+Workload (thermal_1025): Kerr a = 0.94, inclination 163 deg, polarised
+I,Q,U,V transfer at 230 GHz through a power-law thermal plasma, base 129^2
+vertices refined 3 levels to 1025^2 with R_rel = 0.01 and R_abs = 1e-3 x
+(max of the level-0 image), FP64 geodesics with FP32 transfer.
 
-value = traced rays per second of wall time; effective pixels/s = 1025^2 /
-render time.  The image is checked against the uniform (every-pixel) render:
-normalised MSE <= 1e-3 (Sec. 4.1, Eq. 9).  The roofline entry reports the
-tracing kernel's algorithmic FP64 throughput (hand-counted FLOPs per geodesic
-step and per emitting step) against the FP64 vector peak; the CPU baseline is
-the FP64 oracle timed on a random sample of the rays the render traced.
+One step = one learned + batched render: 64 images of this kind (spin x
+inclination x frequency) rendered together, the proposal network looking
+ahead one level and the refinement criterion of Sec. 3.2 judging and
+tracing what it missed, the whole level loop one hipGraph replay.  The
+network is trained first (untimed) on plain renders of 16 other images.
+Compared on the same GPU: the plain adaptive render of one image at a time
+(the paper's method), the plain method batched, and the uniform render.
+Every form's images are checked against the uniform render: normalised
+MSE <= 1e-3 (Sec. 4.1, Eq. 9).
+
+value = traced rays per second of wall time of the learned + batched form;
+effective pixels/s = 64 x 1025^2 / batch time.  The roofline entry reports
+the tracing kernel's algorithmic throughput (hand-counted FLOPs per geodesic
+step and per emitting step) against the vector peak of its precision; the
+CPU baseline is the FP64 oracle's complete adaptive render.
 """
 import argparse
 import json
@@ -77,65 +83,152 @@ def cpu_baseline(cfg, budget_s):
                        % (n, rays // n, cores, dt))
 
 
-def batched(art, torch, art_inputs, args):
-    """64 images (spin x inclination x frequency, 1-4 levels each) in one batch:
-    one work queue per level, the level loop captured once in a hipGraph and
-    replayed; launch shape from the autotuner."""
-    from paper_2103_07417_amd import autotune
-    cfgs = art_inputs.batch_workload(precision="mixed")
-    B = art.Batch(cfgs)
-    npix = sum(im.shape[1] * im.shape[2] for im in B.images)
-    s = torch.cuda.Stream()
-    tune = None
-    if not args.no_autotune:
-        tune = autotune.autotune(B, s, reps=1, use_cache=False, log=log)
-        log("autotune: %s" % {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "ms")})
-    B.render(s)
-    s.synchronize()
-    eager = B.stats()
+def mse_check(art, cfgs, images, truths):
+    """Normalised MSE and flux error of every image against its uniform render."""
+    out = []
+    for k, c in enumerate(cfgs):
+        fe, mse = art.metrics(truths[k], images[k][0])
+        out.append(dict(name=c["name"], mse=mse, flux_error=fe))
+    return dict(mse_max=max(o["mse"] for o in out), mse_mean=sum(o["mse"] for o in out) / len(out),
+                flux_error_max=max(o["flux_error"] for o in out),
+                mse_ok=all(o["mse"] <= 1e-3 for o in out))
+
+
+def time_graph(B, torch, s, reps):
     B.capture(s)
     B.launch(s)
     s.synchronize()
-    st = B.stats()
-    assert st["rays"] == eager["rays"]
-    reps = max(2, args.steps // 2)
     t0 = time.perf_counter()
     for _ in range(reps):
         B.launch(s)
     s.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    # accuracy: one image per refinement depth against its uniform render
-    mses = {}
-    for k in (20, 21, 22, 23):      # a=0.5, i=60 deg, all four frequencies, 1..4 levels
-        truth, _, _ = art.render_uniform(cfgs[k])
-        fe, mse = art.metrics(truth[0], B.images[k][0])
-        mses[cfgs[k]["name"]] = dict(levels=cfgs[k]["levels"], mse=mse, flux_error=fe,
-                                     npix=B.images[k].shape[1] * B.images[k].shape[2])
-    B.close()
-    log("batched: %.1f ms per 64-image batch, %d rays, %d px" % (dt * 1e3, st["rays"], npix))
-    return {
-        "workload": "64 thermal-plasma images: a in {0,0.5,0.94,-0.94} x i in {17,60,90,163} deg x "
-                    "nu in {86,230,345,690} GHz, base 129^2, 1+(k mod 4) levels (257^2..2049^2), "
-                    "IQUV, FP64 geodesic / FP32 transfer, one hipGraph replay per batch",
-        "ms_per_batch": dt * 1e3, "rays": st["rays"], "effective_px": npix,
-        "rays_per_s": st["rays"] / dt, "effective_px_per_s": npix / dt,
-        "interp_frac": st["interp_frac"], "mse_check": mses,
-        "mse_ok": all(v["mse"] <= 1e-3 for v in mses.values()),
-        "launch": tune and {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "ms",
-                                                   "default", "default_ms")},
+    return (time.perf_counter() - t0) / reps
+
+
+def batch_forms(art, torch, art_inputs, args):
+    """Learned + batched and plain batched renders of the 64-image batch."""
+    from paper_2103_07417_amd import autotune, learn
+    s = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    net, tinfo = learn.train(art_inputs.training_workload(precision=args.precision),
+                             steps=args.train_steps, lr=3e-3, seed=4, stream=s)
+    s.synchronize()
+    t_train = time.perf_counter() - t0
+    log("trained proposal network in %.1f s: loss %s -> %s" % (t_train, tinfo["loss_first"],
+                                                              tinfo["loss_last"]))
+    cfgs = art_inputs.batch_workload_1025(precision=args.precision)
+    B = art.Batch(cfgs, feat=True)
+    npix = sum(im.shape[1] * im.shape[2] for im in B.images)
+    tune = None
+    if not args.no_autotune:
+        tune = autotune.autotune(B, s, reps=1, use_cache=False, log=log)
+        log("autotune: %s" % {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "ms")})
+    # uniform renders of every image of the batch: the truth for the MSE check
+    truths = []
+    for c in cfgs:
+        t, _, _ = art.render_uniform(c, stream=s)
+        truths.append(t[0].clone())
+    s.synchronize()
+    forms = {}
+
+    def measure(name, learned_opts):
+        if learned_opts is None:
+            B.set_learned(None)
+        else:
+            B.set_learned(net, **learned_opts)
+        for _ in range(args.warmup):
+            B.render(s)
+        s.synchronize()
+        dt = time_graph(B, torch, s, args.steps)
+        st = B.stats(stream=s)
+        f = dict(ms_per_batch=dt * 1e3, rays=st["rays"], passes=st["trace_launches"],
+                 rays_per_s=st["rays"] / dt, effective_px_per_s=npix / dt,
+                 interp_frac=st["interp_frac"], check=mse_check(art, cfgs, B.images, truths))
+        if learned_opts is not None:
+            f["judge"] = st["learned"]
+            f["options"] = dict(learned_opts)
+        forms[name] = f
+        log("%s: %.1f ms/batch, %d rays, %d passes, mse max %.2e" % (
+            name, dt * 1e3, st["rays"], st["trace_launches"], f["check"]["mse_max"]))
+        return f
+
+    measure("plain_batched", None)
+    zp, zs = args.z_propose, args.z_suppress
+    inf = float("inf")
+    learned_forms = {
+        # look-ahead proposals, the criterion traces what they missed
+        "learned_batched_fallback": dict(z_propose=zp, z_suppress=-inf, fallback=True),
+        # look-ahead proposals, the criterion only counts what they missed
+        "learned_batched_judge": dict(z_propose=zp, z_suppress=-inf, fallback=False),
+        # no look-ahead; flagged points the network rejects stay interpolated
+        "learned_batched_suppress": dict(z_propose=inf, z_suppress=zs, fallback=True),
     }
+    for k, o in learned_forms.items():
+        measure(k, o)
+    # headline: the learned form with the highest effective pixels/s whose 64
+    # images all pass the MSE bar
+    ok = [k for k in learned_forms if forms[k]["check"]["mse_ok"]]
+    head = max(ok, key=lambda k: forms[k]["effective_px_per_s"]) if ok else "learned_batched_fallback"
+    # eager renders of the headline form with HIP events around each tracing
+    # launch (on the render stream): the roofline figures
+    B.set_learned(net, **forms[head]["options"])
+    tr_ms, launches, fl = 0.0, 0, 0
+    for _ in range(2):
+        B.render(s)
+        st = B.stats(stream=s)
+        tr_ms += st["t_trace_ms"]
+        launches += st["trace_launches"]
+        fl += flops(st, cfgs[0])
+    training = dict(seconds=t_train, steps=args.train_steps, images=16, pos_weight=tinfo["pos_weight"],
+                    loss_first={str(k): v for k, v in tinfo["loss_first"].items()},
+                    loss_last={str(k): v for k, v in tinfo["loss_last"].items()})
+    B.close()
+    net.close()
+    roof_src = dict(tr_ms=tr_ms, launches=launches, flops=fl)
+    return forms, head, training, npix, tune, roof_src
+
+
+def plain_single(art, torch, cfg, args):
+    """The paper's method, one image at a time, and the uniform render."""
+    truth, _, ust = art.render_uniform(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    truth, _, ust = art.render_uniform(cfg)
+    torch.cuda.synchronize()
+    t_uniform = time.perf_counter() - t0
+    bufs = art.alloc(cfg)
+    for _ in range(args.warmup):
+        art.render(cfg, out=bufs)
+    torch.cuda.synchronize()
+    rays = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        img, lev, _, st = art.render(cfg, out=bufs)
+        rays += st["rays"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fe, mse = art.metrics(truth[0], img[0])
+    nx, ny = img.shape[2], img.shape[1]
+    plain = dict(ms_per_image=dt * 1e3, rays=rays // args.steps, passes=st["trace_launches"],
+                 rays_per_s=rays / args.steps / dt, effective_px_per_s=nx * ny / dt,
+                 interp_frac=st["interp_frac"], mse=mse, flux_error=fe)
+    uniform = dict(ms=t_uniform * 1e3, rays=ust["rays"], rays_per_s=ust["rays"] / t_uniform,
+                   effective_px_per_s=nx * ny / t_uniform)
+    return plain, uniform
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--z-propose", type=float, default=0.0)
+    ap.add_argument("--z-suppress", type=float, default=-1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -149,65 +242,46 @@ def main():
     cfg = dict(art_inputs.workload("thermal_1025"), precision=args.precision)
     nx, ny = art.image_size(cfg)
     log("workload thermal_1025: %dx%d, precision %s" % (nx, ny, args.precision))
-
-    # truth image (untimed): one ray per pixel
-    truth, _, ust = art.render_uniform(cfg)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    truth, _, ust = art.render_uniform(cfg)
-    torch.cuda.synchronize()
-    t_uniform = time.perf_counter() - t0
-    log("uniform render: %d rays in %.1f ms" % (ust["rays"], t_uniform * 1e3))
-
-    bufs = art.alloc(cfg)
-    for _ in range(args.warmup):
-        art.render(cfg, out=bufs)
-    torch.cuda.synchronize()
-    log("warmup done")
-    tr_ms, launches, fl, rays = 0.0, 0, 0, 0
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        img, lev, _, st = art.render(cfg, out=bufs)
-        tr_ms += st["t_trace_ms"]
-        launches += st["trace_launches"]
-        fl += flops(st, cfg)
-        rays += st["rays"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    log("timed %d renders in %.1f ms" % (args.steps, dt * 1e3))
-    ms = dt / args.steps * 1e3
-    fe, mse = art.metrics(truth[0], img[0])
-    rays_per_render = rays // args.steps
-    value = rays_per_render / (ms * 1e-3)
-    px_s = nx * ny / (ms * 1e-3)
-    achieved = (fl / launches) / (tr_ms / launches * 1e-3)
+    plain, uniform = plain_single(art, torch, cfg, args)
+    log("plain: %.1f ms/image, %d rays, mse %.2e; uniform %.1f ms" % (
+        plain["ms_per_image"], plain["rays"], plain["mse"], uniform["ms"]))
+    forms, head, training, npix, tune, rs = batch_forms(art, torch, art_inputs, args)
+    L = forms[head]
+    achieved = (rs["flops"] / rs["launches"]) / (rs["tr_ms"] / rs["launches"] * 1e-3)
     peak = PEAK_FP64_VECTOR
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                 frac=achieved / peak, traffic=None,
-                kernel="k_trace (FP64 geodesic + %s transfer)" % args.precision,
-                avg_launch_ms=tr_ms / launches, flops_per_render=fl // args.steps,
-                trace_share_of_render=tr_ms / (dt * 1e3))
+                kernel="k_trace (FP64 geodesic + %s transfer), %s render" % (args.precision, head),
+                avg_launch_ms=rs["tr_ms"] / rs["launches"],
+                flops_per_launch=rs["flops"] / rs["launches"])
     out = {
-        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "metric": METRIC, "value": L["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": L["ms_per_batch"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64-geodesic/f32-transfer",
         "data": "synthetic",
-        "config": {"workload": "thermal_1025: Kerr a=0.94, i=163 deg, IQUV at 230 GHz, "
+        "config": {"workload": "learned+batched thermal_1025: 64 images (a in {0,0.5,0.94,-0.94} x "
+                               "i in {17,60,90,163} deg x nu in {86,230,345,690} GHz), IQUV, "
                                "power-law thermal plasma, base 129^2 -> 3 levels -> 1025^2, "
-                               "R_rel=0.01, R_abs=1e-3 max I0",
-                   "base": 129, "final": nx, "levels": 3, "precision": args.precision},
-        "effective_px_per_s": px_s,
-        "rays_per_render": rays_per_render,
-        "interp_frac": st["interp_frac"],
-        "image_mse_vs_uniform": mse, "flux_error_vs_uniform": fe, "mse_ok": mse <= 1e-3,
-        "uniform": {"ms": t_uniform * 1e3, "rays": ust["rays"],
-                    "rays_per_s": ust["rays"] / t_uniform,
-                    "speedup_adaptive_vs_uniform": t_uniform * 1e3 / ms},
+                               "R_rel=0.01, R_abs=1e-3 max I0, one hipGraph replay per batch",
+                   "images": 64, "base": 129, "final": nx, "levels": 3, "precision": args.precision,
+                   "form": head},
+        "effective_px_per_s": L["effective_px_per_s"],
+        "image_mse_vs_uniform_max": L["check"]["mse_max"], "mse_ok": L["check"]["mse_ok"],
+        "forms": forms,
+        "plain": plain,
+        "uniform": uniform,
+        "training": training,
+        "learned_batched_vs_plain": {
+            "effective_px_per_s": L["effective_px_per_s"] / plain["effective_px_per_s"],
+            "rays_per_image": L["rays"] / 64.0 / plain["rays"]},
+        "learned_batched_vs_plain_batched": {
+            "effective_px_per_s": L["effective_px_per_s"] / forms["plain_batched"]["effective_px_per_s"],
+            "rays": L["rays"] / forms["plain_batched"]["rays"]},
+        "launch": tune and {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "ms",
+                                                   "default", "default_ms")},
         "roofline": roof,
     }
-    if not args.no_batch:
-        out["batched"] = batched(art, torch, art_inputs, args)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

@@ -98,7 +98,9 @@ struct art_batch {
     double* dTh = nullptr;         // gridded model: theta table of the batch's snapshot
     double hTh[kMaxThetaCells] = {};
     hipEvent_t ev[2 * kMaxEv] = {};
-    int nev = 0;
+    int nev = 0;                   // timed tracing launches of the last eager render
+    int ntrace = 0;                // tracing launches per render (eager or captured)
+    int graph_ntrace = 0;          // tracing launches in the captured graph
     bool timing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -429,6 +431,7 @@ TraceJob base_job(const art_batch* b, int level)
 
 hipError_t ev_begin(art_batch* b, hipStream_t s)
 {
+    b->ntrace++;
     if (!b->timing || b->nev >= kMaxEv) return hipSuccess;
     return hipEventRecord(b->ev[2 * b->nev], s);
 }
@@ -444,6 +447,7 @@ hipError_t ev_end(art_batch* b, hipStream_t s)
 int enqueue_adaptive(art_batch* b, hipStream_t s)
 {
     b->nev = 0;
+    b->ntrace = 0;
     HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
     HIP_TRY(launch_base_list(b->dD, b->n, b->max_base, b->list, b->ctr, 0, s));
     TraceJob J = base_job(b, 0);
@@ -475,6 +479,7 @@ int enqueue_adaptive(art_batch* b, hipStream_t s)
 int enqueue_learned(art_batch* b, hipStream_t s)
 {
     b->nev = 0;
+    b->ntrace = 0;
     const ImageDesc& D0 = b->hD[0];
     const int N = D0.levels;
     HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
@@ -565,6 +570,7 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
 int enqueue_uniform(art_batch* b, hipStream_t s)
 {
     b->nev = 0;
+    b->ntrace = 0;
     const ImageDesc& D = b->hD[0];
     HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
     HIP_TRY(launch_fill_u32(&b->ctr->count[0], 1, (uint32_t)D.plane, s));
@@ -619,7 +625,7 @@ int batch_stats(art_batch* b, int i, art_stats* st, hipStream_t s)
         tms += ms;
     }
     st->t_trace_ms = tms;
-    st->trace_launches = b->nev;
+    st->trace_launches = b->ntrace;
     for (int k = 0; k < b->n; ++k) {
         if (i >= 0 && k != i) continue;
         for (int j = 0; j < 5; ++j) st->learned[j] += (int64_t)h.judge[k][j];
@@ -810,6 +816,7 @@ int art_batch_capture(art_batch* b, void* stream)
     if (e != hipSuccess) return fail(ART_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
     b->graph = g;
     HIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    b->graph_ntrace = b->ntrace;
     return ART_OK;
 }
 
@@ -818,6 +825,7 @@ int art_batch_launch(art_batch* b, void* stream)
     if (!b) return fail(ART_EINVAL, "NULL batch");
     if (!b->gexec) return fail(ART_EINVAL, "batch has no captured graph (call art_batch_capture)");
     b->nev = 0;
+    b->ntrace = b->graph_ntrace;
     HIP_TRY(hipGraphLaunch(b->gexec, (hipStream_t)stream));
     return ART_OK;
 }

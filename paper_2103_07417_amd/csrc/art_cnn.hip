@@ -115,8 +115,8 @@ hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, co
 // channel), B operand = im2col(in) (columns = k); reduction over positions.
 __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in, int ci, int cin_pad, int B,
                                                  int H, int W, const uint16_t* __restrict__ dZ, int co,
-                                                 int cout_pad, float* __restrict__ part, int nchunks,
-                                                 long long clen)
+                                                 int cout_pad, float* __restrict__ part, float* __restrict__ dbpart,
+                                                 int nchunks, long long clen)
 {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -136,6 +136,7 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
     const int k = kt * 32 + m;                       // this lane's B column
     int c = 0, dy = 0, dx = 0;
     if (k < K) { c = k / 9; const int r = k - 9 * c; dy = r / 3 - 1; dx = (r % 3) - 1; }
+    float sdb = 0.0f;                                // bias gradient partial (k tile 0 only)
     for (long long ps = p0; ps < p1; ps += 8) {
         bf16x4 a, bv;
 #pragma unroll
@@ -143,7 +144,10 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
             const long long p = ps + 4 * kb + t;
             short av = 0, bw = 0;
             if (p < p1) {
-                if (m < co) av = (short)dZ[p * cout_pad + m];
+                if (m < co) {
+                    av = (short)dZ[p * cout_pad + m];
+                    sdb += bf2f((uint16_t)av);
+                }
                 if (k < K) {
                     const long long bi = p / HW;
                     const long long q = p - bi * HW;
@@ -164,36 +168,31 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
         const int row = 8 * (j >> 2) + 4 * kb + (j & 3);      // output channel
         Pp[row * 32 + m] = acc[j];
     }
+    if (kt == 0) {
+        // lanes m and m + 32 hold the two halves of channel m's positions
+        const float other = __shfl_down(sdb, 32);
+        if (kb == 0) dbpart[(long long)chunk * 32 + m] = sdb + other;
+    }
 }
 
-// dW[co][k] (FP32, k < K) = sum over chunks in order.
-__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, int nchunks, int ktiles,
-                                                   int co, int K, float* __restrict__ dW)
+// dW[co][k] (FP32, k < K) and db[co] = sums over chunks in order.
+__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, const float* __restrict__ dbpart,
+                                                   int nchunks, int ktiles, int co, int K, float* __restrict__ dW,
+                                                   float* __restrict__ db)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= co * K) return;
-    const int o = idx / K, k = idx - o * K;
-    const int kt = k >> 5, kk = k & 31;
-    float s = 0.0f;
-    for (int ch = 0; ch < nchunks; ++ch) s += part[((long long)ch * ktiles + kt) * 1024 + o * 32 + kk];
-    dW[idx] = s;
-}
-
-// db[o] = sum over positions of dZ[p][o] (one block per output channel).
-__global__ __launch_bounds__(256) void k_db(const uint16_t* __restrict__ dZ, long long P, int cout_pad,
-                                            float* __restrict__ db)
-{
-    __shared__ float sh[256];
-    const int o = blockIdx.x;
-    float s = 0.0f;
-    for (long long p = threadIdx.x; p < P; p += 256) s += bf2f(dZ[p * cout_pad + o]);
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
+    if (idx < co * K) {
+        const int o = idx / K, k = idx - o * K;
+        const int kt = k >> 5, kk = k & 31;
+        float s = 0.0f;
+        for (int ch = 0; ch < nchunks; ++ch) s += part[((long long)ch * ktiles + kt) * 1024 + o * 32 + kk];
+        dW[idx] = s;
+    } else if (idx < co * K + co) {
+        const int o = idx - co * K;
+        float s = 0.0f;
+        for (int ch = 0; ch < nchunks; ++ch) s += dbpart[(long long)ch * 32 + o];
+        db[o] = s;
     }
-    if (threadIdx.x == 0) db[o] = sh[0];
 }
 
 namespace {
@@ -211,7 +210,7 @@ long long cnn_dw_part_floats(long long positions, int ci)
     int nchunks;
     long long clen;
     dw_split(positions, nchunks, clen);
-    return (long long)nchunks * ((ci * 9 + 31) / 32) * 1024;
+    return (long long)nchunks * ((ci * 9 + 31) / 32) * 1024 + (long long)nchunks * 32;
 }
 
 hipError_t cnn_conv_dw(const uint16_t* in, int ci, int cin_pad, int B, int H, int W, const uint16_t* dZ, int co,
@@ -224,15 +223,13 @@ hipError_t cnn_conv_dw(const uint16_t* in, int ci, int cin_pad, int B, int H, in
     const int K = ci * 9;
     const int ktiles = (K + 31) / 32;
     const long long waves = (long long)nchunks * ktiles;
+    float* dbpart = part + (long long)nchunks * ktiles * 1024;
     hipLaunchKernelGGL(k_conv_dw, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, in, ci, cin_pad, B, H, W,
-                       dZ, co, cout_pad, part, nchunks, clen);
+                       dZ, co, cout_pad, part, dbpart, nchunks, clen);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dw_reduce, dim3((co * K + 255) / 256), dim3(256), 0, s, part, nchunks, ktiles, co,
-                       K, dW);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_db, dim3(co), dim3(256), 0, s, dZ, P, cout_pad, db);
+    hipLaunchKernelGGL(k_dw_reduce, dim3((co * K + co + 255) / 256), dim3(256), 0, s, part, dbpart, nchunks,
+                       ktiles, co, K, dW, db);
     return hipGetLastError();
 }
 
@@ -295,12 +292,30 @@ hipError_t cnn_adam(float* p, const float* g, float* m, float* v, int n, float l
 }
 
 // ------------------------------------------------------------- loss
-__global__ __launch_bounds__(256) void k_count_valid(const uint8_t* __restrict__ valid, long long n,
+// Number of valid outputs: per-block partial counts, then one block sums them
+// in a fixed order and writes 1 / max(count, 1).
+__global__ __launch_bounds__(256) void k_count_partial(const uint8_t* __restrict__ valid, long long n,
+                                                       unsigned long long* __restrict__ part)
+{
+    __shared__ unsigned long long sh[256];
+    unsigned long long c = 0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        c += valid[i] ? 1ull : 0ull;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_count_final(const unsigned long long* __restrict__ part, int nb,
                                                      float* __restrict__ inv_out)
 {
     __shared__ unsigned long long sh[256];
     unsigned long long c = 0;
-    for (long long i = threadIdx.x; i < n; i += 256) c += valid[i] ? 1ull : 0ull;
+    for (int i = threadIdx.x; i < nb; i += 256) c += part[i];
     sh[threadIdx.x] = c;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -310,9 +325,13 @@ __global__ __launch_bounds__(256) void k_count_valid(const uint8_t* __restrict__
     if (threadIdx.x == 0) *inv_out = 1.0f / (float)(sh[0] > 0 ? sh[0] : 1ull);
 }
 
-hipError_t cnn_count_valid(const uint8_t* valid, long long n, float* inv_out, hipStream_t s)
+hipError_t cnn_count_valid(const uint8_t* valid, long long n, unsigned long long* part, int nb, float* inv_out,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_count_valid, dim3(1), dim3(256), 0, s, valid, n, inv_out);
+    hipLaunchKernelGGL(k_count_partial, dim3(nb), dim3(256), 0, s, valid, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_final, dim3(1), dim3(256), 0, s, part, nb, inv_out);
     return hipGetLastError();
 }
 

@@ -40,7 +40,9 @@ hipError_t cnn_adam(float* p, const float* g, float* m, float* v, int n, float l
 // Loss over B images: logits/labels/valid NCHW [B][15][HW]; dz NHWC [B][HW][16].
 hipError_t cnn_bce(const float* z, const uint8_t* y, const uint8_t* valid, long long B, long long HW,
                    float pos_w, const float* inv_dev, uint16_t* dz, float* part, int nblocks, hipStream_t s);
-hipError_t cnn_count_valid(const uint8_t* valid, long long n, float* inv_out, hipStream_t s);
+// 1 / (number of nonzero valid[i], at least 1) into *inv_out; part holds nb counts.
+hipError_t cnn_count_valid(const uint8_t* valid, long long n, unsigned long long* part, int nb, float* inv_out,
+                           hipStream_t s);
 // FP32 NCHW [B][3][HW] -> BF16 NHWC [B][HW][8].
 hipError_t cnn_input_bf16(const float* x, long long B, long long HW, uint16_t* y, hipStream_t s);
 
@@ -94,6 +96,7 @@ struct CnnNet {
     float* part = nullptr;     // weight-gradient partials
     long long part_cap = 0;
     float* lossp = nullptr;    // loss partials [1024] + 1/n_valid
+    unsigned long long* cntp = nullptr;   // valid-count partials [1024]
 };
 
 // Grow a workspace to P positions (synchronises the device when it grows).

@@ -56,8 +56,8 @@ void free_ptr(void* q)
 
 void free_net(CnnNet& n)
 {
-    void* ptrs[] = { n.p, n.g, n.m, n.v, n.dz0, n.dz1, n.part, n.lossp, n.Wf[0], n.Wf[1], n.Wf[2], n.Wf[3],
-                     n.Wb[0], n.Wb[1], n.Wb[2], n.Wb[3] };
+    void* ptrs[] = { n.p, n.g, n.m, n.v, n.dz0, n.dz1, n.part, n.lossp, n.cntp, n.Wf[0], n.Wf[1], n.Wf[2],
+                     n.Wf[3], n.Wb[0], n.Wb[1], n.Wb[2], n.Wb[3] };
     for (void* q : ptrs) free_ptr(q);
     cnn_work_free(&n.ws);
 }
@@ -163,9 +163,11 @@ int grads(CnnNet& n, const float* x, const uint8_t* lab, const uint8_t* val, int
     }
     if (!n.lossp && hipMalloc(&n.lossp, sizeof(float) * (kLossBlocks + 1)) != hipSuccess)
         return api_fail(ART_ENOMEM, "hipMalloc(loss partials) failed");
+    if (!n.cntp && hipMalloc(&n.cntp, sizeof(unsigned long long) * kLossBlocks) != hipSuccess)
+        return api_fail(ART_ENOMEM, "hipMalloc(count partials) failed");
     CNN_TRY(cnn_net_forward(&n, &n.ws, x, B, H, W, n.ws.logits, s));
     // the loss is the mean over valid outputs of the whole batch
-    CNN_TRY(cnn_count_valid(val, (long long)B * HW * kCnnOut, n.lossp + kLossBlocks, s));
+    CNN_TRY(cnn_count_valid(val, (long long)B * HW * kCnnOut, n.cntp, kLossBlocks, n.lossp + kLossBlocks, s));
     CNN_TRY(cnn_bce(n.ws.logits, lab, val, B, HW, pos_w, n.lossp + kLossBlocks, n.dz0, n.lossp, kLossBlocks, s));
     uint16_t* dz = n.dz0;
     uint16_t* dzn = n.dz1;
