@@ -43,6 +43,7 @@ FLOP_TRANSFER_I = 10
 FLOP_PLASMA_TOY = 96
 PEAK_FP64_VECTOR = 78.6e12   # MI355X published FP64 vector peak
 PEAK_FP32_VECTOR = 157.3e12
+COPY_BYTES = 256 << 20       # read and written once by the calibration copy
 
 
 def log(*a):
@@ -122,7 +123,7 @@ def batch_forms(art, torch, art_inputs, args):
     tune = None
     if not args.no_autotune:
         tune = autotune.autotune(B, s, reps=1, use_cache=False, log=log)
-        log("autotune: %s" % {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "ms")})
+        log("autotune: %s" % {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "groups", "ms")})
     # uniform renders of every image of the batch: the truth for the MSE check
     truths = []
     for c in cfgs:
@@ -278,10 +279,18 @@ def main():
         "learned_batched_vs_plain_batched": {
             "effective_px_per_s": L["effective_px_per_s"] / forms["plain_batched"]["effective_px_per_s"],
             "rays": L["rays"] / forms["plain_batched"]["rays"]},
-        "launch": tune and {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "ms",
-                                                   "default", "default_ms")},
+        "launch": tune and {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "groups",
+                                                   "ms", "default", "default_ms")},
         "roofline": roof,
     }
+    # a plain device copy of known size: reference reading for the HBM byte
+    # counters (FETCH_SIZE / WRITE_SIZE) of a profiled run
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = COPY_BYTES
+    del src, dst
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

@@ -69,6 +69,10 @@ extern "C" {
 /* transfer precision */
 #define ART_PREC_FP64  0  /* geodesic, coefficients and transfer in FP64 */
 #define ART_PREC_MIXED 1  /* FP64 geodesic, FP32 plasma/coefficients/transfer */
+#define ART_PREC_MIXED_GEO 2  /* as MIXED, and the geodesic right-hand sides in FP32 for
+                                 every wave whose rays are all outside the sensitive zones
+                                 (art_transfer.fp64_radius / fp64_ktheta); the state,
+                                 the RK4 sums and the step rule stay FP64 */
 
 typedef struct {
     double a_spin;                 /* dimensionless spin, |a| < 1 */
@@ -125,6 +129,10 @@ typedef struct {
     int32_t max_steps;             /* geodesic step cap (> 0) */
     int32_t pad;
     double eps;                    /* step-rule accuracy, 0 < eps <= 0.5 */
+    double fp64_radius;            /* ART_PREC_MIXED_GEO: FP64 steps where r < this [M]
+                                      (photon shell, horizon); <= 0 selects 6 M */
+    double fp64_ktheta;            /* ART_PREC_MIXED_GEO: FP64 steps where |k_theta| < this
+                                      (theta turning points); < 0 selects 0.05 */
 } art_transfer;
 
 typedef struct {
@@ -152,7 +160,8 @@ typedef struct {
     double imax0;                  /* maximum of the level-0 image */
     double n_abs;                  /* normalisation used for eps_abs */
     int64_t steps_emit;            /* steps that evaluated emission and transfer */
-    double t_trace_ms;             /* summed duration of the tracing kernels (HIP events) */
+    double t_trace_ms;             /* summed duration of the tracing kernels (HIP events;
+                                      the launches of concurrent groups overlap) */
     int32_t trace_launches;        /* number of tracing-kernel launches */
     int32_t levels;
     int64_t learned[5];            /* learned renders (else 0): [0] proposed points the
@@ -161,6 +170,8 @@ typedef struct {
                                       criterion traced as fallback after a look-ahead
                                       pass, [3] criterion-flagged points left
                                       interpolated (fallback off), [4] look-ahead rays */
+    double t_render_ms;            /* wall time of the whole render on the caller's stream
+                                      (HIP events; eager renders, else 0) */
 } art_stats;
 
 /* Final grid size n = 2^N (n0 - 1) + 1 per axis (Sec. 3.2) and the image size
@@ -242,14 +253,21 @@ typedef struct {
     int32_t trace_blocks;
     int32_t trace_threads;
     int32_t refill;
-    int32_t pad;
+    int32_t groups;                /* batches: images are split into this many groups of
+                                      consecutive images, each running its level loop on its
+                                      own stream (forked from and joined back into the
+                                      caller's stream) so that one group's long-ray tail
+                                      overlaps the others' work; 0 = two groups from 16
+                                      images on, else one; at most 8 */
 } art_launch;
 
 int art_set_launch(const art_launch* launch);
 int art_get_launch(int32_t precision, int32_t kind, int32_t nstokes, art_launch* launch);
 
 /* Launch shape of one batch (used by its next render or capture; a captured
- * graph keeps the shape it was captured with). */
+ * graph keeps the shape it was captured with, except that a new group count
+ * discards the captured graph).  Synchronises the device when the group
+ * count changes. */
 int art_batch_set_launch(art_batch* b, const art_launch* launch);
 int art_batch_get_launch(const art_batch* b, art_launch* launch);
 

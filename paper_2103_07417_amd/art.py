@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "art.h")
 
 EMIS = {"toy_disk": 1, "thermal": 2, "grid": 3, "screen_ring": 10, "screen_poly": 11}
 NORM = {"mean": 0, "max": 1}
-PREC = {"fp64": 0, "mixed": 1}
+PREC = {"fp64": 0, "mixed": 1, "mixed_geo": 2}
 STATUS_NAMES = ("ok", "captured", "escaped", "step_cap", "thick", "nan")
 
 
@@ -52,7 +52,8 @@ class Refine(ctypes.Structure):
 class Transfer(ctypes.Structure):
     _fields_ = [("nstokes", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_steps", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("eps", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("fp64_radius", ctypes.c_double),
+                ("fp64_ktheta", ctypes.c_double)]
 
 
 class Image(ctypes.Structure):
@@ -67,7 +68,8 @@ class Stats(ctypes.Structure):
                 ("ibar_int", ctypes.c_double), ("imax0", ctypes.c_double),
                 ("n_abs", ctypes.c_double), ("steps_emit", ctypes.c_int64),
                 ("t_trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int32),
-                ("levels", ctypes.c_int32), ("learned", ctypes.c_int64 * 5)]
+                ("levels", ctypes.c_int32), ("learned", ctypes.c_int64 * 5),
+                ("t_render_ms", ctypes.c_double)]
 
 
 class Learned(ctypes.Structure):
@@ -82,7 +84,7 @@ class Job(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("trace_blocks", ctypes.c_int32), ("trace_threads", ctypes.c_int32),
-                ("refill", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("refill", ctypes.c_int32), ("groups", ctypes.c_int32)]
 
 
 FEAT_DTYPE = np.dtype([("rmin", np.float32), ("ncross", np.int32),
@@ -179,7 +181,8 @@ def blocks(cfg):
     rf = Refine(float(cfg.get("r_rel", -1.0)), float(cfg.get("r_abs", -1.0)),
                 NORM[cfg.get("abs_norm", "mean")], 0)
     tr = Transfer(int(cfg.get("nstokes", 1)), PREC[cfg.get("precision", "fp64")],
-                  int(cfg.get("max_steps", 100000)), 0, float(cfg.get("eps", 0.03)))
+                  int(cfg.get("max_steps", 100000)), 0, float(cfg.get("eps", 0.03)),
+                  float(cfg.get("fp64_radius", 0.0)), float(cfg.get("fp64_ktheta", -1.0)))
     return sp, cam, em, rf, tr
 
 
@@ -208,7 +211,8 @@ def stats_dict(st):
                 trace_launches=int(st.trace_launches),
                 learned=dict(proposed_extra=int(st.learned[0]), suppressed=int(st.learned[1]),
                              fallback=int(st.learned[2]), missed=int(st.learned[3]),
-                             lookahead=int(st.learned[4])))
+                             lookahead=int(st.learned[4])),
+                t_render_ms=float(st.t_render_ms))
 
 
 def alloc(cfg, feat=False):
@@ -313,16 +317,17 @@ def feat_numpy(ft):
     return a.view(FEAT_DTYPE).reshape(a.shape[:-1])
 
 
-def set_launch(trace_blocks=0, trace_threads=0, refill=0):
+def set_launch(trace_blocks=0, trace_threads=0, refill=0, groups=0):
     """Persistent-tracer launch shape for later renders (0 = default)."""
-    _check(lib().art_set_launch(ctypes.byref(Launch(trace_blocks, trace_threads, refill, 0))))
+    _check(lib().art_set_launch(ctypes.byref(Launch(trace_blocks, trace_threads, refill, groups))))
 
 
 def get_launch(cfg):
     _, _, em, _, tr = blocks(cfg)
     L = Launch()
     _check(lib().art_get_launch(tr.precision, em.kind, tr.nstokes, ctypes.byref(L)))
-    return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill)
+    return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill,
+                groups=L.groups)
 
 
 class Batch:
@@ -368,14 +373,15 @@ class Batch:
         _check(lib().art_batch_stats(self._h, int(i), ctypes.byref(st), _stream(self._torch, stream)))
         return stats_dict(st)
 
-    def set_launch(self, trace_blocks=0, trace_threads=0, refill=0):
+    def set_launch(self, trace_blocks=0, trace_threads=0, refill=0, groups=0):
         _check(lib().art_batch_set_launch(self._h, ctypes.byref(Launch(trace_blocks, trace_threads,
-                                                                         refill, 0))))
+                                                                         refill, groups))))
 
     def get_launch(self):
         L = Launch()
         _check(lib().art_batch_get_launch(self._h, ctypes.byref(L)))
-        return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill)
+        return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill,
+                    groups=L.groups)
 
     def set_learned(self, net, **opts):
         """Use the network `net` (a Cnn, or None for plain renders) in later

@@ -1,9 +1,9 @@
 """Launch-shape autotuner for the persistent tracer.
 
 Times a batch's adaptive render (HIP events on the render stream) over a small
-grid of launch shapes -- blocks per CU multiple, threads per block, refill
-threshold -- keeps the fastest, and caches the choice per (device, batch
-signature) in a JSON file.
+grid of launch shapes -- image groups rendered concurrently, blocks per CU
+multiple, threads per block, refill threshold -- keeps the fastest, and caches
+the choice per (device, batch signature) in a JSON file.
 """
 import hashlib
 import json
@@ -63,9 +63,9 @@ def autotune(batch, stream=None, reps=2, use_cache=True, log=None):
     dev = torch.cuda.get_device_name(0)
     key = dev + "/" + signature(batch.cfgs)
     cache = _load() if use_cache else {}
-    if key in cache:
+    if key in cache and "groups" in cache[key]:
         c = cache[key]
-        batch.set_launch(c["trace_blocks"], c["trace_threads"], c["refill"])
+        batch.set_launch(c["trace_blocks"], c["trace_threads"], c["refill"], c["groups"])
         return dict(c, cached=True)
     default = batch.get_launch()
     threads0 = default["trace_threads"]
@@ -75,27 +75,33 @@ def autotune(batch, stream=None, reps=2, use_cache=True, log=None):
     t0 = time.perf_counter()
     batch.render(stream)            # warm-up (code objects, caches)
     stream.synchronize()
-    for threads in (64, 128, 256):
-        blocks_per_cu = max(1, per_cu * threads0 // threads)
-        for mult in (0.5, 1, 2, 4):
-            blocks = max(1, int(round(cus * blocks_per_cu * mult)))
-            for refill in (1, 16):
-                batch.set_launch(blocks, threads, refill)
-                ms = time_render(batch, torch, stream, reps)
-                table.append(dict(trace_blocks=blocks, trace_threads=threads, refill=refill, ms=ms))
-                if log:
-                    log("autotune blocks=%d threads=%d refill=%d: %.2f ms" % (blocks, threads, refill, ms))
+    n = len(batch.cfgs)
+    group_choices = sorted({g for g in (1, 2, 4, 8) if g <= n})
+    for groups in group_choices:
+        for threads in (128, 256):
+            blocks_per_cu = max(1, per_cu * threads0 // threads)
+            for mult in (0.25, 0.5, 1, 2):
+                blocks = max(1, int(round(cus * blocks_per_cu * mult)))
+                for refill in (1, 16):
+                    batch.set_launch(blocks, threads, refill, groups)
+                    ms = time_render(batch, torch, stream, reps)
+                    table.append(dict(trace_blocks=blocks, trace_threads=threads, refill=refill,
+                                      groups=groups, ms=ms))
+                    if log:
+                        log("autotune groups=%d blocks=%d threads=%d refill=%d: %.2f ms"
+                            % (groups, blocks, threads, refill, ms))
     best = min(table, key=lambda r: r["ms"])
-    batch.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"])
+    batch.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], best["groups"])
     out = dict(trace_blocks=best["trace_blocks"], trace_threads=best["trace_threads"],
-               refill=best["refill"], ms=best["ms"], default=default,
+               refill=best["refill"], groups=best["groups"], ms=best["ms"], default=default,
                default_ms=next((r["ms"] for r in table if r["trace_threads"] == threads0
                                 and r["trace_blocks"] == default["trace_blocks"]
-                                and r["refill"] == default["refill"]), None),
+                                and r["refill"] == default["refill"]
+                                and r["groups"] == default["groups"]), None),
                search_s=time.perf_counter() - t0)
     if use_cache:
         cache = _load()
-        cache[key] = {k: out[k] for k in ("trace_blocks", "trace_threads", "refill", "ms")}
+        cache[key] = {k: out[k] for k in ("trace_blocks", "trace_threads", "refill", "groups", "ms")}
         _store(cache)
     out["table"] = table
     out["cached"] = False

@@ -81,12 +81,26 @@ constexpr int kMaxEv = kMaxLevels + 2;
 }  // namespace
 
 // A batch: device descriptors, trace list, counters, timing events, graph.
+// Its images are split into groups of consecutive images; every group runs
+// its own level loop (own counters, trace-list slice and stream), so the
+// long-ray tail of one group's pass overlaps the other groups' work.  Group 0
+// runs on the caller's stream; the others fork from it and join back.
+constexpr int kMaxGroups = 8;
+
+struct BatchGroup {
+    int i0 = 0, n = 0;             // images [i0, i0 + n)
+    int lmax = 0, max_base = 0;    // deepest level, largest base grid of the group
+    int nx0m = 0, ny0m = 0;        // largest base grid sizes (estimator launch shape)
+    size_t list_off = 0;           // the group's slice of the trace list
+    hipEvent_t ev[2 * kMaxEv] = {};
+    int nev = 0;                   // timed tracing launches of the last eager render
+    CnnWork ws;                    // network workspace (learned renders)
+};
+
 struct art_batch {
     int dev = 0;
     int n = 0;
     int model = 0, nstokes = 1, precision = 0;
-    int lmax = 0;
-    int max_base = 0;
     bool uniform = false;
     std::vector<Params> hP;
     std::vector<ImageDesc> hD;
@@ -94,11 +108,16 @@ struct art_batch {
     ImageDesc* dD = nullptr;
     unsigned long long* list = nullptr;
     size_t list_cap = 0;
-    Counters* ctr = nullptr;
+    Counters* ctr = nullptr;       // one block of counters per group
     double* dTh = nullptr;         // gridded model: theta table of the batch's snapshot
     double hTh[kMaxThetaCells] = {};
-    hipEvent_t ev[2 * kMaxEv] = {};
-    int nev = 0;                   // timed tracing launches of the last eager render
+    int ngroups = 1;
+    int req_groups = 0;            // requested group count (0: default)
+    BatchGroup grp[kMaxGroups];
+    hipStream_t gs[kMaxGroups] = {};     // streams of groups 1.. (created on demand)
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxGroups] = {};
+    hipEvent_t ev_render[2] = {};  // whole eager render on the caller's stream
+    bool render_timed = false;
     int ntrace = 0;                // tracing launches per render (eager or captured)
     int graph_ntrace = 0;          // tracing launches in the captured graph
     bool timing = false;
@@ -108,7 +127,6 @@ struct art_batch {
     int cus = 0;
     art_cnn* net = nullptr;        // learned renders when set
     art_learned lopt{};
-    CnnWork ws;                    // the batch's own network workspace
 };
 
 namespace {
@@ -125,8 +143,10 @@ int validate(const art_spacetime* sp, const art_camera* cam, const art_emission*
         return fail(ART_EINVAL, "inclination must be in (0, 180) deg");
     if (!(cam->fov_M > 0.0)) return fail(ART_EINVAL, "field of view must be > 0");
     if (tr->nstokes != 1 && tr->nstokes != 4) return fail(ART_EINVAL, "nstokes must be 1 or 4");
-    if (tr->precision != ART_PREC_FP64 && tr->precision != ART_PREC_MIXED)
+    if (tr->precision != ART_PREC_FP64 && tr->precision != ART_PREC_MIXED && tr->precision != ART_PREC_MIXED_GEO)
         return fail(ART_EINVAL, "unknown precision %d", tr->precision);
+    if (std::isnan(tr->fp64_radius) || std::isnan(tr->fp64_ktheta))
+        return fail(ART_EINVAL, "NaN precision-policy threshold");
     if (!(tr->eps > 0.0 && tr->eps <= 0.5)) return fail(ART_EINVAL, "eps must be in (0, 0.5]");
     if (tr->max_steps <= 0) return fail(ART_EINVAL, "max_steps must be > 0");
     const int k = em->kind;
@@ -202,6 +222,8 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
     P.th_cam = cam->inc_deg * (M_PI / 180.0);
     P.r_out = cam->r_out > 0.0 ? cam->r_out : cam->r_cam;
     P.eps = tr->eps;
+    P.r64 = tr->fp64_radius > 0.0 ? tr->fp64_radius : 6.0;
+    P.kth64 = tr->fp64_ktheta >= 0.0 ? tr->fp64_ktheta : 0.05;
     P.nx = nx;
     P.ny = ny;
     if (nx > 1) {
@@ -297,15 +319,29 @@ void free_batch_mem(art_batch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
-    for (int k = 0; k < 2 * kMaxEv; ++k)
-        if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
-    for (int k = 0; k < 2 * kMaxEv; ++k) b->ev[k] = nullptr;
+    for (int g = 0; g < kMaxGroups; ++g) {
+        BatchGroup& G = b->grp[g];
+        for (int k = 0; k < 2 * kMaxEv; ++k) {
+            if (G.ev[k]) (void)hipEventDestroy(G.ev[k]);
+            G.ev[k] = nullptr;
+        }
+        cnn_work_free(&G.ws);
+        if (b->gs[g]) (void)hipStreamDestroy(b->gs[g]);
+        b->gs[g] = nullptr;
+        if (b->ev_join[g]) (void)hipEventDestroy(b->ev_join[g]);
+        b->ev_join[g] = nullptr;
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    b->ev_fork = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        if (b->ev_render[k]) (void)hipEventDestroy(b->ev_render[k]);
+        b->ev_render[k] = nullptr;
+    }
     if (b->list) (void)hipFree(b->list);
     if (b->ctr) (void)hipFree(b->ctr);
     if (b->dP) (void)hipFree(b->dP);
     if (b->dD) (void)hipFree(b->dD);
     if (b->dTh) (void)hipFree(b->dTh);
-    cnn_work_free(&b->ws);
     b->net = nullptr;
     b->list = nullptr; b->ctr = nullptr; b->dP = nullptr; b->dD = nullptr; b->dTh = nullptr;
     b->list_cap = 0;
@@ -315,11 +351,17 @@ void free_batch_mem(art_batch* b)
 int ensure_mem(art_batch* b, size_t list_need)
 {
     if (!b->ctr) {
-        if (hipMalloc(&b->ctr, sizeof(Counters)) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(counters) failed");
+        if (hipMalloc(&b->ctr, sizeof(Counters) * kMaxGroups) != hipSuccess)
+            return fail(ART_ENOMEM, "hipMalloc(counters) failed");
         if (hipMalloc(&b->dP, sizeof(Params) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(params) failed");
         if (hipMalloc(&b->dD, sizeof(ImageDesc) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(descs) failed");
         if (hipMalloc(&b->dTh, sizeof(double) * kMaxThetaCells) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(theta table) failed");
-        for (int k = 0; k < 2 * kMaxEv; ++k) HIP_TRY(hipEventCreate(&b->ev[k]));
+        for (int g = 0; g < kMaxGroups; ++g)
+            for (int k = 0; k < 2 * kMaxEv; ++k) HIP_TRY(hipEventCreate(&b->grp[g].ev[k]));
+        HIP_TRY(hipEventCreate(&b->ev_render[0]));
+        HIP_TRY(hipEventCreate(&b->ev_render[1]));
+        HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        for (int g = 0; g < kMaxGroups; ++g) HIP_TRY(hipEventCreateWithFlags(&b->ev_join[g], hipEventDisableTiming));
         HIP_TRY(hipGetDevice(&b->dev));
         HIP_TRY(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev));
     }
@@ -337,6 +379,48 @@ int ensure_mem(art_batch* b, size_t list_need)
     return ART_OK;
 }
 
+// Default group count: two groups from 16 images on (measured best for the
+// 64-image batches; more concurrent groups than hardware queues serialise).
+int default_groups(int n)
+{
+    return n >= 16 ? 2 : 1;
+}
+
+// Split the images into groups, set each image's base-list offset inside its
+// group's slice of the trace list and upload the descriptors.
+int layout(art_batch* b, hipStream_t s)
+{
+    int G = b->uniform ? 1 : (b->req_groups > 0 ? b->req_groups : default_groups(b->n));
+    if (G > b->n) G = b->n;
+    if (G > kMaxGroups) G = kMaxGroups;
+    b->ngroups = G;
+    size_t off = 0;
+    for (int g = 0; g < G; ++g) {
+        BatchGroup& Gr = b->grp[g];
+        Gr.i0 = (int)((long long)g * b->n / G);
+        Gr.n = (int)((long long)(g + 1) * b->n / G) - Gr.i0;
+        Gr.lmax = 0;
+        Gr.max_base = 0;
+        Gr.nx0m = Gr.ny0m = 0;
+        Gr.list_off = off;
+        int base = 0;
+        for (int k = 0; k < Gr.n; ++k) {
+            ImageDesc& D = b->hD[Gr.i0 + k];
+            D.base_off = base;                 // base items of an image are contiguous in its group's slice
+            base += D.nx0 * D.ny0;
+            Gr.lmax = D.levels > Gr.lmax ? D.levels : Gr.lmax;
+            Gr.max_base = D.nx0 * D.ny0 > Gr.max_base ? D.nx0 * D.ny0 : Gr.max_base;
+            Gr.nx0m = D.nx0 > Gr.nx0m ? D.nx0 : Gr.nx0m;
+            Gr.ny0m = D.ny0 > Gr.ny0m ? D.ny0 : Gr.ny0m;
+            off += (size_t)D.plane;
+        }
+    }
+    for (int g = 1; g < G; ++g)
+        if (!b->gs[g]) HIP_TRY(hipStreamCreateWithFlags(&b->gs[g], hipStreamNonBlocking));
+    HIP_TRY(hipMemcpyAsync(b->dD, b->hD.data(), sizeof(ImageDesc) * b->n, hipMemcpyHostToDevice, s));
+    return ART_OK;
+}
+
 // Validate jobs, fill host descriptors, grow buffers and upload descriptors.
 int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, bool uniform,
             hipStream_t s)
@@ -346,11 +430,13 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
     if (uniform && n != 1) return fail(ART_EINVAL, "uniform renders take one image");
     b->n = n;
     b->uniform = uniform;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        b->req_groups = g_launch.groups;
+    }
     b->hP.resize(n);
     b->hD.resize(n);
-    b->lmax = 0;
-    b->max_base = 0;
-    size_t total = 0, base_total = 0;
+    size_t total = 0;
     for (int i = 0; i < n; ++i) {
         const art_job& J = jobs[i];
         int rc = validate(&J.sp, &J.cam, &J.em, &J.tr);
@@ -390,12 +476,7 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
         D.abs_norm = J.rf.abs_norm;
         D.r_rel = J.rf.r_rel;
         D.r_abs = J.rf.r_abs;
-        D.base_off = (int32_t)base_total;   // base items of image i are contiguous in the list
-        base_total += (size_t)D.nx0 * (size_t)D.ny0;
-        if (!uniform) {
-            b->lmax = D.levels > b->lmax ? D.levels : b->lmax;
-            b->max_base = D.nx0 * D.ny0 > b->max_base ? D.nx0 * D.ny0 : b->max_base;
-        }
+        D.base_off = 0;
         total += (size_t)D.plane;
     }
     if (total >= (1ULL << 31)) return fail(ART_EINVAL, "batch has %zu pixels (limit 2^31)", total);
@@ -409,117 +490,121 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
         for (int i = 0; i < n; ++i) b->hP[i].theta_tab = b->dTh;
     }
     HIP_TRY(hipMemcpyAsync(b->dP, b->hP.data(), sizeof(Params) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b->dD, b->hD.data(), sizeof(ImageDesc) * n, hipMemcpyHostToDevice, s));
-    return ART_OK;
+    return layout(b, s);
 }
 
-TraceJob base_job(const art_batch* b, int level)
+TraceJob base_job(const art_batch* b, int g, int level)
 {
+    const BatchGroup& G = b->grp[g];
+    Counters* ctr = b->ctr + g;
     TraceJob J;
     std::memset(&J, 0, sizeof(J));
     J.src = SRC_LIST;
-    J.nimg = b->n;
-    J.params = b->dP;
-    J.desc = b->dD;
-    J.list = b->list;
-    J.count = &b->ctr->count[level];
-    J.cursor = &b->ctr->cursor[level];
-    J.ctr = b->ctr;
+    J.nimg = G.n;
+    J.params = b->dP + G.i0;
+    J.desc = b->dD + G.i0;
+    J.list = b->list + G.list_off;
+    J.count = &ctr->count[level];
+    J.cursor = &ctr->cursor[level];
+    J.ctr = ctr;
     J.refill = b->L.refill;
     return J;
 }
 
-hipError_t ev_begin(art_batch* b, hipStream_t s)
+hipError_t ev_begin(art_batch* b, int g, hipStream_t s)
 {
     b->ntrace++;
-    if (!b->timing || b->nev >= kMaxEv) return hipSuccess;
-    return hipEventRecord(b->ev[2 * b->nev], s);
+    BatchGroup& G = b->grp[g];
+    if (!b->timing || G.nev >= kMaxEv) return hipSuccess;
+    return hipEventRecord(G.ev[2 * G.nev], s);
 }
-hipError_t ev_end(art_batch* b, hipStream_t s)
+hipError_t ev_end(art_batch* b, int g, hipStream_t s)
 {
-    if (!b->timing || b->nev >= kMaxEv) return hipSuccess;
-    hipError_t e = hipEventRecord(b->ev[2 * b->nev + 1], s);
-    b->nev++;
+    BatchGroup& G = b->grp[g];
+    if (!b->timing || G.nev >= kMaxEv) return hipSuccess;
+    hipError_t e = hipEventRecord(G.ev[2 * G.nev + 1], s);
+    G.nev++;
     return e;
 }
 
-// Enqueue the whole adaptive level loop of a prepared batch.
-int enqueue_adaptive(art_batch* b, hipStream_t s)
+int trace_pass(art_batch* b, int g, int level, hipStream_t s)
 {
-    b->nev = 0;
-    b->ntrace = 0;
-    HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
-    HIP_TRY(launch_base_list(b->dD, b->n, b->max_base, b->list, b->ctr, 0, s));
-    TraceJob J = base_job(b, 0);
-    HIP_TRY(ev_begin(b, s));
+    TraceJob J = base_job(b, g, level);
+    HIP_TRY(ev_begin(b, g, s));
     HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
-    HIP_TRY(ev_end(b, s));
-    HIP_TRY(launch_reduce_base(b->dD, b->n, b->ctr, s));
-    int nx0m = 0, ny0m = 0;
-    for (int i = 0; i < b->n; ++i) {
-        nx0m = b->hD[i].nx0 > nx0m ? b->hD[i].nx0 : nx0m;
-        ny0m = b->hD[i].ny0 > ny0m ? b->hD[i].ny0 : ny0m;
-    }
-    for (int l = 0; l < b->lmax; ++l) {
-        const int nxl = (int)grid_n(nx0m, l + 1), nyl = (int)grid_n(ny0m, l + 1);
-        HIP_TRY(launch_estimate(b->dD, b->n, nxl, nyl, l, b->ctr, b->list, s));
-        J = base_job(b, l + 1);
-        HIP_TRY(ev_begin(b, s));
-        HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
-        HIP_TRY(ev_end(b, s));
+    HIP_TRY(ev_end(b, g, s));
+    return ART_OK;
+}
+
+// Base grid of group g: clear its counters, list and trace the base points,
+// then the per-image level-0 reductions.
+int enqueue_base(art_batch* b, int g, hipStream_t s)
+{
+    const BatchGroup& G = b->grp[g];
+    Counters* ctr = b->ctr + g;
+    HIP_TRY(launch_fill_u32((uint32_t*)ctr, sizeof(Counters) / 4, 0u, s));
+    HIP_TRY(launch_base_list(b->dD + G.i0, G.n, G.max_base, b->list + G.list_off, ctr, 0, s));
+    int rc = trace_pass(b, g, 0, s);
+    if (rc) return rc;
+    HIP_TRY(launch_reduce_base(b->dD + G.i0, G.n, ctr, s));
+    return ART_OK;
+}
+
+// The adaptive level loop of group g (Sec. 3.2).
+int enqueue_adaptive(art_batch* b, int g, hipStream_t s)
+{
+    const BatchGroup& G = b->grp[g];
+    int rc = enqueue_base(b, g, s);
+    if (rc) return rc;
+    for (int l = 0; l < G.lmax; ++l) {
+        const int nxl = (int)grid_n(G.nx0m, l + 1), nyl = (int)grid_n(G.ny0m, l + 1);
+        HIP_TRY(launch_estimate(b->dD + G.i0, G.n, nxl, nyl, l, b->ctr + g, b->list + G.list_off, s));
+        rc = trace_pass(b, g, l + 1, s);
+        if (rc) return rc;
     }
     return ART_OK;
 }
 
-// Learned level loop: where the network can look two levels ahead it runs
-// on the level-l grid of every image, its level-(l+2) proposals are traced in
-// pass l+1 together with the level-(l+1) points (proposed or flagged by the
-// criterion and not suppressed), and the criterion then judges level l+2 and
-// traces what the look-ahead missed (fallback) or only counts it.
-int enqueue_learned(art_batch* b, hipStream_t s)
+// Learned level loop of group g: where the network can look two levels ahead
+// it runs on the level-l grid of every image, its level-(l+2) proposals are
+// traced in pass l+1 together with the level-(l+1) points (proposed or flagged
+// by the criterion and not suppressed), and the criterion then judges level
+// l+2 and traces what the look-ahead missed (fallback) or only counts it.
+int enqueue_learned(art_batch* b, int g, hipStream_t s)
 {
-    b->nev = 0;
-    b->ntrace = 0;
-    const ImageDesc& D0 = b->hD[0];
+    BatchGroup& G = b->grp[g];
+    const ImageDesc& D0 = b->hD[G.i0];
     const int N = D0.levels;
-    HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
-    HIP_TRY(launch_base_list(b->dD, b->n, b->max_base, b->list, b->ctr, 0, s));
-    TraceJob J = base_job(b, 0);
-    HIP_TRY(ev_begin(b, s));
-    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
-    HIP_TRY(ev_end(b, s));
-    HIP_TRY(launch_reduce_base(b->dD, b->n, b->ctr, s));
+    const ImageDesc* dD = b->dD + G.i0;
+    Counters* ctr = b->ctr + g;
+    unsigned long long* list = b->list + G.list_off;
+    int rc = enqueue_base(b, g, s);
+    if (rc) return rc;
     const art_learned& o = b->lopt;
     int l = 0;
     while (l < N) {
         const bool net_here = l + 2 <= N || (o.all_levels && l + 1 <= N);
         const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
         if (!net_here) {
-            HIP_TRY(launch_estimate(b->dD, b->n, nxl, nyl, l, b->ctr, b->list, s));
-            J = base_job(b, l + 1);
-            HIP_TRY(ev_begin(b, s));
-            HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
-            HIP_TRY(ev_end(b, s));
+            HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, s));
+            rc = trace_pass(b, g, l + 1, s);
+            if (rc) return rc;
             l += 1;
             continue;
         }
         const int W = (int)grid_n(D0.nx0, l), H = (int)grid_n(D0.ny0, l);
-        HIP_TRY(cnn_features_batch(b->dD, b->ctr, b->n, l, H, W, b->ws.xf, s));
-        HIP_TRY(cnn_net_forward(&b->net->net, &b->ws, b->ws.xf, b->n, H, W, b->ws.logits, s));
-        HIP_TRY(cnn_propose(b->ws.logits, b->dD, b->n, l, H, W, o.z_propose, o.z_suppress, b->list, b->ctr, s));
-        HIP_TRY(launch_estimate(b->dD, b->n, nxl, nyl, l, b->ctr, b->list, s, 1, 1));
-        J = base_job(b, l + 1);
-        HIP_TRY(ev_begin(b, s));
-        HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
-        HIP_TRY(ev_end(b, s));
+        HIP_TRY(cnn_features_batch(dD, ctr, G.n, l, H, W, G.ws.xf, s));
+        HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, G.ws.xf, G.n, H, W, G.ws.logits, s));
+        HIP_TRY(cnn_propose(G.ws.logits, dD, G.n, l, H, W, o.z_propose, o.z_suppress, list, ctr, s));
+        HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, s, 1, 1));
+        rc = trace_pass(b, g, l + 1, s);
+        if (rc) return rc;
         if (l + 2 <= N) {
             const int nx2 = (int)grid_n(D0.nx0, l + 2), ny2 = (int)grid_n(D0.ny0, l + 2);
-            HIP_TRY(launch_estimate(b->dD, b->n, nx2, ny2, l + 1, b->ctr, b->list, s, 2, o.fallback ? 1 : 0));
+            HIP_TRY(launch_estimate(dD, G.n, nx2, ny2, l + 1, ctr, list, s, 2, o.fallback ? 1 : 0));
             if (o.fallback) {
-                J = base_job(b, l + 2);
-                HIP_TRY(ev_begin(b, s));
-                HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
-                HIP_TRY(ev_end(b, s));
+                rc = trace_pass(b, g, l + 2, s);
+                if (rc) return rc;
             }
             l += 2;
         } else {
@@ -529,12 +614,30 @@ int enqueue_learned(art_batch* b, hipStream_t s)
     return ART_OK;
 }
 
+// One render of the whole batch on stream s: every group's level loop on its
+// own stream, forked from and joined back into s (capturable).
 int enqueue_render(art_batch* b, hipStream_t s)
 {
-    return b->net ? enqueue_learned(b, s) : enqueue_adaptive(b, s);
+    b->ntrace = 0;
+    for (int g = 0; g < b->ngroups; ++g) b->grp[g].nev = 0;
+    b->render_timed = b->timing;
+    if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[0], s));
+    if (b->ngroups > 1) HIP_TRY(hipEventRecord(b->ev_fork, s));
+    for (int g = 0; g < b->ngroups; ++g) {
+        hipStream_t sg = g == 0 ? s : b->gs[g];
+        if (g > 0) HIP_TRY(hipStreamWaitEvent(sg, b->ev_fork, 0));
+        int rc = b->net ? enqueue_learned(b, g, sg) : enqueue_adaptive(b, g, sg);
+        if (rc) return rc;
+        if (g > 0) {
+            HIP_TRY(hipEventRecord(b->ev_join[g], sg));
+            HIP_TRY(hipStreamWaitEvent(s, b->ev_join[g], 0));
+        }
+    }
+    if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[1], s));
+    return ART_OK;
 }
 
-// Check that a prepared batch can run learned renders and size its workspace.
+// Check that a prepared batch can run learned renders and size its workspaces.
 int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
 {
     if (!net) {
@@ -557,10 +660,12 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
     for (int l = 0; l < D0.levels; ++l)
         if (l + 2 <= D0.levels || (opt->all_levels && l + 1 <= D0.levels)) lmax = l;
     if (lmax >= 0) {
-        const long long P = (long long)b->n * grid_n(D0.nx0, lmax) * grid_n(D0.ny0, lmax);
-        if (P > (1LL << 28)) return fail(ART_EINVAL, "network grid of %lld positions too large", P);
-        int rc = cnn_work_reserve(&b->ws, P);
-        if (rc) return rc;
+        for (int g = 0; g < b->ngroups; ++g) {
+            const long long P = (long long)b->grp[g].n * grid_n(D0.nx0, lmax) * grid_n(D0.ny0, lmax);
+            if (P > (1LL << 28)) return fail(ART_EINVAL, "network grid of %lld positions too large", P);
+            int rc = cnn_work_reserve(&b->grp[g].ws, P);
+            if (rc) return rc;
+        }
     }
     b->net = net;
     b->lopt = *opt;
@@ -569,69 +674,84 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
 
 int enqueue_uniform(art_batch* b, hipStream_t s)
 {
-    b->nev = 0;
     b->ntrace = 0;
+    b->grp[0].nev = 0;
+    b->render_timed = b->timing;
+    if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[0], s));
     const ImageDesc& D = b->hD[0];
     HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
     HIP_TRY(launch_fill_u32(&b->ctr->count[0], 1, (uint32_t)D.plane, s));
     if (D.level) HIP_TRY(launch_fill_i8(D.level, D.plane, 0, s));
-    TraceJob J = base_job(b, 0);
+    TraceJob J = base_job(b, 0, 0);
     J.list = nullptr;    // implicit list: item k = pixel k of image 0
-    HIP_TRY(ev_begin(b, s));
+    HIP_TRY(ev_begin(b, 0, s));
     HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
-    HIP_TRY(ev_end(b, s));
+    HIP_TRY(ev_end(b, 0, s));
+    if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[1], s));
     return ART_OK;
 }
 
 // Statistics of image i (i < 0: whole batch).  Synchronises the stream.
+// Step counts and the status histogram are batch-wide.
 int batch_stats(art_batch* b, int i, art_stats* st, hipStream_t s)
 {
-    Counters h;
-    HIP_TRY(hipMemcpyAsync(&h, b->ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    std::vector<Counters> h(b->ngroups);
+    HIP_TRY(hipMemcpyAsync(h.data(), b->ctr, sizeof(Counters) * b->ngroups, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::memset(st, 0, sizeof(*st));
     long long npix = 0, traced = 0;
     int lv = 0;
-    for (int k = 0; k < b->n; ++k) {
-        if (i >= 0 && k != i) continue;
-        const ImageDesc& D = b->hD[k];
-        npix += D.plane;
-        lv = D.levels > lv ? D.levels : lv;
-        for (int l = 0; l <= D.levels && l < 32; ++l) {
-            const long long t = b->uniform ? (long long)D.plane : (long long)h.img_traced[k][l];
-            st->traced[l] += t;
-            traced += t;
-            if (l == 0)
-                st->candidates[0] += b->uniform ? D.plane : (long long)D.nx0 * D.ny0;
-            else
-                st->candidates[l] += grid_n(D.nx0, l) * grid_n(D.ny0, l) -
-                                     grid_n(D.nx0, l - 1) * grid_n(D.ny0, l - 1);
+    for (int g = 0; g < b->ngroups; ++g) {
+        const BatchGroup& G = b->grp[g];
+        const Counters& c = h[g];
+        for (int q = 0; q < G.n; ++q) {
+            const int k = G.i0 + q;
+            if (i >= 0 && k != i) continue;
+            const ImageDesc& D = b->hD[k];
+            npix += D.plane;
+            lv = D.levels > lv ? D.levels : lv;
+            for (int l = 0; l <= D.levels && l < 32; ++l) {
+                const long long t = b->uniform ? (long long)D.plane : (long long)c.img_traced[q][l];
+                st->traced[l] += t;
+                traced += t;
+                if (l == 0)
+                    st->candidates[0] += b->uniform ? D.plane : (long long)D.nx0 * D.ny0;
+                else
+                    st->candidates[l] += grid_n(D.nx0, l) * grid_n(D.ny0, l) -
+                                         grid_n(D.nx0, l - 1) * grid_n(D.ny0, l - 1);
+            }
+            for (int j = 0; j < 5; ++j) st->learned[j] += (int64_t)c.judge[q][j];
+            if (k == (i >= 0 ? i : 0)) {
+                st->ibar_int = c.scal[q][0];
+                st->imax0 = c.scal[q][1];
+                st->n_abs = c.scal[q][2];
+            }
         }
+        st->steps_total += (int64_t)c.steps;
+        st->steps_emit += (int64_t)c.steps_emit;
+        for (int k = 0; k < 8; ++k) st->status_hist[k] += (int64_t)c.status[k];
     }
     st->levels = lv;
     st->rays_traced = traced;
-    st->steps_total = (int64_t)h.steps;
-    st->steps_emit = (int64_t)h.steps_emit;
-    for (int k = 0; k < 8; ++k) st->status_hist[k] = (int64_t)h.status[k];
     st->interp_frac = b->uniform ? 0.0 : (double)(npix - traced) / (double)npix;
-    const int si = i >= 0 ? i : 0;
-    st->ibar_int = h.scal[si][0];
-    st->imax0 = h.scal[si][1];
-    st->n_abs = h.scal[si][2];
     double tms = 0.0;
-    for (int k = 0; k < b->nev; ++k) {
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, b->ev[2 * k], b->ev[2 * k + 1]));
-        tms += ms;
+    for (int g = 0; g < b->ngroups; ++g) {
+        const BatchGroup& G = b->grp[g];
+        for (int k = 0; k < G.nev; ++k) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, G.ev[2 * k], G.ev[2 * k + 1]));
+            tms += ms;
+        }
     }
     st->t_trace_ms = tms;
     st->trace_launches = b->ntrace;
-    for (int k = 0; k < b->n; ++k) {
-        if (i >= 0 && k != i) continue;
-        for (int j = 0; j < 5; ++j) st->learned[j] += (int64_t)h.judge[k][j];
+    if (b->render_timed) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev_render[0], b->ev_render[1]));
+        st->t_render_ms = ms;
     }
-    if (h.status[RAY_NAN] > 0)
-        return fail(ART_ENUMERIC, "%llu rays produced NaN", (unsigned long long)h.status[RAY_NAN]);
+    if (st->status_hist[RAY_NAN] > 0)
+        return fail(ART_ENUMERIC, "%lld rays produced NaN", (long long)st->status_hist[RAY_NAN]);
     return ART_OK;
 }
 
@@ -691,7 +811,7 @@ int art_render(const art_spacetime* sp, const art_camera* cam, const art_emissio
     if (rc) return rc;
     b->timing = st != nullptr;
     b->net = nullptr;
-    rc = enqueue_adaptive(b, s);
+    rc = enqueue_render(b, s);
     if (rc) return rc;
     if (st) return batch_stats(b, 0, st, s);
     return ART_OK;
@@ -712,7 +832,7 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
     rc = setup_learned(b, net, opt);
     if (rc) return rc;
     b->timing = st != nullptr;
-    rc = enqueue_learned(b, s);
+    rc = enqueue_render(b, s);
     b->net = nullptr;             // the single-image batch keeps no network
     if (rc) return rc;
     if (st) return batch_stats(b, 0, st, s);
@@ -753,6 +873,10 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
     rc = ensure_mem(b, 0);
     if (rc) return rc;
     b->n = 1;
+    b->ngroups = 1;
+    b->grp[0].i0 = 0;
+    b->grp[0].n = 1;
+    b->grp[0].list_off = 0;
     b->hP.resize(1);
     make_params(sp, cam, em, tr, 0, 0, b->hP[0]);
     b->L = launch_cfg(b->cus, tr->precision, em->kind, tr->nstokes);
@@ -765,7 +889,7 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
     HIP_TRY(hipMemcpyAsync(b->dP, b->hP.data(), sizeof(Params), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fill_u32((uint32_t*)b->ctr, sizeof(Counters) / 4, 0u, s));
     HIP_TRY(launch_fill_u32(&b->ctr->count[0], 1, (uint32_t)n, s));
-    TraceJob J = base_job(b, 0);
+    TraceJob J = base_job(b, 0, 0);
     J.src = SRC_POINTS;
     J.list = nullptr;
     J.alpha = alpha_dev;
@@ -824,7 +948,8 @@ int art_batch_launch(art_batch* b, void* stream)
 {
     if (!b) return fail(ART_EINVAL, "NULL batch");
     if (!b->gexec) return fail(ART_EINVAL, "batch has no captured graph (call art_batch_capture)");
-    b->nev = 0;
+    for (int g = 0; g < b->ngroups; ++g) b->grp[g].nev = 0;
+    b->render_timed = false;
     b->ntrace = b->graph_ntrace;
     HIP_TRY(hipGraphLaunch(b->gexec, (hipStream_t)stream));
     return ART_OK;
@@ -859,6 +984,7 @@ int art_set_launch(const art_launch* L)
         return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
     if (L->trace_blocks < 0 || L->refill < 0 || L->refill > 64)
         return fail(ART_EINVAL, "trace_blocks >= 0 and 0 <= refill <= 64 required");
+    if (L->groups < 0 || L->groups > kMaxGroups) return fail(ART_EINVAL, "groups must be in 0..%d", kMaxGroups);
     std::lock_guard<std::mutex> lk(g_mu);
     g_launch = *L;
     return ART_OK;
@@ -871,10 +997,26 @@ int art_batch_set_launch(art_batch* b, const art_launch* L)
         return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
     if (L->trace_blocks < 0 || L->refill < 0 || L->refill > 64)
         return fail(ART_EINVAL, "trace_blocks >= 0 and 0 <= refill <= 64 required");
+    if (L->groups < 0 || L->groups > kMaxGroups) return fail(ART_EINVAL, "groups must be in 0..%d", kMaxGroups);
     const LaunchCfg d = launch_cfg(b->cus, b->precision, b->model, b->nstokes);
     b->L.trace_threads = L->trace_threads ? L->trace_threads : d.trace_threads;
     b->L.trace_blocks = L->trace_blocks ? L->trace_blocks : d.trace_blocks;
     b->L.refill = L->refill ? L->refill : d.refill;
+    if (L->groups != b->req_groups) {
+        // a new split of the images: new descriptors, and a captured graph is stale
+        HIP_TRY(hipDeviceSynchronize());
+        if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        b->req_groups = L->groups;
+        int rc = layout(b, nullptr);
+        if (rc) return rc;
+        if (b->net) {
+            const art_learned o = b->lopt;
+            rc = setup_learned(b, b->net, &o);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipStreamSynchronize(nullptr));
+    }
     return ART_OK;
 }
 
@@ -884,7 +1026,7 @@ int art_batch_get_launch(const art_batch* b, art_launch* L)
     L->trace_blocks = b->L.trace_blocks;
     L->trace_threads = b->L.trace_threads;
     L->refill = b->L.refill;
-    L->pad = 0;
+    L->groups = b->ngroups;
     return ART_OK;
 }
 
@@ -898,7 +1040,7 @@ int art_get_launch(int32_t precision, int32_t kind, int32_t nstokes, art_launch*
     L->trace_blocks = c.trace_blocks;
     L->trace_threads = c.trace_threads;
     L->refill = c.refill;
-    L->pad = 0;
+    L->groups = 0;
     return ART_OK;
 }
 

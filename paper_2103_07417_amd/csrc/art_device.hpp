@@ -51,6 +51,9 @@ struct Params {
     const double* theta_tab;       // gridded model: theta of the n2 cell centres
     double B_unit;                 // gridded model: Gauss per code field unit
     int32_t g_n1, g_n2, g_n3, pad2;
+    // precision policy: geodesic right-hand sides stay FP64 where r < r64
+    // (photon shell, horizon) or |k_theta| < kth64 (theta turning points)
+    double r64, kth64;
 };
 
 constexpr int kMaxThetaCells = 256;
@@ -123,32 +126,45 @@ __device__ __forceinline__ void rotate_sc(double s0, double c0, double d, double
 // g^rph = a/S, g^thth = 1/S, g^phph = 1/(S sin^2).  2H = -kt^2 + Qf/S with
 // Qf = -2r kt^2 + 4r kt kr + D kr^2 + 2a kr kph + kth^2 + kph^2/sin^2.
 // (s, c) = (sin, cos) of the evaluation point's theta, supplied by the caller.
-__device__ __forceinline__ void geo_rhs(double a, double kt, double kph, const double y[5],
-                                        double s, double c, double dy[5])
+template <typename T>
+__device__ __forceinline__ void geo_rhs(T a, T kt, T kph, const T y[5], T s, T c, T dy[5])
 {
-    const double r = y[0], kr = y[3], kth = y[4];
-    const double s2 = s * s;
-    const double Sig = r * r + a * a * c * c;
-    const double Del = r * r - 2.0 * r + a * a;
-    const double iS = frcp(Sig);
-    double Lph = 0.0, Lpo = 0.0, dQth = 0.0;
-    if (kph != 0.0) {
-        const double is2 = frcp(s2);
+    const T r = y[0], kr = y[3], kth = y[4];
+    const T s2 = s * s;
+    const T Sig = r * r + a * a * c * c;
+    const T Del = r * r - T(2.0) * r + a * a;
+    const T iS = frcp(Sig);
+    T Lph = T(0.0), Lpo = T(0.0), dQth = T(0.0);
+    if (kph != T(0.0)) {
+        const T is2 = frcp(s2);
         Lpo = kph * is2;
         Lph = kph * Lpo;
-        dQth = -2.0 * Lph * c * (s * is2);
+        dQth = T(-2.0) * Lph * c * (s * is2);
     }
-    const double kt2 = kt * kt;
-    const double Qf = -2.0 * r * kt2 + 4.0 * r * kt * kr + Del * kr * kr
-                      + 2.0 * a * kr * kph + kth * kth + Lph;
-    const double dQr = -2.0 * kt2 + 4.0 * kt * kr + (2.0 * r - 2.0) * kr * kr;
-    const double dSth = -2.0 * a * a * c * s;
-    const double QiS2 = Qf * iS * iS;
-    dy[0] = (2.0 * r * kt + Del * kr + a * kph) * iS;
+    const T kt2 = kt * kt;
+    const T Qf = T(-2.0) * r * kt2 + T(4.0) * r * kt * kr + Del * kr * kr
+                 + T(2.0) * a * kr * kph + kth * kth + Lph;
+    const T dQr = T(-2.0) * kt2 + T(4.0) * kt * kr + (T(2.0) * r - T(2.0)) * kr * kr;
+    const T dSth = T(-2.0) * a * a * c * s;
+    const T QiS2 = Qf * iS * iS;
+    dy[0] = (T(2.0) * r * kt + Del * kr + a * kph) * iS;
     dy[1] = kth * iS;
     dy[2] = (a * kr + Lpo) * iS;
-    dy[3] = -0.5 * (dQr * iS - 2.0 * r * QiS2);
-    dy[4] = -0.5 * (dQth * iS - dSth * QiS2);
+    dy[3] = T(-0.5) * (dQr * iS - T(2.0) * r * QiS2);
+    dy[4] = T(-0.5) * (dQth * iS - dSth * QiS2);
+}
+
+// Right-hand side in FP32 from an FP64 state (precision policy, outside the
+// sensitive zones); the derivative is returned in FP64 for the RK4 sums.
+__device__ __forceinline__ void geo_rhs32(double a, double kt, double kph, const double y[5], double s,
+                                          double c, double dy[5])
+{
+    float yf[5], df[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) yf[i] = (float)y[i];
+    geo_rhs<float>((float)a, (float)kt, (float)kph, yf, (float)s, (float)c, df);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) dy[i] = (double)df[i];
 }
 
 // ------------------------------------------------------------ Walker-Penrose

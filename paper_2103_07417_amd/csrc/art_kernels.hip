@@ -126,15 +126,25 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>
 // Advance one ray by one step.  Returns a RAY_* status (RAY_OK = continue).
 // sin/cos of theta are evaluated once per step; the RK stages and the
 // midpoint rotate them by their (small) theta increments.
-template <typename R, int MODEL, int NS>
+// G32 (precision policy): the four right-hand sides of the step are evaluated
+// in FP32 when no ray of the wave is in a sensitive zone (r < r64: photon
+// shell and horizon; |k_theta| < kth64: theta turning points); the state, the
+// RK4 sums and the step rule stay FP64.  The decision is wave-uniform.
+template <typename R, int MODEL, int NS, bool G32>
 __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayState<R, MODEL, NS>& st,
                                         unsigned& emit)
 {
     const double a = P.a;
     double k1[5], acc[5], yt[5], kk[5];
     double s0, c0;
+    bool fast = false;
+    if constexpr (G32) fast = __ballot(st.y[0] < P.r64 || ::fabs(st.y[4]) < P.kth64) == 0ull;
+    auto rhs = [&](const double* y, double s, double c, double* d) {
+        if (G32 && fast) geo_rhs32(a, st.kt, st.kph, y, s, c, d);
+        else geo_rhs(a, st.kt, st.kph, y, s, c, d);
+    };
     ::sincos(st.y[1], &s0, &c0);
-    geo_rhs(a, st.kt, st.kph, st.y, s0, c0, k1);
+    rhs(st.y, s0, c0, k1);
     if (st.cprev * c0 < 0.0) st.ncross++;
     st.cprev = c0;
     if (st.y[0] < st.rmin) st.rmin = st.y[0];
@@ -156,15 +166,15 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
 #pragma unroll
     for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h2 * k1[i]; acc[i] = k1[i]; }
     rotate_sc(s0, c0, h2 * k1[1], s, c);
-    geo_rhs(a, st.kt, st.kph, yt, s, c, kk);
+    rhs(yt, s, c, kk);
 #pragma unroll
     for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h2 * kk[i]; acc[i] += 2.0 * kk[i]; }
     rotate_sc(s0, c0, h2 * kk[1], s, c);
-    geo_rhs(a, st.kt, st.kph, yt, s, c, kk);
+    rhs(yt, s, c, kk);
 #pragma unroll
     for (int i = 0; i < 5; ++i) { yt[i] = st.y[i] + h * kk[i]; acc[i] += 2.0 * kk[i]; }
     rotate_sc(s0, c0, h * kk[1], s, c);
-    geo_rhs(a, st.kt, st.kph, yt, s, c, kk);
+    rhs(yt, s, c, kk);
     const double h6 = h * (1.0 / 6.0);
 #pragma unroll
     for (int i = 0; i < 5; ++i) yt[i] = st.y[i] + h6 * (acc[i] + kk[i]);
@@ -194,7 +204,7 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
 // a ballot, one lane claims that many items with a single atomic, the items
 // are handed out by lane prefix; then every busy lane advances its ray by one
 // step.  The per-image parameter blocks are staged in LDS once per block.
-template <typename R, int MODEL, int NS>
+template <typename R, int MODEL, int NS, bool G32>
 __global__ __launch_bounds__(256) void k_trace(TraceJob J)
 {
     __shared__ Params sP[kMaxBatch];
@@ -288,7 +298,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
         }
         if (active) {
             const Params& P = sP[st.img];
-            const int status = ray_step<R, MODEL, NS>(P, sTh, st, my_emit);
+            const int status = ray_step<R, MODEL, NS, G32>(P, sTh, st, my_emit);
             if (status != RAY_OK) {
                 double Sd[4] = { 0.0, 0.0, 0.0, 0.0 };
 #pragma unroll
@@ -329,18 +339,25 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
 
 // Kernel instantiation for (precision, model, nstokes): the screen test
 // functions run through the toy-disk instantiation (they never integrate).
+// precision 0: FP64 throughout; 1: FP64 geodesic, FP32 plasma and transfer;
+// 2: as 1 with FP32 geodesic right-hand sides outside the sensitive zones.
 template <typename F>
 static hipError_t dispatch(int precision, int model, int nstokes, F&& f)
 {
     const bool pol = nstokes == 4;
     if (precision == 0) {
-        if (model == MODEL_THERMAL) return pol ? f((k_trace<double, MODEL_THERMAL, 4>)) : f((k_trace<double, MODEL_THERMAL, 1>));
-        if (model == MODEL_GRID) return pol ? f((k_trace<double, MODEL_GRID, 4>)) : f((k_trace<double, MODEL_GRID, 1>));
-        return f((k_trace<double, MODEL_TOY, 1>));
+        if (model == MODEL_THERMAL) return pol ? f((k_trace<double, MODEL_THERMAL, 4, false>)) : f((k_trace<double, MODEL_THERMAL, 1, false>));
+        if (model == MODEL_GRID) return pol ? f((k_trace<double, MODEL_GRID, 4, false>)) : f((k_trace<double, MODEL_GRID, 1, false>));
+        return f((k_trace<double, MODEL_TOY, 1, false>));
     }
-    if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4>)) : f((k_trace<float, MODEL_THERMAL, 1>));
-    if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4>)) : f((k_trace<float, MODEL_GRID, 1>));
-    return f((k_trace<float, MODEL_TOY, 1>));
+    if (precision == 1) {
+        if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4, false>)) : f((k_trace<float, MODEL_THERMAL, 1, false>));
+        if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4, false>)) : f((k_trace<float, MODEL_GRID, 1, false>));
+        return f((k_trace<float, MODEL_TOY, 1, false>));
+    }
+    if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4, true>)) : f((k_trace<float, MODEL_THERMAL, 1, true>));
+    if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4, true>)) : f((k_trace<float, MODEL_GRID, 1, true>));
+    return f((k_trace<float, MODEL_TOY, 1, true>));
 }
 
 hipError_t launch_trace(int precision, int model, int nstokes, const TraceJob& J, const LaunchCfg& L,

@@ -113,12 +113,16 @@ def test_learned_batch_equals_single_and_graph(art):
     singles = [art.render_learned(c, net, **opts) for c in cfgs]
     b = art.Batch(cfgs, feat=True)
     b.set_learned(net, **opts)
-    b.render()
-    torch.cuda.synchronize()
-    for i, (img, lev, _, st) in enumerate(singles):
-        assert torch.equal(b.images[i], img), i
-        assert torch.equal(b.levels[i], lev), i
-        assert b.stats(i)["learned"] == st["learned"]
+    for groups in (3, 1):              # one image per group, then one group
+        b.set_launch(groups=groups)
+        for x in b.images:
+            x.zero_()
+        b.render()
+        torch.cuda.synchronize()
+        for i, (img, lev, _, st) in enumerate(singles):
+            assert torch.equal(b.images[i], img), (groups, i)
+            assert torch.equal(b.levels[i], lev), (groups, i)
+            assert b.stats(i)["learned"] == st["learned"], (groups, i)
     ref = [x.clone() for x in b.images]
     s = torch.cuda.Stream()
     b.capture(s)

@@ -126,16 +126,31 @@ def test_thermal_adaptive_fp64(art, nx0, levels):
     assert st["status"]["nan"] == 0
 
 
-def test_thermal_mixed_precision(art):
+@pytest.mark.parametrize("precision", ["mixed", "mixed_geo"])
+def test_thermal_mixed_precision(art, precision):
     cfg = art_inputs.reduced(art_inputs.workload("thermal_1025"), 33, 2)
-    print_case("mixed precision")
+    print_case("mixed precision", precision=precision)
     g64, _, _ = art.render_uniform(cfg)
-    g32, _, _ = art.render_uniform(dict(cfg, precision="mixed"))
+    g32, _, _ = art.render_uniform(dict(cfg, precision=precision))
     for s in range(4):
         fe, mse = art.metrics(g64[s], g32[s])
+        print("stokes", s, "mse", mse, "flux error", fe)
         assert mse <= 1e-3, (s, mse)
     fe, mse = art.metrics(g64[0], g32[0])
     assert mse <= 1e-6
+
+
+def test_precision_policy_zones(art):
+    """FP32 geodesic steps change the image only through the steps outside the
+    sensitive zones: with every point sensitive the policy equals the mixed
+    form bitwise; with the default zones it differs from it."""
+    cfg = art_inputs.reduced(art_inputs.workload("thermal_1025"), 33, 2)
+    print_case("precision policy zones")
+    mixed, _, _ = art.render_uniform(dict(cfg, precision="mixed"))
+    all64, _, _ = art.render_uniform(dict(cfg, precision="mixed_geo", fp64_radius=1e9))
+    geo, _, _ = art.render_uniform(dict(cfg, precision="mixed_geo"))
+    assert torch.equal(mixed, all64)
+    assert not torch.equal(mixed, geo)
 
 
 def test_device_metrics(art):
