@@ -44,6 +44,38 @@ FLOP_PLASMA_TOY = 96
 PEAK_FP64_VECTOR = 78.6e12   # MI355X published FP64 vector peak
 PEAK_FP32_VECTOR = 157.3e12
 COPY_BYTES = 256 << 20       # read and written once by the calibration copy
+ROOF_RENDERS = 2             # eager renders of the headline form timed for the roofline
+# Algorithmic HBM bytes per traced ray of the thermal model: the list item
+# (8 B) read, I,Q,U,V (32 B), the features (16 B) and the step count (2 B)
+# written.
+BYTES_PER_RAY = 58
+
+# HBM traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE counter runs
+# of this benchmark (profiles/k_trace_learned_batched_thermal_1025.md), per
+# launch of the roofline renders; valid only for the kernel sources it was
+# measured on (hash below), else reported as null.
+TRAFFIC = dict(bytes_per_render=441421192, kernel_hash="6680c250f238656a",
+               source="profiles/k_trace_learned_batched_thermal_1025.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
+                      "(scales from a 256 MiB device copy), k_trace launches of one headline render")
+TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_kernels.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launches):
+    """HBM bytes per tracing launch of the roofline renders (per-render counter
+    total over this run's launches per render), or None for other kernels."""
+    if not TRAFFIC or TRAFFIC["kernel_hash"] != kernel_hash() or launches <= 0:
+        return None
+    return dict(bytes_per_launch=TRAFFIC["bytes_per_render"] * ROOF_RENDERS / launches,
+                source=TRAFFIC["source"])
 
 
 def log(*a):
@@ -173,19 +205,21 @@ def batch_forms(art, torch, art_inputs, args):
     # eager renders of the headline form with HIP events around each tracing
     # launch (on the render stream): the roofline figures
     B.set_learned(net, **forms[head]["options"])
-    tr_ms, launches, fl = 0.0, 0, 0
-    for _ in range(2):
+    tr_ms, launches, fl, render_ms, rays = 0.0, 0, 0, 0.0, 0
+    for _ in range(ROOF_RENDERS):
         B.render(s)
         st = B.stats(stream=s)
         tr_ms += st["t_trace_ms"]
         launches += st["trace_launches"]
         fl += flops(st, cfgs[0])
+        render_ms += st["t_render_ms"]
+        rays += st["rays"]
     training = dict(seconds=t_train, steps=args.train_steps, images=16, pos_weight=tinfo["pos_weight"],
                     loss_first={str(k): v for k, v in tinfo["loss_first"].items()},
                     loss_last={str(k): v for k, v in tinfo["loss_last"].items()})
     B.close()
     net.close()
-    roof_src = dict(tr_ms=tr_ms, launches=launches, flops=fl)
+    roof_src = dict(tr_ms=tr_ms, launches=launches, flops=fl, render_ms=render_ms, rays=rays)
     return forms, head, training, npix, tune, roof_src
 
 
@@ -250,11 +284,19 @@ def main():
     L = forms[head]
     achieved = (rs["flops"] / rs["launches"]) / (rs["tr_ms"] / rs["launches"] * 1e-3)
     peak = PEAK_FP64_VECTOR
+    traffic = measured_traffic(rs["launches"])
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                frac=achieved / peak, traffic=None,
+                frac=achieved / peak, traffic=traffic and traffic["bytes_per_launch"],
                 kernel="k_trace (FP64 geodesic + %s transfer), %s render" % (args.precision, head),
+                launches=rs["launches"], renders=ROOF_RENDERS,
                 avg_launch_ms=rs["tr_ms"] / rs["launches"],
-                flops_per_launch=rs["flops"] / rs["launches"])
+                flops_per_launch=rs["flops"] / rs["launches"],
+                algorithmic_bytes_per_launch=rs["rays"] * BYTES_PER_RAY / rs["launches"],
+                achieved_whole_render=rs["flops"] / (rs["render_ms"] * 1e-3) / 1e12,
+                traffic_source=traffic and traffic["source"],
+                note="achieved = counted FLOPs per tracing launch / mean launch duration (HIP events "
+                     "on the group streams; the launches of concurrent image groups overlap, so "
+                     "achieved_whole_render = FLOPs / render wall time is the chip-level rate)")
     out = {
         "metric": METRIC, "value": L["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": L["ms_per_batch"],
@@ -290,6 +332,7 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     out["copy_calibration_bytes"] = COPY_BYTES
+    out["kernel_hash"] = kernel_hash()
     del src, dst
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")

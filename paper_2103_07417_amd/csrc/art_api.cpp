@@ -92,6 +92,7 @@ struct BatchGroup {
     int lmax = 0, max_base = 0;    // deepest level, largest base grid of the group
     int nx0m = 0, ny0m = 0;        // largest base grid sizes (estimator launch shape)
     size_t list_off = 0;           // the group's slice of the trace list
+    size_t list_len = 0;
     hipEvent_t ev[2 * kMaxEv] = {};
     int nev = 0;                   // timed tracing launches of the last eager render
     CnnWork ws;                    // network workspace (learned renders)
@@ -107,6 +108,7 @@ struct art_batch {
     Params* dP = nullptr;
     ImageDesc* dD = nullptr;
     unsigned long long* list = nullptr;
+    uint16_t* cost = nullptr;      // per pixel: steps of the traced ray (queue ordering)
     size_t list_cap = 0;
     Counters* ctr = nullptr;       // one block of counters per group
     double* dTh = nullptr;         // gridded model: theta table of the batch's snapshot
@@ -301,6 +303,7 @@ LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes)
     L.refill = u.refill > 0 ? u.refill : env_int("ART_REFILL", 1);
     if (L.refill < 1) L.refill = 1;
     if (L.refill > 64) L.refill = 64;
+    L.long_steps = env_int("ART_LONG_STEPS", 800);
     return L;
 }
 
@@ -338,6 +341,8 @@ void free_batch_mem(art_batch* b)
         b->ev_render[k] = nullptr;
     }
     if (b->list) (void)hipFree(b->list);
+    if (b->cost) (void)hipFree(b->cost);
+    b->cost = nullptr;
     if (b->ctr) (void)hipFree(b->ctr);
     if (b->dP) (void)hipFree(b->dP);
     if (b->dD) (void)hipFree(b->dD);
@@ -366,14 +371,18 @@ int ensure_mem(art_batch* b, size_t list_need)
         HIP_TRY(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev));
     }
     if (list_need > b->list_cap) {
-        if (b->list) {
+        if (b->list || b->cost) {
             HIP_TRY(hipDeviceSynchronize());
-            HIP_TRY(hipFree(b->list));
+            if (b->list) HIP_TRY(hipFree(b->list));
+            if (b->cost) HIP_TRY(hipFree(b->cost));
             b->list = nullptr;
+            b->cost = nullptr;
             b->list_cap = 0;
         }
         if (hipMalloc(&b->list, list_need * sizeof(unsigned long long)) != hipSuccess)
             return fail(ART_ENOMEM, "hipMalloc(trace list, %zu entries) failed", list_need);
+        if (hipMalloc(&b->cost, list_need * sizeof(uint16_t)) != hipSuccess)
+            return fail(ART_ENOMEM, "hipMalloc(cost map, %zu entries) failed", list_need);
         b->list_cap = list_need;
     }
     return ART_OK;
@@ -404,6 +413,7 @@ int layout(art_batch* b, hipStream_t s)
         Gr.nx0m = Gr.ny0m = 0;
         Gr.list_off = off;
         int base = 0;
+        const size_t off0 = off;
         for (int k = 0; k < Gr.n; ++k) {
             ImageDesc& D = b->hD[Gr.i0 + k];
             D.base_off = base;                 // base items of an image are contiguous in its group's slice
@@ -412,8 +422,10 @@ int layout(art_batch* b, hipStream_t s)
             Gr.max_base = D.nx0 * D.ny0 > Gr.max_base ? D.nx0 * D.ny0 : Gr.max_base;
             Gr.nx0m = D.nx0 > Gr.nx0m ? D.nx0 : Gr.nx0m;
             Gr.ny0m = D.ny0 > Gr.ny0m ? D.ny0 : Gr.ny0m;
+            D.cost = b->uniform ? nullptr : b->cost + off;   // same offsets as the list slices
             off += (size_t)D.plane;
         }
+        Gr.list_len = off - off0;
     }
     for (int g = 1; g < G; ++g)
         if (!b->gs[g]) HIP_TRY(hipStreamCreateWithFlags(&b->gs[g], hipStreamNonBlocking));
@@ -504,7 +516,9 @@ TraceJob base_job(const art_batch* b, int g, int level)
     J.params = b->dP + G.i0;
     J.desc = b->dD + G.i0;
     J.list = b->list + G.list_off;
+    J.cap = (long long)G.list_len;
     J.count = &ctr->count[level];
+    J.count_back = &ctr->count_back[level];
     J.cursor = &ctr->cursor[level];
     J.ctr = ctr;
     J.refill = b->L.refill;
@@ -558,7 +572,8 @@ int enqueue_adaptive(art_batch* b, int g, hipStream_t s)
     if (rc) return rc;
     for (int l = 0; l < G.lmax; ++l) {
         const int nxl = (int)grid_n(G.nx0m, l + 1), nyl = (int)grid_n(G.ny0m, l + 1);
-        HIP_TRY(launch_estimate(b->dD + G.i0, G.n, nxl, nyl, l, b->ctr + g, b->list + G.list_off, s));
+        HIP_TRY(launch_estimate(b->dD + G.i0, G.n, nxl, nyl, l, b->ctr + g, b->list + G.list_off,
+                                (long long)G.list_len, b->L.long_steps, s));
         rc = trace_pass(b, g, l + 1, s);
         if (rc) return rc;
     }
@@ -578,6 +593,7 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
     const ImageDesc* dD = b->dD + G.i0;
     Counters* ctr = b->ctr + g;
     unsigned long long* list = b->list + G.list_off;
+    const long long cap = (long long)G.list_len;
     int rc = enqueue_base(b, g, s);
     if (rc) return rc;
     const art_learned& o = b->lopt;
@@ -586,7 +602,7 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         const bool net_here = l + 2 <= N || (o.all_levels && l + 1 <= N);
         const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
         if (!net_here) {
-            HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, s));
+            HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s));
             rc = trace_pass(b, g, l + 1, s);
             if (rc) return rc;
             l += 1;
@@ -596,12 +612,13 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         HIP_TRY(cnn_features_batch(dD, ctr, G.n, l, H, W, G.ws.xf, s));
         HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, G.ws.xf, G.n, H, W, G.ws.logits, s));
         HIP_TRY(cnn_propose(G.ws.logits, dD, G.n, l, H, W, o.z_propose, o.z_suppress, list, ctr, s));
-        HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, s, 1, 1));
+        HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 1, 1));
         rc = trace_pass(b, g, l + 1, s);
         if (rc) return rc;
         if (l + 2 <= N) {
             const int nx2 = (int)grid_n(D0.nx0, l + 2), ny2 = (int)grid_n(D0.ny0, l + 2);
-            HIP_TRY(launch_estimate(dD, G.n, nx2, ny2, l + 1, ctr, list, s, 2, o.fallback ? 1 : 0));
+            HIP_TRY(launch_estimate(dD, G.n, nx2, ny2, l + 1, ctr, list, cap, b->L.long_steps, s, 2,
+                                    o.fallback ? 1 : 0));
             if (o.fallback) {
                 rc = trace_pass(b, g, l + 2, s);
                 if (rc) return rc;
@@ -1002,6 +1019,7 @@ int art_batch_set_launch(art_batch* b, const art_launch* L)
     b->L.trace_threads = L->trace_threads ? L->trace_threads : d.trace_threads;
     b->L.trace_blocks = L->trace_blocks ? L->trace_blocks : d.trace_blocks;
     b->L.refill = L->refill ? L->refill : d.refill;
+    b->L.long_steps = d.long_steps;
     if (L->groups != b->req_groups) {
         // a new split of the images: new descriptors, and a captured graph is stale
         HIP_TRY(hipDeviceSynchronize());

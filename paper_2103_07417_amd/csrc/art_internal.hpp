@@ -13,7 +13,8 @@ constexpr int kMaxLevels = 21;
 
 // Device counters of one batch, zeroed by a fill kernel at the start.
 struct Counters {
-    uint32_t count[kMaxLevels + 1];       // per level: work items in the trace list
+    uint32_t count[kMaxLevels + 1];       // per level: work items at the front of the trace list
+    uint32_t count_back[kMaxLevels + 1];  // per level: work items filled from the back
     uint32_t cursor[kMaxLevels + 1];      // per level: work-queue cursor
     unsigned long long steps;             // geodesic steps
     unsigned long long steps_emit;        // steps that evaluated the plasma/transfer
@@ -33,6 +34,7 @@ struct ImageDesc {
     double* img;          // [nstokes][ny][nx]
     int8_t* level;        // [ny][nx]
     RayFeat* feat;        // optional
+    uint16_t* cost;       // steps of each traced ray, neighbours' maximum for interpolated points
     long long plane;      // nx * ny
     int32_t nx, ny, nx0, ny0, levels, nstokes, abs_norm, base_off;
     double r_rel, r_abs;
@@ -51,13 +53,16 @@ struct TraceJob {
     int nimg;                     // images in the batch (Params staged in LDS)
     const Params* params;         // [nimg]
     const ImageDesc* desc;        // [nimg] (pixel sources)
-    const unsigned long long* list;   // SRC_LIST: items
+    const unsigned long long* list;   // SRC_LIST: items; front items in order, then the
+                                  // back-filled items from list[cap - 1] downwards
+    long long cap;                // list capacity (back-filled items)
     long long identity_n;         // > 0: the list is implicit, item = pixel of image 0
     const double* alpha;          // SRC_POINTS
     const double* beta;
     double* out;                  // SRC_POINTS: n x nstokes
     RayFeat* feat;                // SRC_POINTS features (optional)
-    uint32_t* count;              // device count of work items
+    uint32_t* count;              // device count of front work items
+    uint32_t* count_back;         // device count of back-filled work items (or NULL)
     uint32_t* cursor;             // device queue cursor (zeroed)
     Counters* ctr;                // statistics
     int refill;                   // refill when at least this many lanes idle
@@ -67,6 +72,7 @@ struct LaunchCfg {
     int trace_blocks;             // persistent grid size
     int trace_threads;            // 64, 128 or 256
     int refill;                   // refill threshold (1..64)
+    int long_steps;               // expected steps from which a point is queued first
 };
 
 hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
@@ -81,9 +87,12 @@ hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hi
 // criterion decides the rest).  mode 2: learned, after a look-ahead pass
 // (points already traced are kept, suppressed points are interpolated, the
 // criterion decides the rest and its points are traced only if `fallback`).
+// Points whose neighbours needed at least `long_steps` geodesic steps are
+// queued at the front of the list (traced first), the others from the back
+// (list capacity `cap`).
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
-                           Counters* ctr, unsigned long long* list, hipStream_t s, int mode = 0,
-                           int fallback = 1);
+                           Counters* ctr, unsigned long long* list, long long cap, int long_steps,
+                           hipStream_t s, int mode = 0, int fallback = 1);
 hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
                           int nblocks, hipStream_t s);
 int trace_occupancy_blocks(int precision, int model, int nstokes, int threads);

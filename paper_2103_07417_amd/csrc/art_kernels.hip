@@ -229,7 +229,8 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
     unsigned long long my_steps = 0;
     unsigned my_emit = 0;
     unsigned hist[6] = { 0, 0, 0, 0, 0, 0 };
-    const uint32_t cnt = *J.count;
+    const uint32_t cnt_front = *J.count;
+    const uint32_t cnt = cnt_front + (J.count_back ? *J.count_back : 0u);
 
     for (;;) {
         if (!drained) {
@@ -253,7 +254,9 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
                             be = J.beta[my];
                         } else {
                             if (J.list) {
-                                const unsigned long long it = J.list[my];
+                                const long long at = my < cnt_front ? (long long)my
+                                                                    : J.cap - 1 - (long long)(my - cnt_front);
+                                const unsigned long long it = J.list[at];
                                 img = (int)(it >> 32);
                                 pix = (uint32_t)it;
                             }
@@ -314,6 +317,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
                     const ImageDesc& D = J.desc[st.img];
                     for (int s = 0; s < D.nstokes; ++s) D.img[s * D.plane + st.pix] = Sd[s];
                     if (D.feat) D.feat[st.pix] = f;
+                    if (D.cost) D.cost[st.pix] = (uint16_t)(st.nstep < 65535 ? st.nstep : 65535);
                 }
                 my_steps += (unsigned long long)st.nstep;
                 hist[stt]++;
@@ -445,7 +449,8 @@ __device__ __forceinline__ bool axis_D(const double* I, long long nx, int s, int
 // grid (x: 256-wide strips of p, y: q, z: image).  One thread per point of the
 // level-(l+1) grid; new points are classified by index parity (categories 2-4).
 __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
-                                                  unsigned long long* list, int mode, int fallback)
+                                                  unsigned long long* list, long long cap, int long_steps,
+                                                  int mode, int fallback)
 {
     const int img = blockIdx.z;
     const ImageDesc D = desc[img];
@@ -457,6 +462,7 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
     const int q = blockIdx.y;
     const bool isnew = p < nxl && q < nyl && ((p & 1) | (q & 1));
     bool trace = false;
+    bool longr = false;                      // expected to be a long ray: queue at the front
     bool jd[4] = { false, false, false, false };
     long long pix = 0;
     if (isnew) {
@@ -521,6 +527,16 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
                 jd[3] = want && !fallback;
             }
         }
+        if (D.cost && (trace || !keep)) {
+            // expected cost: the most expensive neighbour
+            uint16_t c = D.cost[o[0]];
+            for (int q2 = 1; q2 < nnb; ++q2) {
+                const uint16_t c2 = D.cost[o[q2]];
+                c = c2 > c ? c2 : c;
+            }
+            longr = trace && (int)c >= long_steps;
+            if (!trace) D.cost[pix] = c;
+        }
         if (trace) {
             D.level[pix] = (int8_t)(l + 1);
         } else if (!keep) {
@@ -556,27 +572,33 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
             if (mk && lane == __ffsll((long long)mk) - 1) atomicAdd(&ctr->judge[img][q2], (unsigned long long)__popcll(mk));
         }
     }
-    // wavefront-ballot compaction of the points to trace
-    const unsigned long long mask = __ballot(trace);
-    if (mask) {
+    // wavefront-ballot compaction of the points to trace: expected long rays
+    // to the front of the list, the others from the back
+    const unsigned long long mlong = __ballot(trace && longr);
+    const unsigned long long mshort = __ballot(trace && !longr);
+    if (mlong | mshort) {
         const int lane = __lane_id();
-        const int leader = __ffsll((long long)mask) - 1;
-        const unsigned nset = (unsigned)__popcll(mask);
-        unsigned base = 0;
+        const int leader = __ffsll((long long)(mlong | mshort)) - 1;
+        unsigned bl = 0, bs = 0;
         if (lane == leader) {
-            base = atomicAdd(&ctr->count[l + 1], nset);
-            atomicAdd(&ctr->img_traced[img][l + 1], nset);
+            if (mlong) bl = atomicAdd(&ctr->count[l + 1], (unsigned)__popcll(mlong));
+            if (mshort) bs = atomicAdd(&ctr->count_back[l + 1], (unsigned)__popcll(mshort));
+            atomicAdd(&ctr->img_traced[img][l + 1], (unsigned)__popcll(mlong | mshort));
         }
-        base = __shfl(base, leader);
-        if (trace) list[base + lane_prefix(mask)] = make_item((uint32_t)img, (uint32_t)pix);
+        bl = __shfl(bl, leader);
+        bs = __shfl(bs, leader);
+        const unsigned long long item = make_item((uint32_t)img, (uint32_t)pix);
+        if (trace && longr) list[bl + lane_prefix(mlong)] = item;
+        if (trace && !longr) list[cap - 1 - (long long)(bs + lane_prefix(mshort))] = item;
     }
 }
 
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
-                           Counters* ctr, unsigned long long* list, hipStream_t s, int mode, int fallback)
+                           Counters* ctr, unsigned long long* list, long long cap, int long_steps,
+                           hipStream_t s, int mode, int fallback)
 {
     dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
-    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, mode, fallback);
+    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, cap, long_steps, mode, fallback);
     return hipGetLastError();
 }
 
