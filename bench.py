@@ -223,6 +223,51 @@ def batch_forms(art, torch, art_inputs, args):
     return forms, head, training, npix, tune, roof_src
 
 
+def grid_forms(art, torch, art_inputs, args):
+    """The gridded snapshot at 4097^2 (base 257^2, 4 levels, the paper's GRMHD
+    tolerances): plain adaptive render in FP64 and mixed precision against
+    the uniform (16.8 M-ray) render."""
+    from art_inputs import mks
+    t0 = time.perf_counter()
+    grid, _ = mks.mks_snapshot(seed=2)
+    g = torch.from_numpy(grid).cuda()
+    t_gen = time.perf_counter() - t0
+    out = dict(snapshot_seconds=t_gen, snapshot_bytes=int(grid.nbytes))
+    truth = None
+    for prec in ("mixed", "fp64"):
+        cfg = dict(art_inputs.workload("grid_4097"), grid_dev=g, precision=prec)
+        nx, ny = art.image_size(cfg)
+        if truth is None:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t, _, ust = art.render_uniform(cfg)
+            torch.cuda.synchronize()
+            t_uni = time.perf_counter() - t0
+            truth = t[0].clone()
+            del t
+            out["uniform"] = dict(ms=t_uni * 1e3, rays=ust["rays"], rays_per_s=ust["rays"] / t_uni,
+                                  precision=prec)
+        bufs = art.alloc(cfg)
+        art.render(cfg, out=bufs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            img, lev, _, st = art.render(cfg, out=bufs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        fe, mse = art.metrics(truth, img[0])
+        out[prec] = dict(ms_per_image=dt * 1e3, rays=st["rays"], passes=st["trace_launches"],
+                         rays_per_s=st["rays"] / dt, effective_px_per_s=nx * ny / dt,
+                         interp_frac=st["interp_frac"], mse_vs_uniform_mixed=mse, flux_error=fe)
+        log("grid_4097 %s: %.1f ms, %d rays, IF %.4f, mse %.2e" % (prec, dt * 1e3, st["rays"],
+                                                                  st["interp_frac"], mse))
+        del bufs, img, lev
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def plain_single(art, torch, cfg, args):
     """The paper's method, one image at a time, and the uniform render."""
     truth, _, ust = art.render_uniform(cfg)
@@ -261,6 +306,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--z-propose", type=float, default=0.0)
     ap.add_argument("--z-suppress", type=float, default=-1.0)
@@ -325,6 +371,8 @@ def main():
                                                    "ms", "default", "default_ms")},
         "roofline": roof,
     }
+    if not args.no_grid:
+        out["grid_4097"] = grid_forms(art, torch, art_inputs, args)
     # a plain device copy of known size: reference reading for the HBM byte
     # counters (FETCH_SIZE / WRITE_SIZE) of a profiled run
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
