@@ -66,6 +66,10 @@ def workload(name):
         return dict(common, name=name, a=0.94, inc_deg=163.0, model="grid",
                     mp=mks.grid_params(geo), nstokes=4, nx0=257, ny0=257, levels=4,
                     r_rel=1e-3, r_abs=0.025, abs_norm="mean", freq_hz=230e9, snapshot_seed=2)
+    if name == "grid_16385":
+        # the snapshot refined 6 levels from 257^2 to 16385^2, Stokes I (the
+        # learned proposal's deployment size)
+        return dict(workload("grid_4097"), name=name, levels=6, nstokes=1)
     if name == "thermal_1025_mixed":
         return dict(workload("thermal_1025"), name=name, precision="mixed")
     raise KeyError(name)
@@ -125,6 +129,18 @@ def training_workload(precision="mixed", nx0=129, levels=3):
                              ny0=nx0, levels=levels))
             k += 1
     return cfgs
+
+
+GRID_TRAIN_VIEWS = ((0.94, 17.0), (0.94, 60.0), (0.94, 120.0), (0.5, 163.0))
+
+
+def grid_training_workload(grid_dev, precision="mixed"):
+    """Training images of the snapshot (base 257^2, 4 levels, Stokes I) seen
+    from inclinations / spins other than the deployment view (a = 0.94,
+    i = 163 deg)."""
+    return [dict(workload("grid_4097"), name="gtrain_%d" % k, a=a, inc_deg=inc, nstokes=1,
+                 grid_dev=grid_dev, precision=precision)
+            for k, (a, inc) in enumerate(GRID_TRAIN_VIEWS)]
 
 
 def reduced(cfg, nx0, levels):

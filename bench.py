@@ -268,6 +268,65 @@ def grid_forms(art, torch, art_inputs, args):
     return out
 
 
+def deploy_16385(art, torch, art_inputs, args):
+    """Learned proposal deployed on the snapshot at 16385^2 (base 257^2, 6
+    levels, Stokes I): plain and learned adaptive renders against the uniform
+    render (268 M rays).  The network is trained on plain renders of the
+    snapshot seen from other views (4097^2) and of the thermal images."""
+    from art_inputs import mks
+    from paper_2103_07417_amd import learn
+    grid, _ = mks.mks_snapshot(seed=2)
+    g = torch.from_numpy(grid).cuda()
+    cfg = dict(art_inputs.workload("grid_16385"), grid_dev=g, precision=args.precision)
+    nx, ny = art.image_size(cfg)
+    out = {"workload": "gridded snapshot a=0.94 i=163 deg, 230 GHz, Stokes I, base 257^2 -> 6 levels -> "
+                       "%dx%d, R_rel=1e-3, R_abs=0.025 Ibar_int" % (nx, ny)}
+    t0 = time.perf_counter()
+    train_cfgs = art_inputs.grid_training_workload(g, precision=args.precision) + \
+        art_inputs.training_workload(precision=args.precision)
+    net, tinfo = learn.train(train_cfgs, steps=args.train_steps, lr=3e-3, seed=4)
+    torch.cuda.synchronize()
+    out["training"] = dict(seconds=time.perf_counter() - t0, images=len(train_cfgs),
+                           loss_first={str(k): v for k, v in tinfo["loss_first"].items()},
+                           loss_last={str(k): v for k, v in tinfo["loss_last"].items()})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    truth, _, ust = art.render_uniform(cfg)
+    torch.cuda.synchronize()
+    t_uni = time.perf_counter() - t0
+    truth = truth[0]
+    out["uniform"] = dict(ms=t_uni * 1e3, rays=ust["rays"], rays_per_s=ust["rays"] / t_uni)
+    log("16385^2 uniform: %d rays in %.0f ms" % (ust["rays"], t_uni * 1e3))
+    bufs = art.alloc(cfg, feat=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    (img, lev, ft, st), dt = timed(lambda: art.render(cfg, out=bufs))
+    fe, mse = art.metrics(truth, img[0])
+    out["plain"] = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse=mse, flux_error=fe,
+                        effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt)
+    log("16385^2 plain: %.0f ms, %d rays, mse %.2e" % (dt * 1e3, st["rays"], mse))
+    for name, opts in (("learned_fallback", dict(z_propose=args.z_propose, fallback=True)),
+                       ("learned_judge", dict(z_propose=args.z_propose, fallback=False))):
+        (img, lev, ft, st), dt = timed(lambda: art.render_learned(cfg, net, out=bufs, **opts))
+        fe, mse = art.metrics(truth, img[0])
+        out[name] = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse=mse, flux_error=fe,
+                         effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt, judge=st["learned"],
+                         options=opts)
+        log("16385^2 %s: %.0f ms, %d rays, %d passes, mse %.2e, judge %s" % (
+            name, dt * 1e3, st["rays"], st["trace_launches"], mse, st["learned"]))
+    net.close()
+    del bufs, truth, img, lev, ft, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def plain_single(art, torch, cfg, args):
     """The paper's method, one image at a time, and the uniform render."""
     truth, _, ust = art.render_uniform(cfg)
@@ -307,6 +366,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-deploy", action="store_true")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--z-propose", type=float, default=0.0)
     ap.add_argument("--z-suppress", type=float, default=-1.0)
@@ -373,6 +433,8 @@ def main():
     }
     if not args.no_grid:
         out["grid_4097"] = grid_forms(art, torch, art_inputs, args)
+    if not args.no_deploy:
+        out["deploy_16385"] = deploy_16385(art, torch, art_inputs, args)
     # a plain device copy of known size: reference reading for the HBM byte
     # counters (FETCH_SIZE / WRITE_SIZE) of a profiled run
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")

@@ -66,6 +66,8 @@ def lib():
         L.or_trace_path.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, ctypes.c_double,
                                     dp, ctypes.c_void_p, dp, ctypes.c_int, dp]
         L.or_trace_path.restype = ctypes.c_int
+        L.or_plasma_point.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, ctypes.c_double, dp, dp]
+        L.or_plasma_point.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -134,10 +136,10 @@ def screen_coords(fov, nx, ny, i, j):
     return x0 + np.asarray(i, dtype=np.float64) * dx, y0 + np.asarray(j, dtype=np.float64) * dx
 
 
-def trace_path(cfg, alpha, beta, cap=200000):
+def trace_path(cfg, alpha, beta, cap=200000, grid=None):
     """Trace one ray and return (S, feat, states, kt, kph): states is (n, 6)
     with columns r, theta, phi, k_r (Kerr-Schild), k_theta, step length."""
-    p = make_params(cfg)
+    p = make_params(cfg, grid)
     S = np.zeros(4)
     feat = np.zeros(1, dtype=FEAT_DTYPE)
     rec = np.zeros((cap, 6))
@@ -145,3 +147,14 @@ def trace_path(cfg, alpha, beta, cap=200000):
     n = lib().or_trace_path(ctypes.byref(p), float(alpha), float(beta), _dp(S),
                             feat.ctypes.data_as(ctypes.c_void_p), _dp(rec), cap, _dp(kk))
     return S[:p.nstokes], feat[0], rec[:n].copy(), kk[0], kk[1]
+
+
+def plasma_point(cfg, alpha, beta, y, grid=None):
+    """Coefficients per unit affine length at state y = (r, theta, phi, k_r,
+    k_theta) of the ray through (alpha, beta): (emits, J[4], alpha_I,
+    alpha_QUV[3], rho_QUV[3])."""
+    p = make_params(cfg, grid)
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros(11)
+    ok = lib().or_plasma_point(ctypes.byref(p), float(alpha), float(beta), _dp(yy), _dp(out))
+    return bool(ok), out[:4], out[4], out[5:8], out[8:11]

@@ -779,6 +779,11 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
         if ((pol ? O[0] : T1) < 1e-12) { status = OR_THICK; break; }
         if (!(y[0] == y[0]) || !(y[3] == y[3])) { status = OR_NAN; break; }
         double rate = fabs(k1[0]) / y[0] + fabs(k1[1]) + fabs(k1[2]);
+        /* pole control: within |sin theta| < 0.1 of a pole a ray with k_phi != 0
+         * meets the centrifugal barrier; the theta step is limited to a fraction
+         * of |sin theta| so that no stage lands inside the barrier */
+        double sth = fabs(sin(y[1]));
+        if (kph != 0.0 && sth < 0.1) rate += fabs(k1[1]) * (1.0 / (sth > 1e-12 ? sth : 1e-12) - 10.0);
         double far = y[0] / 20.0;
         if (far < 1.0) far = 1.0;
         if (far > 4.0) far = 4.0;
@@ -870,6 +875,25 @@ int or_trace(const or_params* p, int n, const double* al, const double* be,
 
 /* Trace one ray and record (r, th, ph, k_r, k_th, h) at every step start and
  * the final state (h = 0).  Returns the number of records written (<= cap). */
+/* Plasma and transfer coefficients per unit affine length at one point of the
+ * ray through screen point (al, be) (test and diagnosis helper): out = J[4],
+ * alpha_I, alpha_{Q,U,V}, rho_{Q,U,V}.  Returns 1 where the plasma emits.   */
+int or_plasma_point(const or_params* p, double al, double be, const double* y, double* out)
+{
+    double a = p->a, rh = 1.0 + sqrt(1.0 - a * a);
+    double risco = or_r_isco(a), Eis, Lis;
+    circ_EL(a, risco, &Eis, &Lis);
+    cam_ray cr; camera_ray(p, al, be, &cr);
+    cplx kap0 = walker_penrose(a, cr.y[0], cr.y[1], cr.kup_bl, cr.fup_bl);
+    double J[4], aI, av[3], rv[3];
+    int ok = plasma_point(p, y[0], y[1], y[2], cr.kt, cr.kph, y[3], y[4], &kap0, rh, risco, Eis, Lis,
+                          J, &aI, av, rv);
+    for (int i = 0; i < 4; ++i) out[i] = J[i];
+    out[4] = aI;
+    for (int i = 0; i < 3; ++i) { out[5 + i] = av[i]; out[8 + i] = rv[i]; }
+    return ok;
+}
+
 int or_trace_path(const or_params* p, double al, double be, double* S, void* feat,
                   double* rec, int cap, double* kt_kph)
 {

@@ -128,8 +128,9 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>
 // midpoint rotate them by their (small) theta increments.
 // G32 (precision policy): the four right-hand sides of the step are evaluated
 // in FP32 when no ray of the wave is in a sensitive zone (r < r64: photon
-// shell and horizon; |k_theta| < kth64: theta turning points); the state, the
-// RK4 sums and the step rule stay FP64.  The decision is wave-uniform.
+// shell and horizon; |k_theta| < kth64: theta turning points; |sin theta| <
+// 0.1: the polar barrier); the state, the RK4 sums and the step rule stay
+// FP64.  The decision is wave-uniform.
 template <typename R, int MODEL, int NS, bool G32>
 __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayState<R, MODEL, NS>& st,
                                         unsigned& emit)
@@ -137,13 +138,14 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
     const double a = P.a;
     double k1[5], acc[5], yt[5], kk[5];
     double s0, c0;
+    ::sincos(st.y[1], &s0, &c0);
     bool fast = false;
-    if constexpr (G32) fast = __ballot(st.y[0] < P.r64 || ::fabs(st.y[4]) < P.kth64) == 0ull;
+    if constexpr (G32)
+        fast = __ballot(st.y[0] < P.r64 || ::fabs(st.y[4]) < P.kth64 || ::fabs(s0) < 0.1) == 0ull;
     auto rhs = [&](const double* y, double s, double c, double* d) {
         if (G32 && fast) geo_rhs32(a, st.kt, st.kph, y, s, c, d);
         else geo_rhs(a, st.kt, st.kph, y, s, c, d);
     };
-    ::sincos(st.y[1], &s0, &c0);
     rhs(st.y, s0, c0, k1);
     if (st.cprev * c0 < 0.0) st.ncross++;
     st.cprev = c0;
@@ -153,7 +155,11 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
     if (st.nstep >= P.max_steps) return RAY_STEPCAP;
     if (st.O[0] < R(1e-12)) return RAY_THICK;
     if (!(st.y[0] == st.y[0]) || !(st.y[3] == st.y[3])) return RAY_NAN;
-    const double rate = ::fabs(k1[0]) * frcp(st.y[0]) + ::fabs(k1[1]) + ::fabs(k1[2]);
+    double rate = ::fabs(k1[0]) * frcp(st.y[0]) + ::fabs(k1[1]) + ::fabs(k1[2]);
+    // pole control: within |sin theta| < 0.1 of a pole (k_phi != 0: centrifugal
+    // barrier) the theta step is limited to a fraction of |sin theta|
+    const double as0 = ::fabs(s0);
+    if (st.kph != 0.0 && as0 < 0.1) rate += ::fabs(k1[1]) * (frcp(as0 > 1e-12 ? as0 : 1e-12) - 10.0);
     double far = st.y[0] * (1.0 / 20.0);
     far = far < 1.0 ? 1.0 : (far > 4.0 ? 4.0 : far);
     double h = P.eps * far * frcp(rate);

@@ -19,7 +19,8 @@ def network_levels(levels, all_levels=False):
 
 
 def training_set(cfgs, all_levels=False, stream=None):
-    """{level: (x, labels, valid)} stacked over cfgs (CUDA tensors)."""
+    """{(level, H, W): (x, labels, valid)} stacked over the images whose
+    level-l grids have the same shape (CUDA tensors)."""
     import torch
     by_level = {}
     for c in cfgs:
@@ -31,7 +32,7 @@ def training_set(cfgs, all_levels=False, stream=None):
             if l in ls:
                 x = art.cnn_features(c, img, ft, l, st["n_abs"], stream=stream)
                 y, v = art.cnn_labels(c, lev, l, stream=stream)
-                by_level.setdefault(l, []).append((x, y, v))
+                by_level.setdefault((l,) + tuple(x.shape[2:]), []).append((x, y, v))
                 l += 2
             else:
                 l += 1

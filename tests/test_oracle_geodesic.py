@@ -113,6 +113,25 @@ def test_carter_constant_and_null_norm_conserved(a, inc, al, be):
     assert np.abs(Q2 - Q2[0]).max() <= np.abs(Q - Q[0]).max() + 1e-14
 
 
+@pytest.mark.parametrize("al,be", [(-0.00244140625, 16.97509765625), (1e-4, 16.0), (-3e-3, -16.5)])
+def test_near_polar_rays_keep_their_invariants(al, be):
+    """Rays whose screen point lies almost on the projected spin axis pass a
+    pole with a tiny k_phi: the centrifugal barrier turns them back at
+    sin(theta) ~ |k_phi|/|k_theta|.  The step rule must resolve the turn
+    (Carter constant and null norm conserved, no runaway)."""
+    a = 0.94
+    c = cfg(a=a, inc_deg=163.0, eps=0.03)
+    _, f, st, kt, kph = ray.trace_path(c, al, be)
+    assert f["status"] in (1, 2), f
+    th = st[:, 1]
+    assert np.abs(th).max() < 10.0
+    Q = st[:, 4] ** 2 + np.cos(th) ** 2 * (-a * a * kt * kt + kph ** 2 / np.sin(th) ** 2)
+    nn = np.array([ray.lib().or_null_norm(a, kt, kph, ray._dp(np.ascontiguousarray(s[:5])))
+                   for s in st])
+    assert np.abs(Q - Q[0]).max() < 1e-4 * abs(Q[0])
+    assert np.abs(nn).max() < 1e-4 * kt * kt
+
+
 def _binet_sweep(b, u_end_a, u_end_b):
     """Total orbital sweep of a Schwarzschild photon with impact parameter b
     between radii 1/u_end_a and 1/u_end_b through its turning point:
