@@ -192,7 +192,11 @@ static void camera_ray(const or_params* p, double alpha, double beta, cam_ray* c
     double kt = g.tt * ku_t + g.tp * ku_p;
     double kr_bl = g.rr * ku_r;
     double kth = g.hh * ku_h;
-    double kph = g.tp * ku_t + g.pp * ku_p;
+    /* k_phi = k . d_phi = sqrt(g_phiphi) (k . e_(phi)): only the screen direction
+     * contributes (the ZAMO observer has no angular momentum), so alpha = 0
+     * gives k_phi = 0 exactly */
+    double kph = dp * sqrt(g.pp);
+    (void)ku_p;
     double Del = r * r - 2.0 * r + a * a;
     double kr_ks = kr_bl - (2.0 * r / Del) * kt - (a / Del) * kph;
     cr->y[0] = r; cr->y[1] = th; cr->y[2] = 0.0; cr->y[3] = kr_ks; cr->y[4] = kth;
@@ -781,9 +785,15 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
         double rate = fabs(k1[0]) / y[0] + fabs(k1[1]) + fabs(k1[2]);
         /* pole control: within |sin theta| < 0.1 of a pole a ray with k_phi != 0
          * meets the centrifugal barrier; the theta step is limited to a fraction
-         * of |sin theta| so that no stage lands inside the barrier */
-        double sth = fabs(sin(y[1]));
-        if (kph != 0.0 && sth < 0.1) rate += fabs(k1[1]) * (1.0 / (sth > 1e-12 ? sth : 1e-12) - 10.0);
+         * of the distance to the pole so that no stage lands inside the barrier */
+        if (kph != 0.0) {
+            /* distance to the pole, floored at half the barrier's
+             * sin theta ~ |k_phi| / |k_theta| */
+            double se = fabs(sin(y[1]));
+            double ka = fabs(y[4]);
+            if (0.5 * fabs(kph) > se * ka) se = 0.5 * fabs(kph) / ka;
+            if (se < 0.1) rate += fabs(k1[1]) * (1.0 / se - 10.0);
+        }
         double far = y[0] / 20.0;
         if (far < 1.0) far = 1.0;
         if (far > 4.0) far = 4.0;

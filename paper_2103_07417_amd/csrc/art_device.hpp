@@ -204,7 +204,10 @@ __device__ __forceinline__ void camera_start(const Params& P, double al, double 
     const double kt = P.c_gtt * ku_t + P.c_gtp * ku_p;
     const double kr_bl = P.c_grr * ku_r;
     const double kth = P.c_ghh * ku_h;
-    const double kph = P.c_gtp * ku_t + P.c_gpp * ku_p;
+    // k_phi = sqrt(g_phiphi) (k . e_(phi)) = dp / e_phi: the ZAMO observer has no
+    // angular momentum, so alpha = 0 gives k_phi = 0 exactly
+    const double kph = dp * frcp(P.c_ep);
+    (void)ku_p;
     const double iD = 1.0 / P.c_del;
     R.y[0] = r;
     R.y[1] = P.th_cam;

@@ -157,9 +157,14 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
     if (!(st.y[0] == st.y[0]) || !(st.y[3] == st.y[3])) return RAY_NAN;
     double rate = ::fabs(k1[0]) * frcp(st.y[0]) + ::fabs(k1[1]) + ::fabs(k1[2]);
     // pole control: within |sin theta| < 0.1 of a pole (k_phi != 0: centrifugal
-    // barrier) the theta step is limited to a fraction of |sin theta|
-    const double as0 = ::fabs(s0);
-    if (st.kph != 0.0 && as0 < 0.1) rate += ::fabs(k1[1]) * (frcp(as0 > 1e-12 ? as0 : 1e-12) - 10.0);
+    // barrier) the theta step is limited to a fraction of the distance to the
+    // pole, floored at half the barrier's sin theta ~ |k_phi| / |k_theta|
+    if (st.kph != 0.0) {
+        double se = ::fabs(s0);
+        const double ka = ::fabs(st.y[4]);
+        if (0.5 * ::fabs(st.kph) > se * ka) se = 0.5 * ::fabs(st.kph) / ka;
+        if (se < 0.1) rate += ::fabs(k1[1]) * (frcp(se) - 10.0);
+    }
     double far = st.y[0] * (1.0 / 20.0);
     far = far < 1.0 ? 1.0 : (far > 4.0 ? 4.0 : far);
     double h = P.eps * far * frcp(rate);
