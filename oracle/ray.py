@@ -24,7 +24,7 @@ class OrParams(ctypes.Structure):
         ("a", ctypes.c_double), ("r_cam", ctypes.c_double), ("inc", ctypes.c_double),
         ("r_out", ctypes.c_double), ("eps", ctypes.c_double),
         ("max_steps", ctypes.c_int32), ("nstokes", ctypes.c_int32),
-        ("model", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("nsub", ctypes.c_int32),
         ("freq", ctypes.c_double), ("L_cm", ctypes.c_double),
         ("mp", ctypes.c_double * 16),
         ("grid", ctypes.POINTER(ctypes.c_float)),
@@ -33,6 +33,8 @@ class OrParams(ctypes.Structure):
         ("gp", ctypes.c_double * 8),
     ]
 
+
+MAX_SUB = 8          # subring planes the C oracle can accumulate
 
 FEAT_DTYPE = np.dtype([("rmin", np.float32), ("ncross", np.int32),
                        ("steps", np.int32), ("status", np.int32)])
@@ -91,6 +93,7 @@ def make_params(cfg, grid=None):
     p.eps = float(cfg.get("eps", 0.03))
     p.max_steps = int(cfg.get("max_steps", 100000))
     p.nstokes = int(cfg.get("nstokes", 1))
+    p.nsub = int(cfg.get("subrings", 0))
     p.model = MODEL_IDS[cfg["model"]] if isinstance(cfg["model"], str) else int(cfg["model"])
     p.freq = float(cfg.get("freq_hz", 230e9))
     p.L_cm = length_unit_cm(float(cfg.get("mass_msun", 4.0e6)))
@@ -109,14 +112,15 @@ def make_params(cfg, grid=None):
 def trace(cfg, alpha, beta, nthreads=None, grid=None):
     """Trace rays through screen points (alpha, beta) [M].
 
-    Returns (S, feat): S is (n, nstokes) float64, feat a structured array
-    with fields rmin, ncross, steps, status.
+    Returns (S, feat): S is (n, nstokes + subrings) float64 (Stokes, then the
+    subring planes of I), feat a structured array with fields rmin, ncross,
+    steps, status.
     """
     alpha = np.ascontiguousarray(alpha, dtype=np.float64).ravel()
     beta = np.ascontiguousarray(beta, dtype=np.float64).ravel()
     n = alpha.size
     p = make_params(cfg, grid)
-    S = np.zeros((n, p.nstokes), dtype=np.float64)
+    S = np.zeros((n, p.nstokes + p.nsub), dtype=np.float64)
     feat = np.zeros(n, dtype=FEAT_DTYPE)
     if n == 0:
         return S, feat
@@ -140,7 +144,7 @@ def trace_path(cfg, alpha, beta, cap=200000, grid=None):
     """Trace one ray and return (S, feat, states, kt, kph): states is (n, 6)
     with columns r, theta, phi, k_r (Kerr-Schild), k_theta, step length."""
     p = make_params(cfg, grid)
-    S = np.zeros(4)
+    S = np.zeros(4 + MAX_SUB)
     feat = np.zeros(1, dtype=FEAT_DTYPE)
     rec = np.zeros((cap, 6))
     kk = np.zeros(2)

@@ -57,7 +57,7 @@ typedef struct {
     int32_t max_steps;
     int32_t nstokes;   /* 1 or 4 */
     int32_t model;
-    int32_t pad;
+    int32_t nsub;      /* subring planes (0: none) */
     double freq;       /* observing frequency [Hz] */
     double L_cm;       /* length unit GM/c^2 [cm] */
     double mp[16];     /* model parameters (see or_model_*) */
@@ -66,6 +66,8 @@ typedef struct {
     int32_t n1, n2, n3, pad2;
     double gp[8];      /* x1 start, x1 stop, hslope, ... */
 } or_params;
+
+#define OR_MAX_SUB 8
 
 typedef struct { double re, im; } cplx;
 
@@ -751,10 +753,15 @@ static int plasma_point(const or_params* p, double r, double th, double ph, doub
     return 1;
 }
 
+/* Subring decomposition (Sec. 5.1): the emission of a step belongs to
+ * subring n = the number of turning points of theta (sign changes of
+ * k_theta) the backward ray has passed before the step, i.e. the number of
+ * half-orbits between emission and reception; the last plane collects
+ * n >= nsub - 1.  S[4 + n] accumulates the step's increment of Stokes I.   */
 static void trace_one(const or_params* p, double al, double be, double* S, ray_feat* ft,
                       double* rec, int rec_cap, int* rec_n)
 {
-    for (int i = 0; i < 4; ++i) S[i] = 0.0;
+    for (int i = 0; i < 4 + OR_MAX_SUB; ++i) S[i] = 0.0;
     ft->rmin = 0.0f; ft->ncross = 0; ft->steps = 0; ft->status = OR_OK;
     if (p->model >= OR_MODEL_SCREEN_RING) {
         screen_fn(p, al, be, S);
@@ -772,7 +779,7 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
     double O[16] = { 1,0,0,0, 0,1,0,0, 0,0,1,0, 0,0,0,1 };
     double T1 = 1.0;   /* scalar transmission for the I-only path */
     double rmin = y[0];
-    int ncross = 0, nstep = 0, status = OR_OK;
+    int ncross = 0, nstep = 0, status = OR_OK, nturn = 0;
     int pol = (p->nstokes == 4);
     for (;;) {
         double k1[5], k2[5], k3[5], k4[5], yt[5], yn[5];
@@ -814,6 +821,7 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
         double krm = 0.5 * (y[3] + yn[3]), kthm = 0.5 * (y[4] + yn[4]);
         double J[4], aI, av[3], rv[3];
         if (plasma_point(p, rm, thm, phm, kt, kph, krm, kthm, &kap0, rh, risco, Eis, Lis, J, &aI, av, rv)) {
+            double I0 = S[0];
             if (pol) {
                 transfer_step4(S, O, aI, av, rv, J, h);
             } else {
@@ -821,8 +829,14 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
                 S[0] += T1 * h * phi1(w) * J[0];
                 T1 *= exp(-w);
             }
+            if (p->nsub > 0) {
+                int nq = p->nsub < OR_MAX_SUB ? p->nsub : OR_MAX_SUB;
+                int n = nturn < nq - 1 ? nturn : nq - 1;
+                S[4 + n] += S[0] - I0;
+            }
         }
         if (cos(y[1]) * cos(yn[1]) < 0.0) ncross++;
+        if (y[4] * yn[4] < 0.0) nturn++;
         if (rec && nstep < rec_cap) {
             for (int i = 0; i < 5; ++i) rec[nstep * 6 + i] = y[i];
             rec[nstep * 6 + 5] = h;
@@ -860,15 +874,18 @@ static void* worker(void* arg)
         if (i >= j->n) break;
         int e = i + 16 < j->n ? i + 16 : j->n;
         for (int k = i; k < e; ++k) {
-            double S[4];
+            double S[4 + OR_MAX_SUB];
             trace_one(j->p, j->al[k], j->be[k], S, &j->ft[k], 0, 0, 0);
-            for (int s = 0; s < j->nstokes; ++s) j->S[(size_t)k * j->nstokes + s] = S[s];
+            const int ns = j->nstokes, nq = j->p->nsub < OR_MAX_SUB ? j->p->nsub : OR_MAX_SUB;
+            for (int s = 0; s < ns; ++s) j->S[(size_t)k * (ns + nq) + s] = S[s];
+            for (int q = 0; q < nq; ++q) j->S[(size_t)k * (ns + nq) + ns + q] = S[4 + q];
         }
     }
     return 0;
 }
 
-/* Trace n screen points; S is n x nstokes (row-major), ft is n features. */
+/* Trace n screen points; S is n x (nstokes + nsub) (row-major: Stokes, then
+ * the subring planes of I), ft is n features. */
 int or_trace(const or_params* p, int n, const double* al, const double* be,
              double* S, void* feat, int nthreads)
 {
