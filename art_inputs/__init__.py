@@ -67,9 +67,9 @@ def workload(name):
                     mp=mks.grid_params(geo), nstokes=4, nx0=257, ny0=257, levels=4,
                     r_rel=1e-3, r_abs=0.025, abs_norm="mean", freq_hz=230e9, snapshot_seed=2)
     if name == "grid_16385":
-        # the snapshot refined 6 levels from 257^2 to 16385^2, Stokes I (the
-        # learned proposal's deployment size)
-        return dict(workload("grid_4097"), name=name, levels=6, nstokes=1)
+        # the snapshot refined 6 levels from 257^2 to 16385^2, Stokes I split
+        # into subrings n = 0..3 (the learned proposal's deployment size)
+        return dict(workload("grid_4097"), name=name, levels=6, nstokes=1, subrings=4)
     if name == "thermal_1025_mixed":
         return dict(workload("thermal_1025"), name=name, precision="mixed")
     raise KeyError(name)

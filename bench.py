@@ -279,8 +279,8 @@ def deploy_16385(art, torch, art_inputs, args):
     g = torch.from_numpy(grid).cuda()
     cfg = dict(art_inputs.workload("grid_16385"), grid_dev=g, precision=args.precision)
     nx, ny = art.image_size(cfg)
-    out = {"workload": "gridded snapshot a=0.94 i=163 deg, 230 GHz, Stokes I, base 257^2 -> 6 levels -> "
-                       "%dx%d, R_rel=1e-3, R_abs=0.025 Ibar_int" % (nx, ny)}
+    out = {"workload": "gridded snapshot a=0.94 i=163 deg, 230 GHz, Stokes I split into subrings n=0..3, "
+                       "base 257^2 -> 6 levels -> %dx%d, R_rel=1e-3, R_abs=0.025 Ibar_int" % (nx, ny)}
     t0 = time.perf_counter()
     train_cfgs = art_inputs.grid_training_workload(g, precision=args.precision) + \
         art_inputs.training_workload(precision=args.precision)
@@ -294,8 +294,17 @@ def deploy_16385(art, torch, art_inputs, args):
     truth, _, ust = art.render_uniform(cfg)
     torch.cuda.synchronize()
     t_uni = time.perf_counter() - t0
-    truth = truth[0]
-    out["uniform"] = dict(ms=t_uni * 1e3, rays=ust["rays"], rays_per_s=ust["rays"] / t_uni)
+    nsub = cfg["subrings"]
+
+    def sub_flux(img):
+        f = [float(img[1 + n].sum()) for n in range(nsub)]
+        return dict(flux=f, ratio=[f[n + 1] / f[n] if f[n] else None for n in range(nsub - 1)])
+
+    out["uniform"] = dict(ms=t_uni * 1e3, rays=ust["rays"], rays_per_s=ust["rays"] / t_uni,
+                          subrings=sub_flux(truth))
+
+    def sub_mse(img):
+        return [art.metrics(truth[1 + n], img[1 + n])[1] for n in range(nsub)]
     log("16385^2 uniform: %d rays in %.0f ms" % (ust["rays"], t_uni * 1e3))
     bufs = art.alloc(cfg, feat=True)
 
@@ -308,17 +317,18 @@ def deploy_16385(art, torch, art_inputs, args):
         return r, time.perf_counter() - t0
 
     (img, lev, ft, st), dt = timed(lambda: art.render(cfg, out=bufs))
-    fe, mse = art.metrics(truth, img[0])
+    fe, mse = art.metrics(truth[0], img[0])
     out["plain"] = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse=mse, flux_error=fe,
-                        effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt)
+                        effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt,
+                        subrings=sub_flux(img), subring_mse=sub_mse(img))
     log("16385^2 plain: %.0f ms, %d rays, mse %.2e" % (dt * 1e3, st["rays"], mse))
     for name, opts in (("learned_fallback", dict(z_propose=args.z_propose, fallback=True)),
                        ("learned_judge", dict(z_propose=args.z_propose, fallback=False))):
         (img, lev, ft, st), dt = timed(lambda: art.render_learned(cfg, net, out=bufs, **opts))
-        fe, mse = art.metrics(truth, img[0])
+        fe, mse = art.metrics(truth[0], img[0])
         out[name] = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse=mse, flux_error=fe,
                          effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt, judge=st["learned"],
-                         options=opts)
+                         options=opts, subrings=sub_flux(img), subring_mse=sub_mse(img))
         log("16385^2 %s: %.0f ms, %d rays, %d passes, mse %.2e, judge %s" % (
             name, dt * 1e3, st["rays"], st["trace_launches"], mse, st["learned"]))
     net.close()

@@ -18,7 +18,8 @@
  *    hole's distance; x = -fov/2 + i fov/(nx-1), square cells, y centred.
  *  - Buffers named *_dev are device pointers owned by the caller (the
  *    library never frees them).  Images are planar FP64:
- *    image[s][y][x], s = 0..nstokes-1 (I, Q, U, V).  The level map is int8
+ *    image[s][y][x], s = 0..nstokes-1 (I, Q, U, V), followed by the subring
+ *    planes of I when art_transfer.subrings > 0.  The level map is int8
  *    [y][x]: -1 interpolated, l >= 0 traced at refinement level l.  The
  *    feature buffer is art_ray_feat[y][x]: traced pixels get their ray's
  *    values; an interpolated pixel gets the smallest r_min and the largest
@@ -125,9 +126,16 @@ typedef struct {
 
 typedef struct {
     int32_t nstokes;               /* 1 (I) or 4 (I, Q, U, V) */
-    int32_t precision;             /* ART_PREC_* */
+    int32_t precision;             /* ART_PREC_* (subrings: FP64 or MIXED) */
     int32_t max_steps;             /* geodesic step cap (> 0) */
-    int32_t pad;
+    int32_t subrings;              /* 0..8: subring decomposition of Stokes I (Sec. 5.1).  The
+                                      image then has nstokes + subrings planes; plane
+                                      nstokes + n holds the I emitted on the ray's n-th
+                                      half-orbit, n = the number of theta turning points (sign
+                                      changes of k_theta) the backward ray passed before the
+                                      emission point; the last plane collects n >= subrings-1.
+                                      The planes sum to I.  Refinement decisions use I; the
+                                      planes are interpolated like Q, U, V. */
     double eps;                    /* step-rule accuracy, 0 < eps <= 0.5 */
     double fp64_radius;            /* ART_PREC_MIXED_GEO: FP64 steps where r < this [M]
                                       (photon shell, horizon); <= 0 selects 6 M */
@@ -195,7 +203,8 @@ int art_render_uniform(const art_spacetime* sp, const art_camera* cam, const art
                        const art_transfer* tr, art_image* out, art_stats* st, void* stream);
 
 /* Trace n arbitrary screen points (alpha_dev[i], beta_dev[i]) [M]; writes
- * stokes_dev[i*nstokes + s] (FP64) and, if feat_dev != NULL, art_ray_feat[i].
+ * stokes_dev[i*(nstokes+subrings) + s] (FP64: Stokes, then the subring
+ * planes of I) and, if feat_dev != NULL, art_ray_feat[i].
  * The camera's grid fields are ignored. */
 int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
                      const art_transfer* tr, int64_t n, const double* alpha_dev,

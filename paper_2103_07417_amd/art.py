@@ -51,7 +51,7 @@ class Refine(ctypes.Structure):
 
 class Transfer(ctypes.Structure):
     _fields_ = [("nstokes", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_steps", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("subrings", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("fp64_radius", ctypes.c_double),
                 ("fp64_ktheta", ctypes.c_double)]
 
@@ -181,7 +181,7 @@ def blocks(cfg):
     rf = Refine(float(cfg.get("r_rel", -1.0)), float(cfg.get("r_abs", -1.0)),
                 NORM[cfg.get("abs_norm", "mean")], 0)
     tr = Transfer(int(cfg.get("nstokes", 1)), PREC[cfg.get("precision", "fp64")],
-                  int(cfg.get("max_steps", 100000)), 0, float(cfg.get("eps", 0.03)),
+                  int(cfg.get("max_steps", 100000)), int(cfg.get("subrings", 0)), float(cfg.get("eps", 0.03)),
                   float(cfg.get("fp64_radius", 0.0)), float(cfg.get("fp64_ktheta", -1.0)))
     return sp, cam, em, rf, tr
 
@@ -216,11 +216,11 @@ def stats_dict(st):
 
 
 def alloc(cfg, feat=False):
-    """Output tensors for a render of cfg: image (nstokes, ny, nx) float64,
-    level map (ny, nx) int8, optional features (ny, nx, 4) int32 view."""
+    """Output tensors for a render of cfg: image (nstokes + subrings, ny, nx)
+    float64, level map (ny, nx) int8, optional features (ny, nx, 4) int32 view."""
     torch = _torch()
     nx, ny = image_size(cfg)
-    ns = int(cfg.get("nstokes", 1))
+    ns = int(cfg.get("nstokes", 1)) + int(cfg.get("subrings", 0))
     img = torch.empty((ns, ny, nx), dtype=torch.float64, device="cuda")
     lev = torch.empty((ny, nx), dtype=torch.int8, device="cuda")
     ft = torch.empty((ny, nx, 4), dtype=torch.int32, device="cuda") if feat else None
@@ -284,13 +284,13 @@ def render_learned(cfg, net, out=None, stats=True, stream=None, **opts):
 
 def trace_points(cfg, alpha, beta, feat=True, stream=None):
     """Trace arbitrary screen points.  alpha, beta: CUDA float64 tensors.
-    Returns (stokes (n, nstokes) float64, feat (n, 4) int32 or None)."""
+    Returns (stokes (n, nstokes + subrings) float64, feat (n, 4) int32 or None)."""
     torch = _torch()
     sp, cam, em, rf, tr = blocks(cfg)
     alpha = alpha.contiguous()
     beta = beta.contiguous()
     n = alpha.numel()
-    S = torch.empty((n, tr.nstokes), dtype=torch.float64, device=alpha.device)
+    S = torch.empty((n, tr.nstokes + tr.subrings), dtype=torch.float64, device=alpha.device)
     ft = torch.empty((n, 4), dtype=torch.int32, device=alpha.device) if feat else None
     rc = lib().art_trace_points(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em),
                                 ctypes.byref(tr), n, alpha.data_ptr(), beta.data_ptr(),

@@ -101,7 +101,7 @@ struct BatchGroup {
 struct art_batch {
     int dev = 0;
     int n = 0;
-    int model = 0, nstokes = 1, precision = 0;
+    int model = 0, nstokes = 1, precision = 0, nsub = 0;
     bool uniform = false;
     std::vector<Params> hP;
     std::vector<ImageDesc> hD;
@@ -149,6 +149,9 @@ int validate(const art_spacetime* sp, const art_camera* cam, const art_emission*
         return fail(ART_EINVAL, "unknown precision %d", tr->precision);
     if (std::isnan(tr->fp64_radius) || std::isnan(tr->fp64_ktheta))
         return fail(ART_EINVAL, "NaN precision-policy threshold");
+    if (tr->subrings < 0 || tr->subrings > kMaxSub) return fail(ART_EINVAL, "subrings must be in 0..%d", kMaxSub);
+    if (tr->subrings > 0 && tr->precision == ART_PREC_MIXED_GEO)
+        return fail(ART_EINVAL, "subrings need precision FP64 or MIXED");
     if (!(tr->eps > 0.0 && tr->eps <= 0.5)) return fail(ART_EINVAL, "eps must be in (0, 0.5]");
     if (tr->max_steps <= 0) return fail(ART_EINVAL, "max_steps must be > 0");
     const int k = em->kind;
@@ -252,6 +255,7 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
     circ_EL(a, P.risco, &P.Eis, &P.Lis);
     P.model = em->kind;
     P.nstokes = tr->nstokes;
+    P.nsub = tr->subrings;
     P.max_steps = tr->max_steps;
     P.freq = em->freq_hz;
     const double G = 6.67430e-8, C = 2.99792458e10, MSUN = 1.98847e33;
@@ -287,7 +291,7 @@ void theta_table(double h, int n2, double* out)
     }
 }
 
-LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes)
+LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes, bool sub = false)
 {
     LaunchCfg L;
     art_launch u;
@@ -297,7 +301,7 @@ LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes)
     }
     L.trace_threads = u.trace_threads > 0 ? u.trace_threads : env_int("ART_TRACE_THREADS", 256);
     if (L.trace_threads != 64 && L.trace_threads != 128 && L.trace_threads != 256) L.trace_threads = 256;
-    const int occ = trace_occupancy_blocks(precision, model, nstokes, L.trace_threads);
+    const int occ = trace_occupancy_blocks(precision, model, nstokes, sub, L.trace_threads);
     L.trace_blocks = u.trace_blocks > 0 ? u.trace_blocks : env_int("ART_TRACE_BLOCKS", cus * occ);
     if (L.trace_blocks < 1) L.trace_blocks = 1;
     L.refill = u.refill > 0 ? u.refill : env_int("ART_REFILL", 1);
@@ -463,8 +467,10 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
             b->model = J.em.kind;
             b->nstokes = J.tr.nstokes;
             b->precision = J.tr.precision;
-        } else if (J.em.kind != b->model || J.tr.nstokes != b->nstokes || J.tr.precision != b->precision) {
-            return fail(ART_EINVAL, "image %d: a batch needs one emission kind, nstokes and precision", i);
+            b->nsub = J.tr.subrings;
+        } else if (J.em.kind != b->model || J.tr.nstokes != b->nstokes || J.tr.precision != b->precision ||
+                   J.tr.subrings != b->nsub) {
+            return fail(ART_EINVAL, "image %d: a batch needs one emission kind, nstokes, precision and subring count", i);
         } else if (J.em.kind == ART_EMIS_GRID &&
                    (J.em.grid_dev != jobs[0].em.grid_dev || J.em.params[8] != jobs[0].em.params[8] ||
                     J.em.params[10] != jobs[0].em.params[10])) {
@@ -485,6 +491,8 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
         D.nx0 = J.cam.nx0; D.ny0 = J.cam.ny0;
         D.levels = uniform ? 0 : J.cam.levels;
         D.nstokes = J.tr.nstokes;
+        D.nplanes = J.tr.nstokes + J.tr.subrings;
+        D.pad = 0;
         D.abs_norm = J.rf.abs_norm;
         D.r_rel = J.rf.r_rel;
         D.r_abs = J.rf.r_abs;
@@ -494,7 +502,7 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
     if (total >= (1ULL << 31)) return fail(ART_EINVAL, "batch has %zu pixels (limit 2^31)", total);
     int rc = ensure_mem(b, uniform ? 0 : total);
     if (rc) return rc;
-    b->L = launch_cfg(b->cus, b->precision, b->model, b->nstokes);
+    b->L = launch_cfg(b->cus, b->precision, b->model, b->nstokes, b->nsub > 0);
     if (b->model == ART_EMIS_GRID) {
         const int n2 = (int)jobs[0].em.params[10];
         theta_table(jobs[0].em.params[8], n2, b->hTh);
@@ -545,7 +553,7 @@ int trace_pass(art_batch* b, int g, int level, hipStream_t s)
 {
     TraceJob J = base_job(b, g, level);
     HIP_TRY(ev_begin(b, g, s));
-    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, b->nsub > 0, J, b->L, s));
     HIP_TRY(ev_end(b, g, s));
     return ART_OK;
 }
@@ -702,7 +710,7 @@ int enqueue_uniform(art_batch* b, hipStream_t s)
     TraceJob J = base_job(b, 0, 0);
     J.list = nullptr;    // implicit list: item k = pixel k of image 0
     HIP_TRY(ev_begin(b, 0, s));
-    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, J, b->L, s));
+    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, b->nsub > 0, J, b->L, s));
     HIP_TRY(ev_end(b, 0, s));
     if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[1], s));
     return ART_OK;
@@ -896,7 +904,7 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
     b->grp[0].list_off = 0;
     b->hP.resize(1);
     make_params(sp, cam, em, tr, 0, 0, b->hP[0]);
-    b->L = launch_cfg(b->cus, tr->precision, em->kind, tr->nstokes);
+    b->L = launch_cfg(b->cus, tr->precision, em->kind, tr->nstokes, tr->subrings > 0);
     if (em->kind == ART_EMIS_GRID) {
         const int n2 = (int)em->params[10];
         theta_table(em->params[8], n2, b->hTh);
@@ -913,7 +921,7 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
     J.beta = beta_dev;
     J.out = stokes_dev;
     J.feat = (RayFeat*)feat_dev;
-    HIP_TRY(launch_trace(tr->precision, em->kind, tr->nstokes, J, b->L, s));
+    HIP_TRY(launch_trace(tr->precision, em->kind, tr->nstokes, tr->subrings > 0, J, b->L, s));
     return ART_OK;
 }
 
@@ -1015,7 +1023,7 @@ int art_batch_set_launch(art_batch* b, const art_launch* L)
     if (L->trace_blocks < 0 || L->refill < 0 || L->refill > 64)
         return fail(ART_EINVAL, "trace_blocks >= 0 and 0 <= refill <= 64 required");
     if (L->groups < 0 || L->groups > kMaxGroups) return fail(ART_EINVAL, "groups must be in 0..%d", kMaxGroups);
-    const LaunchCfg d = launch_cfg(b->cus, b->precision, b->model, b->nstokes);
+    const LaunchCfg d = launch_cfg(b->cus, b->precision, b->model, b->nstokes, b->nsub > 0);
     b->L.trace_threads = L->trace_threads ? L->trace_threads : d.trace_threads;
     b->L.trace_blocks = L->trace_blocks ? L->trace_blocks : d.trace_blocks;
     b->L.refill = L->refill ? L->refill : d.refill;

@@ -43,7 +43,7 @@ struct Params {
     double c_gtt, c_gtp, c_grr, c_ghh, c_gpp, c_del;
     // equatorial flow: ISCO radius, energy, angular momentum
     double risco, Eis, Lis;
-    int32_t model, nstokes, max_steps, pad;
+    int32_t model, nstokes, max_steps, nsub;   // nsub: subring planes of I (0..8)
     double freq, L_cm;
     double mp[16];
     double Bref, r_ref, psi_c, psi_s;   // thermal: |B| at r_ref, field phase

@@ -37,8 +37,11 @@ struct ImageDesc {
     uint16_t* cost;       // steps of each traced ray, neighbours' maximum for interpolated points
     long long plane;      // nx * ny
     int32_t nx, ny, nx0, ny0, levels, nstokes, abs_norm, base_off;
+    int32_t nplanes, pad;  // image planes: nstokes + subring planes
     double r_rel, r_abs;
 };
+
+constexpr int kMaxSub = 8;        // subring planes a ray accumulates
 
 enum TraceSrc : int { SRC_LIST = 0, SRC_POINTS = 1 };
 
@@ -79,8 +82,8 @@ hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_i8(int8_t* p, long long n, int8_t v, hipStream_t s);
 hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsigned long long* list,
                             Counters* ctr, int level_slot, hipStream_t s);
-hipError_t launch_trace(int precision, int model, int nstokes, const TraceJob& J, const LaunchCfg& L,
-                        hipStream_t s);
+hipError_t launch_trace(int precision, int model, int nstokes, bool subrings, const TraceJob& J,
+                        const LaunchCfg& L, hipStream_t s);
 hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s);
 // mode 0: plain criterion.  mode 1: learned, level l -> l+1 (points marked
 // proposed are traced, points marked suppressed are interpolated, the
@@ -95,6 +98,6 @@ hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl
                            hipStream_t s, int mode = 0, int fallback = 1);
 hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
                           int nblocks, hipStream_t s);
-int trace_occupancy_blocks(int precision, int model, int nstokes, int threads);
+int trace_occupancy_blocks(int precision, int model, int nstokes, bool subrings, int threads);
 
 }  // namespace art

@@ -89,20 +89,21 @@ hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsig
 }
 
 // ------------------------------------------------------------- ray tracing
-template <typename R, int MODEL, int NS>
+template <typename R, int MODEL, int NS, int SUB = 0>
 struct RayState {
     double y[5];
     double kt, kph, k0r, k0i;
     double cprev, rmin;
     R S[NS];
     R O[NS == 4 ? 16 : 1];
-    int ncross, nstep;
+    R Ssub[SUB > 0 ? SUB : 1];     // subring planes of I
+    int ncross, nstep, nturn;
     uint32_t pix;
     int img;
 };
 
-template <typename R, int MODEL, int NS>
-__device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>& st, double al, double be)
+template <typename R, int MODEL, int NS, int SUB>
+__device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS, SUB>& st, double al, double be)
 {
     RayStart rs;
     camera_start(P, al, be, rs);
@@ -121,6 +122,9 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>
     }
     st.ncross = 0;
     st.nstep = 0;
+    st.nturn = 0;
+#pragma unroll
+    for (int q = 0; q < (SUB > 0 ? SUB : 1); ++q) st.Ssub[q] = R(0);
 }
 
 // Advance one ray by one step.  Returns a RAY_* status (RAY_OK = continue).
@@ -131,8 +135,8 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS>
 // shell and horizon; |k_theta| < kth64: theta turning points; |sin theta| <
 // 0.1: the polar barrier); the state, the RK4 sums and the step rule stay
 // FP64.  The decision is wave-uniform.
-template <typename R, int MODEL, int NS, bool G32>
-__device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayState<R, MODEL, NS>& st,
+template <typename R, int MODEL, int NS, bool G32, int SUB>
+__device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayState<R, MODEL, NS, SUB>& st,
                                         unsigned& emit)
 {
     const double a = P.a;
@@ -197,6 +201,7 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
     Coef<R> C;
     if (plasma_point<R, MODEL>(P, tht, rm, thm, s, c, phm, st.kt, st.kph, krm, kthm, st.k0r, st.k0i, C)) {
         ++emit;
+        const R I0 = st.S[0];
         if constexpr (NS == 4) {
             transfer_step4<R, R>(st.S, st.O, C, R(h));
         } else {
@@ -204,6 +209,18 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
             st.S[0] += st.O[0] * R(h) * phi1_(w) * C.jI;
             st.O[0] *= fexp(-w);
         }
+        if constexpr (SUB > 0) {
+            // subring decomposition (Sec. 5.1): the step's increment of I goes
+            // to the plane of the half-orbits passed so far
+            const int n = st.nturn < P.nsub - 1 ? st.nturn : P.nsub - 1;
+            const R dI = st.S[0] - I0;
+#pragma unroll
+            for (int q = 0; q < SUB; ++q)
+                if (q == n) st.Ssub[q] += dI;
+        }
+    }
+    if constexpr (SUB > 0) {
+        if (st.y[4] * yt[4] < 0.0) st.nturn++;      // theta turning point
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) st.y[i] = yt[i];
@@ -215,7 +232,7 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
 // a ballot, one lane claims that many items with a single atomic, the items
 // are handed out by lane prefix; then every busy lane advances its ray by one
 // step.  The per-image parameter blocks are staged in LDS once per block.
-template <typename R, int MODEL, int NS, bool G32>
+template <typename R, int MODEL, int NS, bool G32, int SUB>
 __global__ __launch_bounds__(256) void k_trace(TraceJob J)
 {
     __shared__ Params sP[kMaxBatch];
@@ -235,7 +252,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
     }
     __syncthreads();
     const int lane = __lane_id();
-    RayState<R, MODEL, NS> st;
+    RayState<R, MODEL, NS, SUB> st;
     bool active = false, drained = false;
     unsigned long long my_steps = 0;
     unsigned my_emit = 0;
@@ -288,17 +305,23 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
                                 double S4[4];
                                 screen_fn(P, al, be, S4);
                                 RayFeat f; f.rmin = (float)P.r_cam; f.ncross = 0; f.steps = 0; f.status = RAY_OK;
+                                // a screen function has no rays: all of I in subring plane 0
                                 if (J.src == SRC_POINTS) {
-                                    for (int s = 0; s < P.nstokes; ++s) J.out[(long long)pix * P.nstokes + s] = S4[s];
+                                    const int np = P.nstokes + P.nsub;
+                                    for (int s = 0; s < P.nstokes; ++s) J.out[(long long)pix * np + s] = S4[s];
+                                    for (int q = 0; q < P.nsub; ++q)
+                                        J.out[(long long)pix * np + P.nstokes + q] = q == 0 ? S4[0] : 0.0;
                                     if (J.feat) J.feat[pix] = f;
                                 } else {
                                     const ImageDesc& D = J.desc[img];
                                     for (int s = 0; s < D.nstokes; ++s) D.img[s * D.plane + pix] = S4[s];
+                                    for (int q = D.nstokes; q < D.nplanes; ++q)
+                                        D.img[q * D.plane + pix] = q == D.nstokes ? S4[0] : 0.0;
                                     if (D.feat) D.feat[pix] = f;
                                 }
                                 hist[RAY_OK]++;
                             } else {
-                                ray_init<R, MODEL, NS>(P, st, al, be);
+                                ray_init<R, MODEL, NS, SUB>(P, st, al, be);
                                 active = true;
                             }
                         }
@@ -312,7 +335,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
         }
         if (active) {
             const Params& P = sP[st.img];
-            const int status = ray_step<R, MODEL, NS, G32>(P, sTh, st, my_emit);
+            const int status = ray_step<R, MODEL, NS, G32, SUB>(P, sTh, st, my_emit);
             if (status != RAY_OK) {
                 double Sd[4] = { 0.0, 0.0, 0.0, 0.0 };
 #pragma unroll
@@ -322,11 +345,22 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
                 RayFeat f;
                 f.rmin = (float)st.rmin; f.ncross = st.ncross; f.steps = st.nstep; f.status = stt;
                 if (J.src == SRC_POINTS) {
-                    for (int s = 0; s < P.nstokes; ++s) J.out[(long long)st.pix * P.nstokes + s] = Sd[s];
+                    const int np = P.nstokes + P.nsub;
+                    for (int s = 0; s < P.nstokes; ++s) J.out[(long long)st.pix * np + s] = Sd[s];
+                    if constexpr (SUB > 0) {
+#pragma unroll
+                        for (int q = 0; q < SUB; ++q)
+                            if (q < P.nsub) J.out[(long long)st.pix * np + P.nstokes + q] = (double)st.Ssub[q];
+                    }
                     if (J.feat) J.feat[st.pix] = f;
                 } else {
                     const ImageDesc& D = J.desc[st.img];
                     for (int s = 0; s < D.nstokes; ++s) D.img[s * D.plane + st.pix] = Sd[s];
+                    if constexpr (SUB > 0) {
+#pragma unroll
+                        for (int q = 0; q < SUB; ++q)
+                            if (D.nstokes + q < D.nplanes) D.img[(D.nstokes + q) * D.plane + st.pix] = (double)st.Ssub[q];
+                    }
                     if (D.feat) D.feat[st.pix] = f;
                     if (D.cost) D.cost[st.pix] = (uint16_t)(st.nstep < 65535 ? st.nstep : 65535);
                 }
@@ -352,42 +386,53 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
     }
 }
 
-// Kernel instantiation for (precision, model, nstokes): the screen test
-// functions run through the toy-disk instantiation (they never integrate).
-// precision 0: FP64 throughout; 1: FP64 geodesic, FP32 plasma and transfer;
-// 2: as 1 with FP32 geodesic right-hand sides outside the sensitive zones.
+// Kernel instantiation for (precision, model, nstokes, subrings): the screen
+// test functions run through the toy-disk instantiation (they never
+// integrate).  precision 0: FP64 throughout; 1: FP64 geodesic, FP32 plasma
+// and transfer; 2: as 1 with FP32 geodesic right-hand sides outside the
+// sensitive zones (no subring variant).
 template <typename F>
-static hipError_t dispatch(int precision, int model, int nstokes, F&& f)
+static hipError_t dispatch(int precision, int model, int nstokes, bool sub, F&& f)
 {
     const bool pol = nstokes == 4;
+    if (sub) {
+        if (precision == 0) {
+            if (model == MODEL_THERMAL) return pol ? f((k_trace<double, MODEL_THERMAL, 4, false, kMaxSub>)) : f((k_trace<double, MODEL_THERMAL, 1, false, kMaxSub>));
+            if (model == MODEL_GRID) return pol ? f((k_trace<double, MODEL_GRID, 4, false, kMaxSub>)) : f((k_trace<double, MODEL_GRID, 1, false, kMaxSub>));
+            return f((k_trace<double, MODEL_TOY, 1, false, kMaxSub>));
+        }
+        if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4, false, kMaxSub>)) : f((k_trace<float, MODEL_THERMAL, 1, false, kMaxSub>));
+        if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4, false, kMaxSub>)) : f((k_trace<float, MODEL_GRID, 1, false, kMaxSub>));
+        return f((k_trace<float, MODEL_TOY, 1, false, kMaxSub>));
+    }
     if (precision == 0) {
-        if (model == MODEL_THERMAL) return pol ? f((k_trace<double, MODEL_THERMAL, 4, false>)) : f((k_trace<double, MODEL_THERMAL, 1, false>));
-        if (model == MODEL_GRID) return pol ? f((k_trace<double, MODEL_GRID, 4, false>)) : f((k_trace<double, MODEL_GRID, 1, false>));
-        return f((k_trace<double, MODEL_TOY, 1, false>));
+        if (model == MODEL_THERMAL) return pol ? f((k_trace<double, MODEL_THERMAL, 4, false, 0>)) : f((k_trace<double, MODEL_THERMAL, 1, false, 0>));
+        if (model == MODEL_GRID) return pol ? f((k_trace<double, MODEL_GRID, 4, false, 0>)) : f((k_trace<double, MODEL_GRID, 1, false, 0>));
+        return f((k_trace<double, MODEL_TOY, 1, false, 0>));
     }
     if (precision == 1) {
-        if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4, false>)) : f((k_trace<float, MODEL_THERMAL, 1, false>));
-        if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4, false>)) : f((k_trace<float, MODEL_GRID, 1, false>));
-        return f((k_trace<float, MODEL_TOY, 1, false>));
+        if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4, false, 0>)) : f((k_trace<float, MODEL_THERMAL, 1, false, 0>));
+        if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4, false, 0>)) : f((k_trace<float, MODEL_GRID, 1, false, 0>));
+        return f((k_trace<float, MODEL_TOY, 1, false, 0>));
     }
-    if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4, true>)) : f((k_trace<float, MODEL_THERMAL, 1, true>));
-    if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4, true>)) : f((k_trace<float, MODEL_GRID, 1, true>));
-    return f((k_trace<float, MODEL_TOY, 1, true>));
+    if (model == MODEL_THERMAL) return pol ? f((k_trace<float, MODEL_THERMAL, 4, true, 0>)) : f((k_trace<float, MODEL_THERMAL, 1, true, 0>));
+    if (model == MODEL_GRID) return pol ? f((k_trace<float, MODEL_GRID, 4, true, 0>)) : f((k_trace<float, MODEL_GRID, 1, true, 0>));
+    return f((k_trace<float, MODEL_TOY, 1, true, 0>));
 }
 
-hipError_t launch_trace(int precision, int model, int nstokes, const TraceJob& J, const LaunchCfg& L,
-                        hipStream_t s)
+hipError_t launch_trace(int precision, int model, int nstokes, bool subrings, const TraceJob& J,
+                        const LaunchCfg& L, hipStream_t s)
 {
-    return dispatch(precision, model, nstokes, [&](auto kern) {
+    return dispatch(precision, model, nstokes, subrings, [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(L.trace_blocks), dim3(L.trace_threads), 0, s, J);
         return hipGetLastError();
     });
 }
 
-int trace_occupancy_blocks(int precision, int model, int nstokes, int threads)
+int trace_occupancy_blocks(int precision, int model, int nstokes, bool subrings, int threads)
 {
     int nb = 0;
-    hipError_t e = dispatch(precision, model, nstokes, [&](auto kern) {
+    hipError_t e = dispatch(precision, model, nstokes, subrings, [&](auto kern) {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, 0);
     });
     if (e != hipSuccess || nb < 1) nb = 1;
@@ -554,7 +599,7 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
             D.level[pix] = (int8_t)-1;
             const double w = 1.0 / m;
             D.img[pix] = Ssum * w;
-            for (int st = 1; st < D.nstokes; ++st) {
+            for (int st = 1; st < D.nplanes; ++st) {
                 const double* Is = I + st * D.plane;
                 const double S = nnb == 4 ? (Is[o[0]] + Is[o[1]]) + (Is[o[2]] + Is[o[3]]) : Is[o[0]] + Is[o[1]];
                 D.img[st * D.plane + pix] = S * w;
