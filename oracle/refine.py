@@ -30,6 +30,13 @@ diagonal unavailable uses twice the other diagonal's term; a point with no
 available axis is traced.  A NaN anywhere in the stencil traces.
 The decision is evaluated without division: trace iff
 |D| > (4 m R_abs) N_abs  and  |D| > (4 R_rel) |S|, m = 2 (1D) or 4 (2D).
+
+Nearest branch of Eqs. 5-6: eps_abs = G / Ibar_int, eps_rel = G / |I_nn| with
+G = sqrt(((I4-I1)/2)^2 + ((I3-I2)/2)^2) and I_nn = I1 (the nearest neighbour
+"chosen arbitrarily" as I1); in 1D G = |c-b|/2 and I_nn = b (reading).  The
+interpolated value is I_nn.  Per-plane criterion (option, A11 reading): the
+OR of the criterion over every plane, each plane's estimate compared with
+N_abs and with |Stokes I| (S or I_nn of plane 0).
 """
 import numpy as np
 
@@ -71,13 +78,14 @@ def _axis_terms(lo_in, hi_in, lo_out, hi_out, has_lo, has_hi):
 
 
 
-def level_stencil(img, nx0, ny0, l, s, nstokes):
+def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False):
     """Stencil sums for every new point of level l+1 (Sec. 3.2 categories 2-4).
 
     img holds the level-l values at multiples of 2s (final-grid units).
     Returns the new points' level-(l+1) indices (p, q), the neighbour sums
-    S per Stokes plane, the second-difference sum D of Stokes I, the
-    no-available-axis flag and the neighbour count m.
+    S per Stokes plane, the second-difference sum D of Stokes I (of every
+    plane, shape (nstokes, n), with all_planes), the no-available-axis flag
+    and the neighbour count m.
     """
     nxl, nyl = grid_size(nx0, l + 1), grid_size(ny0, l + 1)
     q, p = np.meshgrid(np.arange(nyl), np.arange(nxl), indexing="ij")
@@ -95,7 +103,8 @@ def level_stencil(img, nx0, ny0, l, s, nstokes):
 
     npt = p.size
     S_all = np.zeros((nstokes, npt))
-    D = np.zeros(npt)
+    nd = nstokes if all_planes else 1
+    D = np.zeros((nd, npt))
     inf = np.zeros(npt, dtype=bool)
     m = np.where(cat4, 4.0, 2.0)
     # categories 2 and 3: one axis (dx, dy) = (0, 1) or (1, 0)
@@ -105,13 +114,14 @@ def level_stencil(img, nx0, ny0, l, s, nstokes):
             lo_in, _ = val(pc - dx, qc - dy, st)
             hi_in, _ = val(pc + dx, qc + dy, st)
             S_all[st, cat] = lo_in + hi_in
-        lo_in, _ = val(pc - dx, qc - dy, 0)
-        hi_in, _ = val(pc + dx, qc + dy, 0)
-        lo_out, has_lo = val(pc - 3 * dx, qc - 3 * dy, 0)
-        hi_out, has_hi = val(pc + 3 * dx, qc + 3 * dy, 0)
-        _, Dc, infc = _axis_terms(lo_in, hi_in, lo_out, hi_out, has_lo, has_hi)
-        D[cat] = Dc
-        inf[cat] = infc
+        for st in range(nd):
+            lo_in, _ = val(pc - dx, qc - dy, st)
+            hi_in, _ = val(pc + dx, qc + dy, st)
+            lo_out, has_lo = val(pc - 3 * dx, qc - 3 * dy, st)
+            hi_out, has_hi = val(pc + 3 * dx, qc + 3 * dy, st)
+            _, Dc, infc = _axis_terms(lo_in, hi_in, lo_out, hi_out, has_lo, has_hi)
+            D[st, cat] = Dc
+            inf[cat] = infc
     # category 4: diagonals x' (I1 -> I4, outer I5, I8), y' (I2 -> I3, outer I6, I7)
     pc, qc = p[cat4], q[cat4]
     for st in range(nstokes):
@@ -120,27 +130,67 @@ def level_stencil(img, nx0, ny0, l, s, nstokes):
         i2, _ = val(pc + 1, qc - 1, st)
         i3, _ = val(pc - 1, qc + 1, st)
         S_all[st, cat4] = (i1 + i4) + (i2 + i3)
-    i1, _ = val(pc - 1, qc - 1, 0)
-    i4, _ = val(pc + 1, qc + 1, 0)
-    i2, _ = val(pc + 1, qc - 1, 0)
-    i3, _ = val(pc - 1, qc + 1, 0)
-    i5, h5 = val(pc - 3, qc - 3, 0)
-    i8, h8 = val(pc + 3, qc + 3, 0)
-    i6, h6 = val(pc + 3, qc - 3, 0)
-    i7, h7 = val(pc - 3, qc + 3, 0)
-    _, Dx, infx = _axis_terms(i1, i4, i5, i8, h5, h8)
-    _, Dy, infy = _axis_terms(i2, i3, i6, i7, h6, h7)
-    D[cat4] = np.where(infx, 2.0 * Dy, np.where(infy, 2.0 * Dx, Dx + Dy))
-    inf[cat4] = infx & infy
-    return p, q, S_all, D, inf, m
+    for st in range(nd):
+        i1, _ = val(pc - 1, qc - 1, st)
+        i4, _ = val(pc + 1, qc + 1, st)
+        i2, _ = val(pc + 1, qc - 1, st)
+        i3, _ = val(pc - 1, qc + 1, st)
+        i5, h5 = val(pc - 3, qc - 3, st)
+        i8, h8 = val(pc + 3, qc + 3, st)
+        i6, h6 = val(pc + 3, qc - 3, st)
+        i7, h7 = val(pc - 3, qc + 3, st)
+        _, Dx, infx = _axis_terms(i1, i4, i5, i8, h5, h8)
+        _, Dy, infy = _axis_terms(i2, i3, i6, i7, h6, h7)
+        D[st, cat4] = np.where(infx, 2.0 * Dy, np.where(infy, 2.0 * Dx, Dx + Dy))
+        inf[cat4] = infx & infy
+    return p, q, S_all, (D if all_planes else D[0]), inf, m
+
+
+def nearest_stencil(img, nx0, ny0, l, s, nstokes):
+    """Nearest-neighbour branch of Eqs. 5-6 for every new point of level l+1.
+
+    The nearest neighbour is the point's lower-left level-l neighbour: b (the
+    lower of the two neighbours on the point's axis) for categories 2-3, I1
+    for category 4.  Returns (p, q), the nearest values per plane (the
+    interpolated value) and the gradient magnitude per plane,
+    G = |c - b| / 2 (1D) or sqrt(((I4 - I1)/2)^2 + ((I3 - I2)/2)^2) (2D).
+    """
+    nxl, nyl = grid_size(nx0, l + 1), grid_size(ny0, l + 1)
+    q, p = np.meshgrid(np.arange(nyl), np.arange(nxl), indexing="ij")
+    new = (p % 2 == 1) | (q % 2 == 1)
+    p, q = p[new], q[new]
+    cat2 = (p % 2 == 0) & (q % 2 == 1)   # between below (b) and above (c)
+    cat3 = (p % 2 == 1) & (q % 2 == 0)   # between left (b) and right (c)
+    cat4 = (p % 2 == 1) & (q % 2 == 1)   # corners I1 (-,-), I4 (+,+), I2 (+,-), I3 (-,+)
+    Inn = np.zeros((nstokes, p.size))
+    G = np.zeros((nstokes, p.size))
+    for st in range(nstokes):
+        def val(sel, dp, dq):
+            return img[st, (q[sel] + dq) * s, (p[sel] + dp) * s]
+        for sel, (dp, dq) in ((cat2, (0, 1)), (cat3, (1, 0))):
+            b = val(sel, -dp, -dq)
+            c = val(sel, dp, dq)
+            Inn[st, sel] = b
+            G[st, sel] = np.abs(c - b) / 2.0
+        i1, i4 = val(cat4, -1, -1), val(cat4, 1, 1)
+        i2, i3 = val(cat4, 1, -1), val(cat4, -1, 1)
+        Inn[st, cat4] = i1
+        G[st, cat4] = np.sqrt(((i4 - i1) / 2.0) ** 2 + ((i3 - i2) / 2.0) ** 2)
+    return p, q, Inn, G
+
 
 def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
-           nstokes=1, forced_level=None):
+           nstokes=1, forced_level=None, interp="linear", all_planes=False):
     """Adaptive image by recursive subdivision.
 
-    ray_fn(x, y) -> (n, nstokes) array: traces screen points.
+    ray_fn(x, y) -> (n, nstokes) array: traces screen points (nstokes = the
+    number of image planes).
     forced_level: optional final-grid int array; if given, a candidate at
     level l+1 is traced iff forced_level == l+1 (mask-forced replay).
+    interp: "linear" (Eqs. 5-6 linear branch, interpolation by the neighbour
+    mean) or "nearest" (Eqs. 5-6 nearest branch, the nearest neighbour's
+    value).  all_planes: the decision is the OR of the criterion over every
+    plane, each plane's estimate measured against N_abs and |Stokes I|.
 
     Returns dict(img=(nstokes, ny, nx), level=(ny, nx) int8 with -1 for
     interpolated and l for traced at level l, n_abs, ibar, imax0, per-level
@@ -163,19 +213,33 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
     cand, traced = [nx0 * ny0], [nx0 * ny0]
     for l in range(levels):
         s = 1 << (levels - l - 1)          # spacing of the level-(l+1) grid
-        p, q, S_all, D, inf, m = level_stencil(img, nx0, ny0, l, s, nstokes)
-        npt = p.size
-        S = S_all[0]
-        thrA = (4.0 * m * r_abs) * n_abs
-        crel = 4.0 * r_rel
-        with np.errstate(invalid="ignore"):
-            dec = inf | np.isnan(D) | np.isnan(S) | (
-                (np.abs(D) > thrA) & (np.abs(D) > crel * np.abs(S)))
+        if interp == "nearest":
+            p, q, Inn, G = nearest_stencil(img, nx0, ny0, l, s, nstokes)
+            npt = p.size
+            planes = range(nstokes) if all_planes else range(1)
+            dec = np.zeros(npt, dtype=bool)
+            with np.errstate(invalid="ignore"):
+                for st in planes:
+                    dec |= np.isnan(G[st]) | ((G[st] > r_abs * n_abs) & (G[st] > r_rel * np.abs(Inn[0])))
+                dec |= np.isnan(Inn[0])
+            interp_vals = Inn
+        else:
+            p, q, S_all, D, inf, m = level_stencil(img, nx0, ny0, l, s, nstokes, all_planes)
+            npt = p.size
+            S = S_all[0]
+            thrA = (4.0 * m * r_abs) * n_abs
+            crel = 4.0 * r_rel
+            Ds = D if all_planes else D[None, :]
+            with np.errstate(invalid="ignore"):
+                dec = inf | np.isnan(S)
+                for Dp in Ds:
+                    dec |= np.isnan(Dp) | ((np.abs(Dp) > thrA) & (np.abs(Dp) > crel * np.abs(S)))
+            interp_vals = S_all * (1.0 / m)
         if forced_level is not None:
             dec = forced_level[q * s, p * s] == l + 1
         # interpolate everything first (level-l values only), then trace
         for st in range(nstokes):
-            img[st, q * s, p * s] = S_all[st] * (1.0 / m)
+            img[st, q * s, p * s] = interp_vals[st]
         tp, tq = p[dec] * s, q[dec] * s
         if tp.size:
             xs, ys = screen_coords(fov, nx, ny, tp, tq)

@@ -269,3 +269,93 @@ def test_metrics_hand_computed():
     assert metrics.flux_error(t, a) == pytest.approx(0.1, rel=1e-15)
     assert metrics.mse(t, a) == pytest.approx(1.0 / 30.0, rel=1e-15)
     assert metrics.interp_fraction(np.array([[0, -1], [-1, 2]])) == 0.5
+
+
+# ------------------------------------------------ nearest branch, per-plane criterion
+
+def test_nearest_infinite_tolerance_is_floor_upsampling():
+    n0, L = 5, 3
+    out = refine.refine(ring, 20.0, n0, n0, L, np.inf, np.inf, interp="nearest")
+    S = 1 << L
+    n = out["nx"]
+    xs = np.linspace(-10, 10, n)
+    X, Y = np.meshgrid(xs, xs)
+    base = ring(X[::S, ::S], Y[::S, ::S])[..., 0]
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    assert np.array_equal(out["img"][0], base[jj // S, ii // S])
+
+
+def test_nearest_negative_tolerance_is_uniform():
+    out = refine.refine(ring, 20.0, 9, 9, 2, -1.0, -1.0, interp="nearest")
+    assert np.array_equal(out["img"], refine.uniform(ring, 20.0, 33, 33))
+
+
+def _brute_force_nearest(fn, n0, L, r_rel, r_abs, fov):
+    """Per-point loops over the nearest branch of Eqs. 5-6 (one plane)."""
+    n = (1 << L) * (n0 - 1) + 1
+    xs = np.linspace(-fov / 2, fov / 2, n)
+    img = np.full((n, n), np.nan)
+    lev = np.full((n, n), -1, dtype=np.int8)
+    S0 = 1 << L
+    for j in range(0, n, S0):
+        for i in range(0, n, S0):
+            img[j, i] = fn(np.array([xs[i]]), np.array([xs[j]]))[0, 0]
+            lev[j, i] = 0
+    b0 = img[::S0, ::S0]
+    wx = np.ones(n0); wx[0] = wx[-1] = 0.5
+    nabs = float((wx[:, None] * wx[None, :] * b0).sum() / (n0 - 1) ** 2)
+    for l in range(L):
+        s = 1 << (L - l - 1)
+        nl = (1 << (l + 1)) * (n0 - 1) + 1
+        dec = {}
+        for q in range(nl):
+            for p in range(nl):
+                if p % 2 == 0 and q % 2 == 0:
+                    continue
+                v = lambda a, b: img[b * s, a * s]
+                if p % 2 == 1 and q % 2 == 1:
+                    i1, i4, i2, i3 = v(p - 1, q - 1), v(p + 1, q + 1), v(p + 1, q - 1), v(p - 1, q + 1)
+                    G = np.sqrt(((i4 - i1) / 2) ** 2 + ((i3 - i2) / 2) ** 2)
+                    nn = i1
+                elif q % 2 == 1:
+                    b, c = v(p, q - 1), v(p, q + 1)
+                    G, nn = abs(c - b) / 2, b
+                else:
+                    b, c = v(p - 1, q), v(p + 1, q)
+                    G, nn = abs(c - b) / 2, b
+                dec[(p, q)] = (G / nabs > r_abs and G / abs(nn) > r_rel, nn)
+        for (p, q), (t, nn) in dec.items():
+            if t:
+                img[q * s, p * s] = fn(np.array([xs[p * s]]), np.array([xs[q * s]]))[0, 0]
+                lev[q * s, p * s] = l + 1
+            else:
+                img[q * s, p * s] = nn
+    return img, lev
+
+
+def test_nearest_brute_force_9_to_33():
+    out = refine.refine(ring, 20.0, 9, 9, 2, 0.05, 0.02, interp="nearest")
+    img, lev = _brute_force_nearest(ring, 9, 2, 0.05, 0.02, 20.0)
+    assert np.array_equal(out["level"], lev)
+    assert np.array_equal(out["img"][0], img)
+    assert 0 < (lev > 0).sum() < (lev != 0).sum()
+
+
+def _planes(fn2):
+    return lambda x, y: np.concatenate([ring(x, y), fn2(x, y)], -1)
+
+
+@pytest.mark.parametrize("interp", ["linear", "nearest"])
+def test_all_planes_criterion(interp):
+    args = (20.0, 9, 9, 2, 0.02, 0.01, "mean", 2)
+    # a copy of I (or its negative, or zeros) as second plane changes nothing
+    base = refine.refine(_planes(lambda x, y: ring(x, y)), *args, interp=interp)
+    for fn2 in (lambda x, y: ring(x, y), lambda x, y: -ring(x, y), lambda x, y: 0 * ring(x, y)):
+        o = refine.refine(_planes(fn2), *args, interp=interp, all_planes=True)
+        assert np.array_equal(o["level"], base["level"])
+    # a sharp feature only in the second plane adds traced points at level 1
+    sharp = lambda x, y: np.stack([np.tanh((x - 1.3) / 0.2)], -1) * 0.5
+    a = refine.refine(_planes(sharp), 20.0, 9, 9, 1, 0.02, 0.01, "mean", 2, interp=interp)
+    b = refine.refine(_planes(sharp), 20.0, 9, 9, 1, 0.02, 0.01, "mean", 2, interp=interp, all_planes=True)
+    ta, tb = a["level"] == 1, b["level"] == 1
+    assert np.all(tb[ta]) and tb.sum() > ta.sum()
