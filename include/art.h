@@ -117,10 +117,19 @@ typedef struct {
     int64_t grid_len;              /* GRID: number of floats, n1 n2 n3 8 */
 } art_emission;
 
+/* interpolation and error estimate (Eqs. 5-6) */
+#define ART_INTERP_LINEAR  0   /* linear branch: neighbour mean, second differences */
+#define ART_INTERP_NEAREST 1   /* nearest branch: the nearest neighbour's value (I1 in 2D,
+                                  the lower/left neighbour in 1D), gradient estimate */
+
 typedef struct {
     double r_rel;                  /* R_rel (Sec. 3.2); < 0 traces every point */
     double r_abs;                  /* R_abs (Sec. 3.2) */
     int32_t abs_norm;              /* ART_NORM_MEAN or ART_NORM_MAX */
+    int32_t interp;                /* ART_INTERP_* */
+    int32_t all_planes;            /* 0: the criterion on Stokes I; 1: traced if the criterion
+                                      holds on any image plane (Q, U, V, subrings), each
+                                      plane's estimate compared with N_abs and |Stokes I| */
     int32_t pad;
 } art_refine;
 

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "art.h")
 
 EMIS = {"toy_disk": 1, "thermal": 2, "grid": 3, "screen_ring": 10, "screen_poly": 11}
 NORM = {"mean": 0, "max": 1}
+INTERP = {"linear": 0, "nearest": 1}
 PREC = {"fp64": 0, "mixed": 1, "mixed_geo": 2}
 STATUS_NAMES = ("ok", "captured", "escaped", "step_cap", "thick", "nan")
 
@@ -46,7 +47,8 @@ class Emission(ctypes.Structure):
 
 class Refine(ctypes.Structure):
     _fields_ = [("r_rel", ctypes.c_double), ("r_abs", ctypes.c_double),
-                ("abs_norm", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("abs_norm", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("all_planes", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Transfer(ctypes.Structure):
@@ -179,7 +181,8 @@ def blocks(cfg):
         em.grid_dev = g.data_ptr()
         em.grid_len = g.numel()
     rf = Refine(float(cfg.get("r_rel", -1.0)), float(cfg.get("r_abs", -1.0)),
-                NORM[cfg.get("abs_norm", "mean")], 0)
+                NORM[cfg.get("abs_norm", "mean")], INTERP[cfg.get("interp", "linear")],
+                1 if cfg.get("all_planes", False) else 0, 0)
     tr = Transfer(int(cfg.get("nstokes", 1)), PREC[cfg.get("precision", "fp64")],
                   int(cfg.get("max_steps", 100000)), int(cfg.get("subrings", 0)), float(cfg.get("eps", 0.03)),
                   float(cfg.get("fp64_radius", 0.0)), float(cfg.get("fp64_ktheta", -1.0)))

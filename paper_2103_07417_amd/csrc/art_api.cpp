@@ -462,6 +462,8 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
                 return fail(ART_EINVAL, "image %d: unknown abs_norm %d", i, J.rf.abs_norm);
             if (std::isnan(J.rf.r_rel) || std::isnan(J.rf.r_abs))
                 return fail(ART_EINVAL, "image %d: NaN tolerance", i);
+            if (J.rf.interp != ART_INTERP_LINEAR && J.rf.interp != ART_INTERP_NEAREST)
+                return fail(ART_EINVAL, "image %d: unknown interpolation %d", i, J.rf.interp);
         }
         if (i == 0) {
             b->model = J.em.kind;
@@ -492,7 +494,8 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
         D.levels = uniform ? 0 : J.cam.levels;
         D.nstokes = J.tr.nstokes;
         D.nplanes = J.tr.nstokes + J.tr.subrings;
-        D.pad = 0;
+        D.flags = uniform ? 0 : ((J.rf.interp == ART_INTERP_NEAREST ? kRefineNearest : 0) |
+                                 (J.rf.all_planes ? kRefineAllPlanes : 0));
         D.abs_norm = J.rf.abs_norm;
         D.r_rel = J.rf.r_rel;
         D.r_abs = J.rf.r_abs;

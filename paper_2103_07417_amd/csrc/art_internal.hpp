@@ -37,9 +37,13 @@ struct ImageDesc {
     uint16_t* cost;       // steps of each traced ray, neighbours' maximum for interpolated points
     long long plane;      // nx * ny
     int32_t nx, ny, nx0, ny0, levels, nstokes, abs_norm, base_off;
-    int32_t nplanes, pad;  // image planes: nstokes + subring planes
+    int32_t nplanes;       // image planes: nstokes + subring planes
+    int32_t flags;         // kRefine* bits
     double r_rel, r_abs;
 };
+
+constexpr int32_t kRefineNearest = 1;     // nearest branch of Eqs. 5-6 and nearest interpolation
+constexpr int32_t kRefineAllPlanes = 2;   // criterion ORed over every image plane
 
 constexpr int kMaxSub = 8;        // subring planes a ray accumulates
 

@@ -559,10 +559,51 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
             m = 2.0;
         }
         const double nabs = ctr->scal[img][2];
-        const double thrA = (4.0 * m * D.r_abs) * nabs;
-        const double crel = 4.0 * D.r_rel;
-        const double aD = ::fabs(D2);
-        const bool crit = !avail || !(D2 == D2) || !(Ssum == Ssum) || (aD > thrA && aD > crel * ::fabs(Ssum));
+        const bool nearest = (D.flags & kRefineNearest) != 0;
+        const bool allp = (D.flags & kRefineAllPlanes) != 0;
+        bool crit;
+        if (nearest) {
+            // nearest branch of Eqs. 5-6: G = |c - b|/2 (1D) or
+            // sqrt(((I4 - I1)/2)^2 + ((I3 - I2)/2)^2) (2D), against N_abs and |I_nn|
+            const double thrA = D.r_abs * nabs;
+            const double inn = ::fabs(I[o[0]]);
+            crit = !(I[o[0]] == I[o[0]]);
+            for (int st = 0; st < (allp ? D.nplanes : 1); ++st) {
+                const double* Is = I + st * D.plane;
+                double G;
+                if (nnb == 4) {
+                    const double gx = 0.5 * (Is[o[1]] - Is[o[0]]), gy = 0.5 * (Is[o[3]] - Is[o[2]]);
+                    G = ::sqrt(gx * gx + gy * gy);
+                } else {
+                    G = 0.5 * ::fabs(Is[o[1]] - Is[o[0]]);
+                }
+                crit = crit || !(G == G) || (G > thrA && G > D.r_rel * inn);
+            }
+        } else {
+            const double thrA = (4.0 * m * D.r_abs) * nabs;
+            const double crel = 4.0 * D.r_rel;
+            const double aS = ::fabs(Ssum);
+            const double aD = ::fabs(D2);
+            crit = !avail || !(D2 == D2) || !(Ssum == Ssum) || (aD > thrA && aD > crel * aS);
+            if (allp) {
+                // the same estimate on every further plane (Q, U, V, subrings)
+                for (int st = 1; st < D.nplanes; ++st) {
+                    const double* Is = I + st * D.plane;
+                    double Dp;
+                    if (c4) {
+                        double Dx, Dy;
+                        const bool ax = axis_D(Is, NX, s, nxl, nyl, p, q, 1, 1, Is[o[0]], Is[o[1]], Dx);
+                        const bool ay = axis_D(Is, NX, s, nxl, nyl, p, q, -1, 1, Is[o[2]], Is[o[3]], Dy);
+                        Dp = ax ? (ay ? Dx + Dy : 2.0 * Dx) : 2.0 * Dy;
+                    } else {
+                        const int dx = (p & 1) ? 1 : 0, dy = (p & 1) ? 0 : 1;
+                        axis_D(Is, NX, s, nxl, nyl, p, q, dx, dy, Is[o[0]], Is[o[1]], Dp);
+                    }
+                    const double aDp = ::fabs(Dp);
+                    crit = crit || !(Dp == Dp) || (aDp > thrA && aDp > crel * aS);
+                }
+            }
+        }
         bool keep = false;               // point already traced by a look-ahead pass
         if (mode == 0) {
             trace = crit;
@@ -597,12 +638,17 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
             D.level[pix] = (int8_t)(l + 1);
         } else if (!keep) {
             D.level[pix] = (int8_t)-1;
-            const double w = 1.0 / m;
-            D.img[pix] = Ssum * w;
-            for (int st = 1; st < D.nplanes; ++st) {
-                const double* Is = I + st * D.plane;
-                const double S = nnb == 4 ? (Is[o[0]] + Is[o[1]]) + (Is[o[2]] + Is[o[3]]) : Is[o[0]] + Is[o[1]];
-                D.img[st * D.plane + pix] = S * w;
+            if (D.flags & kRefineNearest) {
+                // nearest neighbour: I1 (2D) or the lower neighbour b (1D)
+                for (int st = 0; st < D.nplanes; ++st) D.img[st * D.plane + pix] = I[st * D.plane + o[0]];
+            } else {
+                const double w = 1.0 / m;
+                D.img[pix] = Ssum * w;
+                for (int st = 1; st < D.nplanes; ++st) {
+                    const double* Is = I + st * D.plane;
+                    const double S = nnb == 4 ? (Is[o[0]] + Is[o[1]]) + (Is[o[2]] + Is[o[3]]) : Is[o[0]] + Is[o[1]];
+                    D.img[st * D.plane + pix] = S * w;
+                }
             }
             if (D.feat) {
                 // interpolated points inherit the smallest radius and the largest

@@ -14,8 +14,10 @@ def rel_l2(a, b):
 
 def oracle_adaptive(cfg, forced=None, grid=None):
     fn = lambda x, y: oray.trace(cfg, x, y, grid=grid)[0]
+    planes = cfg["nstokes"] + cfg.get("subrings", 0)
     return oref.refine(fn, cfg["fov"], cfg["nx0"], cfg["ny0"], cfg["levels"], cfg["r_rel"],
-                       cfg["r_abs"], cfg["abs_norm"], cfg["nstokes"], forced_level=forced)
+                       cfg["r_abs"], cfg["abs_norm"], planes, forced_level=forced,
+                       interp=cfg.get("interp", "linear"), all_planes=cfg.get("all_planes", False))
 
 
 def check_adaptive(art, cfg, img_tol, grid=None):
@@ -30,7 +32,7 @@ def check_adaptive(art, cfg, img_tol, grid=None):
     if flips:
         assert flips <= max(2, gl.size // 10000), flips
         o = oracle_adaptive(cfg, forced=gl, grid=grid)
-    for s in range(cfg["nstokes"]):
+    for s in range(cfg["nstokes"] + cfg.get("subrings", 0)):
         assert rel_l2(g[s], o["img"][s]) <= img_tol, (s, rel_l2(g[s], o["img"][s]))
     assert st["rays"] == int((gl >= 0).sum())
     assert abs(st["interp_frac"] - o["interp_frac"]) <= flips / gl.size + 1e-15

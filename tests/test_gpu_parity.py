@@ -175,3 +175,21 @@ def test_invalid_arguments(art):
                 dict(r_cam=1.0), dict(inc_deg=0.0)):
         with pytest.raises(art.ArtError):
             art.render(dict(base, **bad))
+
+
+@pytest.mark.parametrize("interp,all_planes,subrings", [("nearest", False, 0), ("nearest", True, 0),
+                                                       ("linear", True, 0), ("linear", True, 3),
+                                                       ("nearest", True, 3)])
+def test_refinement_variants(art, interp, all_planes, subrings):
+    """Nearest branch of Eqs. 5-6 and the per-plane criterion (Stokes and
+    subring planes) against the oracle: decisions up to floating-point ties,
+    images to 1e-6 after the mask-forced replay."""
+    from gpu_helpers import check_adaptive
+    print_case("refinement variant", interp=interp, all_planes=all_planes, subrings=subrings)
+    cfg = dict(art_inputs.reduced(art_inputs.workload("thermal_1025"), 9, 3), interp=interp,
+               all_planes=all_planes, subrings=subrings, r_rel=0.05, r_abs=0.01)
+    g, gl, st, o = check_adaptive(art, cfg, 1e-6)
+    assert 0.0 < st["interp_frac"] < 1.0
+    if all_planes:
+        one = art.render(dict(cfg, all_planes=False))[3]
+        assert st["rays"] >= one["rays"]
