@@ -322,6 +322,15 @@ def deploy_16385(art, torch, art_inputs, args):
                         effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt,
                         subrings=sub_flux(img), subring_mse=sub_mse(img))
     log("16385^2 plain: %.0f ms, %d rays, mse %.2e" % (dt * 1e3, st["rays"], mse))
+    # the criterion on every plane (I and the four subring planes)
+    cfg_all = dict(cfg, all_planes=True)
+    (img, lev, ft, st), dt = timed(lambda: art.render(cfg_all, out=bufs))
+    fe, mse = art.metrics(truth[0], img[0])
+    out["plain_all_planes"] = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse=mse,
+                                   flux_error=fe, effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt,
+                                   subrings=sub_flux(img), subring_mse=sub_mse(img))
+    log("16385^2 plain, criterion on every plane: %.0f ms, %d rays, mse %.2e, subring mse %s" % (
+        dt * 1e3, st["rays"], mse, ["%.2e" % x for x in out["plain_all_planes"]["subring_mse"]]))
     for name, opts in (("learned_fallback", dict(z_propose=args.z_propose, fallback=True)),
                        ("learned_judge", dict(z_propose=args.z_propose, fallback=False))):
         (img, lev, ft, st), dt = timed(lambda: art.render_learned(cfg, net, out=bufs, **opts))
