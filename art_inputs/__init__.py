@@ -9,6 +9,18 @@ inputs.
 import numpy as np
 
 SGRA_MASS_MSUN = 4.0e6       # Sec. 3.1 semi-analytic model: M = 4e6 Msun, D = 7.78 kpc
+SGRA_DIST_PC = 7780.0
+
+
+def theta_m_rad(mass_msun=SGRA_MASS_MSUN, dist_pc=SGRA_DIST_PC):
+    """Angular size of one gravitational radius GM / (c^2 D) in radians."""
+    G, c, msun, pc = 6.67430e-8, 2.99792458e10, 1.98847e33, 3.0856775814913673e18
+    return G * mass_msun * msun / (c * c) / (dist_pc * pc)
+
+
+def glambda_to_inv_m(u_glambda, mass_msun=SGRA_MASS_MSUN, dist_pc=SGRA_DIST_PC):
+    """Baseline length in G-lambda -> cycles per gravitational radius on the screen."""
+    return float(u_glambda) * 1e9 * theta_m_rad(mass_msun, dist_pc)
 
 
 def thermal_params(seed=1, n0=2.0e6, theta0=100.0, beta_ref=10.0, r_ref=10.0,
@@ -149,3 +161,34 @@ def reduced(cfg, nx0, levels):
     c["nx0"] = c["ny0"] = nx0
     c["levels"] = levels
     return c
+
+
+def vis_image(ny, nx, fov, seed=0, planes=1, ring_radius=None, width=None):
+    """Seeded synthetic screen images for visibility tests, float64 numpy
+    [planes, ny, nx] on the vertex grid of `fov` (pixel dx = fov / (nx - 1)):
+    a thin Gaussian-profile ring with a brightness asymmetry, a few Gaussian
+    blobs and a low-amplitude noise floor, different per plane (evaluated with
+    torch CPU tensors in bands of rows, for speed at 16385^2)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dx = fov / (nx - 1)
+    x = torch.from_numpy((np.arange(nx) - 0.5 * (nx - 1)) * dx)
+    y = torch.from_numpy((np.arange(ny) - 0.5 * (ny - 1)) * dx)
+    out = np.empty((planes, ny, nx))
+    for p in range(planes):
+        r0 = ring_radius if ring_radius is not None else 0.13 * fov * (1.0 + 0.1 * p)
+        w = width if width is not None else max(3.0 * dx, 0.01 * fov)
+        phase = rng.uniform(0, 6.3)
+        blobs = [(rng.uniform(-0.25, 0.25, 2) * fov, rng.uniform(0.02, 0.08) * fov, rng.uniform(0.2, 1.0))
+                 for _ in range(3)]
+        noise = np.random.default_rng([seed, p])
+        for j0 in range(0, ny, 1024):
+            yy = y[j0:j0 + 1024]
+            Y = yy[:, None].expand(yy.numel(), nx)
+            X = x[None, :].expand(yy.numel(), nx)
+            r = torch.hypot(X, Y)
+            img = torch.exp(-0.5 * ((r - r0) / w) ** 2) * (1.0 + 0.6 * torch.cos(torch.atan2(Y, X) - phase))
+            for (cx, cy), s, amp in blobs:
+                img += amp * torch.exp(-0.5 * ((X - cx) ** 2 + (Y - cy) ** 2) / (s * s))
+            out[p, j0:j0 + 1024] = img.numpy() + 0.01 * noise.random((yy.numel(), nx))
+    return out

@@ -390,6 +390,26 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
 int art_metrics(const double* truth_dev, const double* approx_dev, int64_t n,
                 double* flux_error, double* mse, void* stream);
 
+/* Visibilities of screen images (Sec. 4.3): complex Fourier components on a
+ * rectangle of baselines, u_dev[nu] x v_dev[nv] in cycles per unit of screen
+ * coordinate,
+ *   V(u_m, v_l) = dx^2 sum_j sum_i g(x_i) g(y_j) I[j][i] exp(-2 pi i (u_m x_i + v_l y_j)),
+ * pixel (j, i) at x_i = (i - (nx-1)/2) dx, y_j = (j - (ny-1)/2) dx (square
+ * pixels, image centre on the origin), for each of `nplanes` FP64 planes
+ * I = img_dev + z * plane_stride (row-major ny x nx, device).  The Gaussian
+ * taper g(x) = exp(-4 ln 2 x^2 / fwhm^2) is the paper's guard against power
+ * from the field edge (fwhm <= 0: none).  Output vis_dev[nplanes][nv][nu][2]
+ * (re, im) FP64, device; the residual visibilities of Sec. 4.3 are those of
+ * the residual image.  Computed in FP64 (matrix cores) as two separable
+ * stages through the caller's device workspace of art_vis_workspace_bytes()
+ * bytes; asynchronous on `stream`, no allocation.  Empty images give V = 0;
+ * nplanes, nu or nv = 0 is a no-op.  ART_EINVAL for negative or oversized
+ * sizes, dx <= 0, a non-finite fwhm, NULL pointers or a short workspace. */
+size_t art_vis_workspace_bytes(int32_t nplanes, int32_t nx, int32_t ny, int32_t nu, int32_t nv);
+int art_visibility(const double* img_dev, int64_t plane_stride, int32_t nplanes, int32_t nx, int32_t ny,
+                   double dx, double fwhm, const double* u_dev, int32_t nu, const double* v_dev, int32_t nv,
+                   double* vis_dev, void* work_dev, size_t work_bytes, void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* art_last_error(void);
 

@@ -98,7 +98,7 @@ _lib = None
 def header_functions():
     """Names of the functions declared in include/art.h."""
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(art_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(art_\w+)\s*\(", txt, re.M)))
 
 
 def lib():
@@ -143,6 +143,10 @@ def lib():
         L.art_batch_set_learned.argtypes = [vp, vp, P(Learned)]
         L.art_render_learned.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine),
                                          P(Transfer), vp, P(Learned), P(Image), P(Stats), vp]
+        L.art_vis_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
+        L.art_vis_workspace_bytes.restype = ctypes.c_size_t
+        L.art_visibility.argtypes = [vp, i64, i32, i32, i32, ctypes.c_double, ctypes.c_double, vp, i32,
+                                     vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.art_last_error.restype = ctypes.c_char_p
         L.art_last_error.argtypes = []
         L.art_release.argtypes = []
@@ -312,6 +316,39 @@ def metrics(truth, approx, stream=None):
     _check(lib().art_metrics(t.data_ptr(), a.data_ptr(), t.numel(), ctypes.byref(fe),
                              ctypes.byref(mse), _stream(torch, stream)))
     return fe.value, mse.value
+
+
+def visibility(img, dx, u, v, fwhm=0.0, stream=None):
+    """Visibilities V[..., l, m] = V(u_m, v_l) (complex128, device) of FP64
+    image planes img[..., ny, nx] (Sec. 4.3; u, v in cycles per unit of
+    screen coordinate, pixel size dx, Gaussian taper FWHM fwhm, <= 0: none)."""
+    torch = _torch()
+    if img.dtype != torch.float64 or not img.is_cuda:
+        raise ArtError("visibility: the image must be a float64 CUDA tensor")
+    if img.dim() < 2:
+        raise ArtError("visibility: the image needs at least two dimensions (ny, nx)")
+    cur = torch.cuda.current_stream(img.device)
+    st = stream if stream is not None else cur
+    x = img.contiguous()
+    ny, nx = x.shape[-2], x.shape[-1]
+    lead = tuple(x.shape[:-2])
+    P = 1
+    for d in lead:
+        P *= d
+    uu = torch.as_tensor(u, dtype=torch.float64).reshape(-1).to(x.device).contiguous()
+    vv = torch.as_tensor(v, dtype=torch.float64).reshape(-1).to(x.device).contiguous()
+    nu, nv = uu.numel(), vv.numel()
+    out = torch.empty(lead + (nv, nu, 2), dtype=torch.float64, device=x.device)
+    nbytes = lib().art_vis_workspace_bytes(P, nx, ny, nu, nv)
+    work = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=x.device)
+    if st != cur:
+        st.wait_stream(cur)
+        for t in (x, uu, vv, out, work):
+            t.record_stream(st)
+    _check(lib().art_visibility(x.data_ptr() if x.numel() else None, ny * nx, P, nx, ny, float(dx),
+                                float(fwhm), uu.data_ptr(), nu, vv.data_ptr(), nv,
+                                out.data_ptr(), work.data_ptr(), nbytes, ctypes.c_void_p(st.cuda_stream)))
+    return torch.view_as_complex(out)
 
 
 def feat_numpy(ft):

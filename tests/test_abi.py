@@ -55,3 +55,27 @@ def test_product_package_does_not_reference_the_oracle():
                 txt = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "ray_oracle" not in txt, f
+
+
+def test_visibility_validation_host_only():
+    L = art.lib()
+    dp = ctypes.c_void_p
+    # workspace sizes: rows first when the u list is the shorter one
+    assert L.art_vis_workspace_bytes(1, 100, 80, 10, 20) == 8 * (80 * 2 * 10 + 4 * 10 * 20)
+    assert L.art_vis_workspace_bytes(2, 100, 80, 20, 10) == 8 * 2 * (100 * 2 * 10 + 4 * 10 * 20)
+    assert L.art_vis_workspace_bytes(1, 100, 80, 0, 10) == 0
+    fake = dp(0x1000)   # never dereferenced: every case below fails validation or is a no-op
+
+    def call(P=1, nx=16, ny=16, dx=0.1, fwhm=0.0, nu=4, nv=4, work=fake, nbytes=1 << 20, stride=256):
+        return L.art_visibility(fake, stride, P, nx, ny, dx, fwhm, fake, nu, fake, nv, fake, work, nbytes, None)
+
+    assert call(nx=-1) == -1
+    assert call(dx=0.0) == -1
+    assert call(dx=float("nan")) == -1
+    assert call(fwhm=float("inf")) == -1
+    assert call(nu=(1 << 20) + 1) == -1
+    assert call(nbytes=16) == -1
+    assert call(work=None) == -1
+    assert call(P=2, stride=100) == -1
+    assert b"workspace" in L.art_last_error() or b"stride" in L.art_last_error()
+    assert call(nu=0) == 0 and call(nv=0) == 0 and call(P=0) == 0
