@@ -331,8 +331,8 @@ def deploy_16385(art, torch, art_inputs, args):
                                    subrings=sub_flux(img), subring_mse=sub_mse(img))
     log("16385^2 plain, criterion on every plane: %.0f ms, %d rays, mse %.2e, subring mse %s" % (
         dt * 1e3, st["rays"], mse, ["%.2e" % x for x in out["plain_all_planes"]["subring_mse"]]))
-    for name, opts in (("learned_fallback", dict(z_propose=args.z_propose, fallback=True)),
-                       ("learned_judge", dict(z_propose=args.z_propose, fallback=False))):
+    for name, opts in (("learned_judge", dict(z_propose=args.z_propose, fallback=False)),
+                       ("learned_fallback", dict(z_propose=args.z_propose, fallback=True))):
         (img, lev, ft, st), dt = timed(lambda: art.render_learned(cfg, net, out=bufs, **opts))
         fe, mse = art.metrics(truth[0], img[0])
         out[name] = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse=mse, flux_error=fe,
@@ -341,9 +341,93 @@ def deploy_16385(art, torch, art_inputs, args):
         log("16385^2 %s: %.0f ms, %d rays, %d passes, mse %.2e, judge %s" % (
             name, dt * 1e3, st["rays"], st["trace_launches"], mse, st["learned"]))
     net.close()
+    out["visibility"] = deploy_visibility(art, torch, art_inputs, cfg, img, truth)
     del bufs, truth, img, lev, ft, g
     torch.cuda.empty_cache()
     return out
+
+
+def deploy_visibility(art, torch, art_inputs, cfg, img, truth):
+    """Visibility domain of the learned 16385^2 render (Sec. 4.3): the 2D
+    window |u|, |v| <= 1000 G-lambda (Sgr A* mass and distance) on the
+    1/FOV grid, u >= 0 half plane, taper FWHM = FOV/4, for Stokes I and the
+    four subring planes, and for the residual image (learned - uniform)."""
+    fov = float(cfg["fov"])
+    ny, nx = img.shape[1], img.shape[2]
+    dx = fov / (nx - 1)
+    per_gl = art_inputs.glambda_to_inv_m(1.0)            # cycles per M per G-lambda
+    du = 1.0 / fov
+    k = int(np.floor(art_inputs.glambda_to_inv_m(1000.0) / du + 1e-9))
+    u = torch.arange(0, k + 1, dtype=torch.float64, device="cuda") * du
+    v = torch.arange(-k, k + 1, dtype=torch.float64, device="cuda") * du
+    P = img.shape[0]
+    art.visibility(img, dx, u, v, fwhm=fov / 4)          # warm (workspace in the caching allocator)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    V = art.visibility(img, dx, u, v, fwhm=fov / 4)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nu, nv = u.numel(), v.numel()
+    flops = 2.0 * P * (ny * nx * 2.0 * nu + 2.0 * nu * ny * 2.0 * nv)
+    resid = (img[0] - truth[0]).unsqueeze(0).contiguous()
+    Vr = art.visibility(resid, dx, u, v, fwhm=fov / 4)[0]
+    Vt = art.visibility(truth[0:1].contiguous(), dx, u, v, fwhm=fov / 4)[0]
+    torch.cuda.synchronize()
+    A = V.abs()
+    ratio = (Vr.abs() / Vt.abs().clamp_min(1e-300)).flatten()
+    q = torch.quantile(ratio[torch.randperm(ratio.numel(), device="cuda")[:1 << 20]],
+                       torch.tensor([0.5, 0.99], dtype=torch.float64, device="cuda")).cpu().tolist()
+    uaxis = A[:, k, :].cpu().numpy()                     # |V(u, 0)| per plane
+    vaxis = A[:, :, 0].cpu().numpy()[:, k:]              # |V(0, v)|, v >= 0
+    ug = u.cpu().numpy() / per_gl
+
+    def envelope(a, w=9):
+        pad = np.pad(a, w // 2, mode="edge")
+        return np.lib.stride_tricks.sliding_window_view(pad, w).max(-1)
+
+    def crossings(ax):
+        # first baseline where the envelope of subring s+1 exceeds that of subring s
+        out = []
+        for s_ in range(P - 2):
+            idx = np.nonzero(envelope(ax[2 + s_]) > envelope(ax[1 + s_]))[0]
+            out.append(float(ug[idx[0]]) if idx.size else None)
+        return out
+
+    # ring period (Sec. 4.3.1): |V(u, 0)| of a ring of diameter d oscillates
+    # with period 1/d; measured on subring n = 2 (the sharpest resolved ring)
+    # as the dominant oscillation of its amplitude over 50-800 G-lambda, and
+    # compared with the image-domain diameter (peak separation of the
+    # projection of subrings n = 2 and 3 onto the u direction)
+    uf = torch.linspace(50.0 * per_gl, 800.0 * per_gl, 8001, dtype=torch.float64, device="cuda")
+    a2 = art.visibility(img[3:4].contiguous(), dx, uf, [0.0], fwhm=fov / 4)[0, 0].abs().cpu().numpy()
+    dfu = float(uf[1] - uf[0])
+    sig = (a2 - a2.mean()) * np.hanning(a2.size)
+    spec = np.abs(np.fft.rfft(sig, 8 * sig.size))
+    xs = np.fft.rfftfreq(8 * sig.size, dfu)
+    ok = xs > 2.0
+    d_vis = float(xs[ok][np.argmax(spec[ok])])
+    xg = (np.arange(nx) - 0.5 * (nx - 1)) * dx
+    d_img = []
+    for pl in (3, 4):
+        pr = img[pl].sum(dim=0).cpu().numpy()
+        d_img.append(float(xg[np.argmax(np.where(xg > 0, pr, -1.0))] - xg[np.argmax(np.where(xg < 0, pr, -1.0))]))
+    res = dict(window_glambda=1000.0, nu=nu, nv=nv, planes=P, taper_fwhm=fov / 4, ms=ms,
+               tflops=flops / ms / 1e9, frac_fp64_peak=flops / ms / 1e9 / (PEAK_FP64_VECTOR / 1e12),
+               residual_ratio_median=q[0], residual_ratio_p99=q[1],
+               residual_ratio_u_axis_max=float((Vr.abs()[k] / Vt.abs()[k]).max()),
+               u_axis_samples_glambda=[0, 100, 250, 500, 1000],
+               u_axis_amplitude=[[float(uaxis[p][int(round(g * per_gl / du))]) for g in (0, 100, 250, 500, 1000)]
+                                 for p in range(P)],
+               subring_dominance_u_glambda=crossings(uaxis), subring_dominance_v_glambda=crossings(vaxis),
+               ring_diameter_from_visibility_m=d_vis, ring_diameter_from_image_m=d_img)
+    log("16385^2 visibilities: %d planes x %d x %d baselines in %.1f ms (%.1f TFLOP/s), residual/|V| "
+        "median %.2e p99 %.2e, ring diameter %.2f M (image: %s), subring dominance along u at %s G-lambda" % (
+            P, nv, nu, ms, res["tflops"], q[0], q[1], d_vis, ["%.2f" % x for x in d_img],
+            ["%.0f" % x if x is not None else None for x in res["subring_dominance_u_glambda"]]))
+    del V, Vr, Vt, resid
+    return res
 
 
 def plain_single(art, torch, cfg, args):

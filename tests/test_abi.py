@@ -61,8 +61,8 @@ def test_visibility_validation_host_only():
     L = art.lib()
     dp = ctypes.c_void_p
     # workspace sizes: rows first when the u list is the shorter one
-    assert L.art_vis_workspace_bytes(1, 100, 80, 10, 20) == 8 * (80 * 2 * 10 + 4 * 10 * 20)
-    assert L.art_vis_workspace_bytes(2, 100, 80, 20, 10) == 8 * 2 * (100 * 2 * 10 + 4 * 10 * 20)
+    assert L.art_vis_workspace_bytes(1, 100, 80, 10, 20) == 8 * (80 * 2 * 10 + 4 * 10 * 20 + 180)
+    assert L.art_vis_workspace_bytes(2, 100, 80, 20, 10) == 8 * (2 * (100 * 2 * 10 + 4 * 10 * 20) + 180)
     assert L.art_vis_workspace_bytes(1, 100, 80, 0, 10) == 0
     fake = dp(0x1000)   # never dereferenced: every case below fails validation or is a no-op
 
