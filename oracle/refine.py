@@ -179,8 +179,11 @@ def nearest_stencil(img, nx0, ny0, l, s, nstokes):
     return p, q, Inn, G
 
 
+SPECTRAL = -3     # level-map mark: value taken from the spectral alternative
+
+
 def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
-           nstokes=1, forced_level=None, interp="linear", all_planes=False):
+           nstokes=1, forced_level=None, interp="linear", all_planes=False, alt=None):
     """Adaptive image by recursive subdivision.
 
     ray_fn(x, y) -> (n, nstokes) array: traces screen points (nstokes = the
@@ -191,6 +194,10 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
     mean) or "nearest" (Eqs. 5-6 nearest branch, the nearest neighbour's
     value).  all_planes: the decision is the OR of the criterion over every
     plane, each plane's estimate measured against N_abs and |Stokes I|.
+    alt: optional cheaper source of values, alt(i, j) -> (ok, values) for
+    final-grid points (i, j); it is consulted for every base point and for
+    every point the criterion flags, and points where ok holds take its
+    values (level-map mark SPECTRAL) instead of being traced.
 
     Returns dict(img=(nstokes, ny, nx), level=(ny, nx) int8 with -1 for
     interpolated and l for traced at level l, n_abs, ibar, imax0, per-level
@@ -202,15 +209,34 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
     st0 = 1 << levels
     jj, ii = np.meshgrid(np.arange(ny0) * st0, np.arange(nx0) * st0, indexing="ij")
     x, y = screen_coords(fov, nx, ny, ii.ravel(), jj.ravel())
-    S0 = np.asarray(ray_fn(x, y)).reshape(-1, nstokes)
-    for s in range(nstokes):
-        img[s, jj, ii] = S0[:, s].reshape(ny0, nx0)
-    lev[jj, ii] = 0
+    nspec = 0
+    if alt is None:
+        S0 = np.asarray(ray_fn(x, y)).reshape(-1, nstokes)
+        for s in range(nstokes):
+            img[s, jj, ii] = S0[:, s].reshape(ny0, nx0)
+        lev[jj, ii] = 0
+        ntr0 = nx0 * ny0
+    else:
+        bi, bj = ii.ravel(), jj.ravel()
+        ok, vals = alt(bi, bj)
+        if forced_level is not None:
+            ok = forced_level[bj, bi] == SPECTRAL
+        for s in range(nstokes):
+            img[s, bj[ok], bi[ok]] = vals[s][ok]
+        lev[bj[ok], bi[ok]] = SPECTRAL
+        tr = ~ok
+        if tr.any():
+            St = np.asarray(ray_fn(x[tr], y[tr])).reshape(-1, nstokes)
+            for s in range(nstokes):
+                img[s, bj[tr], bi[tr]] = St[:, s]
+        lev[bj[tr], bi[tr]] = 0
+        ntr0 = int(tr.sum())
+        nspec += int(ok.sum())
     I0 = img[0, jj, ii]
     ibar = trapezoid_mean(I0)
     imax0 = float(I0.max())
     n_abs = ibar if abs_norm == "mean" else imax0
-    cand, traced = [nx0 * ny0], [nx0 * ny0]
+    cand, traced = [nx0 * ny0], [ntr0]
     for l in range(levels):
         s = 1 << (levels - l - 1)          # spacing of the level-(l+1) grid
         if interp == "nearest":
@@ -235,11 +261,26 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
                 for Dp in Ds:
                     dec |= np.isnan(Dp) | ((np.abs(Dp) > thrA) & (np.abs(Dp) > crel * np.abs(S)))
             interp_vals = S_all * (1.0 / m)
+        spec = np.zeros(npt, dtype=bool)
+        if alt is not None:
+            ok, avals = alt(p[dec] * s, q[dec] * s)
+            spec[np.nonzero(dec)[0][ok]] = True
         if forced_level is not None:
-            dec = forced_level[q * s, p * s] == l + 1
-        # interpolate everything first (level-l values only), then trace
+            fl = forced_level[q * s, p * s]
+            dec = fl == l + 1
+            spec = fl == SPECTRAL
+        else:
+            dec = dec & ~spec
+        # interpolate everything first (level-l values only), then the
+        # alternative's values, then trace
         for st in range(nstokes):
             img[st, q * s, p * s] = interp_vals[st]
+        if spec.any():
+            _, avals = alt(p[spec] * s, q[spec] * s)
+            for st in range(nstokes):
+                img[st, q[spec] * s, p[spec] * s] = avals[st]
+            lev[q[spec] * s, p[spec] * s] = SPECTRAL
+            nspec += int(spec.sum())
         tp, tq = p[dec] * s, q[dec] * s
         if tp.size:
             xs, ys = screen_coords(fov, nx, ny, tp, tq)
@@ -251,7 +292,7 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
         traced.append(int(dec.sum()))
     n_interp = int((lev < 0).sum())
     return dict(img=img, level=lev, n_abs=n_abs, ibar=ibar, imax0=imax0,
-                candidates=cand, traced=traced, rays=int(sum(traced)),
+                candidates=cand, traced=traced, rays=int(sum(traced)), spectral=nspec,
                 interp_frac=n_interp / float(nx * ny), nx=nx, ny=ny)
 
 
