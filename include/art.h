@@ -189,6 +189,8 @@ typedef struct {
                                       interpolated (fallback off), [4] look-ahead rays */
     double t_render_ms;            /* wall time of the whole render on the caller's stream
                                       (HIP events; eager renders, else 0) */
+    int64_t spectral;              /* spectral cube renders: points that took the spectral
+                                      neighbours' value instead of a ray (else 0) */
 } art_stats;
 
 /* Final grid size n = 2^N (n0 - 1) + 1 per axis (Sec. 3.2) and the image size
@@ -382,6 +384,35 @@ int art_batch_set_learned(art_batch* b, art_cnn* net, const art_learned* opt);
 int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
                        const art_refine* rf, const art_transfer* tr, art_cnn* net,
                        const art_learned* opt, art_image* out, art_stats* st, void* stream);
+
+/* Adaptive sampling along frequency (the extension to the frequency domain
+ * that Sec. 6 proposes, built from the one-axis rule of Sec. 3.2).  The cube
+ * has n = 2^levels (n0 - 1) + 1 images (n <= 64) at frequencies equally spaced
+ * in ln nu from nu_min_hz to nu_max_hz (em->freq_hz is ignored); out[i] is
+ * image i in frequency order, each with the camera's final grid and a level
+ * map, and st (if non-NULL) receives n per-image statistics (step counts,
+ * status histogram and timings are cube-wide).  Images at indices k 2^levels
+ * are the base frequencies: plain adaptive renders (Sec. 3.2).  Spectral
+ * level s adds the odd multiples of h = 2^(levels - s).  In those images every
+ * base point and every point the spatial criterion flags first tries the
+ * spectral value (b + c)/2 of the finished images b, c at indices i -+ h,
+ * accepted unless, with the continuations a, d at i -+ 3h,
+ *   |D| > 8 r_abs N_abs  and  |D| > 4 r_rel |b + c|,   D = (a + d) - (b + c)
+ * (twice the one-sided second difference if a or d is outside the cube, never
+ * accepted if both are; N_abs the mean of b's and c's own N_abs; every plane
+ * with rf->all_planes); points it rejects are traced.  Level map: l = traced at
+ * spatial level l, -1 spatially interpolated, -3 spectral value.  Eager (not
+ * capturable); needs (levels + 1)(camera levels + 1) <= 64 passes. */
+typedef struct {
+    double nu_min_hz, nu_max_hz;   /* first and last frequency, 0 < nu_min < nu_max */
+    int32_t n0;                    /* base frequencies, >= 2 */
+    int32_t levels;                /* refinements along ln nu, 0..6 */
+    double r_rel, r_abs;           /* tolerances of the spectral rule (< 0: never accepted) */
+} art_spectral;
+
+int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                        const art_refine* rf, const art_transfer* tr, const art_spectral* spec,
+                        art_image* out, art_stats* st, void* stream);
 
 /* Image metrics of Sec. 4.1 on n FP64 values (one Stokes plane), computed on
  * the device with a deterministic two-pass reduction; synchronises:

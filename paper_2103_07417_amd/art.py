@@ -71,7 +71,13 @@ class Stats(ctypes.Structure):
                 ("n_abs", ctypes.c_double), ("steps_emit", ctypes.c_int64),
                 ("t_trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("learned", ctypes.c_int64 * 5),
-                ("t_render_ms", ctypes.c_double)]
+                ("t_render_ms", ctypes.c_double), ("spectral", ctypes.c_int64)]
+
+
+class Spectral(ctypes.Structure):
+    _fields_ = [("nu_min_hz", ctypes.c_double), ("nu_max_hz", ctypes.c_double),
+                ("n0", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("r_rel", ctypes.c_double), ("r_abs", ctypes.c_double)]
 
 
 class Learned(ctypes.Structure):
@@ -143,6 +149,8 @@ def lib():
         L.art_batch_set_learned.argtypes = [vp, vp, P(Learned)]
         L.art_render_learned.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine),
                                          P(Transfer), vp, P(Learned), P(Image), P(Stats), vp]
+        L.art_render_spectral.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine), P(Transfer),
+                                          P(Spectral), P(Image), P(Stats), vp]
         L.art_vis_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
         L.art_vis_workspace_bytes.restype = ctypes.c_size_t
         L.art_visibility.argtypes = [vp, i64, i32, i32, i32, ctypes.c_double, ctypes.c_double, vp, i32,
@@ -219,7 +227,7 @@ def stats_dict(st):
                 learned=dict(proposed_extra=int(st.learned[0]), suppressed=int(st.learned[1]),
                              fallback=int(st.learned[2]), missed=int(st.learned[3]),
                              lookahead=int(st.learned[4])),
-                t_render_ms=float(st.t_render_ms))
+                t_render_ms=float(st.t_render_ms), spectral=int(st.spectral))
 
 
 def alloc(cfg, feat=False):
@@ -266,6 +274,31 @@ def render_uniform(cfg, out=None, feat=False, stats=True, stream=None):
                                   ctypes.byref(st) if stats else None, _stream(torch, stream))
     _check(rc)
     return img, ft, (stats_dict(st) if stats else None)
+
+
+def cube_size(n0, levels):
+    return (1 << int(levels)) * (int(n0) - 1) + 1
+
+
+def render_spectral(cfg, nu_min, nu_max, n0, levels, r_rel=None, r_abs=None, feat=False, stream=None):
+    """Spectral cube by adaptive sampling along ln nu (the frequency-domain
+    extension of Sec. 3.2 proposed in Sec. 6).  Returns (images, levels,
+    feats, stats), lists in frequency order; r_rel / r_abs default to the
+    spatial tolerances."""
+    torch = _torch()
+    sp, cam, em, rf, tr = blocks(cfg)
+    n = cube_size(n0, levels)
+    bufs = [alloc(cfg, feat) for _ in range(n)]
+    ims = (Image * n)(*[_image(*b) for b in bufs])
+    sts = (Stats * n)()
+    spec = Spectral(float(nu_min), float(nu_max), int(n0), int(levels),
+                    float(cfg["r_rel"] if r_rel is None else r_rel),
+                    float(cfg["r_abs"] if r_abs is None else r_abs))
+    rc = lib().art_render_spectral(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em), ctypes.byref(rf),
+                                   ctypes.byref(tr), ctypes.byref(spec), ims, sts, _stream(torch, stream))
+    _check(rc)
+    out = [stats_dict(sts[i]) for i in range(n)]
+    return [b[0] for b in bufs], [b[1] for b in bufs], [b[2] for b in bufs], out
 
 
 def learned_opts(z_propose=2.0, z_suppress=float("-inf"), fallback=True, all_levels=False):

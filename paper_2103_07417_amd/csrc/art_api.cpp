@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -76,7 +77,7 @@ int env_int(const char* name, int dflt)
 art_launch g_launch = { 0, 0, 0, 0 };   // user override (0 = default)
 std::mutex g_mu;
 
-constexpr int kMaxEv = kMaxLevels + 2;
+constexpr int kMaxEv = 64;   // timed tracing launches per group and render
 
 }  // namespace
 
@@ -103,6 +104,7 @@ struct art_batch {
     int n = 0;
     int model = 0, nstokes = 1, precision = 0, nsub = 0;
     bool uniform = false;
+    bool spectral = false;         // spectral cube render in progress (one group)
     std::vector<Params> hP;
     std::vector<ImageDesc> hD;
     Params* dP = nullptr;
@@ -403,7 +405,7 @@ int default_groups(int n)
 // group's slice of the trace list and upload the descriptors.
 int layout(art_batch* b, hipStream_t s)
 {
-    int G = b->uniform ? 1 : (b->req_groups > 0 ? b->req_groups : default_groups(b->n));
+    int G = (b->uniform || b->spectral) ? 1 : (b->req_groups > 0 ? b->req_groups : default_groups(b->n));
     if (G > b->n) G = b->n;
     if (G > kMaxGroups) G = kMaxGroups;
     b->ngroups = G;
@@ -500,6 +502,8 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
         D.r_rel = J.rf.r_rel;
         D.r_abs = J.rf.r_abs;
         D.base_off = 0;
+        D.sa = D.sb = D.sc = D.sd = -1;
+        D.sr_rel = D.sr_abs = 0.0;
         total += (size_t)D.plane;
     }
     if (total >= (1ULL << 31)) return fail(ART_EINVAL, "batch has %zu pixels (limit 2^31)", total);
@@ -665,6 +669,56 @@ int enqueue_render(art_batch* b, hipStream_t s)
     return ART_OK;
 }
 
+// Spectral cube (one group; images in internal order: the n0 base
+// frequencies, then each spectral level's images): plain adaptive renders of
+// the base frequencies, then per spectral level a base pass where points take
+// the spectral value or are traced, the level-0 reduction and the spatial
+// levels in mode 3 (flagged points take the spectral value where accepted).
+int enqueue_spectral(art_batch* b, int n0, int slevels, hipStream_t s)
+{
+    b->ntrace = 0;
+    BatchGroup& G = b->grp[0];
+    G.nev = 0;
+    b->render_timed = b->timing;
+    if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[0], s));
+    Counters* ctr = b->ctr;
+    unsigned long long* list = b->list + G.list_off;
+    const long long cap = (long long)G.list_len;
+    const ImageDesc& D0 = b->hD[0];
+    const int N = D0.levels;
+    const int nb = D0.nx0 * D0.ny0;
+    HIP_TRY(launch_fill_u32((uint32_t*)ctr, sizeof(Counters) / 4, 0u, s));
+    HIP_TRY(launch_base_list(b->dD, n0, nb, list, ctr, 0, s));
+    int rc = trace_pass(b, 0, 0, s);
+    if (rc) return rc;
+    HIP_TRY(launch_reduce_base(b->dD, n0, ctr, s));
+    for (int l = 0; l < N; ++l) {
+        const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
+        HIP_TRY(launch_estimate(b->dD, n0, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s));
+        rc = trace_pass(b, 0, l + 1, s);
+        if (rc) return rc;
+    }
+    int off = n0;
+    for (int sl = 1; sl <= slevels; ++sl) {
+        const int m = (n0 - 1) << (sl - 1);
+        // fresh per-pass work counters (count, count_back, cursor) for this level's passes
+        HIP_TRY(launch_fill_u32((uint32_t*)ctr, offsetof(Counters, steps) / 4, 0u, s));
+        HIP_TRY(launch_spectral_base(b->dD, off, m, nb, ctr, list, cap, b->L.long_steps, s));
+        rc = trace_pass(b, 0, 0, s);
+        if (rc) return rc;
+        HIP_TRY(launch_reduce_base(b->dD, m, ctr, s, off));
+        for (int l = 0; l < N; ++l) {
+            const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
+            HIP_TRY(launch_estimate(b->dD, m, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 3, 1, off));
+            rc = trace_pass(b, 0, l + 1, s);
+            if (rc) return rc;
+        }
+        off += m;
+    }
+    if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[1], s));
+    return ART_OK;
+}
+
 // Check that a prepared batch can run learned renders and size its workspaces.
 int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
 {
@@ -749,6 +803,7 @@ int batch_stats(art_batch* b, int i, art_stats* st, hipStream_t s)
                                          grid_n(D.nx0, l - 1) * grid_n(D.ny0, l - 1);
             }
             for (int j = 0; j < 5; ++j) st->learned[j] += (int64_t)c.judge[q][j];
+            st->spectral += (int64_t)c.judge[q][5];
             if (k == (i >= 0 ? i : 0)) {
                 st->ibar_int = c.scal[q][0];
                 st->imax0 = c.scal[q][1];
@@ -864,6 +919,79 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
     b->net = nullptr;             // the single-image batch keeps no network
     if (rc) return rc;
     if (st) return batch_stats(b, 0, st, s);
+    return ART_OK;
+}
+
+int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                        const art_refine* rf, const art_transfer* tr, const art_spectral* spec, art_image* out,
+                        art_stats* st, void* stream)
+{
+    if (!sp || !cam || !em || !rf || !tr || !spec || !out) return fail(ART_EINVAL, "null argument");
+    const int n0 = spec->n0, L = spec->levels;
+    if (n0 < 2 || L < 0 || L > 6) return fail(ART_EINVAL, "spectral cube needs n0 >= 2 and 0 <= levels <= 6");
+    const long long n = ((long long)(n0 - 1) << L) + 1;
+    if (n > kMaxBatch) return fail(ART_EINVAL, "spectral cube of %lld images (limit %d)", n, kMaxBatch);
+    if (!(spec->nu_min_hz > 0.0) || !(spec->nu_max_hz > spec->nu_min_hz) || !std::isfinite(spec->nu_max_hz))
+        return fail(ART_EINVAL, "spectral cube needs 0 < nu_min < nu_max (finite)");
+    if (std::isnan(spec->r_rel) || std::isnan(spec->r_abs)) return fail(ART_EINVAL, "NaN spectral tolerance");
+    if ((long long)(cam->levels + 1) * (L + 1) > kMaxEv)
+        return fail(ART_EINVAL, "spectral cube of %d x %d passes (limit %d)", cam->levels + 1, L + 1, kMaxEv);
+    // internal order: base frequencies, then each spectral level; perm[k] = cube index
+    std::vector<int> perm, inv(n, -1);
+    for (int k = 0; k < n0; ++k) perm.push_back(k << L);
+    for (int sl = 1; sl <= L; ++sl) {
+        const int h = 1 << (L - sl);
+        for (long long i = h; i < n; i += 2 * h) perm.push_back((int)i);
+    }
+    for (int k = 0; k < (int)n; ++k) inv[perm[k]] = k;
+    std::vector<art_job> jobs((size_t)n);
+    std::vector<art_image> imgs((size_t)n);
+    for (int k = 0; k < (int)n; ++k) {
+        art_emission e = *em;
+        const double t = (double)perm[k] / (double)(n - 1);
+        e.freq_hz = spec->nu_min_hz * std::pow(spec->nu_max_hz / spec->nu_min_hz, t);
+        jobs[k] = make_job(sp, cam, &e, rf, tr);
+        imgs[k] = out[perm[k]];
+    }
+    std::lock_guard<std::mutex> lk(g_single_mu);
+    art_batch* b = single_batch();
+    if (!b) return fail(ART_EDEVICE, "no current device");
+    hipStream_t s = (hipStream_t)stream;
+    b->spectral = true;
+    int rc = prepare(b, (int)n, jobs.data(), imgs.data(), false, s);
+    if (rc) {
+        b->spectral = false;
+        return rc;
+    }
+    for (int k = n0; k < (int)n; ++k) {
+        const int i = perm[k];
+        int lvl = L;
+        for (int j = i; j % 2 == 0; j /= 2) --lvl;
+        const int h = 1 << (L - lvl);
+        ImageDesc& D = b->hD[k];
+        D.sb = inv[i - h];
+        D.sc = inv[i + h];
+        D.sa = i - 3 * h >= 0 ? inv[i - 3 * h] : -1;
+        D.sd = i + 3 * h < n ? inv[i + 3 * h] : -1;
+        D.sr_rel = spec->r_rel;
+        D.sr_abs = spec->r_abs;
+    }
+    hipError_t e = hipMemcpyAsync(b->dD, b->hD.data(), sizeof(ImageDesc) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        b->spectral = false;
+        return fail(ART_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+    }
+    b->timing = st != nullptr;
+    b->net = nullptr;
+    rc = enqueue_spectral(b, n0, L, s);
+    b->spectral = false;
+    if (rc) return rc;
+    if (st) {
+        for (int k = 0; k < (int)n; ++k) {
+            rc = batch_stats(b, k, &st[perm[k]], s);
+            if (rc) return rc;
+        }
+    }
     return ART_OK;
 }
 

@@ -25,7 +25,7 @@ struct Counters {
     // not trace, [1] criterion-flagged points the network rejected, [2] points
     // traced by the criterion as fallback after a look-ahead pass, [3]
     // criterion-flagged points left interpolated (judge-only mode), [4]
-    // look-ahead proposals
+    // look-ahead proposals; [5] points taken from the spectral neighbours
     unsigned long long judge[kMaxBatch][8];
 };
 
@@ -40,12 +40,19 @@ struct ImageDesc {
     int32_t nplanes;       // image planes: nstokes + subring planes
     int32_t flags;         // kRefine* bits
     double r_rel, r_abs;
+    // spectral cube renders: the one-axis stencil along ln nu (indices of the
+    // images a, b, c, d in the same descriptor array; sb < 0: not a spectral
+    // image, sa or sd < 0: that continuation is outside the cube) and its
+    // tolerances
+    int32_t sa, sb, sc, sd;
+    double sr_rel, sr_abs;
 };
 
 constexpr int32_t kRefineNearest = 1;     // nearest branch of Eqs. 5-6 and nearest interpolation
 constexpr int32_t kRefineAllPlanes = 2;   // criterion ORed over every image plane
 
 constexpr int kMaxSub = 8;        // subring planes a ray accumulates
+constexpr int8_t kMarkSpectral = -3;   // level map: value taken from the spectral neighbours
 
 enum TraceSrc : int { SRC_LIST = 0, SRC_POINTS = 1 };
 
@@ -88,8 +95,16 @@ hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsig
                             Counters* ctr, int level_slot, hipStream_t s);
 hipError_t launch_trace(int precision, int model, int nstokes, bool subrings, const TraceJob& J,
                         const LaunchCfg& L, hipStream_t s);
-hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s);
-// mode 0: plain criterion.  mode 1: learned, level l -> l+1 (points marked
+hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s, int img_off = 0);
+// Base points of the spectral-level images [img_off, img_off + nimg): the
+// spectral value where the one-axis rule along ln nu accepts it, else the
+// point is queued for tracing in slot 0 (front: expected long rays).
+hipError_t launch_spectral_base(const ImageDesc* desc, int img_off, int nimg, int max_base, Counters* ctr,
+                                unsigned long long* list, long long cap, int long_steps, hipStream_t s);
+// Images [img_off, img_off + nimg) of desc.
+// mode 0: plain criterion.  mode 3: spectral images: a point the criterion
+// flags takes the spectral value where the rule along ln nu accepts it and is
+// traced otherwise.  mode 1: learned, level l -> l+1 (points marked
 // proposed are traced, points marked suppressed are interpolated, the
 // criterion decides the rest).  mode 2: learned, after a look-ahead pass
 // (points already traced are kept, suppressed points are interpolated, the
@@ -99,7 +114,7 @@ hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hi
 // (list capacity `cap`).
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
                            Counters* ctr, unsigned long long* list, long long cap, int long_steps,
-                           hipStream_t s, int mode = 0, int fallback = 1);
+                           hipStream_t s, int mode = 0, int fallback = 1, int img_off = 0);
 hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
                           int nblocks, hipStream_t s);
 int trace_occupancy_blocks(int precision, int model, int nstokes, bool subrings, int threads);

@@ -441,11 +441,11 @@ int trace_occupancy_blocks(int precision, int model, int nstokes, bool subrings,
 
 // ------------------------------------------------------ level-0 reduction
 // One block per image: trapezoid-weighted mean and maximum of the base grid.
-__global__ __launch_bounds__(1024) void k_reduce_base(const ImageDesc* desc, Counters* ctr)
+__global__ __launch_bounds__(1024) void k_reduce_base(const ImageDesc* desc, Counters* ctr, int img_off)
 {
     __shared__ double ssum[1024];
     __shared__ double smax[1024];
-    const int img = blockIdx.x;
+    const int img = img_off + blockIdx.x;
     const ImageDesc D = desc[img];
     const int t = threadIdx.x;
     const int st0 = 1 << D.levels;
@@ -477,9 +477,128 @@ __global__ __launch_bounds__(1024) void k_reduce_base(const ImageDesc* desc, Cou
     }
 }
 
-hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s)
+hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s, int img_off)
 {
-    hipLaunchKernelGGL(k_reduce_base, dim3(nimg), dim3(1024), 0, s, desc, ctr);
+    hipLaunchKernelGGL(k_reduce_base, dim3(nimg), dim3(1024), 0, s, desc, ctr, img_off);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ spectral cube
+// The one-axis rule of Sec. 3.2 along ln nu at pixel pix of a spectral-level
+// image: with the bracketing images b, c and the continuations a, d (finished
+// coarser levels), D = (a + d) - (b + c), twice the one-sided second
+// difference if one continuation is outside the cube, no estimate (trace) if
+// both are; the spectral value (b + c)/2 is accepted unless |D| > 8 R_abs N_abs
+// and |D| > 4 R_rel |b + c|, N_abs the mean of b's and c's own N_abs (every
+// plane with the per-plane option).
+__device__ bool spectral_ok(const ImageDesc* desc, const ImageDesc& D, long long pix, const Counters* ctr)
+{
+    if (D.sa < 0 && D.sd < 0) return false;
+    const double* Ib = desc[D.sb].img;
+    const double* Ic = desc[D.sc].img;
+    const double* Ia = D.sa >= 0 ? desc[D.sa].img : nullptr;
+    const double* Id = D.sd >= 0 ? desc[D.sd].img : nullptr;
+    const double nabs = 0.5 * (ctr->scal[D.sb][2] + ctr->scal[D.sc][2]);
+    const double thrA = 8.0 * D.sr_abs * nabs;
+    const double crel = 4.0 * D.sr_rel;
+    const double S0 = Ib[pix] + Ic[pix];
+    if (!(S0 == S0)) return false;
+    const double aS = ::fabs(S0);
+    const int np = (D.flags & kRefineAllPlanes) ? D.nplanes : 1;
+    for (int st = 0; st < np; ++st) {
+        const long long o = st * D.plane + pix;
+        const double b = Ib[o], c = Ic[o];
+        double Dv;
+        if (Ia && Id)
+            Dv = (Ia[o] + Id[o]) - (b + c);
+        else if (Id)
+            Dv = 2.0 * ((Id[o] - 2.0 * c) + b);
+        else
+            Dv = 2.0 * ((Ia[o] - 2.0 * b) + c);
+        const double aD = ::fabs(Dv);
+        if (!(Dv == Dv) || (aD > thrA && aD > crel * aS)) return false;
+    }
+    return true;
+}
+
+// Spectral value at pix: (b + c)/2 on every plane; features from b and c
+// (smallest radius, largest crossing count); the costlier neighbour's cost.
+__device__ void spectral_write(const ImageDesc* desc, const ImageDesc& D, long long pix)
+{
+    const ImageDesc& B = desc[D.sb];
+    const ImageDesc& C = desc[D.sc];
+    for (int st = 0; st < D.nplanes; ++st) {
+        const long long o = st * D.plane + pix;
+        D.img[o] = (B.img[o] + C.img[o]) * 0.5;
+    }
+    D.level[pix] = kMarkSpectral;
+    if (D.feat && B.feat && C.feat) {
+        RayFeat f = B.feat[pix];
+        const RayFeat g = C.feat[pix];
+        f.rmin = g.rmin < f.rmin ? g.rmin : f.rmin;
+        f.ncross = g.ncross > f.ncross ? g.ncross : f.ncross;
+        f.steps = 0;
+        f.status = RAY_OK;
+        D.feat[pix] = f;
+    }
+    if (D.cost) {
+        const uint16_t cb = B.cost[pix], cc = C.cost[pix];
+        D.cost[pix] = cb > cc ? cb : cc;
+    }
+}
+
+// grid (x: base points, y: image).  Base points of spectral-level images.
+__global__ __launch_bounds__(256) void k_spectral_base(const ImageDesc* desc, int img_off, Counters* ctr,
+                                                       unsigned long long* list, long long cap, int long_steps)
+{
+    const int img = img_off + blockIdx.y;
+    const ImageDesc D = desc[img];
+    const int n = D.nx0 * D.ny0;
+    const int st0 = 1 << D.levels;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    bool trace = false, longr = false, spec = false;
+    long long pix = 0;
+    if (t < n) {
+        const int i = t % D.nx0, j = t / D.nx0;
+        pix = (long long)(j * st0) * D.nx + (long long)(i * st0);
+        if (spectral_ok(desc, D, pix, ctr)) {
+            spectral_write(desc, D, pix);
+            spec = true;
+        } else {
+            trace = true;
+            D.level[pix] = 0;
+            if (D.cost) {
+                const uint16_t cb = desc[D.sb].cost[pix], cc = desc[D.sc].cost[pix];
+                longr = (int)(cb > cc ? cb : cc) >= long_steps;
+            }
+        }
+    }
+    const int lane = __lane_id();
+    const unsigned long long ms = __ballot(spec);
+    if (ms && lane == __ffsll((long long)ms) - 1) atomicAdd(&ctr->judge[img][5], (unsigned long long)__popcll(ms));
+    const unsigned long long mlong = __ballot(trace && longr);
+    const unsigned long long mshort = __ballot(trace && !longr);
+    if (mlong | mshort) {
+        const int leader = __ffsll((long long)(mlong | mshort)) - 1;
+        unsigned bl = 0, bs = 0;
+        if (lane == leader) {
+            if (mlong) bl = atomicAdd(&ctr->count[0], (unsigned)__popcll(mlong));
+            if (mshort) bs = atomicAdd(&ctr->count_back[0], (unsigned)__popcll(mshort));
+            atomicAdd(&ctr->img_traced[img][0], (unsigned)__popcll(mlong | mshort));
+        }
+        bl = __shfl(bl, leader);
+        bs = __shfl(bs, leader);
+        const unsigned long long item = make_item((uint32_t)img, (uint32_t)pix);
+        if (trace && longr) list[bl + lane_prefix(mlong)] = item;
+        if (trace && !longr) list[cap - 1 - (long long)(bs + lane_prefix(mshort))] = item;
+    }
+}
+
+hipError_t launch_spectral_base(const ImageDesc* desc, int img_off, int nimg, int max_base, Counters* ctr,
+                                unsigned long long* list, long long cap, int long_steps, hipStream_t s)
+{
+    dim3 grid((max_base + 255) / 256, nimg);
+    hipLaunchKernelGGL(k_spectral_base, grid, dim3(256), 0, s, desc, img_off, ctr, list, cap, long_steps);
     return hipGetLastError();
 }
 
@@ -506,9 +625,9 @@ __device__ __forceinline__ bool axis_D(const double* I, long long nx, int s, int
 // level-(l+1) grid; new points are classified by index parity (categories 2-4).
 __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
                                                   unsigned long long* list, long long cap, int long_steps,
-                                                  int mode, int fallback)
+                                                  int mode, int fallback, int img_off)
 {
-    const int img = blockIdx.z;
+    const int img = img_off + blockIdx.z;
     const ImageDesc D = desc[img];
     if (l >= D.levels) return;                     // uniform over the block
     const int nxl = (1 << (l + 1)) * (D.nx0 - 1) + 1;
@@ -519,6 +638,7 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
     const bool isnew = p < nxl && q < nyl && ((p & 1) | (q & 1));
     bool trace = false;
     bool longr = false;                      // expected to be a long ray: queue at the front
+    bool spec = false;                       // value taken from the spectral neighbours
     bool jd[4] = { false, false, false, false };
     long long pix = 0;
     if (isnew) {
@@ -607,6 +727,9 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
         bool keep = false;               // point already traced by a look-ahead pass
         if (mode == 0) {
             trace = crit;
+        } else if (mode == 3) {
+            spec = crit && spectral_ok(desc, D, pix, ctr);
+            trace = crit && !spec;
         } else {
             const int8_t mk = D.level[pix];
             const bool sup = mk == kMarkSuppress;
@@ -624,7 +747,9 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
                 jd[3] = want && !fallback;
             }
         }
-        if (D.cost && (trace || !keep)) {
+        if (spec) {
+            spectral_write(desc, D, pix);
+        } else if (D.cost && (trace || !keep)) {
             // expected cost: the most expensive neighbour
             uint16_t c = D.cost[o[0]];
             for (int q2 = 1; q2 < nnb; ++q2) {
@@ -636,7 +761,7 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
         }
         if (trace) {
             D.level[pix] = (int8_t)(l + 1);
-        } else if (!keep) {
+        } else if (!keep && !spec) {
             D.level[pix] = (int8_t)-1;
             if (D.flags & kRefineNearest) {
                 // nearest neighbour: I1 (2D) or the lower neighbour b (1D)
@@ -665,7 +790,11 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
             }
         }
     }
-    if (mode != 0) {
+    if (mode == 3) {
+        const unsigned long long mk = __ballot(spec);
+        if (mk && __lane_id() == __ffsll((long long)mk) - 1)
+            atomicAdd(&ctr->judge[img][5], (unsigned long long)__popcll(mk));
+    } else if (mode != 0) {
         // judge counters: one atomic per wave and counter
         const int lane = __lane_id();
 #pragma unroll
@@ -697,10 +826,11 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
 
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
                            Counters* ctr, unsigned long long* list, long long cap, int long_steps,
-                           hipStream_t s, int mode, int fallback)
+                           hipStream_t s, int mode, int fallback, int img_off)
 {
     dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
-    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, cap, long_steps, mode, fallback);
+    hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, cap, long_steps, mode, fallback,
+                       img_off);
     return hipGetLastError();
 }
 
