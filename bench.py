@@ -20,6 +20,13 @@ effective pixels/s = 64 x 1025^2 / batch time.  The roofline entry reports
 the tracing kernel's algorithmic throughput (hand-counted FLOPs per geodesic
 step and per emitting step) against the vector peak of its precision; the
 CPU baseline is the FP64 oracle's complete adaptive render.
+
+Further sections (reported beside the headline, each with its own timing):
+the gridded snapshot at 4097^2 (FP64 and mixed precision); the snapshot at
+16385^2 with subrings n = 0..3 (plain, per-plane criterion, learned forms)
+and the visibility domain of its learned render (Sec. 4.3: 2D window to
+1000 G-lambda on FP64 matrix cores, residual visibilities, ring period); the
+thermal view as a 17-frequency cube sampled adaptively along ln nu.
 """
 import argparse
 import json
@@ -396,18 +403,24 @@ def deploy_visibility(art, torch, art_inputs, cfg, img, truth):
         return out
 
     # ring period (Sec. 4.3.1): |V(u, 0)| of a ring of diameter d oscillates
-    # with period 1/d; measured on subring n = 2 (the sharpest resolved ring)
-    # as the dominant oscillation of its amplitude over 50-800 G-lambda, and
-    # compared with the image-domain diameter (peak separation of the
-    # projection of subrings n = 2 and 3 onto the u direction)
+    # with period 1/d (two limbs: |V|^2 = A1^2 + A2^2 + 2 A1 A2 cos(2 pi u d));
+    # d is read off as the dominant oscillation of |V(u, 0)|^2 over
+    # 50-800 G-lambda for subrings n = 2 and 3 of the adaptive and the uniform
+    # render, and compared with the image-domain diameter (peak separation of
+    # their projections onto the u direction)
     uf = torch.linspace(50.0 * per_gl, 800.0 * per_gl, 8001, dtype=torch.float64, device="cuda")
-    a2 = art.visibility(img[3:4].contiguous(), dx, uf, [0.0], fwhm=fov / 4)[0, 0].abs().cpu().numpy()
     dfu = float(uf[1] - uf[0])
-    sig = (a2 - a2.mean()) * np.hanning(a2.size)
-    spec = np.abs(np.fft.rfft(sig, 8 * sig.size))
-    xs = np.fft.rfftfreq(8 * sig.size, dfu)
-    ok = xs > 2.0
-    d_vis = float(xs[ok][np.argmax(spec[ok])])
+
+    def ring_d(plane_img):
+        a = art.visibility(plane_img.unsqueeze(0).contiguous(), dx, uf, [0.0], fwhm=fov / 4)[0, 0]
+        p2 = (a.abs() ** 2).cpu().numpy()
+        sig = (p2 - p2.mean()) * np.hanning(p2.size)
+        spec = np.abs(np.fft.rfft(sig, 8 * sig.size))
+        xs = np.fft.rfftfreq(8 * sig.size, dfu)
+        ok = xs > 2.0
+        return float(xs[ok][np.argmax(spec[ok])])
+    d_vis = {"adaptive_n2": ring_d(img[3]), "adaptive_n3": ring_d(img[4]),
+             "uniform_n2": ring_d(truth[3]), "uniform_n3": ring_d(truth[4])}
     xg = (np.arange(nx) - 0.5 * (nx - 1)) * dx
     d_img = []
     for pl in (3, 4):
@@ -423,11 +436,62 @@ def deploy_visibility(art, torch, art_inputs, cfg, img, truth):
                subring_dominance_u_glambda=crossings(uaxis), subring_dominance_v_glambda=crossings(vaxis),
                ring_diameter_from_visibility_m=d_vis, ring_diameter_from_image_m=d_img)
     log("16385^2 visibilities: %d planes x %d x %d baselines in %.1f ms (%.1f TFLOP/s), residual/|V| "
-        "median %.2e p99 %.2e, ring diameter %.2f M (image: %s), subring dominance along u at %s G-lambda" % (
-            P, nv, nu, ms, res["tflops"], q[0], q[1], d_vis, ["%.2f" % x for x in d_img],
+        "median %.2e p99 %.2e, ring diameter %s M (image: %s), subring dominance along u at %s G-lambda" % (
+            P, nv, nu, ms, res["tflops"], q[0], q[1], {k: round(v, 2) for k, v in d_vis.items()},
+            ["%.2f" % x for x in d_img],
             ["%.0f" % x if x is not None else None for x in res["subring_dominance_u_glambda"]]))
     del V, Vr, Vt, resid
     return res
+
+
+def spectral_1025(art, torch, art_inputs, args):
+    """Adaptive sampling along frequency (the Sec. 6 extension): the
+    thermal_1025 view as a 17-frequency cube from 86 to 690 GHz (3 base
+    frequencies, 3 spectral levels), against plain adaptive renders of the
+    same 17 frequencies (one batch, hipGraph replay) and uniform truths."""
+    from paper_2103_07417_amd import art as A
+    cfg = dict(art_inputs.workload("thermal_1025"), precision=args.precision)
+    n0, L = 3, 3
+    lo, hi = 86e9, 690e9
+    n = A.cube_size(n0, L)
+    nus = [lo * (hi / lo) ** (i / (n - 1.0)) for i in range(n)]
+    truths = []
+    for nu in nus:
+        t, _, _ = art.render_uniform(dict(cfg, freq_hz=nu))
+        truths.append(t[0].clone())
+    art.render_spectral(cfg, lo, hi, n0, L)              # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    imgs, levs, _, sts = art.render_spectral(cfg, lo, hi, n0, L)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rays = sum(st["rays"] for st in sts)
+    spec = sum(st["spectral"] for st in sts)
+    mses = [art.metrics(truths[i], imgs[i][0])[1] for i in range(n)]
+    cube = dict(ms=sts[0]["t_render_ms"], wall_ms=wall * 1e3, rays=rays, spectral_values=spec,
+                passes=sts[0]["trace_launches"], mse_max=max(mses), mse_mean=sum(mses) / n,
+                mse_ok=max(mses) <= 1e-3)
+    del imgs, levs
+    cfgs = [dict(cfg, name="nu_%02d" % i, freq_hz=nu) for i, nu in enumerate(nus)]
+    B = art.Batch(cfgs)
+    s = torch.cuda.Stream()
+    B.render(s)
+    s.synchronize()
+    dt = time_graph(B, torch, s, 3)
+    st = B.stats(stream=s)
+    chk = mse_check(art, cfgs, B.images, truths)
+    plain = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse_max=chk["mse_max"],
+                 mse_mean=chk["mse_mean"], mse_ok=chk["mse_ok"])
+    B.close()
+    out = dict(workload="thermal_1025 view (a=0.94, i=163 deg, IQUV) at %d frequencies 86-690 GHz equally "
+                        "spaced in ln nu (3 base + 3 spectral levels), 1025^2, R_rel=0.01, R_abs=1e-3 max I0 "
+                        "on both axes" % n,
+               cube=cube, plain_batched=plain, rays_ratio=rays / max(plain["rays"], 1))
+    log("spectral cube %d x 1025^2: %.1f ms (wall %.1f), %d rays (+%d spectral values), mse max %.2e; "
+        "plain batch %.1f ms, %d rays, mse max %.2e" % (n, cube["ms"], cube["wall_ms"], rays, spec,
+                                                       cube["mse_max"], plain["ms"], plain["rays"],
+                                                       plain["mse_max"]))
+    return out
 
 
 def plain_single(art, torch, cfg, args):
@@ -470,6 +534,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-deploy", action="store_true")
+    ap.add_argument("--no-spectral", action="store_true")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--z-propose", type=float, default=0.0)
     ap.add_argument("--z-suppress", type=float, default=-1.0)
@@ -538,6 +603,8 @@ def main():
         out["grid_4097"] = grid_forms(art, torch, art_inputs, args)
     if not args.no_deploy:
         out["deploy_16385"] = deploy_16385(art, torch, art_inputs, args)
+    if not args.no_spectral:
+        out["spectral_1025"] = spectral_1025(art, torch, art_inputs, args)
     # a plain device copy of known size: reference reading for the HBM byte
     # counters (FETCH_SIZE / WRITE_SIZE) of a profiled run
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")

@@ -402,7 +402,9 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
  * accepted if both are; N_abs the mean of b's and c's own N_abs; every plane
  * with rf->all_planes); points it rejects are traced.  Level map: l = traced at
  * spatial level l, -1 spatially interpolated, -3 spectral value.  Eager (not
- * capturable); needs (levels + 1)(camera levels + 1) <= 64 passes. */
+ * capturable); camera levels + spectral levels <= 21.  The decisions of
+ * spectral level s at spatial level l need only the coarser levels, so they
+ * run as a wavefront: camera levels + levels + 1 tracing passes. */
 typedef struct {
     double nu_min_hz, nu_max_hz;   /* first and last frequency, 0 < nu_min < nu_max */
     int32_t n0;                    /* base frequencies, >= 2 */

@@ -670,10 +670,14 @@ int enqueue_render(art_batch* b, hipStream_t s)
 }
 
 // Spectral cube (one group; images in internal order: the n0 base
-// frequencies, then each spectral level's images): plain adaptive renders of
-// the base frequencies, then per spectral level a base pass where points take
-// the spectral value or are traced, the level-0 reduction and the spatial
-// levels in mode 3 (flagged points take the spectral value where accepted).
+// frequencies, then each spectral level's images).  Step (s, l) decides the
+// level-l points of the spectral-level-s images: for s = 0 the plain
+// criterion (base list at l = 0), for s > 0 the spectral base pass (l = 0)
+// or the criterion with the spectral alternative (mode 3).  It needs the
+// image's own level l-1 and the spectral neighbours' level l, so the steps
+// run as a wavefront: pass t decides and traces every (s, l) with s + l = t
+// (N + L + 1 passes instead of (N + 1)(L + 1)), each pass in its own list
+// slot; the level-0 reduction of level-s images follows pass s.
 int enqueue_spectral(art_batch* b, int n0, int slevels, hipStream_t s)
 {
     b->ntrace = 0;
@@ -687,33 +691,32 @@ int enqueue_spectral(art_batch* b, int n0, int slevels, hipStream_t s)
     const ImageDesc& D0 = b->hD[0];
     const int N = D0.levels;
     const int nb = D0.nx0 * D0.ny0;
-    HIP_TRY(launch_fill_u32((uint32_t*)ctr, sizeof(Counters) / 4, 0u, s));
-    HIP_TRY(launch_base_list(b->dD, n0, nb, list, ctr, 0, s));
-    int rc = trace_pass(b, 0, 0, s);
-    if (rc) return rc;
-    HIP_TRY(launch_reduce_base(b->dD, n0, ctr, s));
-    for (int l = 0; l < N; ++l) {
-        const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
-        HIP_TRY(launch_estimate(b->dD, n0, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s));
-        rc = trace_pass(b, 0, l + 1, s);
-        if (rc) return rc;
-    }
-    int off = n0;
+    int off[8], m[8];
+    off[0] = 0;
+    m[0] = n0;
     for (int sl = 1; sl <= slevels; ++sl) {
-        const int m = (n0 - 1) << (sl - 1);
-        // fresh per-pass work counters (count, count_back, cursor) for this level's passes
-        HIP_TRY(launch_fill_u32((uint32_t*)ctr, offsetof(Counters, steps) / 4, 0u, s));
-        HIP_TRY(launch_spectral_base(b->dD, off, m, nb, ctr, list, cap, b->L.long_steps, s));
-        rc = trace_pass(b, 0, 0, s);
-        if (rc) return rc;
-        HIP_TRY(launch_reduce_base(b->dD, m, ctr, s, off));
-        for (int l = 0; l < N; ++l) {
-            const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
-            HIP_TRY(launch_estimate(b->dD, m, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 3, 1, off));
-            rc = trace_pass(b, 0, l + 1, s);
-            if (rc) return rc;
+        off[sl] = off[sl - 1] + m[sl - 1];
+        m[sl] = (n0 - 1) << (sl - 1);
+    }
+    HIP_TRY(launch_fill_u32((uint32_t*)ctr, sizeof(Counters) / 4, 0u, s));
+    for (int t = 0; t <= N + slevels; ++t) {
+        for (int sl = 0; sl <= slevels; ++sl) {
+            const int l = t - sl;
+            if (l < 0 || l > N) continue;
+            if (l == 0) {
+                if (sl == 0)
+                    HIP_TRY(launch_base_list(b->dD, n0, nb, list, ctr, t, s));
+                else
+                    HIP_TRY(launch_spectral_base(b->dD, off[sl], m[sl], nb, ctr, list, cap, b->L.long_steps, t, s));
+            } else {
+                const int nxl = (int)grid_n(D0.nx0, l), nyl = (int)grid_n(D0.ny0, l);
+                HIP_TRY(launch_estimate(b->dD, m[sl], nxl, nyl, l - 1, ctr, list, cap, b->L.long_steps, s,
+                                        sl == 0 ? 0 : 3, 1, off[sl], t));
+            }
         }
-        off += m;
+        int rc = trace_pass(b, 0, t, s);
+        if (rc) return rc;
+        if (t <= slevels) HIP_TRY(launch_reduce_base(b->dD, m[t], ctr, s, off[t]));
     }
     if (b->timing) HIP_TRY(hipEventRecord(b->ev_render[1], s));
     return ART_OK;
@@ -934,8 +937,8 @@ int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const ar
     if (!(spec->nu_min_hz > 0.0) || !(spec->nu_max_hz > spec->nu_min_hz) || !std::isfinite(spec->nu_max_hz))
         return fail(ART_EINVAL, "spectral cube needs 0 < nu_min < nu_max (finite)");
     if (std::isnan(spec->r_rel) || std::isnan(spec->r_abs)) return fail(ART_EINVAL, "NaN spectral tolerance");
-    if ((long long)(cam->levels + 1) * (L + 1) > kMaxEv)
-        return fail(ART_EINVAL, "spectral cube of %d x %d passes (limit %d)", cam->levels + 1, L + 1, kMaxEv);
+    if (cam->levels + L > kMaxLevels)
+        return fail(ART_EINVAL, "spectral cube of %d + %d levels (limit %d)", cam->levels, L, kMaxLevels);
     // internal order: base frequencies, then each spectral level; perm[k] = cube index
     std::vector<int> perm, inv(n, -1);
     for (int k = 0; k < n0; ++k) perm.push_back(k << L);

@@ -98,10 +98,12 @@ hipError_t launch_trace(int precision, int model, int nstokes, bool subrings, co
 hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s, int img_off = 0);
 // Base points of the spectral-level images [img_off, img_off + nimg): the
 // spectral value where the one-axis rule along ln nu accepts it, else the
-// point is queued for tracing in slot 0 (front: expected long rays).
+// point is queued for tracing in list slot `slot` (front: expected long rays).
 hipError_t launch_spectral_base(const ImageDesc* desc, int img_off, int nimg, int max_base, Counters* ctr,
-                                unsigned long long* list, long long cap, int long_steps, hipStream_t s);
-// Images [img_off, img_off + nimg) of desc.
+                                unsigned long long* list, long long cap, int long_steps, int slot,
+                                hipStream_t s);
+// Images [img_off, img_off + nimg) of desc; work items go to list slot
+// `slot` (< 0: l + 1, the level's own slot).
 // mode 0: plain criterion.  mode 3: spectral images: a point the criterion
 // flags takes the spectral value where the rule along ln nu accepts it and is
 // traced otherwise.  mode 1: learned, level l -> l+1 (points marked
@@ -114,7 +116,7 @@ hipError_t launch_spectral_base(const ImageDesc* desc, int img_off, int nimg, in
 // (list capacity `cap`).
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
                            Counters* ctr, unsigned long long* list, long long cap, int long_steps,
-                           hipStream_t s, int mode = 0, int fallback = 1, int img_off = 0);
+                           hipStream_t s, int mode = 0, int fallback = 1, int img_off = 0, int slot = -1);
 hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
                           int nblocks, hipStream_t s);
 int trace_occupancy_blocks(int precision, int model, int nstokes, bool subrings, int threads);

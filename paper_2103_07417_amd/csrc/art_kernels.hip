@@ -549,7 +549,8 @@ __device__ void spectral_write(const ImageDesc* desc, const ImageDesc& D, long l
 
 // grid (x: base points, y: image).  Base points of spectral-level images.
 __global__ __launch_bounds__(256) void k_spectral_base(const ImageDesc* desc, int img_off, Counters* ctr,
-                                                       unsigned long long* list, long long cap, int long_steps)
+                                                       unsigned long long* list, long long cap, int long_steps,
+                                                       int slot)
 {
     const int img = img_off + blockIdx.y;
     const ImageDesc D = desc[img];
@@ -582,8 +583,8 @@ __global__ __launch_bounds__(256) void k_spectral_base(const ImageDesc* desc, in
         const int leader = __ffsll((long long)(mlong | mshort)) - 1;
         unsigned bl = 0, bs = 0;
         if (lane == leader) {
-            if (mlong) bl = atomicAdd(&ctr->count[0], (unsigned)__popcll(mlong));
-            if (mshort) bs = atomicAdd(&ctr->count_back[0], (unsigned)__popcll(mshort));
+            if (mlong) bl = atomicAdd(&ctr->count[slot], (unsigned)__popcll(mlong));
+            if (mshort) bs = atomicAdd(&ctr->count_back[slot], (unsigned)__popcll(mshort));
             atomicAdd(&ctr->img_traced[img][0], (unsigned)__popcll(mlong | mshort));
         }
         bl = __shfl(bl, leader);
@@ -595,10 +596,10 @@ __global__ __launch_bounds__(256) void k_spectral_base(const ImageDesc* desc, in
 }
 
 hipError_t launch_spectral_base(const ImageDesc* desc, int img_off, int nimg, int max_base, Counters* ctr,
-                                unsigned long long* list, long long cap, int long_steps, hipStream_t s)
+                                unsigned long long* list, long long cap, int long_steps, int slot, hipStream_t s)
 {
     dim3 grid((max_base + 255) / 256, nimg);
-    hipLaunchKernelGGL(k_spectral_base, grid, dim3(256), 0, s, desc, img_off, ctr, list, cap, long_steps);
+    hipLaunchKernelGGL(k_spectral_base, grid, dim3(256), 0, s, desc, img_off, ctr, list, cap, long_steps, slot);
     return hipGetLastError();
 }
 
@@ -625,7 +626,7 @@ __device__ __forceinline__ bool axis_D(const double* I, long long nx, int s, int
 // level-(l+1) grid; new points are classified by index parity (categories 2-4).
 __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
                                                   unsigned long long* list, long long cap, int long_steps,
-                                                  int mode, int fallback, int img_off)
+                                                  int mode, int fallback, int img_off, int slot)
 {
     const int img = img_off + blockIdx.z;
     const ImageDesc D = desc[img];
@@ -812,8 +813,8 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
         const int leader = __ffsll((long long)(mlong | mshort)) - 1;
         unsigned bl = 0, bs = 0;
         if (lane == leader) {
-            if (mlong) bl = atomicAdd(&ctr->count[l + 1], (unsigned)__popcll(mlong));
-            if (mshort) bs = atomicAdd(&ctr->count_back[l + 1], (unsigned)__popcll(mshort));
+            if (mlong) bl = atomicAdd(&ctr->count[slot], (unsigned)__popcll(mlong));
+            if (mshort) bs = atomicAdd(&ctr->count_back[slot], (unsigned)__popcll(mshort));
             atomicAdd(&ctr->img_traced[img][l + 1], (unsigned)__popcll(mlong | mshort));
         }
         bl = __shfl(bl, leader);
@@ -826,11 +827,11 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
 
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
                            Counters* ctr, unsigned long long* list, long long cap, int long_steps,
-                           hipStream_t s, int mode, int fallback, int img_off)
+                           hipStream_t s, int mode, int fallback, int img_off, int slot)
 {
     dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
     hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, cap, long_steps, mode, fallback,
-                       img_off);
+                       img_off, slot < 0 ? l + 1 : slot);
     return hipGetLastError();
 }
 
