@@ -44,8 +44,9 @@ def gaussian_field(shape, rng, slope=-5.0 / 3.0):
 
 def mks_snapshot(seed=2, n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, hslope=0.3,
                  r_c=12.0, width=3.0, atmosphere=1e-4, sigma_turb=0.0998, beta=10.0,
-                 gamma_ad=13.0 / 9.0):
-    """Returns (grid float32 [n3][n2][n1][8], geometry dict)."""
+                 gamma_ad=13.0 / 9.0, turb=None):
+    """Returns (grid float32 [n3][n2][n1][8], geometry dict).  turb: optional
+    unit Gaussian field [n3][n2][n1] replacing the seeded one."""
     rng = np.random.default_rng(seed)
     x1_0 = np.log(r_in)
     dx1 = (np.log(r_out) - x1_0) / n1
@@ -56,7 +57,7 @@ def mks_snapshot(seed=2, n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, hslope=
     R = r * np.sin(th)
     z = r * np.cos(th)
     rho_bar = np.exp(-((R - r_c) ** 2 + z ** 2) / (2.0 * width ** 2)) + atmosphere * (r / r_c) ** -1.5
-    G = gaussian_field((n3, n2, n1), rng)
+    G = gaussian_field((n3, n2, n1), rng) if turb is None else turb
     rho = rho_bar * np.exp(sigma_turb * G - 0.5 * sigma_turb ** 2)
     p = rho / (3.0 * r)
     u = p / (gamma_ad - 1.0)
@@ -75,6 +76,41 @@ def mks_snapshot(seed=2, n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, hslope=
     grid[..., 7] = bmag * dirn[2]
     geo = dict(x1_0=x1_0, dx1=dx1, hslope=hslope, n1=n1, n2=n2, n3=n3, gamma_ad=gamma_ad)
     return grid, geo
+
+
+def mks_movie(times, seed=2, t_mix=200.0, n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, **kw):
+    """Snapshots of an evolving flow at the given times [M] (a movie for
+    adaptive sampling in time): the turbulence field is carried around in phi
+    at the Keplerian rate Omega(r) = r^-3/2 (periodic linear interpolation
+    along x3, a different shift per radial zone) and turned into an
+    independent field over t_mix (G_t = cos(w t) G_a + sin(w t) G_b,
+    w = pi / (2 t_mix)).  At t = 0 the snapshot equals mks_snapshot(seed).
+    Returns (list of float32 grids, geometry dict)."""
+    rng = np.random.default_rng(seed)
+    Ga = gaussian_field((n3, n2, n1), rng)
+    Gb = gaussian_field((n3, n2, n1), np.random.default_rng([seed, 1]))
+    x1_0 = np.log(r_in)
+    dx1 = (np.log(r_out) - x1_0) / n1
+    r = np.exp(x1_0 + (np.arange(n1) + 0.5) * dx1)
+    i3 = np.arange(n3)[:, None]
+    grids = []
+    geo = None
+    for t in times:
+        shift = (r ** -1.5) * float(t) / (2.0 * np.pi / n3)        # cells per radial zone
+        k = np.floor(shift).astype(np.int64)
+        f = shift - k
+        lo = (i3 - k[None, :]) % n3                                 # [n3, n1]
+        hi = (lo - 1) % n3
+
+        def carry(G):
+            g_lo = np.take_along_axis(G, np.broadcast_to(lo[:, None, :], G.shape), axis=0)
+            g_hi = np.take_along_axis(G, np.broadcast_to(hi[:, None, :], G.shape), axis=0)
+            return (1.0 - f)[None, None, :] * g_lo + f[None, None, :] * g_hi
+        w = 0.5 * np.pi * float(t) / t_mix
+        G = np.cos(w) * carry(Ga) + np.sin(w) * carry(Gb) if t != 0 else Ga
+        grid, geo = mks_snapshot(seed, n1, n2, n3, r_in, r_out, turb=G, **kw)
+        grids.append(grid)
+    return grids, geo
 
 
 def mks_snapshot_geometry(n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, hslope=0.3,

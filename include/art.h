@@ -227,7 +227,9 @@ int art_trace_points(const art_spacetime* sp, const art_camera* cam, const art_e
  * of levels) rendered together: every level's new rays of every image go into
  * one work queue of the persistent tracer, so long photon-ring rays of one
  * image overlap with the work of the others.  All images of a batch use the
- * same emission kind, nstokes and precision; at most 64 images. */
+ * same emission kind, nstokes, precision and subring count, and gridded-model
+ * images the same theta grid (h and n2; the snapshots themselves may differ);
+ * at most 64 images. */
 typedef struct {
     art_spacetime sp;
     art_camera cam;
@@ -415,6 +417,17 @@ typedef struct {
 int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
                         const art_refine* rf, const art_transfer* tr, const art_spectral* spec,
                         art_image* out, art_stats* st, void* stream);
+
+/* The same adaptive sampling along any sequence axis (time, frequency, ...):
+ * jobs[n] in axis order, taken as equally spaced along it (snapshots of a
+ * movie at a fixed cadence, frequencies equally spaced in ln nu, ...), with
+ * n = 2^levels (n0 - 1) + 1 <= 64 and one base grid and level count; the
+ * rule above with tolerances r_rel, r_abs decides between the axis
+ * neighbours' mean and a ray.  Gridded-model images may use different
+ * snapshots of one theta grid (same h and n2).  Sec. 6 names time sampling
+ * for movies as the other target of the extension. */
+int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, double r_rel, double r_abs,
+                    art_image* out, art_stats* st, void* stream);
 
 /* Image metrics of Sec. 4.1 on n FP64 values (one Stokes plane), computed on
  * the device with a deterministic two-pass reduction; synchronises:

@@ -1,7 +1,10 @@
-"""Adaptive sampling along frequency (test oracle).
+"""Adaptive sampling along frequency or time (test oracle).
 
 Test infrastructure only.  The paper closes (Sec. 6) by proposing to extend
-the recursive subdivision of Sec. 3.2 to the frequency (and time) domain.
+the recursive subdivision of Sec. 3.2 to the frequency and time domains.
+The cube below is written for frequency; the same rule along any equally
+spaced sequence axis (snapshots of a movie at a fixed cadence) is
+render_cube.
 This module is this project's reading of that extension, built from the
 paper's own one-axis rule:
 
@@ -106,16 +109,14 @@ def spectral_alt(imgs, nabs, stencil, r_rel, r_abs, all_planes=False):
     return alt
 
 
-def render_spectral(ray_fn_nu, fov, nx0, ny0, levels, r_rel, r_abs, nu_min, nu_max, n0, slevels,
-                    sr_rel, sr_abs, abs_norm="mean", nstokes=1, all_planes=False, forced_levels=None):
-    """Spectral cube by adaptive sampling in ln nu.
+def render_cube(ray_fn_k, fov, nx0, ny0, levels, r_rel, r_abs, n0, slevels, sr_rel, sr_abs,
+                abs_norm="mean", nstokes=1, all_planes=False, forced_levels=None):
+    """Cube along any equally spaced sequence axis (time, ln nu, ...).
 
-    ray_fn_nu(nu) -> ray_fn(x, y) of that frequency.  Returns (results,
-    frequencies): results[i] is oracle.refine's dict for cube image i (in
-    frequency order).  forced_levels: optional list of final-grid level maps
-    (mask-forced replay of every image's decisions)."""
+    ray_fn_k(k) -> ray_fn(x, y) of cube image k.  Returns results[k] =
+    oracle.refine's dict of image k, in axis order.  forced_levels: optional
+    list of final-grid level maps (mask-forced replay of every image)."""
     n = cube_size(n0, slevels)
-    nus = frequencies(nu_min, nu_max, n0, slevels)
     res = [None] * n
     order = [i for i in range(n) if spectral_level(i, slevels) == 0]
     for s in range(1, slevels + 1):
@@ -128,6 +129,16 @@ def render_spectral(ray_fn_nu, fov, nx0, ny0, levels, r_rel, r_abs, nu_min, nu_m
             imgs = {k: res[k]["img"] for k in st if k is not None}
             nabs = {k: res[k]["n_abs"] for k in st if k is not None}
             alt = spectral_alt(imgs, nabs, st, sr_rel, sr_abs, all_planes)
-        res[i] = oref.refine(ray_fn_nu(nus[i]), fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstokes,
+        res[i] = oref.refine(ray_fn_k(i), fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstokes,
                              forced_level=fl, all_planes=all_planes, alt=alt)
+    return res
+
+
+def render_spectral(ray_fn_nu, fov, nx0, ny0, levels, r_rel, r_abs, nu_min, nu_max, n0, slevels,
+                    sr_rel, sr_abs, abs_norm="mean", nstokes=1, all_planes=False, forced_levels=None):
+    """Spectral cube: the cube along ln nu.  ray_fn_nu(nu) -> ray_fn(x, y) of
+    that frequency.  Returns (results, frequencies)."""
+    nus = frequencies(nu_min, nu_max, n0, slevels)
+    res = render_cube(lambda k: ray_fn_nu(nus[k]), fov, nx0, ny0, levels, r_rel, r_abs, n0, slevels,
+                      sr_rel, sr_abs, abs_norm, nstokes, all_planes, forced_levels)
     return res, nus

@@ -151,6 +151,8 @@ def lib():
                                          P(Transfer), vp, P(Learned), P(Image), P(Stats), vp]
         L.art_render_spectral.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine), P(Transfer),
                                           P(Spectral), P(Image), P(Stats), vp]
+        L.art_render_cube.argtypes = [i32, P(Job), i32, i32, ctypes.c_double, ctypes.c_double, P(Image),
+                                      P(Stats), vp]
         L.art_vis_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
         L.art_vis_workspace_bytes.restype = ctypes.c_size_t
         L.art_visibility.argtypes = [vp, i64, i32, i32, i32, ctypes.c_double, ctypes.c_double, vp, i32,
@@ -299,6 +301,30 @@ def render_spectral(cfg, nu_min, nu_max, n0, levels, r_rel=None, r_abs=None, fea
     _check(rc)
     out = [stats_dict(sts[i]) for i in range(n)]
     return [b[0] for b in bufs], [b[1] for b in bufs], [b[2] for b in bufs], out
+
+
+def render_cube(cfgs, n0, levels, r_rel=None, r_abs=None, feat=False, stream=None):
+    """Adaptive sampling along a sequence axis (time, frequency, ...): cfgs in
+    axis order, equally spaced along it, len(cfgs) = 2^levels (n0 - 1) + 1.
+    Returns (images, levels, feats, stats) in axis order; r_rel / r_abs
+    default to the spatial tolerances of cfgs[0]."""
+    torch = _torch()
+    n = len(cfgs)
+    jobs = (Job * n)()
+    bufs = []
+    for i, c in enumerate(cfgs):
+        sp, cam, em, rf, tr = blocks(c)
+        jobs[i] = Job(sp, cam, em, rf, tr)
+        bufs.append(alloc(c, feat))
+    ims = (Image * n)(*[_image(*b) for b in bufs])
+    sts = (Stats * n)()
+    rc = lib().art_render_cube(n, jobs, int(n0), int(levels),
+                               float(cfgs[0]["r_rel"] if r_rel is None else r_rel),
+                               float(cfgs[0]["r_abs"] if r_abs is None else r_abs),
+                               ims, sts, _stream(torch, stream))
+    _check(rc)
+    return [b[0] for b in bufs], [b[1] for b in bufs], [b[2] for b in bufs], \
+        [stats_dict(sts[i]) for i in range(n)]
 
 
 def learned_opts(z_propose=2.0, z_suppress=float("-inf"), fallback=True, all_levels=False):

@@ -476,9 +476,8 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
                    J.tr.subrings != b->nsub) {
             return fail(ART_EINVAL, "image %d: a batch needs one emission kind, nstokes, precision and subring count", i);
         } else if (J.em.kind == ART_EMIS_GRID &&
-                   (J.em.grid_dev != jobs[0].em.grid_dev || J.em.params[8] != jobs[0].em.params[8] ||
-                    J.em.params[10] != jobs[0].em.params[10])) {
-            return fail(ART_EINVAL, "image %d: all images of a batch must share one snapshot", i);
+                   (J.em.params[8] != jobs[0].em.params[8] || J.em.params[10] != jobs[0].em.params[10])) {
+            return fail(ART_EINVAL, "image %d: all snapshots of a batch need the same theta grid (h, n2)", i);
         }
         int32_t nx, ny;
         rc = grid_size(&J.cam, J.tr.nstokes, &nx, &ny);
@@ -925,35 +924,35 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
     return ART_OK;
 }
 
-int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
-                        const art_refine* rf, const art_transfer* tr, const art_spectral* spec, art_image* out,
-                        art_stats* st, void* stream)
+int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, double r_rel, double r_abs,
+                    art_image* out, art_stats* st, void* stream)
 {
-    if (!sp || !cam || !em || !rf || !tr || !spec || !out) return fail(ART_EINVAL, "null argument");
-    const int n0 = spec->n0, L = spec->levels;
-    if (n0 < 2 || L < 0 || L > 6) return fail(ART_EINVAL, "spectral cube needs n0 >= 2 and 0 <= levels <= 6");
-    const long long n = ((long long)(n0 - 1) << L) + 1;
-    if (n > kMaxBatch) return fail(ART_EINVAL, "spectral cube of %lld images (limit %d)", n, kMaxBatch);
-    if (!(spec->nu_min_hz > 0.0) || !(spec->nu_max_hz > spec->nu_min_hz) || !std::isfinite(spec->nu_max_hz))
-        return fail(ART_EINVAL, "spectral cube needs 0 < nu_min < nu_max (finite)");
-    if (std::isnan(spec->r_rel) || std::isnan(spec->r_abs)) return fail(ART_EINVAL, "NaN spectral tolerance");
-    if (cam->levels + L > kMaxLevels)
-        return fail(ART_EINVAL, "spectral cube of %d + %d levels (limit %d)", cam->levels, L, kMaxLevels);
-    // internal order: base frequencies, then each spectral level; perm[k] = cube index
+    if (!jobs || !out) return fail(ART_EINVAL, "null argument");
+    const int L = levels;
+    if (n0 < 2 || L < 0 || L > 6) return fail(ART_EINVAL, "a cube needs n0 >= 2 and 0 <= levels <= 6");
+    if ((long long)n != ((long long)(n0 - 1) << L) + 1)
+        return fail(ART_EINVAL, "a cube of n0 = %d and %d levels has %lld images, not %d", n0, L,
+                    ((long long)(n0 - 1) << L) + 1, n);
+    if (n > kMaxBatch) return fail(ART_EINVAL, "cube of %d images (limit %d)", n, kMaxBatch);
+    if (std::isnan(r_rel) || std::isnan(r_abs)) return fail(ART_EINVAL, "NaN cube tolerance");
+    for (int i = 1; i < n; ++i)
+        if (jobs[i].cam.nx0 != jobs[0].cam.nx0 || jobs[i].cam.ny0 != jobs[0].cam.ny0 ||
+            jobs[i].cam.levels != jobs[0].cam.levels)
+            return fail(ART_EINVAL, "cube image %d: every image needs the same base grid and levels", i);
+    if (jobs[0].cam.levels + L > kMaxLevels)
+        return fail(ART_EINVAL, "cube of %d + %d levels (limit %d)", jobs[0].cam.levels, L, kMaxLevels);
+    // internal order: base images, then each cube level; perm[k] = axis index
     std::vector<int> perm, inv(n, -1);
     for (int k = 0; k < n0; ++k) perm.push_back(k << L);
     for (int sl = 1; sl <= L; ++sl) {
         const int h = 1 << (L - sl);
-        for (long long i = h; i < n; i += 2 * h) perm.push_back((int)i);
+        for (int i = h; i < n; i += 2 * h) perm.push_back(i);
     }
-    for (int k = 0; k < (int)n; ++k) inv[perm[k]] = k;
-    std::vector<art_job> jobs((size_t)n);
+    for (int k = 0; k < n; ++k) inv[perm[k]] = k;
+    std::vector<art_job> J((size_t)n);
     std::vector<art_image> imgs((size_t)n);
-    for (int k = 0; k < (int)n; ++k) {
-        art_emission e = *em;
-        const double t = (double)perm[k] / (double)(n - 1);
-        e.freq_hz = spec->nu_min_hz * std::pow(spec->nu_max_hz / spec->nu_min_hz, t);
-        jobs[k] = make_job(sp, cam, &e, rf, tr);
+    for (int k = 0; k < n; ++k) {
+        J[k] = jobs[perm[k]];
         imgs[k] = out[perm[k]];
     }
     std::lock_guard<std::mutex> lk(g_single_mu);
@@ -961,23 +960,23 @@ int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const ar
     if (!b) return fail(ART_EDEVICE, "no current device");
     hipStream_t s = (hipStream_t)stream;
     b->spectral = true;
-    int rc = prepare(b, (int)n, jobs.data(), imgs.data(), false, s);
+    int rc = prepare(b, n, J.data(), imgs.data(), false, s);
     if (rc) {
         b->spectral = false;
         return rc;
     }
-    for (int k = n0; k < (int)n; ++k) {
+    for (int k = n0; k < n; ++k) {
         const int i = perm[k];
         int lvl = L;
-        for (int j = i; j % 2 == 0; j /= 2) --lvl;
+        for (int q = i; q % 2 == 0; q /= 2) --lvl;
         const int h = 1 << (L - lvl);
         ImageDesc& D = b->hD[k];
         D.sb = inv[i - h];
         D.sc = inv[i + h];
         D.sa = i - 3 * h >= 0 ? inv[i - 3 * h] : -1;
         D.sd = i + 3 * h < n ? inv[i + 3 * h] : -1;
-        D.sr_rel = spec->r_rel;
-        D.sr_abs = spec->r_abs;
+        D.sr_rel = r_rel;
+        D.sr_abs = r_abs;
     }
     hipError_t e = hipMemcpyAsync(b->dD, b->hD.data(), sizeof(ImageDesc) * n, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
@@ -990,12 +989,32 @@ int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const ar
     b->spectral = false;
     if (rc) return rc;
     if (st) {
-        for (int k = 0; k < (int)n; ++k) {
+        for (int k = 0; k < n; ++k) {
             rc = batch_stats(b, k, &st[perm[k]], s);
             if (rc) return rc;
         }
     }
     return ART_OK;
+}
+
+int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                        const art_refine* rf, const art_transfer* tr, const art_spectral* spec, art_image* out,
+                        art_stats* st, void* stream)
+{
+    if (!sp || !cam || !em || !rf || !tr || !spec || !out) return fail(ART_EINVAL, "null argument");
+    const int n0 = spec->n0, L = spec->levels;
+    if (n0 < 2 || L < 0 || L > 6) return fail(ART_EINVAL, "spectral cube needs n0 >= 2 and 0 <= levels <= 6");
+    const long long n = ((long long)(n0 - 1) << L) + 1;
+    if (n > kMaxBatch) return fail(ART_EINVAL, "spectral cube of %lld images (limit %d)", n, kMaxBatch);
+    if (!(spec->nu_min_hz > 0.0) || !(spec->nu_max_hz > spec->nu_min_hz) || !std::isfinite(spec->nu_max_hz))
+        return fail(ART_EINVAL, "spectral cube needs 0 < nu_min < nu_max (finite)");
+    std::vector<art_job> jobs((size_t)n);
+    for (int i = 0; i < (int)n; ++i) {
+        art_emission e = *em;
+        e.freq_hz = spec->nu_min_hz * std::pow(spec->nu_max_hz / spec->nu_min_hz, (double)i / (double)(n - 1));
+        jobs[i] = make_job(sp, cam, &e, rf, tr);
+    }
+    return art_render_cube((int32_t)n, jobs.data(), n0, L, spec->r_rel, spec->r_abs, out, st, stream);
 }
 
 int art_render_uniform(const art_spacetime* sp, const art_camera* cam, const art_emission* em,

@@ -9,6 +9,8 @@ the Sec. 3.2 rule) against the oracle.
 - A negative spectral tolerance reproduces plain adaptive renders at every
   frequency bitwise; statistics count spectral values and rays consistently;
   mixed precision stays within MSE 1e-3 of FP64; invalid cubes are refused.
+- Time: 5 snapshots of an evolving synthetic flow (gridded model) as a cube
+  along t, against the oracle's cube on the same snapshots.
 """
 import numpy as np
 import pytest
@@ -113,3 +115,43 @@ def test_invalid_cubes(art):
         art.render_spectral(cfg, NU[0], NU[1], 9, 3)          # 65 images
     with pytest.raises(art.ArtError):
         art.render_spectral(cfg, NU[1], NU[0], 3, 1)
+
+
+def test_time_cube_parity(art):
+    """Adaptive sampling in time: 5 snapshots of the evolving synthetic flow
+    (t = 0, 25, ..., 100 M; 3 base times, 1 level), gridded model, 17^2 ->
+    65^2, FP64, against the oracle cube (ties replayed)."""
+    from art_inputs import mks
+    print("CASE time cube parity", flush=True)
+    times = [0.0, 25.0, 50.0, 75.0, 100.0]
+    grids, geo = mks.mks_movie(times, seed=2)
+    gdev = [torch.from_numpy(g).cuda() for g in grids]
+    base = dict(art_inputs.workload("grid_4097"), nx0=17, ny0=17, levels=2, nstokes=1, precision="fp64")
+    cfgs = [dict(base, grid_dev=gd) for gd in gdev]
+    sr = (0.05, 0.025)
+    imgs, levs, _, sts = art.render_cube(cfgs, 3, 1, *sr)
+    torch.cuda.synchronize()
+    g = [i.cpu().numpy() for i in imgs]
+    gl = [l.cpu().numpy() for l in levs]
+
+    def oracle(forced=None):
+        fn_k = lambda k: (lambda x, y: oray.trace(base, x, y, grid=grids[k])[0])
+        return osp.render_cube(fn_k, base["fov"], base["nx0"], base["ny0"], base["levels"], base["r_rel"],
+                               base["r_abs"], 3, 1, sr[0], sr[1], base["abs_norm"], 1, forced_levels=forced)
+    o = oracle()
+    flips = sum(int((a != b["level"]).sum()) for a, b in zip(gl, o))
+    if flips:
+        assert flips <= 2 * len(gl), flips
+        o = oracle(forced=gl)
+    for k in range(len(times)):
+        assert rel_l2(g[k][0], o[k]["img"][0]) <= 1e-6, (k, rel_l2(g[k][0], o[k]["img"][0]))
+        assert sts[k]["spectral"] == int((gl[k] == -3).sum())
+    assert sum(s["spectral"] for s in sts) > 0
+
+
+def test_cube_validation(art):
+    cfg = small_cfg()
+    with pytest.raises(art.ArtError):
+        art.render_cube([cfg] * 4, 3, 1)                        # 4 != 5 images
+    with pytest.raises(art.ArtError):
+        art.render_cube([cfg] * 4 + [dict(cfg, nx0=11, ny0=11)], 3, 1)
