@@ -110,9 +110,11 @@ hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, co
 
 // ------------------------------------------------------- weight gradients
 // Positions are split into nchunks chunks of clen (a multiple of 8); one wave
-// per (chunk, 32-wide tile of k = c * 9 + tap in master order) writes
-// part[chunk][ktile][32 c_out][32 k].  A operand = dZ (rows = output
-// channel), B operand = im2col(in) (columns = k); reduction over positions.
+// per (chunk, 32-wide tile of the tap-major depth k = tap * cin_pad + c)
+// writes part[chunk][ktile][32 c_out][32 k].  A operand = dZ (rows = output
+// channel), B operand = im2col(in) (columns = k, 32 consecutive channels of
+// one shifted position per lane group); reduction over positions, whose
+// (image, row, column) is advanced incrementally (no divisions in the loop).
 __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in, int ci, int cin_pad, int B,
                                                  int H, int W, const uint16_t* __restrict__ dZ, int co,
                                                  int cout_pad, float* __restrict__ part, float* __restrict__ dbpart,
@@ -120,8 +122,8 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
 {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int K = ci * 9;
-    const int ktiles = (K + 31) >> 5;
+    const int Kp = 9 * cin_pad;
+    const int ktiles = (Kp + 31) >> 5;
     const int chunk = wave / ktiles;
     if (chunk >= nchunks) return;
     const int kt = wave - chunk * ktiles;
@@ -133,34 +135,43 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
     floatx16 acc;
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-    const int k = kt * 32 + m;                       // this lane's B column
-    int c = 0, dy = 0, dx = 0;
-    if (k < K) { c = k / 9; const int r = k - 9 * c; dy = r / 3 - 1; dx = (r % 3) - 1; }
+    const int k = kt * 32 + m;                       // this lane's B column (tap-major)
+    const int tap = k / cin_pad, c = k - tap * cin_pad;
+    const bool kval = tap < 9 && c < ci;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    // (image, row, column) of the first position of each 8-position step
+    int pb = (int)(p0 / HW);
+    const long long q0 = p0 - (long long)pb * HW;
+    int py = (int)(q0 / W), px = (int)(q0 - (long long)py * W);
     float sdb = 0.0f;                                // bias gradient partial (k tile 0 only)
     for (long long ps = p0; ps < p1; ps += 8) {
         bf16x4 a, bv;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const long long p = ps + 4 * kb + t;
+            const int o = 4 * kb + t;
+            const long long p = ps + o;
             short av = 0, bw = 0;
             if (p < p1) {
                 if (m < co) {
                     av = (short)dZ[p * cout_pad + m];
                     sdb += bf2f((uint16_t)av);
                 }
-                if (k < K) {
-                    const long long bi = p / HW;
-                    const long long q = p - bi * HW;
-                    const int y = (int)(q / W), x = (int)(q - (long long)y * W);
+                if (kval) {
+                    int x = px + o, y = py, b = pb;
+                    while (x >= W) { x -= W; ++y; }
+                    while (y >= H) { y -= H; ++b; }
                     const int yy = y + dy, xx = x + dx;
                     if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                        bw = (short)in[(bi * HW + (long long)yy * W + xx) * cin_pad + c];
+                        bw = (short)in[((long long)b * HW + (long long)yy * W + xx) * cin_pad + c];
                 }
             }
             a[t] = av;
             bv[t] = bw;
         }
         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+        px += 8;
+        while (px >= W) { px -= W; ++py; }
+        while (py >= H) { py -= H; ++pb; }
     }
     float* Pp = part + ((long long)chunk * ktiles + kt) * 1024;
 #pragma unroll
@@ -175,42 +186,73 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
     }
 }
 
-// dW[co][k] (FP32, k < K) and db[co] = sums over chunks in order.
-__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, const float* __restrict__ dbpart,
-                                                   int nchunks, int ktiles, int co, int K, float* __restrict__ dW,
-                                                   float* __restrict__ db)
+// Deterministic two-stage sum over the position chunks.  Stage 1: thread
+// (output e, slice sl) sums chunks sl, sl + S, sl + 2S, ... in order into
+// red[sl][e]; outputs e < co * K are the weights in master order
+// (e = o * K + c * 9 + tap, read from the tap-major partials), then co
+// biases.  Stage 2 sums the S slices in order.
+constexpr int kDwSlices = 16;
+
+__global__ __launch_bounds__(256) void k_dw_reduce1(const float* __restrict__ part, const float* __restrict__ dbpart,
+                                                    int nchunks, int ktiles, int co, int ci, int cin_pad,
+                                                    float* __restrict__ red)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < co * K) {
-        const int o = idx / K, k = idx - o * K;
-        const int kt = k >> 5, kk = k & 31;
-        float s = 0.0f;
-        for (int ch = 0; ch < nchunks; ++ch) s += part[((long long)ch * ktiles + kt) * 1024 + o * 32 + kk];
-        dW[idx] = s;
-    } else if (idx < co * K + co) {
-        const int o = idx - co * K;
-        float s = 0.0f;
-        for (int ch = 0; ch < nchunks; ++ch) s += dbpart[(long long)ch * 32 + o];
-        db[o] = s;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sl = blockIdx.y;
+    const int K = ci * 9;
+    const int nout = co * K + co;
+    if (e >= nout) return;
+    float s = 0.0f;
+    if (e < co * K) {
+        const int o = e / K, km = e - o * K;
+        const int c = km / 9, tap = km - 9 * c;
+        const int kp = tap * cin_pad + c;
+        const int kt = kp >> 5, kk = kp & 31;
+        for (int ch = sl; ch < nchunks; ch += kDwSlices)
+            s += part[((long long)ch * ktiles + kt) * 1024 + o * 32 + kk];
+    } else {
+        const int o = e - co * K;
+        for (int ch = sl; ch < nchunks; ch += kDwSlices) s += dbpart[(long long)ch * 32 + o];
     }
+    red[(long long)sl * nout + e] = s;
+}
+
+__global__ __launch_bounds__(256) void k_dw_reduce2(const float* __restrict__ red, int co, int ci,
+                                                    float* __restrict__ dW, float* __restrict__ db)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = ci * 9;
+    const int nout = co * K + co;
+    if (e >= nout) return;
+    float s = 0.0f;
+    for (int sl = 0; sl < kDwSlices; ++sl) s += red[(long long)sl * nout + e];
+    if (e < co * K)
+        dW[e] = s;
+    else
+        db[e - co * K] = s;
 }
 
 namespace {
+// Position chunks of the weight-gradient reduction: about 1024 positions
+// each (enough waves to fill the chip at 1025^2 grids), at least 64.
 void dw_split(long long P, int& nchunks, long long& clen)
 {
-    clen = (P + 127) / 128;
+    clen = 1024;
+    if (P < 64LL * 1024) clen = (P + 63) / 64;
     clen = (clen + 7) / 8 * 8;
     if (clen < 64) clen = 64;
     nchunks = (int)((P + clen - 1) / clen);
 }
 }  // namespace
 
-long long cnn_dw_part_floats(long long positions, int ci)
+long long cnn_dw_part_floats(long long positions, int cin_pad)
 {
     int nchunks;
     long long clen;
     dw_split(positions, nchunks, clen);
-    return (long long)nchunks * ((ci * 9 + 31) / 32) * 1024 + (long long)nchunks * 32;
+    // partials, bias partials, and the stage-1 slices (at most 32 x (32 x 9 x 32 + 32) outputs)
+    return (long long)nchunks * ((9 * cin_pad + 31) / 32) * 1024 + (long long)nchunks * 32 +
+           (long long)kDwSlices * (32 * 9 * cin_pad + 32);
 }
 
 hipError_t cnn_conv_dw(const uint16_t* in, int ci, int cin_pad, int B, int H, int W, const uint16_t* dZ, int co,
@@ -221,15 +263,20 @@ hipError_t cnn_conv_dw(const uint16_t* in, int ci, int cin_pad, int B, int H, in
     long long clen;
     dw_split(P, nchunks, clen);
     const int K = ci * 9;
-    const int ktiles = (K + 31) / 32;
+    const int ktiles = (9 * cin_pad + 31) / 32;
     const long long waves = (long long)nchunks * ktiles;
     float* dbpart = part + (long long)nchunks * ktiles * 1024;
     hipLaunchKernelGGL(k_conv_dw, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, in, ci, cin_pad, B, H, W,
                        dZ, co, cout_pad, part, dbpart, nchunks, clen);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dw_reduce, dim3((co * K + co + 255) / 256), dim3(256), 0, s, part, dbpart, nchunks,
-                       ktiles, co, K, dW, db);
+    float* red = dbpart + (long long)nchunks * 32;
+    const int nout = co * K + co;
+    hipLaunchKernelGGL(k_dw_reduce1, dim3((nout + 255) / 256, kDwSlices), dim3(256), 0, s, part, dbpart, nchunks,
+                       ktiles, co, ci, cin_pad, red);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dw_reduce2, dim3((nout + 255) / 256), dim3(256), 0, s, red, co, ci, dW, db);
     return hipGetLastError();
 }
 

@@ -27,10 +27,10 @@ hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, co
                         hipStream_t s);
 // Weight and bias gradients of a convolution: dW[co][ci][3][3] (FP32, master
 // order) = sum over positions of dZ x im2col(in); in NHWC cin_pad, dZ NHWC
-// cout_pad.  part holds cnn_dw_part_floats(B*H*W, ci) floats.
+// cout_pad.  part holds cnn_dw_part_floats(B*H*W, cin_pad) floats.
 hipError_t cnn_conv_dw(const uint16_t* in, int ci, int cin_pad, int B, int H, int W, const uint16_t* dZ, int co,
                        int cout_pad, float* part, float* dW, float* db, hipStream_t s);
-long long cnn_dw_part_floats(long long positions, int ci);
+long long cnn_dw_part_floats(long long positions, int cin_pad);
 // FP32 master W[co][ci][3][3] -> BF16 forward matrix Wf[32][9 cin_pad] and
 // (if Wb != NULL) input-gradient matrix Wb[32][9 cout_pad].
 hipError_t cnn_pack(const float* Wt, int ci, int co, int cin_pad, int cout_pad, uint16_t* Wf, uint16_t* Wb,

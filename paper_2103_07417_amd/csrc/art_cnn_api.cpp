@@ -149,7 +149,7 @@ int grads(CnnNet& n, const float* x, const uint8_t* lab, const uint8_t* val, int
     }
     long long need = 0;
     for (int l = 0; l < 4; ++l) {
-        const long long q = cnn_dw_part_floats(P, n.ci[l]);
+        const long long q = cnn_dw_part_floats(P, n.cin_pad[l]);
         need = q > need ? q : need;
     }
     if (need > n.part_cap) {
