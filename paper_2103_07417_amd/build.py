@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libart.so")
-SOURCES = ["art_kernels.hip", "art_api.cpp", "art_cnn.hip", "art_cnn_api.cpp", "art_vis.hip"]
+SOURCES = ["art_kernels.hip", "art_trace.hip", "art_api.cpp", "art_cnn.hip", "art_cnn_api.cpp", "art_vis.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -56,6 +56,12 @@ constexpr int8_t kMarkSpectral = -3;   // level map: value taken from the spectr
 
 enum TraceSrc : int { SRC_LIST = 0, SRC_POINTS = 1 };
 
+// Number of set bits of mask below the calling lane (wave-wide prefix).
+__device__ __forceinline__ unsigned lane_prefix(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
 // Work item of the pixel queue: image index in the high 32 bits.
 __host__ __device__ inline unsigned long long make_item(uint32_t img, uint32_t pix)
 {
