@@ -171,12 +171,11 @@ __device__ __forceinline__ void geo_rhs32(double a, double kt, double kph, const
 // kappa = (A1 - i A2)(r - i a cos th) with (BL contravariant components)
 //   A1 = (k^t f^r - k^r f^t) + a sin^2 (k^r f^ph - k^ph f^r)
 //   A2 = [(r^2+a^2)(k^ph f^th - k^th f^ph) - a (k^t f^th - k^th f^t)] sin
-__device__ __forceinline__ void walker_penrose(double a, double r, double s, double c,
-                                               const double k[4], const double f[4],
-                                               double& re, double& im)
+template <typename T>
+__device__ __forceinline__ void walker_penrose(T a, T r, T s, T c, const T k[4], const T f[4], T& re, T& im)
 {
-    const double A1 = (k[0] * f[1] - k[1] * f[0]) + a * s * s * (k[1] * f[3] - k[3] * f[1]);
-    const double A2 = ((r * r + a * a) * (k[3] * f[2] - k[2] * f[3]) - a * (k[0] * f[2] - k[2] * f[0])) * s;
+    const T A1 = (k[0] * f[1] - k[1] * f[0]) + a * s * s * (k[1] * f[3] - k[3] * f[1]);
+    const T A2 = ((r * r + a * a) * (k[3] * f[2] - k[2] * f[3]) - a * (k[0] * f[2] - k[2] * f[0])) * s;
     re = A1 * r - A2 * a * c;
     im = -(A1 * a * c + A2 * r);
 }
@@ -231,28 +230,29 @@ __device__ __forceinline__ void camera_start(const Params& P, double al, double 
 // ZAMO-frame 3-velocity of the equatorial flow at radius r (Keplerian
 // Omega = 1/(r^1.5 + a) outside the ISCO, the plunging geodesic with the ISCO
 // energy and angular momentum inside), applied at every theta.
-__device__ __forceinline__ void flow_v3(const Params& P, double r, double& vr, double& vp)
+template <typename G>
+__device__ __forceinline__ void flow_v3(const Params& P, G r, G dr, G& vr, G& vp)
 {
-    const double a = P.a;
-    const double Del = r * r - 2.0 * r + a * a;
-    const double A = (r * r + a * a) * (r * r + a * a) - a * a * Del;
-    const double iA = frcp(A);
-    const double al = ::sqrt(r * r * Del * iA);
-    const double ial = frcp(al);
-    const double om = 2.0 * a * r * iA;
-    const double sA = ::sqrt(A);
-    const double ir = frcp(r);
-    const double vpi = sA * ir;
-    if (r >= P.risco) {
-        const double Om = frcp(r * ::sqrt(r) + a);
+    const G a = G(P.a);
+    const G Del = dr * (r - G(2.0 - P.rh));          // (r - r+)(r - r-), dr = r - r+ from FP64
+    const G A = (r * r + a * a) * (r * r + a * a) - a * a * Del;
+    const G iA = frcp(A);
+    const G al = fsqrt(r * r * Del * iA);
+    const G ial = frcp(al);
+    const G om = G(2) * a * r * iA;
+    const G sA = fsqrt(A);
+    const G ir = frcp(r);
+    const G vpi = sA * ir;
+    if (r >= G(P.risco)) {
+        const G Om = frcp(r * fsqrt(r) + a);
         vp = vpi * (Om - om) * ial;
-        vr = 0.0;
+        vr = G(0);
     } else {
-        const double Gam = (P.Eis - om * P.Lis) * ial;
-        vp = (P.Lis * r * frcp(sA)) * frcp(Gam);
-        const double iG = frcp(Gam);
-        const double q = 1.0 - iG * iG - vp * vp;
-        vr = -::sqrt(q > 0.0 ? q : 0.0);
+        const G Gam = (G(P.Eis) - om * G(P.Lis)) * ial;
+        vp = (G(P.Lis) * r * frcp(sA)) * frcp(Gam);
+        const G iG = frcp(Gam);
+        const G q = G(1) - iG * iG - vp * vp;
+        vr = -fsqrt(q > G(0) ? q : G(0));
     }
 }
 
@@ -360,45 +360,52 @@ __device__ __forceinline__ void grid_sample(const Params& P, const double* tht, 
 }
 
 // Plasma and coefficients at a midpoint.  Returns false where nothing emits.
-// (s, c) = (sin, cos) of th, supplied by the caller.
+// (s, c) = (sin, cos) of th, supplied by the caller.  The emission-point
+// geometry (ZAMO frame, fluid 4-velocity, comoving field, photon direction,
+// polarisation angle) is evaluated in the transfer precision R; Delta is
+// formed as (r - r+)(r - r-) from the FP64 distance to the horizon, so no
+// cancellation is left near it.
 template <typename R, int MODEL>
-__device__ __forceinline__ bool plasma_point(const Params& P, const double* tht, double r, double th,
-                                             double s, double c, double ph, double kt, double kph,
-                                             double kr_ks, double kth, double k0r, double k0i,
+__device__ __forceinline__ bool plasma_point(const Params& P, const double* tht, double r_d, double th,
+                                             double s_d, double c_d, double ph, double kt_d, double kph_d,
+                                             double kr_ks_d, double kth_d, double k0r_d, double k0i_d,
                                              Coef<R>& C)
 {
-    const double a = P.a;
-    if (r <= P.rh * 1.0001) return false;
+    if (r_d <= P.rh * 1.0001) return false;
     if constexpr (MODEL == MODEL_TOY) {
-        if (r <= P.mp[0]) return false;
+        if (r_d <= P.mp[0]) return false;
     } else {
-        if (r >= P.mp[5]) return false;
+        if (r_d >= P.mp[5]) return false;
     }
-    const double s2 = s * s;
-    const double Sig = r * r + a * a * c * c;
-    const double Del = r * r - 2.0 * r + a * a;
-    const double A = (r * r + a * a) * (r * r + a * a) - a * a * Del * s2;
-    const double iD = frcp(Del);
-    const double iS = frcp(Sig);
-    const double iA = frcp(A);
-    const double is = frcp(s);
-    const double kr_bl = kr_ks + (2.0 * r * iD) * kt + (a * iD) * kph;
+    using G = R;
+    const G a = G(P.a), r = G(r_d), s = G(s_d), c = G(c_d);
+    const G kt = G(kt_d), kph = G(kph_d), kth = G(kth_d);
+    const G dr = G(r_d - P.rh);
+    const G s2 = s * s;
+    const G Sig = r * r + a * a * c * c;
+    const G Del = dr * (r - G(2.0 - P.rh));
+    const G A = (r * r + a * a) * (r * r + a * a) - a * a * Del * s2;
+    const G iD = frcp(Del);
+    const G iS = frcp(Sig);
+    const G iA = frcp(A);
+    const G is = frcp(s);
+    const G kr_bl = G(kr_ks_d) + (G(2) * r * iD) * kt + (a * iD) * kph;
     // ZAMO frame at (r, th)
-    const double zal = ::sqrt(Sig * Del * iA);
-    const double izal = frcp(zal);
-    const double zom = 2.0 * a * r * iA;
-    const double zer = ::sqrt(Del * iS);
-    const double zeh = ::sqrt(iS);
-    const double zep = ::sqrt(Sig * iA) * is;
+    const G zal = fsqrt(Sig * Del * iA);
+    const G izal = frcp(zal);
+    const G zom = G(2) * a * r * iA;
+    const G zer = fsqrt(Del * iS);
+    const G zeh = fsqrt(iS);
+    const G zep = fsqrt(Sig * iA) * is;
     if constexpr (MODEL == MODEL_TOY) {
-        double vr, vp;
-        flow_v3(P, r, vr, vp);
-        const double Gam = frcp(::sqrt(1.0 - vr * vr - vp * vp));
-        const double u0 = Gam * izal, u1 = Gam * vr * zer, u3 = Gam * (zom * izal + vp * zep);
-        const double ku = kt * u0 + kr_bl * u1 + kph * u3;
-        const double hr = P.mp[1];
-        const double iku = frcp(ku);
-        const double j = ::exp(-c * c * frcp(2.0 * hr * hr)) * frcp(r * r);
+        G vr, vp;
+        flow_v3<G>(P, r, dr, vr, vp);
+        const G Gam = frcp(fsqrt(G(1) - vr * vr - vp * vp));
+        const G u0 = Gam * izal, u1 = Gam * vr * zer, u3 = Gam * (zom * izal + vp * zep);
+        const G ku = kt * u0 + kr_bl * u1 + kph * u3;
+        const G hr = G(P.mp[1]);
+        const G iku = frcp(ku);
+        const G j = fexp(-c * c * frcp(G(2) * hr * hr)) * frcp(r * r);
         C.jI = R(j * iku * iku);
         C.jQ = C.jU = C.jV = R(0);
         C.aI = C.aQ = C.aU = C.aV = R(0);
@@ -406,20 +413,20 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
         return true;
     } else {
         R ne, Th, Bm;
-        double v3[3], B3[3];
+        G v3[3], B3[3];
         if constexpr (MODEL == MODEL_THERMAL) {
             // power-law plasma: scalars in R
             const R lr = flog(R(r));
             ne = R(P.mp[0]) * fexp(-R(P.mp[6]) * lr);
             Th = R(P.mp[1]) * fexp(-R(P.mp[7]) * lr);
             Bm = R(P.Bref) * fexp(-R(P.mp[8]) * (lr - flog(R(P.r_ref))));
-            double vr, vp;
-            flow_v3(P, r, vr, vp);
-            v3[0] = vr; v3[1] = 0.0; v3[2] = vp;
-            B3[0] = P.psi_s; B3[1] = 0.0; B3[2] = P.psi_c;
+            G vr, vp;
+            flow_v3<G>(P, r, dr, vr, vp);
+            v3[0] = vr; v3[1] = G(0); v3[2] = vp;
+            B3[0] = G(P.psi_s); B3[1] = G(0); B3[2] = G(P.psi_c);
         } else {
             R f[8];
-            grid_sample<R>(P, tht, r, th, ph, f);
+            grid_sample<R>(P, tht, r_d, th, ph, f);
             const R rho = f[0];
             if (!(rho > R(0))) return false;
             const R pg = (R(P.mp[3]) - R(1)) * f[1];
@@ -433,54 +440,55 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
             ne = rho * R(P.mp[0]);
             Bm = fsqrt(b2) * R(P.B_unit);
             if (!(Bm > R(0))) return false;
-            v3[0] = (double)f[2]; v3[1] = (double)f[3]; v3[2] = (double)f[4];
-            B3[0] = (double)f[5]; B3[1] = (double)f[6]; B3[2] = (double)f[7];
+            v3[0] = G(f[2]); v3[1] = G(f[3]); v3[2] = G(f[4]);
+            B3[0] = G(f[5]); B3[1] = G(f[6]); B3[2] = G(f[7]);
         }
         // fluid 4-velocity and unit comoving field direction from ZAMO components
-        const double vv = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2];
-        const double Gam = frcp(::sqrt(1.0 - vv));
-        const double u0 = Gam * izal, u1 = Gam * v3[0] * zer, u2 = Gam * v3[1] * zeh;
-        const double u3 = Gam * (zom * izal + v3[2] * zep);
-        const double ku = kt * u0 + kr_bl * u1 + kth * u2 + kph * u3;
-        const double iBn = frcp(::sqrt(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]));
-        const double Bt0 = B3[0] * iBn, Bt1 = B3[1] * iBn, Bt2 = B3[2] * iBn;
-        const double Bdu = Gam * (v3[0] * Bt0 + v3[1] * Bt1 + v3[2] * Bt2);
-        const double resc = frcp(::sqrt(1.0 + Bdu * Bdu));
-        const double b0 = Bdu * u0 * resc;
-        const double b1 = (Bt0 * zer + Bdu * u1) * resc;
-        const double b2_ = (Bt1 * zeh + Bdu * u2) * resc;
-        const double b3 = (Bt2 * zep + Bdu * u3) * resc;
-        const double kb = kt * b0 + kr_bl * b1 + kth * b2_ + kph * b3;
-        const double iku = frcp(ku);
-        double cth = -kb * iku;
-        cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
+        const G vv = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2];
+        const G Gam = frcp(fsqrt(G(1) - vv));
+        const G u0 = Gam * izal, u1 = Gam * v3[0] * zer, u2 = Gam * v3[1] * zeh;
+        const G u3 = Gam * (zom * izal + v3[2] * zep);
+        const G ku = kt * u0 + kr_bl * u1 + kth * u2 + kph * u3;
+        const G iBn = frcp(fsqrt(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]));
+        const G Bt0 = B3[0] * iBn, Bt1 = B3[1] * iBn, Bt2 = B3[2] * iBn;
+        const G Bdu = Gam * (v3[0] * Bt0 + v3[1] * Bt1 + v3[2] * Bt2);
+        const G resc = frcp(fsqrt(G(1) + Bdu * Bdu));
+        const G b0 = Bdu * u0 * resc;
+        const G b1 = (Bt0 * zer + Bdu * u1) * resc;
+        const G b2_ = (Bt1 * zeh + Bdu * u2) * resc;
+        const G b3 = (Bt2 * zep + Bdu * u3) * resc;
+        const G kb = kt * b0 + kr_bl * b1 + kth * b2_ + kph * b3;
+        const G iku = frcp(ku);
+        G cth = -kb * iku;
+        cth = cth > G(1) ? G(1) : (cth < G(-1) ? G(-1) : cth);
         // contravariant k (BL)
-        const double iSD = iS * iD;
-        const double gitt = -A * iSD, gitp = -2.0 * a * r * iSD;
-        const double girr = Del * iS, gihh = iS, gipp = (Del - a * a * s2) * iSD * (is * is);
-        const double kup[4] = { gitt * kt + gitp * kph, girr * kr_bl, gihh * kth, gitp * kt + gipp * kph };
+        const G iSD = iS * iD;
+        const G gitt = -A * iSD, gitp = G(-2) * a * r * iSD;
+        const G girr = Del * iS, gihh = iS, gipp = (Del - a * a * s2) * iSD * (is * is);
+        const G kup[4] = { gitt * kt + gitp * kph, girr * kr_bl, gihh * kth, gitp * kt + gipp * kph };
         // photon direction n = k/ku - u; b_perp = b - (b.n) n
-        const double n0 = kup[0] * iku - u0, n1 = kup[1] * iku - u1, n2 = kup[2] * iku - u2;
-        const double n3 = kup[3] * iku - u3;
-        const double gtt = -(1.0 - 2.0 * r * iS), gtp = -2.0 * a * r * s2 * iS;
-        const double grr = Sig * iD, ghh = Sig, gpp = (r * r + a * a + 2.0 * a * a * r * s2 * iS) * s2;
-        const double bl0 = gtt * b0 + gtp * b3, bl1 = grr * b1, bl2 = ghh * b2_, bl3 = gtp * b0 + gpp * b3;
-        const double bn = bl0 * n0 + bl1 * n1 + bl2 * n2 + bl3 * n3;
-        const double bp[4] = { b0 - bn * n0, b1 - bn * n1, b2_ - bn * n2, b3 - bn * n3 };
-        double kbr, kbi;
-        walker_penrose(a, r, s, c, kup, bp, kbr, kbi);
-        const double zr = k0r * kbr + k0i * kbi;
-        const double zi = k0i * kbr - k0r * kbi;
-        const double zn = zr * zr + zi * zi;
-        double c2x = 1.0, s2x = 0.0;
-        if (zn > 0.0) {
-            const double izn = frcp(zn);
+        const G n0 = kup[0] * iku - u0, n1 = kup[1] * iku - u1, n2 = kup[2] * iku - u2;
+        const G n3 = kup[3] * iku - u3;
+        const G gtt = -(G(1) - G(2) * r * iS), gtp = G(-2) * a * r * s2 * iS;
+        const G grr = Sig * iD, ghh = Sig, gpp = (r * r + a * a + G(2) * a * a * r * s2 * iS) * s2;
+        const G bl0 = gtt * b0 + gtp * b3, bl1 = grr * b1, bl2 = ghh * b2_, bl3 = gtp * b0 + gpp * b3;
+        const G bn = bl0 * n0 + bl1 * n1 + bl2 * n2 + bl3 * n3;
+        const G bp[4] = { b0 - bn * n0, b1 - bn * n1, b2_ - bn * n2, b3 - bn * n3 };
+        G kbr, kbi;
+        walker_penrose<G>(a, r, s, c, kup, bp, kbr, kbi);
+        const G k0r = G(k0r_d), k0i = G(k0i_d);
+        const G zr = k0r * kbr + k0i * kbi;
+        const G zi = k0i * kbr - k0r * kbi;
+        const G zn = zr * zr + zi * zi;
+        G c2x = G(1), s2x = G(0);
+        if (zn > G(0)) {
+            const G izn = frcp(zn);
             c2x = (zr * zr - zi * zi) * izn;
-            s2x = 2.0 * zr * zi * izn;
+            s2x = G(2) * zr * zi * izn;
         }
         R jI, jQ, jV, aI, aQ, aV, rQ, rV;
-        thermal_coefs<R>(ne, Th, Bm, R(P.freq * ku), R(cth), jI, jQ, jV, aI, aQ, aV, rQ, rV);
-        const R fJ = R(P.L_cm * iku * iku), fK = R(P.L_cm * ku);
+        thermal_coefs<R>(ne, Th, Bm, R(P.freq) * R(ku), R(cth), jI, jQ, jV, aI, aQ, aV, rQ, rV);
+        const R fJ = R(P.L_cm) * R(iku) * R(iku), fK = R(P.L_cm) * R(ku);
         const R c2 = R(c2x), s2r = R(s2x);
         C.jI = fJ * jI; C.jQ = fJ * jQ * c2; C.jU = fJ * jQ * s2r; C.jV = fJ * jV;
         C.aI = fK * aI; C.aQ = fK * aQ * c2; C.aU = fK * aQ * s2r; C.aV = fK * aV;
