@@ -79,3 +79,19 @@ def test_visibility_validation_host_only():
     assert call(P=2, stride=100) == -1
     assert b"workspace" in L.art_last_error() or b"stride" in L.art_last_error()
     assert call(nu=0) == 0 and call(nv=0) == 0 and call(P=0) == 0
+
+
+def test_visibility_binding_refuses_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(art.ArtError):
+        art.visibility(torch.zeros((4, 4), dtype=torch.float64), 0.1, [0.0], [0.0])
+
+
+def test_cube_validation_host_only():
+    L = art.lib()
+    jobs = (art.Job * 5)()
+    ims = (art.Image * 5)()
+    # 4 images cannot form a cube with n0 = 3 (needs 5 at one level)
+    assert L.art_render_cube(4, jobs, 3, 1, 0.01, 1e-3, ims, None, None) == -1
+    assert L.art_render_cube(4, jobs, 1, 1, 0.01, 1e-3, ims, None, None) == -1
+    assert L.art_render_cube(5, jobs, 3, 1, float("nan"), 1e-3, ims, None, None) == -1
