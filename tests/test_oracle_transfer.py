@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 from scipy import integrate, linalg, special
 
+import art_inputs
 from oracle import ray
 
 
@@ -247,3 +248,28 @@ def test_flow_normalised_keplerian_and_plunging(a):
                 else:
                     assert abs(-ucov[0] - E[0]) < 1e-10 and abs(ucov[3] - Lz[0]) < 1e-10
                     assert u[1] < 0
+
+
+def test_evpa_conventions_face_on_ordered_field():
+    """Synchrotron E-vectors are perpendicular to the projected field: a
+    face-on (i = 1 deg) Schwarzschild view of a purely toroidal field gives
+    E radial on the screen, a purely radial field E azimuthal.  With Q > 0
+    for E along the screen's vertical (the polarisation reference) and U > 0
+    for E rotated from the vertical toward -alpha: toroidal -> Q/I < 0 on the
+    alpha axis, > 0 on the beta axis, U/I < 0 at (+,+) and > 0 at (-,+);
+    radial flips every sign.  Low density and 690 GHz keep Faraday rotation
+    negligible; light bending at 15 M barely turns the projection."""
+    from oracle import ray as oray
+    mp = art_inputs.thermal_params(seed=1, n0=2e5)
+    pts = [(15.0, 0.0), (-15.0, 0.0), (0.0, 15.0), (0.0, -15.0), (10.6, 10.6), (-10.6, 10.6)]
+    al = np.array([p[0] for p in pts])
+    be = np.array([p[1] for p in pts])
+    for psi, sgn in ((0.0, 1.0), (np.pi / 2, -1.0)):
+        mp[4] = psi
+        cfg = dict(art_inputs.workload("thermal_1025"), a=0.0, inc_deg=1.0, mp=list(mp), freq_hz=690e9,
+                   nstokes=4)
+        S, _ = oray.trace(cfg, al, be)
+        q, u = S[:, 1] / S[:, 0], S[:, 2] / S[:, 0]
+        assert np.all(sgn * q[:2] < -0.8) and np.all(np.abs(u[:2]) < 0.01), (psi, q, u)
+        assert np.all(sgn * q[2:4] > 0.8) and np.all(np.abs(u[2:4]) < 0.01), (psi, q, u)
+        assert sgn * u[4] < -0.8 and sgn * u[5] > 0.8 and np.all(np.abs(q[4:]) < 0.01), (psi, q, u)
