@@ -87,6 +87,8 @@ typedef struct {
     int32_t nx0, ny0;              /* base vertex grid, >= 2 each */
     int32_t levels;                /* refinement levels N, 0..20 */
     int32_t pad;
+    double phi_deg;                /* camera azimuth [deg] (matters only for non-axisymmetric
+                                      models: the gridded snapshot) */
 } art_camera;
 
 typedef struct {

@@ -31,6 +31,7 @@ class OrParams(ctypes.Structure):
         ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
         ("pad2", ctypes.c_int32),
         ("gp", ctypes.c_double * 8),
+        ("phi_cam", ctypes.c_double),
     ]
 
 
@@ -89,6 +90,7 @@ def make_params(cfg, grid=None):
     p.a = float(cfg["a"])
     p.r_cam = float(cfg["r_cam"])
     p.inc = np.deg2rad(float(cfg["inc_deg"]))
+    p.phi_cam = np.deg2rad(float(cfg.get("phi_deg", 0.0)))
     p.r_out = float(cfg.get("r_out", cfg["r_cam"]))
     p.eps = float(cfg.get("eps", 0.03))
     p.max_steps = int(cfg.get("max_steps", 100000))

@@ -65,6 +65,7 @@ typedef struct {
     const float* grid; /* [8][n3][n2][n1] fields rho,u,U1,U2,U3,B1,B2,B3 */
     int32_t n1, n2, n3, pad2;
     double gp[8];      /* x1 start, x1 stop, hslope, ... */
+    double phi_cam;    /* camera azimuth [rad] */
 } or_params;
 
 #define OR_MAX_SUB 8
@@ -201,7 +202,7 @@ static void camera_ray(const or_params* p, double alpha, double beta, cam_ray* c
     (void)ku_p;
     double Del = r * r - 2.0 * r + a * a;
     double kr_ks = kr_bl - (2.0 * r / Del) * kt - (a / Del) * kph;
-    cr->y[0] = r; cr->y[1] = th; cr->y[2] = 0.0; cr->y[3] = kr_ks; cr->y[4] = kth;
+    cr->y[0] = r; cr->y[1] = th; cr->y[2] = p->phi_cam; cr->y[3] = kr_ks; cr->y[4] = kth;
     cr->kt = kt; cr->kph = kph;
     cr->kup_bl[0] = ku_t; cr->kup_bl[1] = ku_r; cr->kup_bl[2] = ku_h; cr->kup_bl[3] = ku_p;
     /* f = -e_th projected orthogonal to d in the camera frame, normalised */

@@ -35,7 +35,7 @@ class Camera(ctypes.Structure):
     _fields_ = [("r_cam", ctypes.c_double), ("inc_deg", ctypes.c_double),
                 ("fov_M", ctypes.c_double), ("r_out", ctypes.c_double),
                 ("nx0", ctypes.c_int32), ("ny0", ctypes.c_int32),
-                ("levels", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("levels", ctypes.c_int32), ("pad", ctypes.c_int32), ("phi_deg", ctypes.c_double)]
 
 
 class Emission(ctypes.Structure):
@@ -182,7 +182,8 @@ def blocks(cfg):
     sp = Spacetime(float(cfg["a"]))
     cam = Camera(float(cfg["r_cam"]), float(cfg["inc_deg"]), float(cfg["fov"]),
                  float(cfg.get("r_out", cfg["r_cam"])), int(cfg.get("nx0", 2)),
-                 int(cfg.get("ny0", cfg.get("nx0", 2))), int(cfg.get("levels", 0)), 0)
+                 int(cfg.get("ny0", cfg.get("nx0", 2))), int(cfg.get("levels", 0)), 0,
+                 float(cfg.get("phi_deg", 0.0)))
     em = Emission()
     em.kind = EMIS[cfg["model"]]
     em.freq_hz = float(cfg.get("freq_hz", 230e9))

@@ -143,6 +143,7 @@ int validate(const art_spacetime* sp, const art_camera* cam, const art_emission*
     if (!(std::fabs(a) < 1.0)) return fail(ART_EINVAL, "spin |a| must be < 1 (got %g)", a);
     const double rh = 1.0 + std::sqrt(1.0 - a * a);
     if (!(cam->r_cam > 1.01 * rh)) return fail(ART_EINVAL, "camera radius %g inside the horizon", cam->r_cam);
+    if (!std::isfinite(cam->phi_deg)) return fail(ART_EINVAL, "camera azimuth must be finite");
     if (!(cam->inc_deg > 0.0 && cam->inc_deg < 180.0))
         return fail(ART_EINVAL, "inclination must be in (0, 180) deg");
     if (!(cam->fov_M > 0.0)) return fail(ART_EINVAL, "field of view must be > 0");
@@ -227,6 +228,7 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
     P.rstop = 1.01 * P.rh;
     P.r_cam = cam->r_cam;
     P.th_cam = cam->inc_deg * (M_PI / 180.0);
+    P.phi_cam = cam->phi_deg * (M_PI / 180.0);
     P.r_out = cam->r_out > 0.0 ? cam->r_out : cam->r_cam;
     P.eps = tr->eps;
     P.r64 = tr->fp64_radius > 0.0 ? tr->fp64_radius : 6.0;

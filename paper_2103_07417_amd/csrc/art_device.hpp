@@ -54,6 +54,7 @@ struct Params {
     // precision policy: geodesic right-hand sides stay FP64 where r < r64
     // (photon shell, horizon) or |k_theta| < kth64 (theta turning points)
     double r64, kth64;
+    double phi_cam;                // camera azimuth [rad]
 };
 
 constexpr int kMaxThetaCells = 256;
@@ -210,7 +211,7 @@ __device__ __forceinline__ void camera_start(const Params& P, double al, double 
     const double iD = 1.0 / P.c_del;
     R.y[0] = r;
     R.y[1] = P.th_cam;
-    R.y[2] = 0.0;
+    R.y[2] = P.phi_cam;
     R.y[3] = kr_bl - (2.0 * r * iD) * kt - (P.a * iD) * kph;
     R.y[4] = kth;
     R.kt = kt;

@@ -115,3 +115,29 @@ def test_sigma_cut():
     cfg, g, geo, x1, th, ph = small_grid(fn)
     ok, _ = grid_plasma(cfg, g, 5.0, 1.0, 0.3)
     assert ok == 0
+
+
+def test_camera_azimuth_equals_rotated_snapshot():
+    """A camera at azimuth k dphi sees a snapshot rotated by k cells exactly as
+    a camera at 0 sees the original (the same sample positions up to the
+    rounding of phi); an axisymmetric model ignores the azimuth bitwise; the
+    snapshot itself is not axisymmetric (the azimuth changes its image)."""
+    import art_inputs
+    grid, geo = mks.mks_snapshot(seed=2, n1=48, n2=32, n3=32)
+    cfg = dict(art_inputs.workload("grid_4097"), mp=mks.grid_params(geo), nstokes=4)
+    k = 5
+    rot = np.ascontiguousarray(np.roll(grid, k, axis=0))         # rot[i3] = grid[i3 - k]
+    rng = np.random.default_rng(6)
+    al = rng.uniform(-15, 15, 160)
+    be = rng.uniform(-15, 15, 160)
+    S0, _ = ray.trace(cfg, al, be, grid=grid)
+    S1, _ = ray.trace(dict(cfg, phi_deg=k * 360.0 / 32), al, be, grid=rot)
+    scale = np.abs(S0[:, 0]).max()
+    assert scale > 0
+    assert np.abs(S1 - S0).max() <= 1e-8 * scale
+    S2, _ = ray.trace(dict(cfg, phi_deg=k * 360.0 / 32), al, be, grid=grid)
+    assert np.abs(S2 - S0).max() > 1e-3 * scale
+    th = dict(art_inputs.workload("thermal_1025"))
+    A, _ = ray.trace(th, al, be)
+    B, _ = ray.trace(dict(th, phi_deg=37.0), al, be)
+    assert np.array_equal(A, B)
