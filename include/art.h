@@ -458,6 +458,15 @@ int art_visibility(const double* img_dev, int64_t plane_stride, int32_t nplanes,
                    double dx, double fwhm, const double* u_dev, int32_t nu, const double* v_dev, int32_t nv,
                    double* vis_dev, void* work_dev, size_t work_bytes, void* stream);
 
+/* A non-blocking HIP stream created by the library for the current device
+ * (the runtime gives each new stream its least-used hardware queue).  Batches
+ * replayed on distinct such streams run concurrently: with two batches in
+ * flight one batch's latency-bound refinement passes overlap the other's
+ * base pass.  Streams taken from a framework's pool can share one hardware
+ * queue and then serialise.  Destroy with art_stream_destroy (synchronises). */
+int art_stream_create(void** stream);
+int art_stream_destroy(void* stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char* art_last_error(void);
 

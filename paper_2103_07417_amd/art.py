@@ -157,6 +157,8 @@ def lib():
         L.art_vis_workspace_bytes.restype = ctypes.c_size_t
         L.art_visibility.argtypes = [vp, i64, i32, i32, i32, ctypes.c_double, ctypes.c_double, vp, i32,
                                      vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.art_stream_create.argtypes = [P(vp)]
+        L.art_stream_destroy.argtypes = [vp]
         L.art_last_error.restype = ctypes.c_char_p
         L.art_last_error.argtypes = []
         L.art_release.argtypes = []
@@ -409,6 +411,30 @@ def visibility(img, dx, u, v, fwhm=0.0, stream=None):
                                 float(fwhm), uu.data_ptr(), nu, vv.data_ptr(), nv,
                                 out.data_ptr(), work.data_ptr(), nbytes, ctypes.c_void_p(st.cuda_stream)))
     return torch.view_as_complex(out)
+
+
+class Stream:
+    """A library-created non-blocking HIP stream (art_stream_create) as a
+    torch stream (`.torch`); batches replayed on distinct such streams run
+    concurrently."""
+
+    def __init__(self):
+        torch = _torch()
+        h = ctypes.c_void_p()
+        _check(lib().art_stream_create(ctypes.byref(h)))
+        self._h = h
+        self.torch = torch.cuda.ExternalStream(h.value)
+
+    def close(self):
+        if self._h:
+            _check(lib().art_stream_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def feat_numpy(ft):

@@ -106,3 +106,47 @@ def autotune(batch, stream=None, reps=2, use_cache=True, log=None):
     out["table"] = table
     out["cached"] = False
     return out
+
+
+def time_in_flight(batches, torch, streams, reps):
+    """Time per batch with the batches replayed round robin, each on its own
+    stream (graphs captured first); the clock stops when every stream is done."""
+    for b, s in zip(batches, streams):
+        b.capture(s)
+    for b, s in zip(batches, streams):
+        b.launch(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        batches[k % len(batches)].launch(streams[k % len(batches)])
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def autotune_in_flight(batches, streams, reps=4, log=None):
+    """Launch shape for several batches in flight (one image group each, the
+    streams take the groups' role): each batch's persistent grid should fill
+    only its share of the chip so the batches co-reside.  Searches blocks per
+    CU and threads per block with the refill threshold; applies the fastest
+    shape to every batch.  Returns the choice and the table."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    table = []
+    t0 = time.perf_counter()
+    for threads in (128, 256):
+        for waves_per_cu in (4, 8, 12, 16):
+            blocks = max(1, cus * waves_per_cu * 64 // threads)
+            for refill in (1, 16):
+                for b in batches:
+                    b.set_launch(blocks, threads, refill, 1)
+                ms = time_in_flight(batches, torch, streams, reps)
+                table.append(dict(trace_blocks=blocks, trace_threads=threads, refill=refill, groups=1, ms=ms))
+                if log:
+                    log("autotune in flight blocks=%d threads=%d refill=%d: %.2f ms/batch"
+                        % (blocks, threads, refill, ms))
+    best = min(table, key=lambda r: r["ms"])
+    for b in batches:
+        b.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], 1)
+    return dict(trace_blocks=best["trace_blocks"], trace_threads=best["trace_threads"], refill=best["refill"],
+                groups=1, ms=best["ms"], in_flight=len(batches), search_s=time.perf_counter() - t0,
+                table=table)

@@ -1250,6 +1250,23 @@ int art_metrics(const double* truth_dev, const double* approx_dev, int64_t n, do
     return ART_OK;
 }
 
+int art_stream_create(void** stream)
+{
+    if (!stream) return fail(ART_EINVAL, "NULL stream pointer");
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    *stream = (void*)s;
+    return ART_OK;
+}
+
+int art_stream_destroy(void* stream)
+{
+    if (!stream) return fail(ART_EINVAL, "NULL stream");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    HIP_TRY(hipStreamDestroy((hipStream_t)stream));
+    return ART_OK;
+}
+
 int art_release(void)
 {
     std::lock_guard<std::mutex> lk(g_single_mu);

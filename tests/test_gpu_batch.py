@@ -133,3 +133,32 @@ def test_image_groups_do_not_change_results(art, precision):
             for i in range(len(cfgs)):
                 assert torch.equal(B.images[i], ref[i]), (groups, rep, i)
     B.close()
+
+
+def test_two_batches_in_flight(art):
+    """Two batches replayed alternately on two library streams (concurrently)
+    give, on every replay, images bitwise equal to one eager render."""
+    print("CASE two batches in flight", flush=True)
+    cfgs = small_batch("mixed")
+    ref = art.Batch(cfgs)
+    ref.render()
+    torch.cuda.synchronize()
+    want = [im.clone() for im in ref.images]
+    ref.close()
+    S1, S2 = art.Stream(), art.Stream()
+    A, B = art.Batch(cfgs), art.Batch(cfgs)
+    for X in (A, B):
+        X.set_launch(256, 256, 1, 1)
+    A.capture(S1.torch)
+    B.capture(S2.torch)
+    for k in range(6):
+        (A if k % 2 == 0 else B).launch(S1.torch if k % 2 == 0 else S2.torch)
+        if k % 2 == 1:
+            torch.cuda.synchronize()
+            for X in (A, B):
+                for w, g in zip(want, X.images):
+                    assert torch.equal(w, g)
+    A.close()
+    B.close()
+    S1.close()
+    S2.close()
