@@ -9,9 +9,10 @@ One step = one learned + batched render: 64 images of this kind (spin x
 inclination x frequency) rendered together, the proposal network looking
 ahead one level and the refinement criterion of Sec. 3.2 judging and
 tracing what it missed, the whole level loop one hipGraph replay.  Steps
-are timed with two batches in flight on two streams (one image group
-each), so one batch's latency-bound refinement passes overlap the next
-batch's base pass; the latency of one batch alone is reported beside it.
+are timed with several batches in flight (2 to 4, the depth autotuned),
+each on its own stream with one image group, so one batch's latency-bound
+refinement passes overlap the next batches' base passes; the latency of one
+batch alone is reported beside it.
 The network is trained first (untimed) on plain renders of 16 other images.
 Compared on the same GPU: the plain adaptive render of one image at a time
 (the paper's method), the plain method batched, and the uniform render.
@@ -149,6 +150,11 @@ def time_graph(B, torch, s, reps):
     return (time.perf_counter() - t0) / reps
 
 
+# depths searched for the batches in flight (the box gives a process four
+# hardware queues)
+IN_FLIGHT_DEPTHS = (2, 3, 4)
+
+
 def time_pipelined(Bs, torch, streams, reps):
     """Time per batch with len(Bs) batches in flight: batch k % n is replayed
     on its own stream, so one batch's latency-bound refinement passes overlap
@@ -160,13 +166,15 @@ def time_pipelined(Bs, torch, streams, reps):
 
 def batch_forms(art, torch, art_inputs, args):
     """Learned + batched and plain batched renders of the 64-image batch:
-    throughput with two batches in flight (the timed step) and the latency
-    of one batch alone."""
+    throughput with several batches in flight (the timed step) and the
+    latency of one batch alone."""
     from paper_2103_07417_amd import autotune, learn
-    # library-created streams: each gets its own hardware queue, so the two
+    # library-created streams: each gets its own hardware queue, so the
     # batches in flight really run concurrently
-    S1, S2 = art.Stream(), art.Stream()
-    s, s2 = S1.torch, S2.torch
+    nmax = args.in_flight or max(IN_FLIGHT_DEPTHS)
+    Ss = [art.Stream() for _ in range(nmax)]
+    ss = [S.torch for S in Ss]
+    s = ss[0]
     t0 = time.perf_counter()
     net, tinfo = learn.train(art_inputs.training_workload(precision=args.precision),
                              steps=args.train_steps, lr=3e-3, seed=4, stream=s)
@@ -175,21 +183,27 @@ def batch_forms(art, torch, art_inputs, args):
     log("trained proposal network in %.1f s: loss %s -> %s" % (t_train, tinfo["loss_first"],
                                                               tinfo["loss_last"]))
     cfgs = art_inputs.batch_workload_1025(precision=args.precision)
-    B = art.Batch(cfgs, feat=True)
-    B2 = art.Batch(cfgs, feat=True)
+    Bs = [art.Batch(cfgs, feat=True) for _ in range(nmax)]
+    B = Bs[0]
     npix = sum(im.shape[1] * im.shape[2] for im in B.images)
     tune = None
     if not args.no_autotune:
         tune = autotune.autotune(B, s, reps=1, use_cache=False, log=log)
         log("autotune: %s" % {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "groups", "ms")})
     lat_launch = B.get_launch()
-    # two batches in flight, one image group each (their streams take the role
-    # of the groups), each persistent grid sized to its share of the chip
+    # batches in flight, one image group each (their streams take the role of
+    # the groups), each persistent grid sized to its share of the chip
     pipe_launch = dict(trace_blocks=512, trace_threads=256, refill=1, groups=1)
+    depth = nmax
     if not args.no_autotune:
-        pt = autotune.autotune_in_flight([B, B2], [s, s2], reps=4, log=log)
+        pt = autotune.autotune_in_flight(Bs, ss, depths=(args.in_flight,) if args.in_flight else IN_FLIGHT_DEPTHS,
+                                         log=log)
         pipe_launch = {k: pt[k] for k in ("trace_blocks", "trace_threads", "refill", "groups")}
-        log("autotune, two batches in flight: %s, %.1f ms/batch" % (pipe_launch, pt["ms"]))
+        depth = pt["in_flight"]
+        log("autotune, batches in flight: depth %d, %s, %.1f ms/batch" % (depth, pipe_launch, pt["ms"]))
+    for X in Bs[depth:]:
+        X.close()
+    Bs, ss = Bs[:depth], ss[:depth]
     # uniform renders of every image of the batch: the truth for the MSE check
     truths = []
     for c in cfgs:
@@ -199,7 +213,7 @@ def batch_forms(art, torch, art_inputs, args):
     forms = {}
 
     def measure(name, learned_opts):
-        for X in (B, B2):
+        for X in Bs:
             if learned_opts is None:
                 X.set_learned(None)
             else:
@@ -210,26 +224,26 @@ def batch_forms(art, torch, art_inputs, args):
             B.render(s)
         s.synchronize()
         lat = time_graph(B, torch, s, args.steps)
-        # throughput: two batches in flight
-        for X in (B, B2):
+        # throughput: batches in flight
+        for X in Bs:
             X.set_launch(**pipe_launch)
         for _ in range(args.warmup):
-            B.render(s)
-            B2.render(s2)
+            for X, sx in zip(Bs, ss):
+                X.render(sx)
         torch.cuda.synchronize()
-        dt = time_pipelined([B, B2], torch, [s, s2], args.steps)
+        dt = time_pipelined(Bs, torch, ss, args.steps)
         st = B.stats(stream=s)
         chk = mse_check(art, cfgs, B.images, truths)
-        same = all(torch.equal(a, b) for a, b in zip(B.images, B2.images))
+        same = all(torch.equal(a, b) for X in Bs[1:] for a, b in zip(B.images, X.images))
         f = dict(ms_per_batch=dt * 1e3, latency_ms=lat * 1e3, rays=st["rays"], passes=st["trace_launches"],
                  rays_per_s=st["rays"] / dt, effective_px_per_s=npix / dt,
-                 interp_frac=st["interp_frac"], check=chk, batches_identical=same)
+                 interp_frac=st["interp_frac"], check=chk, batches_identical=same, in_flight=depth)
         if learned_opts is not None:
             f["judge"] = st["learned"]
             f["options"] = dict(learned_opts)
         forms[name] = f
-        log("%s: %.1f ms/batch (two in flight; %.1f ms alone), %d rays, %d passes, mse max %.2e" % (
-            name, dt * 1e3, lat * 1e3, st["rays"], st["trace_launches"], f["check"]["mse_max"]))
+        log("%s: %.1f ms/batch (%d in flight; %.1f ms alone), %d rays, %d passes, mse max %.2e" % (
+            name, dt * 1e3, depth, lat * 1e3, st["rays"], st["trace_launches"], f["check"]["mse_max"]))
         return f
 
     measure("plain_batched", None)
@@ -264,14 +278,14 @@ def batch_forms(art, torch, art_inputs, args):
     training = dict(seconds=t_train, steps=args.train_steps, images=16, pos_weight=tinfo["pos_weight"],
                     loss_first={str(k): v for k, v in tinfo["loss_first"].items()},
                     loss_last={str(k): v for k, v in tinfo["loss_last"].items()})
-    B.close()
-    B2.close()
+    for X in Bs:
+        X.close()
     net.close()
-    S1.close()
-    S2.close()
+    for S in Ss:
+        S.close()
     roof_src = dict(tr_ms=tr_ms, launches=launches, flops=fl, render_ms=render_ms, rays=rays)
     if tune is not None:
-        tune = dict(tune, pipelined=pipe_launch, latency=lat_launch)
+        tune = dict(tune, pipelined=dict(pipe_launch, in_flight=depth), latency=lat_launch)
     return forms, head, training, npix, tune, roof_src
 
 
@@ -629,6 +643,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--in-flight", type=int, default=0, choices=[0, 1, 2, 3, 4],
+                    help="batches in flight in the timed step (0: autotuned over 2-4)")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-deploy", action="store_true")
     ap.add_argument("--no-spectral", action="store_true")
@@ -669,7 +685,7 @@ def main():
                 note="achieved = counted FLOPs per tracing launch / mean launch duration (HIP events "
                      "around each launch of two eager renders of one batch, one image group); "
                      "achieved_whole_render = FLOPs / eager render wall time; achieved_pipelined = "
-                     "FLOPs per batch / timed step with two batches in flight (the chip-level rate)")
+                     "FLOPs per batch / timed step with %d batches in flight (the chip-level rate)" % L["in_flight"])
     out = {
         "metric": METRIC, "value": L["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": L["ms_per_batch"],
@@ -680,7 +696,7 @@ def main():
                                "i in {17,60,90,163} deg x nu in {86,230,345,690} GHz), IQUV, "
                                "power-law thermal plasma, base 129^2 -> 3 levels -> 1025^2, "
                                "R_rel=0.01, R_abs=1e-3 max I0, one hipGraph replay per batch, "
-                               "two batches in flight on two streams",
+                               "%d batches in flight on %d streams" % (L["in_flight"], L["in_flight"]),
                    "images": 64, "base": 129, "final": nx, "levels": 3, "precision": args.precision,
                    "form": head},
         "effective_px_per_s": L["effective_px_per_s"],

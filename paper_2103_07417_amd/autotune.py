@@ -123,30 +123,35 @@ def time_in_flight(batches, torch, streams, reps):
     return (time.perf_counter() - t0) / reps * 1e3
 
 
-def autotune_in_flight(batches, streams, reps=4, log=None):
-    """Launch shape for several batches in flight (one image group each, the
-    streams take the groups' role): each batch's persistent grid should fill
-    only its share of the chip so the batches co-reside.  Searches blocks per
-    CU and threads per block with the refill threshold; applies the fastest
-    shape to every batch.  Returns the choice and the table."""
+def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
+    """Launch shape and depth for batches in flight (one image group each, the
+    streams take the groups' role): with d batches in flight each batch's
+    persistent grid should fill only its share of the chip so the batches
+    co-reside.  For every depth d in `depths` (default: all the batches)
+    the first d batches are replayed round robin on the first d streams,
+    searching blocks per CU and threads per block; the fastest (depth, shape)
+    is applied to every batch.  Returns the choice and the table."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
+    depths = tuple(depths or (len(batches),))
+    if max(depths) > len(batches) or max(depths) > len(streams) or min(depths) < 1:
+        raise ValueError("depths %s need as many batches and streams" % (depths,))
     table = []
     t0 = time.perf_counter()
-    for threads in (128, 256):
-        for waves_per_cu in (4, 8, 12, 16):
-            blocks = max(1, cus * waves_per_cu * 64 // threads)
-            for refill in (1, 16):
-                for b in batches:
-                    b.set_launch(blocks, threads, refill, 1)
-                ms = time_in_flight(batches, torch, streams, reps)
-                table.append(dict(trace_blocks=blocks, trace_threads=threads, refill=refill, groups=1, ms=ms))
+    for d in depths:
+        n = reps or max(4, 2 * d)
+        for threads in (128, 256):
+            for waves_per_cu in (4, 8, 12, 16):
+                blocks = max(1, cus * waves_per_cu * 64 // threads)
+                for b in batches[:d]:
+                    b.set_launch(blocks, threads, 1, 1)
+                ms = time_in_flight(batches[:d], torch, streams[:d], n)
+                table.append(dict(in_flight=d, trace_blocks=blocks, trace_threads=threads, refill=1, groups=1,
+                                  ms=ms))
                 if log:
-                    log("autotune in flight blocks=%d threads=%d refill=%d: %.2f ms/batch"
-                        % (blocks, threads, refill, ms))
+                    log("autotune in flight depth=%d blocks=%d threads=%d: %.2f ms/batch"
+                        % (d, blocks, threads, ms))
     best = min(table, key=lambda r: r["ms"])
     for b in batches:
         b.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], 1)
-    return dict(trace_blocks=best["trace_blocks"], trace_threads=best["trace_threads"], refill=best["refill"],
-                groups=1, ms=best["ms"], in_flight=len(batches), search_s=time.perf_counter() - t0,
-                table=table)
+    return dict(best, search_s=time.perf_counter() - t0, table=table)

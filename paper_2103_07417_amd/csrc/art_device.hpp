@@ -69,19 +69,27 @@ constexpr double kH  = 6.62607015e-27;     // Planck constant [erg s]
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kMp = 1.67262192369e-24;   // proton mass [g]
 
-// math wrappers resolving to the precision of R
+// math wrappers resolving to the precision of R.  FP64: the library
+// functions.  FP32 (the transfer precision): the hardware units directly
+// (v_exp_f32 = 2^x, v_log_f32 = log2 x, v_sqrt_f32, v_rsq_f32, each about one
+// ulp) with the base change as one multiply, instead of the correctly rounded
+// library sequences (four to fifteen times the instructions); the relative
+// error of e^x is then about |x| 2^-24, far inside what FP32 transfer carries.
+// log1p and expm1 compensate the rounding of u = 1 + x and u = e^x
+// (Goldberg, "What every computer scientist should know about floating-point
+// arithmetic", 1991, Theorem 4; Kahan's expm1 analogue), which keeps their
+// relative accuracy for small |x| without a series.  fcbrt(float) takes
+// x > 0 only.
 __device__ __forceinline__ double fexp(double x) { return ::exp(x); }
-__device__ __forceinline__ float  fexp(float x)  { return ::expf(x); }
-__device__ __forceinline__ double fexpm1(double x) { return ::expm1(x); }
-__device__ __forceinline__ float  fexpm1(float x)  { return ::expm1f(x); }
+__device__ __forceinline__ float  fexp(float x)  { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 __device__ __forceinline__ double fsqrt(double x) { return ::sqrt(x); }
-__device__ __forceinline__ float  fsqrt(float x)  { return ::sqrtf(x); }
-__device__ __forceinline__ double fcbrt(double x) { return ::cbrt(x); }
-__device__ __forceinline__ float  fcbrt(float x)  { return ::cbrtf(x); }
-__device__ __forceinline__ double flog1p(double x) { return ::log1p(x); }
-__device__ __forceinline__ float  flog1p(float x)  { return ::log1pf(x); }
+__device__ __forceinline__ float  fsqrt(float x)  { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double flog(double x) { return ::log(x); }
-__device__ __forceinline__ float  flog(float x)  { return ::logf(x); }
+__device__ __forceinline__ float  flog(float x)  { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+__device__ __forceinline__ double fcbrt(double x) { return ::cbrt(x); }
+__device__ __forceinline__ float  fcbrt(float x)  { return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f)); }
+__device__ __forceinline__ double flog1p(double x) { return ::log1p(x); }
+__device__ __forceinline__ double fexpm1(double x) { return ::expm1(x); }
 __device__ __forceinline__ double fsin(double x) { return ::sin(x); }
 __device__ __forceinline__ float  fsin(float x)  { return ::sinf(x); }
 __device__ __forceinline__ double fabs_(double x) { return ::fabs(x); }
@@ -101,6 +109,22 @@ __device__ __forceinline__ float frcp(float x)
 {
     float r = __builtin_amdgcn_rcpf(x);
     return ::fmaf(::fmaf(-x, r, 1.0f), r, r);
+}
+// 1/sqrt(x): FP64 as the reciprocal of the square root, FP32 on v_rsq_f32.
+__device__ __forceinline__ double frsq(double x) { return frcp(::sqrt(x)); }
+__device__ __forceinline__ float  frsq(float x)  { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float flog1p(float x)
+{
+    const float u = 1.0f + x;
+    return u == 1.0f ? x : flog(u) * (x * frcp(u - 1.0f));
+}
+__device__ __forceinline__ float fexpm1(float x)
+{
+    const float u = fexp(x);
+    if (u == 1.0f) return x;
+    const float um = u - 1.0f;
+    if (um == -1.0f || __builtin_isinf(u)) return um;
+    return um * (x * frcp(flog(u)));
 }
 
 // sin and cos of theta + d from sin, cos of theta for a small increment d
@@ -291,7 +315,7 @@ __device__ __forceinline__ void thermal_coefs(R ne, R Th, R B, R nu, R cth,
     const R ex = fexp(R(-1.8899) * x13);
     const R II = R(2.5651) * (R(1) + R(1.92) * xm13 + R(0.9977) * xm23) * ex;
     const R IQ = R(2.5651) * (R(1) + R(0.932) * xm13 + R(0.4998) * xm23) * ex;
-    const R IV = (R(1.8138) * (xm13 * xm23) + R(3.423) * xm23 + R(0.02955) * frcp(fsqrt(x))
+    const R IV = (R(1.8138) * (xm13 * xm23) + R(3.423) * xm23 + R(0.02955) * frsq(x)
                   + R(2.0377) * xm13) * ex;
     const R pref = nee * nu * (iTh * iTh) * R(1.0 / (2.0 * 1.7320508075688772 * kC));
     R jI_ = pref * II;
@@ -392,8 +416,7 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
     const G is = frcp(s);
     const G kr_bl = G(kr_ks_d) + (G(2) * r * iD) * kt + (a * iD) * kph;
     // ZAMO frame at (r, th)
-    const G zal = fsqrt(Sig * Del * iA);
-    const G izal = frcp(zal);
+    const G izal = frsq(Sig * Del * iA);
     const G zom = G(2) * a * r * iA;
     const G zer = fsqrt(Del * iS);
     const G zeh = fsqrt(iS);
@@ -401,7 +424,7 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
     if constexpr (MODEL == MODEL_TOY) {
         G vr, vp;
         flow_v3<G>(P, r, dr, vr, vp);
-        const G Gam = frcp(fsqrt(G(1) - vr * vr - vp * vp));
+        const G Gam = frsq(G(1) - vr * vr - vp * vp);
         const G u0 = Gam * izal, u1 = Gam * vr * zer, u3 = Gam * (zom * izal + vp * zep);
         const G ku = kt * u0 + kr_bl * u1 + kph * u3;
         const G hr = G(P.mp[1]);
@@ -446,14 +469,14 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
         }
         // fluid 4-velocity and unit comoving field direction from ZAMO components
         const G vv = v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2];
-        const G Gam = frcp(fsqrt(G(1) - vv));
+        const G Gam = frsq(G(1) - vv);
         const G u0 = Gam * izal, u1 = Gam * v3[0] * zer, u2 = Gam * v3[1] * zeh;
         const G u3 = Gam * (zom * izal + v3[2] * zep);
         const G ku = kt * u0 + kr_bl * u1 + kth * u2 + kph * u3;
-        const G iBn = frcp(fsqrt(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]));
+        const G iBn = frsq(B3[0] * B3[0] + B3[1] * B3[1] + B3[2] * B3[2]);
         const G Bt0 = B3[0] * iBn, Bt1 = B3[1] * iBn, Bt2 = B3[2] * iBn;
         const G Bdu = Gam * (v3[0] * Bt0 + v3[1] * Bt1 + v3[2] * Bt2);
-        const G resc = frcp(fsqrt(G(1) + Bdu * Bdu));
+        const G resc = frsq(G(1) + Bdu * Bdu);
         const G b0 = Bdu * u0 * resc;
         const G b1 = (Bt0 * zer + Bdu * u1) * resc;
         const G b2_ = (Bt1 * zeh + Bdu * u2) * resc;

@@ -15,6 +15,7 @@ namespace art {
 template <typename R, int MODEL, int NS, int SUB = 0>
 struct RayState {
     double y[5];
+    double sth, cth;               // sin, cos of y[1]
     double kt, kph, k0r, k0i;
     double cprev, rmin;
     R S[NS];
@@ -33,7 +34,8 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS,
 #pragma unroll
     for (int i = 0; i < 5; ++i) st.y[i] = rs.y[i];
     st.kt = rs.kt; st.kph = rs.kph; st.k0r = rs.k0r; st.k0i = rs.k0i;
-    st.cprev = ::cos(rs.y[1]);
+    ::sincos(rs.y[1], &st.sth, &st.cth);
+    st.cprev = st.cth;
     st.rmin = rs.y[0];
 #pragma unroll
     for (int i = 0; i < NS; ++i) st.S[i] = R(0);
@@ -51,8 +53,9 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS,
 }
 
 // Advance one ray by one step.  Returns a RAY_* status (RAY_OK = continue).
-// sin/cos of theta are evaluated once per step; the RK stages and the
-// midpoint rotate them by their (small) theta increments.
+// sin/cos of theta are evaluated once per ray and carried in the state: the
+// RK stages, the midpoint and the step's end rotate them by their (small)
+// theta increments (angle addition, error ~1e-16 per step).
 // G32 (precision policy): the four right-hand sides of the step are evaluated
 // in FP32 when no ray of the wave is in a sensitive zone (r < r64: photon
 // shell and horizon; |k_theta| < kth64: theta turning points; |sin theta| <
@@ -64,8 +67,7 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
 {
     const double a = P.a;
     double k1[5], acc[5], yt[5], kk[5];
-    double s0, c0;
-    ::sincos(st.y[1], &s0, &c0);
+    const double s0 = st.sth, c0 = st.cth;
     bool fast = false;
     if constexpr (G32)
         fast = __ballot(st.y[0] < P.r64 || ::fabs(st.y[4]) < P.kth64 || ::fabs(s0) < 0.1) == 0ull;
@@ -145,6 +147,7 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
     if constexpr (SUB > 0) {
         if (st.y[4] * yt[4] < 0.0) st.nturn++;      // theta turning point
     }
+    rotate_sc(s0, c0, yt[1] - st.y[1], st.sth, st.cth);
 #pragma unroll
     for (int i = 0; i < 5; ++i) st.y[i] = yt[i];
     st.nstep++;
