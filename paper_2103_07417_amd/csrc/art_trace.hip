@@ -79,11 +79,16 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
     if (st.cprev * c0 < 0.0) st.ncross++;
     st.cprev = c0;
     if (st.y[0] < st.rmin) st.rmin = st.y[0];
-    if (st.y[0] > P.r_out && k1[0] > 0.0) return RAY_ESCAPED;
-    if (st.y[0] < P.rstop) return RAY_CAPTURED;
-    if (st.nstep >= P.max_steps) return RAY_STEPCAP;
-    if (st.O[0] < R(1e-12)) return RAY_THICK;
-    if (!(st.y[0] == st.y[0]) || !(st.y[3] == st.y[3])) return RAY_NAN;
+    // termination, first matching test wins (escape, capture, step cap,
+    // optically thick, NaN); one status select per test and a single exit, so
+    // the ray state is not copied once per test
+    int status = RAY_OK;
+    status = (!(st.y[0] == st.y[0]) || !(st.y[3] == st.y[3])) ? RAY_NAN : status;
+    status = st.O[0] < R(1e-12) ? RAY_THICK : status;
+    status = st.nstep >= P.max_steps ? RAY_STEPCAP : status;
+    status = st.y[0] < P.rstop ? RAY_CAPTURED : status;
+    status = (st.y[0] > P.r_out && k1[0] > 0.0) ? RAY_ESCAPED : status;
+    if (status != RAY_OK) return status;
     double rate = ::fabs(k1[0]) * frcp(st.y[0]) + ::fabs(k1[1]) + ::fabs(k1[2]);
     // pole control: within |sin theta| < 0.1 of a pole (k_phi != 0: centrifugal
     // barrier) the theta step is limited to a fraction of the distance to the
