@@ -266,7 +266,14 @@ __global__ __launch_bounds__(256) void k_trace(TraceJob J)
         }
         if (active) {
             const Params& P = sP[st.img];
-            const int status = ray_step<R, MODEL, NS, G32, SUB>(P, sTh, st, my_emit);
+            // step until a ray of the wave terminates: the state stays in the
+            // same registers across steps (the refill path above merges into
+            // it once per termination, not once per step); every ray ends by
+            // the step cap at the latest, so the loop is bounded
+            int status;
+            do {
+                status = ray_step<R, MODEL, NS, G32, SUB>(P, sTh, st, my_emit);
+            } while (!__any(status != RAY_OK));
             if (status != RAY_OK) {
                 double Sd[4] = { 0.0, 0.0, 0.0, 0.0 };
 #pragma unroll
