@@ -50,7 +50,8 @@ METRIC = "rays/s and effective pixels/s at image MSE ≤0.1%; learned+batched vs
 # from the method's expressions:
 FLOP_GEO_STEP = 381          # 4 right-hand sides, RK4 combination, step rule, midpoint
 FLOP_PLASMA_THERMAL = 390    # flow, field, frame, Walker-Penrose angle, coefficients
-FLOP_TRANSFER_IQUV = 790     # two closed-form Lorentz exponentials, O update, emission
+FLOP_TRANSFER_IQUV = 639     # two closed-form Lorentz exponentials (261), mean depth (20),
+                             # emission (124), propagator matrix M (89) and O M (112)
 FLOP_TRANSFER_I = 10
 FLOP_PLASMA_TOY = 96
 PEAK_FP64_VECTOR = 78.6e12   # MI355X published FP64 vector peak

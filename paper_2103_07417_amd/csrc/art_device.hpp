@@ -523,26 +523,31 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
 
 // ---------------------------------------------------------- transfer maths
 // Polynomial parts (u, v < 1) of sinh(u)/u, sin(v)/v, (sinh(u)/u - 1)/u^2 and
-// (1 - sin(v)/v)/v^2.
+// (1 - sin(v)/v)/v^2: Taylor series to the 1/15! term in Horner form (one FMA
+// per term).
 template <typename R>
 __device__ __forceinline__ R shc_poly(R u2)
 {
-    return R(1) + u2 * R(1.0 * (1.0 / 6.0)) * (R(1) + u2 * R(1.0 * (1.0 / 20.0)) * (R(1) + u2 * R(1.0 * (1.0 / 42.0)) * (R(1) + u2 * R(1.0 * (1.0 / 72.0)) * (R(1) + u2 * R(1.0 * (1.0 / 110.0)) * (R(1) + u2 * R(1.0 * (1.0 / 156.0)))))));
+    return R(1) + u2 * (R(1.0 / 6.0) + u2 * (R(1.0 / 120.0) + u2 * (R(1.0 / 5040.0) + u2 * (R(1.0 / 362880.0)
+           + u2 * (R(1.0 / 39916800.0) + u2 * R(1.0 / 6227020800.0))))));
 }
 template <typename R>
 __device__ __forceinline__ R sinc_poly(R v2)
 {
-    return R(1) - v2 * R(1.0 * (1.0 / 6.0)) * (R(1) - v2 * R(1.0 * (1.0 / 20.0)) * (R(1) - v2 * R(1.0 * (1.0 / 42.0)) * (R(1) - v2 * R(1.0 * (1.0 / 72.0)) * (R(1) - v2 * R(1.0 * (1.0 / 110.0)) * (R(1) - v2 * R(1.0 * (1.0 / 156.0)))))));
+    return R(1) + v2 * (R(-1.0 / 6.0) + v2 * (R(1.0 / 120.0) + v2 * (R(-1.0 / 5040.0) + v2 * (R(1.0 / 362880.0)
+           + v2 * (R(-1.0 / 39916800.0) + v2 * R(1.0 / 6227020800.0))))));
 }
 template <typename R>
 __device__ __forceinline__ R g_poly(R u2)
 {
-    return R(1) * R(1.0 * (1.0 / 6.0)) * (R(1) + u2 * R(1.0 * (1.0 / 20.0)) * (R(1) + u2 * R(1.0 * (1.0 / 42.0)) * (R(1) + u2 * R(1.0 * (1.0 / 72.0)) * (R(1) + u2 * R(1.0 * (1.0 / 110.0)) * (R(1) + u2 * R(1.0 * (1.0 / 156.0)) * (R(1) + u2 * R(1.0 * (1.0 / 210.0))))))));
+    return R(1.0 / 6.0) + u2 * (R(1.0 / 120.0) + u2 * (R(1.0 / 5040.0) + u2 * (R(1.0 / 362880.0)
+           + u2 * (R(1.0 / 39916800.0) + u2 * (R(1.0 / 6227020800.0) + u2 * R(1.0 / 1307674368000.0))))));
 }
 template <typename R>
 __device__ __forceinline__ R h_poly(R v2)
 {
-    return R(1) * R(1.0 * (1.0 / 6.0)) * (R(1) - v2 * R(1.0 * (1.0 / 20.0)) * (R(1) - v2 * R(1.0 * (1.0 / 42.0)) * (R(1) - v2 * R(1.0 * (1.0 / 72.0)) * (R(1) - v2 * R(1.0 * (1.0 / 110.0)) * (R(1) - v2 * R(1.0 * (1.0 / 156.0)) * (R(1) - v2 * R(1.0 * (1.0 / 210.0))))))));
+    return R(1.0 / 6.0) + v2 * (R(-1.0 / 120.0) + v2 * (R(1.0 / 5040.0) + v2 * (R(-1.0 / 362880.0)
+           + v2 * (R(1.0 / 39916800.0) + v2 * (R(-1.0 / 6227020800.0) + v2 * R(1.0 / 1307674368000.0))))));
 }
 __device__ __forceinline__ void fsincos(double x, double* s, double* c) { ::sincos(x, s, c); }
 __device__ __forceinline__ void fsincos(float x, float* s, float* c) { ::sincosf(x, s, c); }
@@ -628,13 +633,13 @@ __device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3
 template <typename R>
 __device__ __forceinline__ R phi1_(R w)
 {
-    if (w < R(1e-4)) return R(1) - w * R(1.0 * (1.0 / 2.0)) + w * w * R(1.0 * (1.0 / 6.0)) - w * w * w * R(1.0 * (1.0 / 24.0));
+    if (w < R(1e-4)) return R(1) + w * (R(-1.0 / 2.0) + w * (R(1.0 / 6.0) + w * R(-1.0 / 24.0)));
     return -fexpm1(-w) * frcp(w);
 }
 template <typename R>
 __device__ __forceinline__ R mean_depth_(R w)
 {
-    if (w < R(0.1)) { const R w2 = w * w; return R(0.5) - w * R(1.0 * (1.0 / 12.0)) + w * w2 * R(1.0 * (1.0 / 720.0)) - w * w2 * w2 * R(1.0 * (1.0 / 30240.0)); }
+    if (w < R(0.1)) { const R w2 = w * w; return R(0.5) + w * (R(-1.0 / 12.0) + w2 * (R(1.0 / 720.0) + w2 * R(-1.0 / 30240.0))); }
     return frcp(w) - frcp(fexpm1(w));
 }
 

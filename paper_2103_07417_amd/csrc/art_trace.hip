@@ -164,7 +164,7 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
 // are handed out by lane prefix; then every busy lane advances its ray by one
 // step.  The per-image parameter blocks are staged in LDS once per block.
 template <typename R, int MODEL, int NS, bool G32, int SUB>
-__global__ __launch_bounds__(256) void k_trace(TraceJob J)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_trace(TraceJob J)
 {
     __shared__ Params sP[kMaxBatch];
     {
