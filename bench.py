@@ -67,7 +67,7 @@ BYTES_PER_RAY = 58
 # of this benchmark (profiles/k_trace_learned_batched_thermal_1025.md), per
 # launch of the roofline renders; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=432593653, kernel_hash="dd01d89ac90b30c9",
+TRAFFIC = dict(bytes_per_render=430190664, kernel_hash="1825eab2d48205b2",
                source="profiles/k_trace_learned_batched_thermal_1025.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of one headline render")
 TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
