@@ -31,7 +31,8 @@ the gridded snapshot at 4097^2 (FP64 and mixed precision); the snapshot at
 and the visibility domain of its learned render (Sec. 4.3: 2D window to
 1000 G-lambda on FP64 matrix cores, residual visibilities, ring period); the
 thermal view as a 17-frequency cube sampled adaptively along ln nu, and a
-9-frame movie of the evolving snapshot sampled adaptively in time.
+9-frame movie of the evolving snapshot sampled adaptively in time; the
+64-image batch with uneven refinement (1 to 4 levels per image).
 """
 import argparse
 import json
@@ -288,6 +289,48 @@ def batch_forms(art, torch, art_inputs, args):
     if tune is not None:
         tune = dict(tune, pipelined=dict(pipe_launch, in_flight=depth), latency=lat_launch)
     return forms, head, training, npix, tune, roof_src
+
+
+def uneven_batch(art, torch, art_inputs, args):
+    """The batch with uneven refinement: the same 64 view/spin/frequency
+    combinations, image k refined 1 + (k mod 4) levels from 129^2 (257^2 to
+    2049^2), plain criterion, one graph replay per batch: alone and three
+    batches in flight (one image group each, 256 x 256 persistent grid), with
+    every image's MSE against its uniform render."""
+    cfgs = art_inputs.batch_workload(precision=args.precision)
+    Ss = [art.Stream() for _ in range(3)]
+    Bs = [art.Batch(cfgs) for _ in range(3)]
+    s = Ss[0].torch
+    lat = time_graph(Bs[0], torch, s, max(2, args.steps // 2))
+    for X in Bs:
+        X.set_launch(256, 256, 1, 1)
+    dt = time_pipelined(Bs, torch, [S.torch for S in Ss], args.steps)
+    st = Bs[0].stats(stream=s)
+    truths = []
+    for c in cfgs:
+        t, _, _ = art.render_uniform(c, stream=s)
+        truths.append(t[0].clone())
+        del t
+    s.synchronize()
+    chk = mse_check(art, cfgs, Bs[0].images, truths)
+    worst = max(range(len(cfgs)), key=lambda k: art.metrics(truths[k], Bs[0].images[k][0])[1])
+    npix = sum(im.shape[1] * im.shape[2] for im in Bs[0].images)
+    out = dict(ms_per_batch=dt * 1e3, latency_ms=lat * 1e3, rays=st["rays"], passes=st["trace_launches"],
+               rays_per_s=st["rays"] / dt, effective_px_per_s=npix / dt, pixels=npix,
+               mse_max=chk["mse_max"], mse_mean=chk["mse_mean"], mse_ok=chk["mse_ok"],
+               n_over_bar=sum(1 for k in range(len(cfgs))
+                              if art.metrics(truths[k], Bs[0].images[k][0])[1] > 1e-3),
+               worst=cfgs[worst]["name"], in_flight=3)
+    log("uneven batch (1-4 levels): %.1f ms/batch (3 in flight; %.1f ms alone), %d rays, %.3g px, "
+        "mse max %.2e (%s), %d images over 1e-3" % (out["ms_per_batch"], out["latency_ms"], out["rays"],
+                                                   npix, out["mse_max"], out["worst"], out["n_over_bar"]))
+    del truths
+    for X in Bs:
+        X.close()
+    for S in Ss:
+        S.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def grid_forms(art, torch, art_inputs, args):
@@ -649,6 +692,7 @@ def main():
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-deploy", action="store_true")
     ap.add_argument("--no-spectral", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--z-propose", type=float, default=0.0)
     ap.add_argument("--z-suppress", type=float, default=-1.0)
@@ -723,6 +767,8 @@ def main():
     if not args.no_spectral:
         out["spectral_1025"] = spectral_1025(art, torch, art_inputs, args)
         out["movie_1025"] = movie_1025(art, torch, art_inputs, args)
+    if not args.no_uneven:
+        out["uneven_batch"] = uneven_batch(art, torch, art_inputs, args)
     # a plain device copy of known size: reference reading for the HBM byte
     # counters (FETCH_SIZE / WRITE_SIZE) of a profiled run
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
