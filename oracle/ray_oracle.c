@@ -4,8 +4,8 @@
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may call, link or
  * load this file; only tests/, the smoke check and the bench's CPU-baseline leg
- * use it.  It shares no code with the HIP path: both implement the written
- * method ("Method") independently.
+ * use it.  It shares no code with the HIP path: both implement the method
+ * written out below independently.
  *
  * The paper delegates everything per ray to an external GRRT code (Sec. 4.1,
  * "Models and Implementation"); it only fixes that a ray is traced for each
@@ -29,6 +29,10 @@
  *     Lorentz-algebra part of K is evaluated in closed form.
  *   - Polarisation basis: Walker-Penrose constant of the camera's screen-up
  *     vector, compared at each point with that of the projected magnetic field.
+ *
+ * Parity unpinned: the fitting form of the thermal circular emissivity j_V
+ * (thermal_coefs below) has no closed form or published value to pin it to
+ * here; only Kirchhoff's law and its sign are checked.
  */
 #include <math.h>
 #include <stdint.h>
