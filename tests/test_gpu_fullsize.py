@@ -193,3 +193,46 @@ def test_uneven_batch_image_error(art, uneven):
         assert mse <= 2e-3, (k, mse)
         if k != 63:
             assert mse <= 1e-3, (k, mse)
+
+
+# --------------------------------------------------------------------------
+# What the trained network gains at the 0.1 % bar on the 64-image batch: the
+# plain criterion passes only at R_rel = 0.01 of the grid {0.01, 0.0125,
+# 0.015}; the look-ahead form (proposal threshold z = 4, criterion as
+# fallback) passes at R_rel = 0.015 with fewer traced rays than the plain
+# criterion at 0.01.
+
+def test_learned_operating_point_gain(art):
+    from paper_2103_07417_amd import learn
+    import bench
+    print("CASE learned operating point", flush=True)
+    S = art.Stream()
+    s = S.torch
+    net, _ = learn.train(art_inputs.training_workload(precision="mixed"), steps=300, lr=3e-3, seed=4, stream=s)
+    cfgs = art_inputs.batch_workload_1025(precision="mixed")
+    truths = []
+    for c in cfgs:
+        t, _, _ = art.render_uniform(c, stream=s)
+        truths.append(t[0].clone())
+    s.synchronize()
+    res = {}
+    for rr in (0.01, 0.0125, 0.015):
+        c_rr = [dict(c, r_rel=rr) for c in cfgs]
+        B = art.Batch(c_rr, feat=True)
+        for form in ("plain", "lookahead"):
+            if form == "plain":
+                B.set_learned(None)
+            else:
+                B.set_learned(net, z_propose=4.0, z_suppress=-float("inf"), fallback=True)
+            B.render(s)
+            st = B.stats(stream=s)
+            chk = bench.mse_check(art, c_rr, B.images, truths)
+            res[(form, rr)] = (st["rays"], chk["mse_max"], chk["mse_ok"])
+            print(form, rr, res[(form, rr)], flush=True)
+        B.close()
+    net.close()
+    S.close()
+    assert res[("plain", 0.01)][2]
+    assert not res[("plain", 0.0125)][2] and not res[("plain", 0.015)][2]
+    assert res[("lookahead", 0.015)][2]
+    assert res[("lookahead", 0.015)][0] < res[("plain", 0.01)][0]
