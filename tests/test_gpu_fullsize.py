@@ -236,3 +236,63 @@ def test_learned_operating_point_gain(art):
     assert not res[("plain", 0.0125)][2] and not res[("plain", 0.015)][2]
     assert res[("lookahead", 0.015)][2]
     assert res[("lookahead", 0.015)][0] < res[("plain", 0.01)][0]
+
+
+# --------------------------------------------------------------------------
+# The gridded snapshot at its full sizes: 4097^2 IQUV (base 257^2, 4 levels,
+# mixed precision) and 16385^2 Stokes I with subring planes n = 0..3 (6
+# levels), single adaptive renders: sampled traced points of every level
+# against the oracle's FP64 tracer on the same snapshot.
+
+@pytest.fixture(scope="module")
+def snapshot():
+    from art_inputs import mks
+    grid, _ = mks.mks_snapshot(seed=2)
+    return grid, torch.from_numpy(grid).cuda()
+
+
+def sampled_vs_oracle(cfg, img, lev, grid, per_level, seed, tol):
+    rng = np.random.default_rng(seed)
+    lv = lev.cpu().numpy()
+    ny, nx = lv.shape
+    ii, jj = [], []
+    for lvl in range(cfg["levels"] + 1):
+        j, i = np.nonzero(lv == lvl)
+        if len(i):
+            pick = rng.choice(len(i), size=min(per_level, len(i)), replace=False)
+            ii += list(i[pick])
+            jj += list(j[pick])
+    ii, jj = np.array(ii), np.array(jj)
+    got = img[:, jj, ii].cpu().numpy().T
+    x, y = oray.screen_coords(cfg["fov"], nx, ny, ii, jj)
+    want, _ = oray.trace(cfg, x, y, grid=grid)
+    planes = cfg["nstokes"] + cfg.get("subrings", 0)
+    for s in range(planes):
+        err = rel_l2(got[:, s], want[:, s])
+        print("plane", s, "samples", len(ii), "rel L2", err, flush=True)
+        assert err <= tol, (s, err)
+
+
+def test_grid_4097_sampled(art, snapshot):
+    print("CASE grid 4097 full size", flush=True)
+    cfg = dict(art_inputs.workload("grid_4097"), grid_dev=snapshot[1], precision="mixed")
+    img, lev, _, st = art.render(cfg)
+    torch.cuda.synchronize()
+    assert tuple(lev.shape) == (4097, 4097) and st["rays"] == int((lev >= 0).sum())
+    sampled_vs_oracle(cfg, img, lev, snapshot[0], 10, 13, 1e-4)
+    del img, lev
+
+
+def test_grid_16385_subrings_sampled(art, snapshot):
+    print("CASE grid 16385 subrings full size", flush=True)
+    cfg = dict(art_inputs.workload("grid_16385"), grid_dev=snapshot[1], precision="mixed")
+    img, lev, _, st = art.render(cfg)
+    torch.cuda.synchronize()
+    assert tuple(lev.shape) == (16385, 16385) and st["rays"] == int((lev >= 0).sum())
+    # the subring planes add up to the image (every step's increment goes to
+    # exactly one plane)
+    tot = img[1:5].sum(dim=0)
+    assert float((tot - img[0]).abs().max()) <= 1e-5 * float(img[0].abs().max())
+    sampled_vs_oracle(cfg, img, lev, snapshot[0], 8, 14, 1e-4)
+    del img, lev
+    torch.cuda.empty_cache()
