@@ -405,8 +405,9 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
  * (twice the one-sided second difference if a or d is outside the cube, never
  * accepted if both are; N_abs the mean of b's and c's own N_abs; every plane
  * with rf->all_planes); points it rejects are traced.  Level map: l = traced at
- * spatial level l, -1 spatially interpolated, -3 spectral value.  Eager (not
- * capturable); camera levels + spectral levels <= 21.  The decisions of
+ * spatial level l, -1 spatially interpolated, -3 spectral value.  Eager (for
+ * capture and replay see art_cube_create); camera levels + spectral levels
+ * <= 21.  The decisions of
  * spectral level s at spatial level l need only the coarser levels, so they
  * run as a wavefront: camera levels + levels + 1 tracing passes. */
 typedef struct {
@@ -430,6 +431,18 @@ int art_render_spectral(const art_spacetime* sp, const art_camera* cam, const ar
  * for movies as the other target of the extension. */
 int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, double r_rel, double r_abs,
                     art_image* out, art_stats* st, void* stream);
+
+/* The cube of art_render_cube as a batch object, set up once: jobs and the
+ * caller-owned images (as for art_batch_create) in axis order.  It takes
+ * art_batch_render (eager, timed), art_batch_capture / art_batch_launch (one
+ * hipGraph of the whole wavefront), art_batch_stats (image index in axis
+ * order, -1 for the whole cube), art_batch_set_launch (tracing grid and
+ * refill; always one image group) and art_batch_destroy; art_batch_set_learned
+ * rejects a network (the cube renders with the criterion).  Cubes on
+ * different streams can be in flight together.  Synchronises the null
+ * stream. */
+int art_cube_create(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, double r_rel, double r_abs,
+                    const art_image* images, art_batch** out);
 
 /* Image metrics of Sec. 4.1 on n FP64 values (one Stokes plane), computed on
  * the device with a deterministic two-pass reduction; synchronises:

@@ -126,6 +126,8 @@ def lib():
                                        vp, vp, vp, vp, vp]
         L.art_metrics.argtypes = [vp, vp, i64, P(ctypes.c_double), P(ctypes.c_double), vp]
         L.art_batch_create.argtypes = [ctypes.c_int32, P(Job), P(Image), P(vp)]
+        L.art_cube_create.argtypes = [ctypes.c_int32, P(Job), ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_double, P(Image), P(vp)]
         L.art_batch_render.argtypes = [vp, vp]
         L.art_batch_capture.argtypes = [vp, vp]
         L.art_batch_launch.argtypes = [vp, vp]
@@ -464,7 +466,9 @@ class Batch:
     self.levels[i] (ny, nx) int8, self.feats[i] or None.
     """
 
-    def __init__(self, cfgs, feat=False):
+    def __init__(self, cfgs, feat=False, cube=None):
+        """cube=(n0, levels, r_rel, r_abs): the images form an axis-sampled
+        cube (cfgs in axis order, see render_cube) rendered as one batch."""
         self._torch = _torch()
         n = len(cfgs)
         self.cfgs = list(cfgs)
@@ -481,7 +485,11 @@ class Batch:
             ims[i] = _image(img, lev, ft)
         self._torch.cuda.synchronize()
         h = ctypes.c_void_p()
-        _check(lib().art_batch_create(n, jobs, ims, ctypes.byref(h)))
+        if cube is None:
+            _check(lib().art_batch_create(n, jobs, ims, ctypes.byref(h)))
+        else:
+            n0, lv, rr, ra = cube
+            _check(lib().art_cube_create(n, jobs, int(n0), int(lv), float(rr), float(ra), ims, ctypes.byref(h)))
         self._h = h
 
     def render(self, stream=None):

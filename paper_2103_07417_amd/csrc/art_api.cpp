@@ -131,6 +131,10 @@ struct art_batch {
     int cus = 0;
     art_cnn* net = nullptr;        // learned renders when set
     art_learned lopt{};
+    int cube_n0 = 0;               // axis-sampled cube (cube_levels >= 0): base images
+    int cube_levels = -1;          // refinements along the axis (-1: not a cube)
+    std::vector<int> cube_perm;    // internal index -> axis index
+    std::vector<int> cube_inv;     // axis index -> internal index
 };
 
 namespace {
@@ -649,8 +653,11 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
 
 // One render of the whole batch on stream s: every group's level loop on its
 // own stream, forked from and joined back into s (capturable).
+int enqueue_spectral(art_batch* b, int n0, int slevels, hipStream_t s);
+
 int enqueue_render(art_batch* b, hipStream_t s)
 {
+    if (b->cube_levels >= 0) return enqueue_spectral(b, b->cube_n0, b->cube_levels, s);
     b->ntrace = 0;
     for (int g = 0; g < b->ngroups; ++g) b->grp[g].nev = 0;
     b->render_timed = b->timing;
@@ -926,11 +933,16 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
     return ART_OK;
 }
 
-int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, double r_rel, double r_abs,
-                    art_image* out, art_stats* st, void* stream)
+namespace {
+
+// Set up batch b as an axis-sampled cube: jobs and images in axis order are
+// stored in the internal order (the n0 base images, then each axis level's
+// images), every non-base image gets its axis neighbours a, b, c, d (-1
+// outside the cube) and the axis tolerances; descriptors are uploaded on s.
+int check_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t L, double r_rel, double r_abs,
+               const art_image* out)
 {
     if (!jobs || !out) return fail(ART_EINVAL, "null argument");
-    const int L = levels;
     if (n0 < 2 || L < 0 || L > 6) return fail(ART_EINVAL, "a cube needs n0 >= 2 and 0 <= levels <= 6");
     if ((long long)n != ((long long)(n0 - 1) << L) + 1)
         return fail(ART_EINVAL, "a cube of n0 = %d and %d levels has %lld images, not %d", n0, L,
@@ -943,7 +955,14 @@ int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, 
             return fail(ART_EINVAL, "cube image %d: every image needs the same base grid and levels", i);
     if (jobs[0].cam.levels + L > kMaxLevels)
         return fail(ART_EINVAL, "cube of %d + %d levels (limit %d)", jobs[0].cam.levels, L, kMaxLevels);
-    // internal order: base images, then each cube level; perm[k] = axis index
+    return ART_OK;
+}
+
+int setup_cube(art_batch* b, int32_t n, const art_job* jobs, int32_t n0, int32_t L, double r_rel, double r_abs,
+               const art_image* out, hipStream_t s)
+{
+    int rc = check_cube(n, jobs, n0, L, r_rel, r_abs, out);
+    if (rc) return rc;
     std::vector<int> perm, inv(n, -1);
     for (int k = 0; k < n0; ++k) perm.push_back(k << L);
     for (int sl = 1; sl <= L; ++sl) {
@@ -957,12 +976,8 @@ int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, 
         J[k] = jobs[perm[k]];
         imgs[k] = out[perm[k]];
     }
-    std::lock_guard<std::mutex> lk(g_single_mu);
-    art_batch* b = single_batch();
-    if (!b) return fail(ART_EDEVICE, "no current device");
-    hipStream_t s = (hipStream_t)stream;
     b->spectral = true;
-    int rc = prepare(b, n, J.data(), imgs.data(), false, s);
+    rc = prepare(b, n, J.data(), imgs.data(), false, s);
     if (rc) {
         b->spectral = false;
         return rc;
@@ -985,17 +1000,65 @@ int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, 
         b->spectral = false;
         return fail(ART_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
     }
-    b->timing = st != nullptr;
     b->net = nullptr;
-    rc = enqueue_spectral(b, n0, L, s);
+    b->cube_n0 = n0;
+    b->cube_levels = L;
+    b->cube_perm = perm;
+    b->cube_inv = inv;
+    return ART_OK;
+}
+
+void clear_cube(art_batch* b)
+{
     b->spectral = false;
+    b->cube_levels = -1;
+    b->cube_n0 = 0;
+    b->cube_perm.clear();
+    b->cube_inv.clear();
+}
+
+}  // namespace
+
+int art_render_cube(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, double r_rel, double r_abs,
+                    art_image* out, art_stats* st, void* stream)
+{
+    int rc = check_cube(n, jobs, n0, levels, r_rel, r_abs, out);
     if (rc) return rc;
-    if (st) {
-        for (int k = 0; k < n; ++k) {
-            rc = batch_stats(b, k, &st[perm[k]], s);
-            if (rc) return rc;
-        }
+    std::lock_guard<std::mutex> lk(g_single_mu);
+    art_batch* b = single_batch();
+    if (!b) return fail(ART_EDEVICE, "no current device");
+    hipStream_t s = (hipStream_t)stream;
+    rc = setup_cube(b, n, jobs, n0, levels, r_rel, r_abs, out, s);
+    if (rc) {
+        clear_cube(b);
+        return rc;
     }
+    b->timing = st != nullptr;
+    rc = enqueue_spectral(b, n0, levels, s);
+    if (rc == ART_OK && st) {
+        for (int k = 0; k < n && rc == ART_OK; ++k) rc = batch_stats(b, k, &st[b->cube_perm[k]], s);
+    }
+    clear_cube(b);
+    return rc;
+}
+
+int art_cube_create(int32_t n, const art_job* jobs, int32_t n0, int32_t levels, double r_rel, double r_abs,
+                    const art_image* images, art_batch** out)
+{
+    if (!out) return fail(ART_EINVAL, "NULL output handle");
+    *out = nullptr;
+    int rc = check_cube(n, jobs, n0, levels, r_rel, r_abs, images);
+    if (rc) return rc;
+    art_batch* b = new (std::nothrow) art_batch();
+    if (!b) return fail(ART_ENOMEM, "out of host memory");
+    rc = setup_cube(b, n, jobs, n0, levels, r_rel, r_abs, images, nullptr);
+    if (rc == ART_OK && hipStreamSynchronize(nullptr) != hipSuccess) rc = fail(ART_EDEVICE, "upload failed");
+    if (rc) {
+        free_batch_mem(b);
+        delete b;
+        return rc;
+    }
+    *out = b;
     return ART_OK;
 }
 
@@ -1138,6 +1201,7 @@ int art_batch_launch(art_batch* b, void* stream)
 int art_batch_set_learned(art_batch* b, art_cnn* net, const art_learned* opt)
 {
     if (!b) return fail(ART_EINVAL, "NULL batch");
+    if (net && b->cube_levels >= 0) return fail(ART_EINVAL, "axis-sampled cubes render with the criterion only");
     return setup_learned(b, net, opt);
 }
 
@@ -1145,7 +1209,8 @@ int art_batch_stats(art_batch* b, int32_t i, art_stats* st, void* stream)
 {
     if (!b || !st) return fail(ART_EINVAL, "NULL argument");
     if (i >= b->n) return fail(ART_EINVAL, "image index %d outside batch of %d", i, b->n);
-    return batch_stats(b, i, st, (hipStream_t)stream);
+    const int k = (i >= 0 && b->cube_levels >= 0) ? b->cube_inv[i] : i;   // cubes: axis order
+    return batch_stats(b, k, st, (hipStream_t)stream);
 }
 
 int art_batch_destroy(art_batch* b)

@@ -95,3 +95,15 @@ def test_cube_validation_host_only():
     assert L.art_render_cube(4, jobs, 3, 1, 0.01, 1e-3, ims, None, None) == -1
     assert L.art_render_cube(4, jobs, 1, 1, 0.01, 1e-3, ims, None, None) == -1
     assert L.art_render_cube(5, jobs, 3, 1, float("nan"), 1e-3, ims, None, None) == -1
+
+
+def test_cube_batch_validation_host_only():
+    L = art.lib()
+    jobs = (art.Job * 5)()
+    ims = (art.Image * 5)()
+    h = ctypes.c_void_p()
+    assert L.art_cube_create(4, jobs, 3, 1, 0.01, 1e-3, ims, ctypes.byref(h)) == -1
+    assert L.art_cube_create(5, jobs, 3, 7, 0.01, 1e-3, ims, ctypes.byref(h)) == -1
+    assert L.art_cube_create(5, jobs, 3, 1, 0.01, float("nan"), ims, ctypes.byref(h)) == -1
+    assert L.art_cube_create(5, jobs, 3, 1, 0.01, 1e-3, ims, None) == -1
+    assert not h.value

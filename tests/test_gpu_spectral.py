@@ -155,3 +155,55 @@ def test_cube_validation(art):
         art.render_cube([cfg] * 4, 3, 1)                        # 4 != 5 images
     with pytest.raises(art.ArtError):
         art.render_cube([cfg] * 4 + [dict(cfg, nx0=11, ny0=11)], 3, 1)
+
+
+def spectral_cfgs(cfg, n0, L):
+    return [dict(cfg, freq_hz=float(nu)) for nu in osp.frequencies(NU[0], NU[1], n0, L)]
+
+
+def test_cube_batch_equals_eager_cube(art):
+    """The cube as a batch object (art_cube_create): an eager render, three
+    graph replays and two cube batches in flight on two library streams all
+    give the images, level maps and per-image statistics (axis order) of
+    art_render_cube, bitwise."""
+    print("CASE cube batch", flush=True)
+    cfg = small_cfg(precision="mixed")
+    n0, L, sr = 3, 2, (0.01, 1e-3)
+    cfgs = spectral_cfgs(cfg, n0, L)
+    want_i, want_l, _, want_s = art.render_cube(cfgs, n0, L, *sr)
+    torch.cuda.synchronize()
+    S1, S2 = art.Stream(), art.Stream()
+    A = art.Batch(cfgs, cube=(n0, L) + sr)
+    A.render(S1.torch)
+    S1.torch.synchronize()
+    for i in range(len(cfgs)):
+        assert torch.equal(A.images[i], want_i[i]) and torch.equal(A.levels[i], want_l[i]), i
+        st = A.stats(i, stream=S1.torch)
+        assert st["rays"] == want_s[i]["rays"] and st["spectral"] == want_s[i]["spectral"], i
+    B = art.Batch(cfgs, cube=(n0, L) + sr)
+    for X, S in ((A, S1), (B, S2)):
+        X.set_launch(256, 256, 1, 1)
+        X.capture(S.torch)
+    for rep in range(3):
+        A.launch(S1.torch)
+        B.launch(S2.torch)
+        torch.cuda.synchronize()
+        for X in (A, B):
+            for i in range(len(cfgs)):
+                assert torch.equal(X.images[i], want_i[i]) and torch.equal(X.levels[i], want_l[i]), (rep, i)
+    assert A.stats(stream=S1.torch)["rays"] == sum(s["rays"] for s in want_s)
+    A.close()
+    B.close()
+    S1.close()
+    S2.close()
+
+
+def test_cube_batch_rejects_network(art):
+    cfg = small_cfg(precision="mixed")
+    cfgs = spectral_cfgs(cfg, 3, 1)
+    A = art.Batch(cfgs, cube=(3, 1, 0.01, 1e-3))
+    net = art.Cnn(seed=1)
+    with pytest.raises(art.ArtError):
+        A.set_learned(net)
+    A.close()
+    net.close()
