@@ -612,6 +612,22 @@ def deploy_visibility(art, torch, art_inputs, cfg, img, truth):
     return res
 
 
+def in_flight_ms(art, torch, make, steps, depth=3):
+    """Time per batch (ms) with `depth` batches from make() in flight on
+    library streams, one image group each at the 256 x 256 persistent grid,
+    every batch a captured graph."""
+    Ss = [art.Stream() for _ in range(depth)]
+    Bs = [make() for _ in range(depth)]
+    for X in Bs:
+        X.set_launch(256, 256, 1, 1)
+    dt = time_pipelined(Bs, torch, [S.torch for S in Ss], steps)
+    for X in Bs:
+        X.close()
+    for S in Ss:
+        S.close()
+    return dt * 1e3
+
+
 def spectral_1025(art, torch, art_inputs, args):
     """Adaptive sampling along frequency (the Sec. 6 extension): the
     thermal_1025 view as a 17-frequency cube from 86 to 690 GHz (3 base
@@ -651,6 +667,12 @@ def spectral_1025(art, torch, art_inputs, args):
     plain = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse_max=chk["mse_max"],
                  mse_mean=chk["mse_mean"], mse_ok=chk["mse_ok"])
     B.close()
+    # throughput: three cubes / three plain batches in flight
+    cube["ms_in_flight"] = in_flight_ms(art, torch, lambda: art.Batch(cfgs, cube=(n0, L, cfg["r_rel"],
+                                                                                    cfg["r_abs"])), args.steps)
+    plain["ms_in_flight"] = in_flight_ms(art, torch, lambda: art.Batch(cfgs), args.steps)
+    log("spectral cube in flight: %.1f ms per cube, plain %.1f ms per batch (3 in flight)" % (
+        cube["ms_in_flight"], plain["ms_in_flight"]))
     out = dict(workload="thermal_1025 view (a=0.94, i=163 deg, IQUV) at %d frequencies 86-690 GHz equally "
                         "spaced in ln nu (3 base + 3 spectral levels), 1025^2, R_rel=0.01, R_abs=1e-3 max I0 "
                         "on both axes" % n,
@@ -703,6 +725,11 @@ def movie_1025(art, torch, art_inputs, args):
     plain = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse_max=chk["mse_max"],
                  mse_mean=chk["mse_mean"], mse_ok=chk["mse_ok"])
     B.close()
+    cube["ms_in_flight"] = in_flight_ms(art, torch, lambda: art.Batch(cfgs, cube=(3, 2, base["r_rel"],
+                                                                                    base["r_abs"])), args.steps)
+    plain["ms_in_flight"] = in_flight_ms(art, torch, lambda: art.Batch(cfgs), args.steps)
+    log("movie cube in flight: %.1f ms per cube, plain %.1f ms per batch (3 in flight)" % (
+        cube["ms_in_flight"], plain["ms_in_flight"]))
     log("movie cube 9 x 1025^2: %.1f ms, %d rays (+%d values from neighbouring frames), mse max %.2e; "
         "plain batch %.1f ms, %d rays, mse max %.2e" % (cube["ms"], rays, spec, cube["mse_max"], plain["ms"],
                                                        plain["rays"], plain["mse_max"]))
