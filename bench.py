@@ -71,7 +71,7 @@ BYTES_PER_RAY = 58
 # of this benchmark (profiles/k_trace_learned_batched_thermal_1025.md), per
 # launch of the roofline renders; valid only for the kernel sources it was
 # measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=369027424, kernel_hash="1825eab2d48205b2", form="learned_batched_op",
+TRAFFIC = dict(bytes_per_render=369572233, kernel_hash="1825eab2d48205b2", form="learned_batched_op",
                source="profiles/k_trace_learned_batched_thermal_1025.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of one headline render")
 TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
@@ -259,7 +259,8 @@ def batch_forms(art, torch, art_inputs, args):
         st = B0.stats(stream=s)
         chk = mse_check(art, bcfgs, B0.images, truths)
         same = all(torch.equal(a, b) for X in bset[1:] for a, b in zip(B0.images, X.images))
-        f = dict(ms_per_batch=dt * 1e3, latency_ms=lat * 1e3, rays=st["rays"], passes=st["trace_launches"],
+        f = dict(ms_per_batch=dt * 1e3, latency_ms=lat * 1e3, rays=st["rays"], steps=st["steps"],
+                 passes=st["trace_launches"],
                  rays_per_s=st["rays"] / dt, effective_px_per_s=npix / dt, r_rel=bcfgs[0]["r_rel"],
                  interp_frac=st["interp_frac"], check=chk, batches_identical=same, in_flight=depth)
         if learned_opts is not None:
@@ -267,9 +268,9 @@ def batch_forms(art, torch, art_inputs, args):
             f["options"] = dict(learned_opts)
         forms[name] = f
         batch_of[name] = (bset, bcfgs)
-        log("%s: %.1f ms/batch (%d in flight; %.1f ms alone), R_rel %g, %d rays, %d passes, mse max %.2e" % (
-            name, dt * 1e3, depth, lat * 1e3, bcfgs[0]["r_rel"], st["rays"], st["trace_launches"],
-            f["check"]["mse_max"]))
+        log("%s: %.1f ms/batch (%d in flight; %.1f ms alone), R_rel %g, %d rays, %.4g steps, %d passes, "
+            "mse max %.2e" % (name, dt * 1e3, depth, lat * 1e3, bcfgs[0]["r_rel"], st["rays"], st["steps"],
+                              st["trace_launches"], f["check"]["mse_max"]))
         return f
 
     measure("plain_batched", None, Bs, cfgs)
