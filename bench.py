@@ -35,7 +35,8 @@ and the visibility domain of its learned render (Sec. 4.3: 2D window to
 1000 G-lambda on FP64 matrix cores, residual visibilities, ring period); the
 thermal view as a 17-frequency cube sampled adaptively along ln nu, and a
 9-frame movie of the evolving snapshot sampled adaptively in time; the
-64-image batch with uneven refinement (1 to 4 levels per image).
+64-image batch with uneven refinement (1 to 4 levels per image); the
+nearest-neighbour branch and the per-plane criterion on the thermal view.
 """
 import argparse
 import json
@@ -742,6 +743,34 @@ def movie_1025(art, torch, art_inputs, args):
                 cube=cube, plain_batched=plain, rays_ratio=rays / max(plain["rays"], 1))
 
 
+def refine_variants(art, torch, cfg, args):
+    """The refinement variants on the thermal_1025 view, one image at a time:
+    the linear branch of Eqs. 5-6 (the paper's method), the nearest-neighbour
+    branch, and the linear branch with the criterion on every Stokes plane;
+    time, rays and the MSE of every plane against the uniform render."""
+    truth, _, _ = art.render_uniform(cfg)
+    truth = truth.clone()
+    torch.cuda.synchronize()
+    out = {}
+    for name, kw in (("linear", {}), ("nearest", dict(interp="nearest")), ("linear_all_planes", dict(all_planes=True))):
+        c = dict(cfg, **kw)
+        bufs = art.alloc(c)
+        art.render(c, out=bufs)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 3)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            img, lev, _, st = art.render(c, out=bufs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        mses = [art.metrics(truth[q], img[q])[1] for q in range(c["nstokes"])]
+        out[name] = dict(ms=dt * 1e3, rays=st["rays"], interp_frac=st["interp_frac"], mse_iquv=mses)
+        log("refinement %s: %.1f ms, %d rays, IF %.4f, mse I,Q,U,V %s" % (
+            name, dt * 1e3, st["rays"], st["interp_frac"], ["%.2e" % m for m in mses]))
+        del bufs, img, lev
+    return out
+
+
 def plain_single(art, torch, cfg, args):
     """The paper's method, one image at a time, and the uniform render."""
     truth, _, ust = art.render_uniform(cfg)
@@ -868,6 +897,7 @@ def main():
         out["movie_1025"] = movie_1025(art, torch, art_inputs, args)
     if not args.no_uneven:
         out["uneven_batch"] = uneven_batch(art, torch, art_inputs, args)
+        out["refinement_variants"] = refine_variants(art, torch, cfg, args)
     # a plain device copy of known size: reference reading for the HBM byte
     # counters (FETCH_SIZE / WRITE_SIZE) of a profiled run
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
