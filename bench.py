@@ -187,6 +187,30 @@ def time_pipelined(Bs, torch, streams, reps):
     return autotune.time_in_flight(Bs, torch, streams, reps) * 1e-3
 
 
+def operating_points(search, op_forms):
+    """Per form, the search row with the loosest R_rel at which every image
+    passed the bar (forms that never pass are left out)."""
+    op = {}
+    for name, opts in op_forms:
+        passing = [r for r in search if r["form"] == name and r["ok"]]
+        if passing:
+            op[name] = dict(max(passing, key=lambda r: r["r_rel"]), options=opts)
+    return op
+
+
+def forms_to_time(op, r_rel0):
+    """The operating-point forms to time: the plain criterion's if it is not
+    the workload's own tolerance r_rel0, and the learned form with the fewest
+    rays at its operating point."""
+    extra = []
+    if "plain" in op and op["plain"]["r_rel"] != r_rel0:
+        extra.append(("plain_batched_op", op["plain"]))
+    lop = [v for k, v in op.items() if k != "plain"]
+    if lop:
+        extra.append(("learned_batched_op", min(lop, key=lambda v: v["rays"])))
+    return extra
+
+
 def batch_forms(art, torch, art_inputs, args):
     """Learned + batched and plain batched renders of the 64-image batch:
     throughput with several batches in flight (the timed step) and the
@@ -306,18 +330,9 @@ def batch_forms(art, torch, art_inputs, args):
             chk = mse_check(art, c_rr, X.images, truths)
             search.append(dict(form=name, r_rel=rr, rays=st["rays"], mse_max=chk["mse_max"], ok=chk["mse_ok"]))
         X.close()
-    op = {}
-    for name, opts in op_forms:
-        passing = [r for r in search if r["form"] == name and r["ok"]]
-        if passing:
-            op[name] = dict(max(passing, key=lambda r: r["r_rel"]), options=opts)
+    op = operating_points(search, op_forms)
     log("operating points: %s" % {k: (v["r_rel"], v["rays"], "%.2e" % v["mse_max"]) for k, v in op.items()})
-    extra = []
-    if "plain" in op and op["plain"]["r_rel"] != cfgs[0]["r_rel"]:
-        extra.append(("plain_batched_op", op["plain"]))
-    lop = [v for k, v in op.items() if k != "plain"]
-    if lop:
-        extra.append(("learned_batched_op", min(lop, key=lambda v: v["rays"])))
+    extra = forms_to_time(op, cfgs[0]["r_rel"])
     for name, o in extra:
         c_op = [dict(c, r_rel=o["r_rel"]) for c in cfgs]
         bset = [art.Batch(c_op, feat=True) for _ in range(depth)]

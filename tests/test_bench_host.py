@@ -39,3 +39,24 @@ def test_flop_count_of_a_step():
 def test_search_grids():
     assert list(bench.OP_RREL) == sorted(bench.OP_RREL) and bench.OP_RREL[0] == 0.01
     assert all(1 <= d <= 4 for d in bench.IN_FLIGHT_DEPTHS)
+
+
+def test_operating_points_pick_the_loosest_passing_tolerance():
+    forms = [("plain", None), ("lookahead_z4", {"z_propose": 4.0})]
+    search = [
+        dict(form="plain", r_rel=0.01, rays=100, ok=True),
+        dict(form="lookahead_z4", r_rel=0.01, rays=104, ok=True),
+        dict(form="plain", r_rel=0.015, rays=95, ok=False),
+        dict(form="lookahead_z4", r_rel=0.015, rays=97, ok=True),
+        dict(form="lookahead_z4", r_rel=0.02, rays=93, ok=False),
+    ]
+    op = bench.operating_points(search, forms)
+    assert op["plain"]["r_rel"] == 0.01 and op["lookahead_z4"]["r_rel"] == 0.015
+    assert op["lookahead_z4"]["options"] == {"z_propose": 4.0}
+    extra = bench.forms_to_time(op, 0.01)
+    assert [n for n, _ in extra] == ["learned_batched_op"] and extra[0][1]["rays"] == 97
+    # a plain operating point looser than the workload's tolerance is timed too
+    op2 = bench.operating_points(search + [dict(form="plain", r_rel=0.0125, rays=98, ok=True)], forms)
+    assert [n for n, _ in bench.forms_to_time(op2, 0.01)] == ["plain_batched_op", "learned_batched_op"]
+    # a form that never passes has no operating point
+    assert "x" not in bench.operating_points([dict(form="x", r_rel=0.01, rays=1, ok=False)], [("x", None)])
