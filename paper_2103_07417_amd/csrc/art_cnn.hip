@@ -65,18 +65,144 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
     floatx16 acc;
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-    for (int r = 0; r < 9; ++r) {
+    // operands of one tap (up to 32 channels = 4 MFMA steps) are loaded
+    // together, and the next tap's loads are issued before this tap's MFMAs,
+    // so a wave waits for one memory round trip per tap, not one per step
+    bf16x4 A[2][4], Bw[2][4];
+    auto load_tap = [&](int r, bf16x4* Ar, bf16x4* Br) {
         const int yy = y + r / 3 - 1, xx = x + (r % 3) - 1;
         const bool inside = x < W && yy >= 0 && yy < H && xx >= 0 && xx < W;
         const long long so = inside ? ((long long)yy * W + xx) * cin_pad : 0;
-        for (int c8 = 0; c8 < cin_pad; c8 += 8) {
-            bf16x4 a = { 0, 0, 0, 0 };
-            if (inside) a = *(const bf16x4*)(inb + so + c8 + 4 * kb);
-            const bf16x4 bw = *(const bf16x4*)(Wm + (long long)m * Kp + r * cin_pad + c8 + 4 * kb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            Ar[q] = bf16x4{ 0, 0, 0, 0 };
+            Br[q] = bf16x4{ 0, 0, 0, 0 };
+            if (8 * q < cin_pad) {
+                if (inside) Ar[q] = *(const bf16x4*)(inb + so + 8 * q + 4 * kb);
+                Br[q] = *(const bf16x4*)(Wm + (long long)m * Kp + r * cin_pad + 8 * q + 4 * kb);
+            }
+        }
+    };
+    load_tap(0, A[0], Bw[0]);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        if (r + 1 < 9) load_tap(r + 1, A[(r + 1) & 1], Bw[(r + 1) & 1]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (8 * q < cin_pad)
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[r & 1][q], Bw[r & 1][q], acc, 0, 0, 0);
+    }
+    // D[row][col]: col = lane % 32 (output channel), row = 8 (j/4) + 4 (lane/32) + j%4
+    const int oc = m;
+    if (mode == 1 && oc >= co) return;
+    const float bb = (mode == 2 || oc >= co) ? 0.0f : bias[oc];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int xo = x0 + 8 * (j >> 2) + 4 * kb + (j & 3);
+        if (xo >= W) continue;
+        const long long pos = (long long)y * W + xo;
+        const float v = acc[j] + bb;
+        if (mode == 0) {
+            ((uint16_t*)out)[((long long)b * HW + pos) * 32 + oc] = f2bf(v > 0.0f ? v : 0.0f);
+        } else if (mode == 1) {
+            ((float*)out)[((long long)b * co + oc) * HW + pos] = v;
+        } else {
+            const long long o = ((long long)b * HW + pos) * 32 + oc;
+            ((uint16_t*)out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? v : 0.0f);
+        }
+    }
+}
+
+// The same convolution with its operands staged in LDS (CIN = 8 or 32): the
+// block's four waves copy the weight matrix once ([32][9 CIN], rows padded by
+// 4) and each wave its 3 x 34 input halo (rows y-1..y+1, zero outside the
+// image, positions padded by 4 channels), every staging load issued before
+// the first LDS store; the nine taps then read LDS.  Scattered 8-byte global
+// reads of one cache line per lane (the plain kernel's A and B operands) are
+// what limits the plain kernel.  Halo lanes of the last tile beyond the image
+// width produce output rows that are discarded.
+template <int CIN>
+__global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict__ in, int B, int H, int W,
+                                                      const uint16_t* __restrict__ Wm,
+                                                      const float* __restrict__ bias, int co, int mode,
+                                                      void* __restrict__ out, const uint16_t* __restrict__ mask)
+{
+    constexpr int KP = 9 * CIN;          // GEMM depth
+    constexpr int WS = KP + 4;           // staged weight row stride (bf16)
+    constexpr int CS = CIN + 4;          // staged position stride (bf16)
+    constexpr int NPOS = 3 * 34;
+    constexpr int NA = NPOS * (CIN / 4); // 8-byte chunks of a wave's halo
+    constexpr int NAL = (NA + 63) / 64;  // per lane
+    constexpr int NW = 32 * (KP / 4);    // 8-byte chunks of the weights
+    constexpr int NWT = (NW + 255) / 256;
+    __shared__ __align__(16) uint16_t sW[32 * WS];
+    __shared__ __align__(16) uint16_t sA[4][NPOS * CS];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long wave = (long long)blockIdx.x * 4 + wv;
+    const int tiles_x = (W + 31) >> 5;
+    const long long row = wave / tiles_x;                 // b * H + y
+    const bool valid = row < (long long)B * H;            // uniform per wave
+    const int b = valid ? (int)(row / H) : 0;
+    const int y = valid ? (int)(row - (long long)b * H) : 0;
+    const int x0 = valid ? (int)(wave - row * tiles_x) << 5 : 0;
+    const long long HW = (long long)H * W;
+    const uint16_t* inb = in + (long long)b * HW * CIN;
+    bf16x4 wv_[NWT], av_[NAL];
+#pragma unroll
+    for (int t = 0; t < NWT; ++t) {
+        const int q = threadIdx.x + 256 * t;
+        wv_[t] = bf16x4{ 0, 0, 0, 0 };
+        if (q < NW) {
+            const int r = q / (KP / 4), c4 = q - r * (KP / 4);
+            wv_[t] = *(const bf16x4*)(Wm + (long long)r * KP + 4 * c4);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NAL; ++t) {
+        const int q = lane + 64 * t;
+        av_[t] = bf16x4{ 0, 0, 0, 0 };
+        if (q < NA) {
+            const int pos = q / (CIN / 4), c4 = q - pos * (CIN / 4);
+            const int pr = pos / 34, pc = pos - pr * 34;
+            const int yy = y - 1 + pr, xx = x0 - 1 + pc;
+            if (valid && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                av_[t] = *(const bf16x4*)(inb + ((long long)yy * W + xx) * CIN + 4 * c4);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NWT; ++t) {
+        const int q = threadIdx.x + 256 * t;
+        if (q < NW) {
+            const int r = q / (KP / 4), c4 = q - r * (KP / 4);
+            *(bf16x4*)&sW[r * WS + 4 * c4] = wv_[t];
+        }
+    }
+    uint16_t* a_s = sA[wv];
+#pragma unroll
+    for (int t = 0; t < NAL; ++t) {
+        const int q = lane + 64 * t;
+        if (q < NA) {
+            const int pos = q / (CIN / 4), c4 = q - pos * (CIN / 4);
+            *(bf16x4*)&a_s[pos * CS + 4 * c4] = av_[t];
+        }
+    }
+    __syncthreads();
+    if (!valid) return;
+    const int m = lane & 31, kb = lane >> 5;
+    floatx16 acc;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const int dy = r / 3, dx = r % 3;
+#pragma unroll
+        for (int c8 = 0; c8 < CIN; c8 += 8) {
+            const bf16x4 a = *(const bf16x4*)&a_s[(dy * 34 + m + dx) * CS + c8 + 4 * kb];
+            const bf16x4 bw = *(const bf16x4*)&sW[m * WS + r * CIN + c8 + 4 * kb];
             acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bw, acc, 0, 0, 0);
         }
     }
-    // D[row][col]: col = lane % 32 (output channel), row = 8 (j/4) + 4 (lane/32) + j%4
     const int oc = m;
     if (mode == 1 && oc >= co) return;
     const float bb = (mode == 2 || oc >= co) ? 0.0f : bias[oc];
@@ -103,8 +229,15 @@ hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, co
 {
     const long long waves = (long long)B * H * ((W + 31) / 32);
     const long long blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL(k_conv_fwd, dim3((unsigned)blocks), dim3(256), 0, s, in, cin_pad, B, H, W, Wm, Kp, bias,
-                       co, mode, out, mask);
+    if (cin_pad == 32 && Kp == 9 * 32)
+        hipLaunchKernelGGL(k_conv_fwd_lds<32>, dim3((unsigned)blocks), dim3(256), 0, s, in, B, H, W, Wm, bias, co,
+                           mode, out, mask);
+    else if (cin_pad == 8 && Kp == 9 * 8)
+        hipLaunchKernelGGL(k_conv_fwd_lds<8>, dim3((unsigned)blocks), dim3(256), 0, s, in, B, H, W, Wm, bias, co,
+                           mode, out, mask);
+    else
+        hipLaunchKernelGGL(k_conv_fwd, dim3((unsigned)blocks), dim3(256), 0, s, in, cin_pad, B, H, W, Wm, Kp,
+                           bias, co, mode, out, mask);
     return hipGetLastError();
 }
 
