@@ -30,9 +30,13 @@
  *   - Polarisation basis: Walker-Penrose constant of the camera's screen-up
  *     vector, compared at each point with that of the projected magnetic field.
  *
- * Parity unpinned: the fitting form of the thermal circular emissivity j_V
- * (thermal_coefs below) has no closed form or published value to pin it to
- * here; only Kirchhoff's law and its sign are checked.
+ * Pins (tests/test_oracle_*.py) tie each piece to something outside this
+ * file: closed forms of Kerr geodesics and of constant-coefficient slabs,
+ * textbook synchrotron integrals for j_I, j_Q and j_V, and whole equatorial
+ * Schwarzschild rays whose intensity is recomputed by quadrature (toy disk)
+ * or by an ODE solver of the transfer equation (thermal plasma), which fixes
+ * the redshift factors g^2 of the emission and 1/g of the absorption.  The
+ * sign convention of V (positive for cos th_B > 0) is a reading.
  */
 #include <math.h>
 #include <stdint.h>
