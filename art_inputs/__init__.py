@@ -109,6 +109,28 @@ def batch_workload(precision="mixed", base=129):
     return cfgs
 
 
+HELDOUT_SPINS = (0.2, 0.7, 0.9, -0.6)
+HELDOUT_INCS = (30.0, 45.0, 115.0, 150.0)
+
+
+def batch_workload_heldout(precision="mixed", base=129):
+    """A batch of the same structure as batch_workload (64 thermal images,
+    the same four frequencies, image k refined 1 + (k mod 4) levels) at
+    spins, inclinations and field phases (seeds 201..264) disjoint from it
+    and from the training images: the batch on which tolerances are chosen
+    before they are applied, unchanged, to batch_workload."""
+    cfgs = []
+    k = 0
+    for a in HELDOUT_SPINS:
+        for inc in HELDOUT_INCS:
+            for nu in BATCH_FREQS:
+                cfgs.append(dict(workload("thermal_1025"), name="heldout_%02d" % k, a=a, inc_deg=inc,
+                                 freq_hz=nu, levels=1 + (k % 4), precision=precision,
+                                 mp=thermal_params(seed=201 + k), nx0=base, ny0=base))
+                k += 1
+    return cfgs
+
+
 def batch_workload_1025(precision="mixed"):
     """64 images of the thermal_1025 kind (base 129^2, 3 levels -> 1025^2):
     spin x inclination x frequency in lexicographic order, one level count

@@ -29,7 +29,7 @@ import numpy as np
 
 from . import cnn
 from .ray import screen_coords
-from .refine import grid_size, level_stencil, trapezoid_mean
+from .refine import grid_size, level_stencil, linear_margin, trapezoid_mean
 
 UNSET, PROPOSE, SUPPRESS = 0, 1, 2
 
@@ -49,10 +49,18 @@ def _neighbours(p, q):
 
 
 def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstokes, logits_fn,
-                   z_hi, z_lo, fallback=True, all_levels=False):
+                   z_hi, z_lo, fallback=True, all_levels=False, forced_level=None):
     """ray_fn(x, y) -> (S (n, nstokes), rmin (n,), ncross (n,)).
     logits_fn(x) -> (15, H, W) for the features x (3, H, W) of a level.
-    Returns dict(img, level, judge, passes, rays, n_abs)."""
+    forced_level: optional final-grid level map to replay (a point new at
+    level l+1 or l+2 of a network pass is traced iff the map says so).
+    Returns dict(img, level, judge, passes, rays, n_abs, audit): audit lists,
+    per decision pass, the final-grid points (i, j) judged, the state this
+    oracle's own rule gives them from its own values and logits (-1 or the
+    level traced at), the tie margin of the criterion's part of the decision
+    (relative perturbation, see refine.and_margin) and the distance of the
+    point's logit from the nearer of z_hi and z_lo (inf for points no logit
+    decides).  In a forced replay the image follows forced_level."""
     nx, ny = grid_size(nx0, levels), grid_size(ny0, levels)
     img = np.full((nstokes, ny, nx), np.nan)
     lev = np.full((ny, nx), -1, dtype=np.int8)
@@ -60,6 +68,7 @@ def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstoke
     ncr = np.zeros((ny, nx), dtype=np.int64)
     judge = [0] * 5
     passes = 0
+    audit = []
 
     def trace(tp, tq, level):
         if tp.size:
@@ -80,14 +89,18 @@ def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstoke
     n_abs = trapezoid_mean(I0) if abs_norm == "mean" else float(I0.max())
 
     def criterion(l):
-        """Points new at level l+1, their stencil sums and the criterion's flag."""
+        """Points new at level l+1, their stencil sums, the criterion's flag
+        and its tie margin."""
         s = 1 << (levels - l - 1)
-        p, q, S_all, D, inf, m = level_stencil(img, nx0, ny0, l, s, nstokes)
+        p, q, S_all, D, inf, m, magD, magS = level_stencil(img, nx0, ny0, l, s, nstokes,
+                                                           with_mag=True)
         thrA = (4.0 * m * r_abs) * n_abs
         with np.errstate(invalid="ignore"):
-            crit = inf | np.isnan(D) | np.isnan(S_all[0]) | (
-                (np.abs(D) > thrA) & (np.abs(D) > (4.0 * r_rel) * np.abs(S_all[0])))
-        return p, q, s, S_all, m, crit
+            crit, margin = linear_margin(D, S_all[0], magD, magS, thrA, 4.0 * r_rel)
+            forced = inf | np.isnan(D) | np.isnan(S_all[0])
+            crit = crit | forced
+            margin = np.where(forced, np.inf, margin)
+        return p, q, s, S_all, m, crit, margin
 
     def interpolate(p, q, s, S_all, m, sel):
         pp, qq = p[sel], q[sel]
@@ -106,22 +119,33 @@ def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstoke
         ncr[qq * s, pp * s] = c
         lev[qq * s, pp * s] = -1
 
+    def record(p, q, s, own_dec, level, cmargin, zmargin):
+        audit.append(dict(i=p * s, j=q * s, own=np.where(own_dec, level, -1).astype(np.int8),
+                          margin=cmargin, zmargin=zmargin))
+
+    def forced_at(p, q, s, level):
+        return forced_level[q * s, p * s] == level
+
     l = 0
     while l < levels:
         net_here = l + 2 <= levels or (all_levels and l + 1 <= levels)
         if not net_here:
-            p, q, s, S_all, m, crit = criterion(l)
-            interpolate(p, q, s, S_all, m, ~crit)
-            trace(p[crit] * s, q[crit] * s, l + 1)
+            p, q, s, S_all, m, crit, cm = criterion(l)
+            record(p, q, s, crit, l + 1, cm, np.full(p.shape, np.inf))
+            dec = crit if forced_level is None else forced_at(p, q, s, l + 1)
+            interpolate(p, q, s, S_all, m, ~dec)
+            trace(p[dec] * s, q[dec] * s, l + 1)
             passes += 1
             l += 1
             continue
         z = logits_fn(cnn.features(img[0], rmin, ncr, nx0, ny0, levels, l, n_abs))
         mark = np.full((ny, nx), UNSET, dtype=np.int8)
+        zgap = np.full((ny, nx), np.inf)
         ahead_p, ahead_q = [], []
         for k, (lv, fp, fq, ok) in enumerate(cnn.owned_points(nx0, ny0, levels, l)):
             hi = ok & (z[k] > z_hi)
             lo = ok & ~(z[k] > z_hi) & (z[k] < z_lo)
+            zgap[fq[ok], fp[ok]] = np.minimum(np.abs(z[k] - z_hi), np.abs(z[k] - z_lo))[ok]
             if lv == l + 1:
                 mark[fq[hi], fp[hi]] = PROPOSE
             else:
@@ -131,12 +155,18 @@ def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstoke
         ahead_p = np.concatenate(ahead_p) if ahead_p else np.zeros(0, dtype=np.int64)
         ahead_q = np.concatenate(ahead_q) if ahead_q else np.zeros(0, dtype=np.int64)
         # level l+1
-        p, q, s, S_all, m, crit = criterion(l)
+        p, q, s, S_all, m, crit, cm = criterion(l)
         mk = mark[q * s, p * s]
         prop, sup = mk == PROPOSE, mk == SUPPRESS
         dec = prop | (crit & ~sup)
+        record(p, q, s, dec, l + 1, cm, zgap[q * s, p * s])
         judge[0] += int((prop & ~crit).sum())
         judge[1] += int((crit & sup).sum())
+        if forced_level is not None:
+            dec = forced_at(p, q, s, l + 1)
+            if l + 2 <= levels:
+                fq2, fp2 = np.nonzero(forced_level == l + 2)
+                ahead_p, ahead_q = fp2, fq2
         interpolate(p, q, s, S_all, m, ~dec)
         trace(np.concatenate([p[dec] * s, ahead_p]), np.concatenate([q[dec] * s, ahead_q]), l + 1)
         lev[ahead_q, ahead_p] = l + 2
@@ -146,10 +176,24 @@ def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstoke
             l += 1
             continue
         # level l+2, judged by the criterion on the level-(l+1) values
-        p, q, s, S_all, m, crit = criterion(l + 1)
+        p, q, s, S_all, m, crit, cm = criterion(l + 1)
         keep = lev[q * s, p * s] == l + 2
         sup = mark[q * s, p * s] == SUPPRESS
-        want = crit & ~sup & ~keep
+        zg = zgap[q * s, p * s]
+        if forced_level is None:
+            want = crit & ~sup & ~keep
+            record(p, q, s, keep | (want if fallback else np.zeros_like(want)), l + 2, cm, zg)
+        else:
+            # own rule: look-ahead proposals, then fallback on flagged points
+            look = np.zeros((ny, nx), dtype=bool)
+            for k, (lv, fp, fq, ok) in enumerate(cnn.owned_points(nx0, ny0, levels, l)):
+                if lv == l + 2:
+                    hi = ok & (z[k] > z_hi)
+                    look[fq[hi], fp[hi]] = True
+            la = look[q * s, p * s]
+            own = la | ((crit & ~sup & ~la) if fallback else np.zeros_like(la))
+            record(p, q, s, own, l + 2, cm, zg)
+            want = np.zeros_like(keep)
         judge[1] += int((crit & sup & ~keep).sum())
         if fallback:
             judge[2] += int(want.sum())
@@ -162,4 +206,4 @@ def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstoke
             passes += 1
         l += 2
     return dict(img=img, level=lev, judge=judge, passes=passes, rays=int((lev >= 0).sum()),
-                n_abs=n_abs, rmin=rmin, ncross=ncr)
+                n_abs=n_abs, rmin=rmin, ncross=ncr, audit=audit)

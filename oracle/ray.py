@@ -75,6 +75,16 @@ def lib():
     return _lib
 
 
+def default_threads():
+    """Threads of a trace call: the process's CPUs, at most 16 (the CPU share
+    of one GPU on the machines this runs on beside a GPU job)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def _dp(x):
     return x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
@@ -127,7 +137,7 @@ def trace(cfg, alpha, beta, nthreads=None, grid=None):
     if n == 0:
         return S, feat
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        nthreads = default_threads()
     lib().or_trace(ctypes.byref(p), n, _dp(alpha), _dp(beta), _dp(S),
                    feat.ctypes.data_as(ctypes.c_void_p), int(nthreads))
     return S, feat

@@ -72,19 +72,21 @@ def neighbours(i, n, levels):
     return ok(i - 3 * h), ok(i - h), ok(i + h), ok(i + 3 * h)
 
 
-def second_difference(a, b, c, d):
-    """The spectral D of the stencil (arrays; a or d may be None)."""
+def second_difference(a, b, c, d, with_mag=False):
+    """The spectral D of the stencil (arrays; a or d may be None); with_mag
+    also the magnitude sum of its terms."""
     has_a = a is not None
     has_d = d is not None
     z = np.zeros_like(b)
-    _, D, inf = _axis_terms(b, c, a if has_a else z, d if has_d else z,
-                            np.full(b.shape, has_a), np.full(b.shape, has_d))
-    return D, inf
+    out = _axis_terms(b, c, a if has_a else z, d if has_d else z,
+                      np.full(b.shape, has_a), np.full(b.shape, has_d), with_mag)
+    return out[1:] if with_mag else (out[1], out[2])
 
 
 def spectral_alt(imgs, nabs, stencil, r_rel, r_abs, all_planes=False):
     """alt(i, j) for oracle.refine: the spectral check and value at final-grid
-    points (i, j) from the finished images of the stencil (a, b, c, d)."""
+    points (i, j) from the finished images of the stencil (a, b, c, d), with
+    the tie margin of the check (see oracle.refine.and_margin)."""
     ia, ib, ic, id_ = stencil
     n_abs = 0.5 * (nabs[ib] + nabs[ic])
     thrA = 8.0 * r_abs * n_abs
@@ -98,14 +100,22 @@ def spectral_alt(imgs, nabs, stencil, r_rel, r_abs, all_planes=False):
         a = imgs[ia][:, jj, ii] if ia is not None else None
         d = imgs[id_][:, jj, ii] if id_ is not None else None
         S = b + c
+        magS = np.abs(b[0]) + np.abs(c[0])
         planes = range(b.shape[0]) if all_planes else range(1)
+        decs, margins = [], []
         with np.errstate(invalid="ignore"):
-            bad = np.isnan(S[0])
             for st in planes:
-                Dp, inf = second_difference(a[st] if a is not None else None, b[st], c[st],
-                                            d[st] if d is not None else None)
-                bad |= inf | np.isnan(Dp) | ((np.abs(Dp) > thrA) & (np.abs(Dp) > crel * np.abs(S[0])))
-        return ~bad, S * 0.5
+                Dp, inf, mag = second_difference(a[st] if a is not None else None, b[st], c[st],
+                                                 d[st] if d is not None else None, with_mag=True)
+                dd, mg = oref.linear_margin(Dp, S[0], mag, magS, thrA, crel)
+                forced = inf | np.isnan(Dp)
+                decs.append(dd | forced)
+                margins.append(np.where(forced, np.inf, mg))
+            bad, margin = oref.or_margin(decs, margins)
+            nan0 = np.isnan(S[0])
+            bad = bad | nan0
+            margin = np.where(nan0, np.inf, margin)
+        return ~bad, S * 0.5, margin
     return alt
 
 

@@ -605,11 +605,15 @@ int enqueue_adaptive(art_batch* b, int g, hipStream_t s)
 // traced in pass l+1 together with the level-(l+1) points (proposed or flagged
 // by the criterion and not suppressed), and the criterion then judges level
 // l+2 and traces what the look-ahead missed (fallback) or only counts it.
+// Images may have different level counts (one base grid): at level l an image
+// with levels >= l+2 takes the look-ahead, one with l+1 levels its last level
+// by the criterion alone (the network too with all_levels), and one with fewer
+// is finished; every kernel skips the images a level does not concern.
 int enqueue_learned(art_batch* b, int g, hipStream_t s)
 {
     BatchGroup& G = b->grp[g];
     const ImageDesc& D0 = b->hD[G.i0];
-    const int N = D0.levels;
+    const int N = G.lmax;
     const ImageDesc* dD = b->dD + G.i0;
     Counters* ctr = b->ctr + g;
     unsigned long long* list = b->list + G.list_off;
@@ -617,9 +621,15 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
     int rc = enqueue_base(b, g, s);
     if (rc) return rc;
     const art_learned& o = b->lopt;
+    auto any_with = [&](int lo) {             // an image of the group with >= lo levels
+        for (int i = G.i0; i < G.i0 + G.n; ++i)
+            if (b->hD[i].levels >= lo) return true;
+        return false;
+    };
     int l = 0;
     while (l < N) {
-        const bool net_here = l + 2 <= N || (o.all_levels && l + 1 <= N);
+        const bool ahead = any_with(l + 2);
+        const bool net_here = ahead || (o.all_levels && any_with(l + 1));
         const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
         if (!net_here) {
             HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s));
@@ -631,11 +641,12 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         const int W = (int)grid_n(D0.nx0, l), H = (int)grid_n(D0.ny0, l);
         HIP_TRY(cnn_features_batch(dD, ctr, G.n, l, H, W, G.ws.xf, s));
         HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, G.ws.xf, G.n, H, W, G.ws.logits, s));
-        HIP_TRY(cnn_propose(G.ws.logits, dD, G.n, l, H, W, o.z_propose, o.z_suppress, list, ctr, s));
+        HIP_TRY(cnn_propose(G.ws.logits, dD, G.n, l, H, W, o.z_propose, o.z_suppress, o.all_levels, list, ctr,
+                            s));
         HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 1, 1));
         rc = trace_pass(b, g, l + 1, s);
         if (rc) return rc;
-        if (l + 2 <= N) {
+        if (ahead) {
             const int nx2 = (int)grid_n(D0.nx0, l + 2), ny2 = (int)grid_n(D0.ny0, l + 2);
             HIP_TRY(launch_estimate(dD, G.n, nx2, ny2, l + 1, ctr, list, cap, b->L.long_steps, s, 2,
                                     o.fallback ? 1 : 0));
@@ -742,16 +753,18 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
         return fail(ART_EINVAL, "need z_suppress <= z_propose (no NaN)");
     if (b->uniform) return fail(ART_EINVAL, "uniform renders have no refinement");
     const ImageDesc& D0 = b->hD[0];
+    int nmax = 0;
     for (int i = 0; i < b->n; ++i) {
         const ImageDesc& D = b->hD[i];
-        if (D.nx0 != D0.nx0 || D.ny0 != D0.ny0 || D.levels != D0.levels)
-            return fail(ART_EINVAL, "learned renders need one base grid and level count for the whole batch");
+        if (D.nx0 != D0.nx0 || D.ny0 != D0.ny0)
+            return fail(ART_EINVAL, "learned renders need one base grid for the whole batch");
         if (!D.feat) return fail(ART_EINVAL, "image %d: learned renders need a feature buffer", i);
+        nmax = D.levels > nmax ? D.levels : nmax;
     }
-    // largest level the network runs at
+    // largest level the network runs at (any image's)
     int lmax = -1;
-    for (int l = 0; l < D0.levels; ++l)
-        if (l + 2 <= D0.levels || (opt->all_levels && l + 1 <= D0.levels)) lmax = l;
+    for (int l = 0; l < nmax; ++l)
+        if (l + 2 <= nmax || (opt->all_levels && l + 1 <= nmax)) lmax = l;
     if (lmax >= 0) {
         for (int g = 0; g < b->ngroups; ++g) {
             const long long P = (long long)b->grp[g].n * grid_n(D0.nx0, lmax) * grid_n(D0.ny0, lmax);

@@ -639,11 +639,19 @@ __global__ void k_cnn_features_batch(const ImageDesc* __restrict__ desc, const C
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= HW) return;
     const ImageDesc& D = desc[b];
+    float* xb = x + (long long)b * kCnnIn * HW;
+    if (D.levels < l) {
+        // an image of the batch with fewer levels: it has no level-l grid and
+        // the network's output for it is not read; its input is zero
+        xb[t] = 0.0f;
+        xb[HW + t] = 0.0f;
+        xb[2 * HW + t] = 0.0f;
+        return;
+    }
     const int s = 1 << (D.levels - l);
     const int j = (int)(t / W), i = (int)(t - (long long)j * W);
     float c0, c1, c2;
     feature_at(D.img, D.feat, (long long)j * s * D.nx + (long long)i * s, ctr->scal[b][2], c0, c1, c2);
-    float* xb = x + (long long)b * kCnnIn * HW;
     xb[t] = c0;
     xb[HW + t] = c1;
     xb[2 * HW + t] = c2;
@@ -711,7 +719,7 @@ hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N
 // proposals are compacted with a wave ballot into the trace list of pass l+1.
 __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ logits,
                                                      const ImageDesc* __restrict__ desc, int l, int H, int W,
-                                                     float z_hi, float z_lo,
+                                                     float z_hi, float z_lo, int all_levels,
                                                      unsigned long long* __restrict__ list,
                                                      Counters* __restrict__ ctr)
 {
@@ -719,6 +727,10 @@ __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ l
     const ImageDesc& D = desc[b];
     const long long HW = (long long)H * W;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    // the network decides for this image only where it can look ahead (its
+    // level count reaches l + 2) or everywhere with all_levels; an image with
+    // one level left keeps the plain criterion (marks left undecided)
+    const bool decides = D.levels >= l + 2 || all_levels;
     bool app = false;
     long long pix = 0;
     if (t < HW * kCnnOut) {
@@ -728,7 +740,9 @@ __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ l
         int lev;
         if (owned_point(k, i, j, l, D.levels, D.nx0, D.ny0, D.nx, pix, lev)) {
             const float z = logits[(long long)b * kCnnOut * HW + t];
-            if (z > z_hi) {
+            if (!decides) {
+                D.level[pix] = kMarkUnset;
+            } else if (z > z_hi) {
                 if (k < 3) {
                     D.level[pix] = kMarkPropose;
                 } else {
@@ -763,11 +777,11 @@ __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ l
 }
 
 hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int l, int H, int W, float z_hi,
-                       float z_lo, unsigned long long* list, Counters* ctr, hipStream_t s)
+                       float z_lo, int all_levels, unsigned long long* list, Counters* ctr, hipStream_t s)
 {
     const long long n = (long long)H * W * kCnnOut;
     hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((n + 255) / 256), nimg), dim3(256), 0, s, logits, desc, l, H,
-                       W, z_hi, z_lo, list, ctr);
+                       W, z_hi, z_lo, all_levels, list, ctr);
     return hipGetLastError();
 }
 

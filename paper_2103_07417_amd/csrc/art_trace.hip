@@ -57,10 +57,12 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS,
 // RK stages, the midpoint and the step's end rotate them by their (small)
 // theta increments (angle addition, error ~1e-16 per step).
 // G32 (precision policy): the four right-hand sides of the step are evaluated
-// in FP32 when no ray of the wave is in a sensitive zone (r < r64: photon
-// shell and horizon; |k_theta| < kth64: theta turning points; |sin theta| <
-// 0.1: the polar barrier); the state, the RK4 sums and the step rule stay
-// FP64.  The decision is wave-uniform.
+// in FP32 when the ray is outside every sensitive zone (r < r64: photon shell
+// and horizon; |k_theta| < kth64: theta turning points; |sin theta| < 0.1:
+// the polar barrier); the state, the RK4 sums and the step rule stay FP64.
+// The decision is the ray's own (per lane), so a ray's result does not depend
+// on which rays share its wave: batches, launch shapes and queue orders give
+// the same bits.
 template <typename R, int MODEL, int NS, bool G32, int SUB>
 __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayState<R, MODEL, NS, SUB>& st,
                                         unsigned& emit)
@@ -70,7 +72,7 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
     const double s0 = st.sth, c0 = st.cth;
     bool fast = false;
     if constexpr (G32)
-        fast = __ballot(st.y[0] < P.r64 || ::fabs(st.y[4]) < P.kth64 || ::fabs(s0) < 0.1) == 0ull;
+        fast = !(st.y[0] < P.r64 || ::fabs(st.y[4]) < P.kth64 || ::fabs(s0) < 0.1);
     auto rhs = [&](const double* y, double s, double c, double* d) {
         if (G32 && fast) geo_rhs32(a, st.kt, st.kph, y, s, c, d);
         else geo_rhs(a, st.kt, st.kph, y, s, c, d);

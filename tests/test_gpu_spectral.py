@@ -2,13 +2,15 @@
 the Sec. 3.2 rule) against the oracle.
 
 - Thermal plasma, IQUV, 9 frequencies from 86 to 690 GHz (3 base, 2 spectral
-  levels) on a 9^2 -> 33^2 grid, FP64: every level map equals the oracle's
-  cube (floating-point ties allowed; the oracle is then replayed with the
-  GPU's decisions) and every image agrees to relative L2 1e-6; the same with
-  the per-plane rule.
+  levels) on a 9^2 -> 33^2 grid, FP64: the oracle replays the GPU's level
+  maps and every decision (spatial criterion and the axis check) its own
+  rule takes differently must sit at a tie (margin < 1e-9); every image
+  agrees with the replay to relative L2 1e-6; the same with the per-plane
+  rule.
 - A negative spectral tolerance reproduces plain adaptive renders at every
   frequency bitwise; statistics count spectral values and rays consistently;
-  mixed precision stays within MSE 1e-3 of FP64; invalid cubes are refused.
+  mixed precision stays within MSE 1e-3 of the FP64 oracle; invalid cubes
+  are refused.
 - Time: 5 snapshots of an evolving synthetic flow (gridded model) as a cube
   along t, against the oracle's cube on the same snapshots.
 """
@@ -16,7 +18,7 @@ import numpy as np
 import pytest
 
 import art_inputs
-from gpu_helpers import rel_l2
+from gpu_helpers import ETA_FP64, ETA_MIXED, check_ties, nmse, rel_l2
 from oracle import ray as oray
 from oracle import spectral as osp
 
@@ -59,11 +61,9 @@ def test_spectral_cube_parity(art, all_planes):
     torch.cuda.synchronize()
     g = [i.cpu().numpy() for i in imgs]
     gl = [l.cpu().numpy() for l in levs]
-    o = oracle_cube(cfg, n0, L, sr)
-    flips = sum(int((a != b["level"]).sum()) for a, b in zip(gl, o))
-    if flips:
-        assert flips <= 2 * len(gl), flips
-        o = oracle_cube(cfg, n0, L, sr, forced=gl)
+    o = oracle_cube(cfg, n0, L, sr, forced=gl)
+    for i in range(len(gl)):
+        check_ties(o[i], gl[i], ETA_FP64, label=" (image %d)" % i)
     nspec = 0
     for i in range(len(g)):
         for s in range(4):
@@ -89,14 +89,23 @@ def test_negative_tolerance_is_plain_render(art):
 
 
 def test_mixed_precision_cube(art):
+    """Mixed-precision cube against the FP64 oracle: decisions off the
+    oracle's own rule only at reduced-precision ties, every plane of every
+    image within MSE 1e-3 of the oracle's replay and of its own cube."""
     print("CASE spectral mixed", flush=True)
     cfg = small_cfg()
-    a, _, _, s64 = art.render_spectral(cfg, NU[0], NU[1], 3, 2, 0.01, 1e-3)
-    b, _, _, s32 = art.render_spectral(dict(cfg, precision="mixed"), NU[0], NU[1], 3, 2, 0.01, 1e-3)
-    for x, y in zip(a, b):
+    sr = (0.01, 1e-3)
+    b, lv, _, s32 = art.render_spectral(dict(cfg, precision="mixed"), NU[0], NU[1], 3, 2, *sr)
+    gl = [l.cpu().numpy() for l in lv]
+    rep = oracle_cube(cfg, 3, 2, sr, forced=gl)
+    own = oracle_cube(cfg, 3, 2, sr)
+    for i, y in enumerate(b):
+        check_ties(rep[i], gl[i], ETA_MIXED, label=" (image %d)" % i)
+        y = y.cpu().numpy()
         for s in range(4):
-            if float(x[s].abs().max()) > 0:
-                assert art.metrics(x[s], y[s])[1] <= 1e-3
+            if np.abs(own[i]["img"][s]).max() > 0:
+                e1, e2 = nmse(y[s], rep[i]["img"][s]), nmse(y[s], own[i]["img"][s])
+                assert e1 <= 1e-3 and e2 <= 1e-3, (i, s, e1, e2)
 
 
 def test_spectral_cube_saves_rays(art):
@@ -138,11 +147,9 @@ def test_time_cube_parity(art):
         fn_k = lambda k: (lambda x, y: oray.trace(base, x, y, grid=grids[k])[0])
         return osp.render_cube(fn_k, base["fov"], base["nx0"], base["ny0"], base["levels"], base["r_rel"],
                                base["r_abs"], 3, 1, sr[0], sr[1], base["abs_norm"], 1, forced_levels=forced)
-    o = oracle()
-    flips = sum(int((a != b["level"]).sum()) for a, b in zip(gl, o))
-    if flips:
-        assert flips <= 2 * len(gl), flips
-        o = oracle(forced=gl)
+    o = oracle(forced=gl)
+    for k in range(len(gl)):
+        check_ties(o[k], gl[k], ETA_FP64, label=" (frame %d)" % k)
     for k in range(len(times)):
         assert rel_l2(g[k][0], o[k]["img"][0]) <= 1e-6, (k, rel_l2(g[k][0], o[k]["img"][0]))
         assert sts[k]["spectral"] == int((gl[k] == -3).sum())

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import art_inputs
-from gpu_helpers import rel_l2
+from gpu_helpers import ETA_FP64, check_ties, nmse, rel_l2
 from oracle import ray as oray
 from oracle import refine as oref
 
@@ -79,19 +79,22 @@ def test_subring_adaptive_render(art):
     fn = lambda x, y: oray.trace(cfg, x, y)[0]
     o = oref.refine(fn, cfg["fov"], 9, 9, 3, cfg["r_rel"], cfg["r_abs"], cfg["abs_norm"], 7,
                     forced_level=gl)
+    check_ties(o, gl, ETA_FP64)
     for s in range(7):
         if np.abs(o["img"][s]).max() > 0:
             assert rel_l2(g[s], o["img"][s]) <= 1e-6, (s, rel_l2(g[s], o["img"][s]))
 
 
 def test_subring_mixed_precision(art):
+    """Mixed-precision subring planes against the FP64 oracle's (uniform)."""
     print("CASE subring mixed", flush=True)
     cfg = dict(art_inputs.reduced(art_inputs.workload("thermal_1025"), 33, 1), nstokes=4, subrings=4)
-    g64, _, _ = art.render_uniform(cfg)
     g32, _, _ = art.render_uniform(dict(cfg, precision="mixed"))
-    for s in range(8):
-        if float(g64[s].abs().max()) > 0:
-            fe, mse = art.metrics(g64[s], g32[s])
-            assert mse <= 1e-3, (s, mse)
     a = g32.cpu().numpy()
+    truth = oref.uniform(lambda x, y: oray.trace(cfg, x, y)[0], cfg["fov"], 65, 65, 8)
+    for s in range(8):
+        if np.abs(truth[s]).max() > 0:
+            e = nmse(a[s], truth[s])
+            print("plane", s, "mse vs oracle", e, flush=True)
+            assert e <= 1e-3, (s, e)
     assert np.abs(a[4:].sum(0) - a[0]).max() <= 1e-5 * np.abs(a[0]).max()
