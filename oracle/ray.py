@@ -174,3 +174,43 @@ def plasma_point(cfg, alpha, beta, y, grid=None):
     out = np.zeros(11)
     ok = lib().or_plasma_point(ctypes.byref(p), float(alpha), float(beta), _dp(yy), _dp(out))
     return bool(ok), out[:4], out[4], out[5:8], out[8:11]
+
+
+_count_lib = None
+
+
+def count_ops(cfg, alpha, beta, grid=None):
+    """Operation counts of the oracle's rays through (alpha, beta), from its
+    instrumented build (opcount.cpp): structured array with steps, emitting
+    steps and the operations (+, -, *, /, sqrt and transcendental calls) of
+    the geodesic, of the plasma point (its non-emitting calls separately)
+    and of the transfer update."""
+    global _count_lib
+    if _count_lib is None:
+        L = ctypes.CDLL(_build.build_count())
+        L.or_count_ray.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
+        L.or_count_ray.restype = ctypes.c_int
+        L.or_count_probe.argtypes = [ctypes.c_int]
+        L.or_count_probe.restype = ctypes.c_longlong
+        _count_lib = L
+    p = make_params(cfg, grid)
+    alpha = np.atleast_1d(np.asarray(alpha, dtype=np.float64))
+    beta = np.atleast_1d(np.asarray(beta, dtype=np.float64))
+    dt = np.dtype([("steps", np.int64), ("emit", np.int64), ("geo", np.int64), ("plasma", np.int64),
+                   ("transfer", np.int64), ("plasma_noemit", np.int64), ("S", np.float64, 4)])
+    out = np.zeros(alpha.size, dtype=dt)
+    buf = np.zeros(6, dtype=np.int64)
+    sb = np.zeros(4)
+    for k in range(alpha.size):
+        _count_lib.or_count_ray(ctypes.byref(p), float(alpha[k]), float(beta[k]),
+                                buf.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _dp(sb))
+        out[k] = tuple(buf) + (sb.copy(),)
+    return out
+
+
+def count_probe(which):
+    """Operations the counter records for one oracle routine (0: a 4x4
+    matrix product, 1: the horizon radius)."""
+    count_ops({"a": 0.0, "r_cam": 1000.0, "inc_deg": 60.0, "model": "toy_disk"}, [], [])
+    return int(_count_lib.or_count_probe(int(which)))

@@ -44,6 +44,15 @@
 #include <string.h>
 #include <pthread.h>
 
+/* Operation-count categories (used only by the instrumented build,
+ * opcount.cpp): 0 geodesic, 1 plasma point, 2 transfer update. */
+#ifndef OR_CAT
+#define OR_CAT(c) ((void)0)
+#endif
+#ifndef OR_EMIT
+#define OR_EMIT(e) ((void)0)
+#endif
+
 /* ----------------------------------------------------------------- consts */
 #define OR_E      4.80320471e-10   /* electron charge [esu] */
 #define OR_ME     9.1093837015e-28 /* electron mass [g] */
@@ -829,7 +838,11 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
         double rm = 0.5 * (y[0] + yn[0]), thm = 0.5 * (y[1] + yn[1]), phm = 0.5 * (y[2] + yn[2]);
         double krm = 0.5 * (y[3] + yn[3]), kthm = 0.5 * (y[4] + yn[4]);
         double J[4], aI, av[3], rv[3];
-        if (plasma_point(p, rm, thm, phm, kt, kph, krm, kthm, &kap0, rh, risco, Eis, Lis, J, &aI, av, rv)) {
+        OR_CAT(1);
+        int emits = plasma_point(p, rm, thm, phm, kt, kph, krm, kthm, &kap0, rh, risco, Eis, Lis, J, &aI, av, rv);
+        OR_EMIT(emits);
+        if (emits) {
+            OR_CAT(2);
             double I0 = S[0];
             if (pol) {
                 transfer_step4(S, O, aI, av, rv, J, h);
@@ -844,6 +857,7 @@ static void trace_one(const or_params* p, double al, double be, double* S, ray_f
                 S[4 + n] += S[0] - I0;
             }
         }
+        OR_CAT(0);
         if (cos(y[1]) * cos(yn[1]) < 0.0) ncross++;
         if (y[4] * yn[4] < 0.0) nturn++;
         if (rec && nstep < rec_cap) {

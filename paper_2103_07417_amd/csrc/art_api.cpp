@@ -97,6 +97,11 @@ struct BatchGroup {
     hipEvent_t ev[2 * kMaxEv] = {};
     int nev = 0;                   // timed tracing launches of the last eager render
     CnnWork ws;                    // network workspace (learned renders)
+    // learned renders: the group-local images the network runs on at level l
+    // are imap[imap_off[l] .. imap_off[l] + nnet[l]) (device)
+    int* imap = nullptr;
+    int imap_off[kMaxLevels + 1] = {};
+    int nnet[kMaxLevels + 1] = {};
 };
 
 struct art_batch {
@@ -341,6 +346,8 @@ void free_batch_mem(art_batch* b)
             G.ev[k] = nullptr;
         }
         cnn_work_free(&G.ws);
+        if (G.imap) (void)hipFree(G.imap);
+        G.imap = nullptr;
         if (b->gs[g]) (void)hipStreamDestroy(b->gs[g]);
         b->gs[g] = nullptr;
         if (b->ev_join[g]) (void)hipEventDestroy(b->ev_join[g]);
@@ -629,7 +636,7 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
     int l = 0;
     while (l < N) {
         const bool ahead = any_with(l + 2);
-        const bool net_here = ahead || (o.all_levels && any_with(l + 1));
+        const bool net_here = G.nnet[l] > 0;
         const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
         if (!net_here) {
             HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s));
@@ -638,12 +645,16 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
             l += 1;
             continue;
         }
+        // the network only on the images it decides for at this level
         const int W = (int)grid_n(D0.nx0, l), H = (int)grid_n(D0.ny0, l);
-        HIP_TRY(cnn_features_batch(dD, ctr, G.n, l, H, W, G.ws.xf, s));
-        HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, G.ws.xf, G.n, H, W, G.ws.logits, s));
-        HIP_TRY(cnn_propose(G.ws.logits, dD, G.n, l, H, W, o.z_propose, o.z_suppress, o.all_levels, list, ctr,
-                            s));
-        HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 1, 1));
+        const int* im = G.imap + G.imap_off[l];
+        HIP_TRY(cnn_features_batch(dD, ctr, G.nnet[l], l, H, W, G.ws.xf, s, im));
+        HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, G.ws.xf, G.nnet[l], H, W, G.ws.logits, s));
+        HIP_TRY(cnn_propose(G.ws.logits, dD, G.nnet[l], l, H, W, o.z_propose, o.z_suppress, o.all_levels, list,
+                            ctr, s, im));
+        // mode 1: images the network decided for read its marks; the others
+        // (one level left, no all_levels) take the plain criterion
+        HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 1, o.all_levels ? 1 : 0));
         rc = trace_pass(b, g, l + 1, s);
         if (rc) return rc;
         if (ahead) {
@@ -761,16 +772,39 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
         if (!D.feat) return fail(ART_EINVAL, "image %d: learned renders need a feature buffer", i);
         nmax = D.levels > nmax ? D.levels : nmax;
     }
-    // largest level the network runs at (any image's)
-    int lmax = -1;
-    for (int l = 0; l < nmax; ++l)
-        if (l + 2 <= nmax || (opt->all_levels && l + 1 <= nmax)) lmax = l;
-    if (lmax >= 0) {
-        for (int g = 0; g < b->ngroups; ++g) {
-            const long long P = (long long)b->grp[g].n * grid_n(D0.nx0, lmax) * grid_n(D0.ny0, lmax);
-            if (P > (1LL << 28)) return fail(ART_EINVAL, "network grid of %lld positions too large", P);
-            int rc = cnn_work_reserve(&b->grp[g].ws, P);
+    // per group and level, the images the network decides for: those that
+    // can look two levels ahead (levels >= l + 2), with all_levels also those
+    // with one level left; the workspace holds the largest such set's grids
+    for (int g = 0; g < b->ngroups; ++g) {
+        BatchGroup& G = b->grp[g];
+        std::vector<int> h;
+        long long P = 0;
+        for (int l = 0; l <= kMaxLevels; ++l) {
+            G.imap_off[l] = (int)h.size();
+            G.nnet[l] = 0;
+            for (int i = 0; i < G.n; ++i) {
+                const int Li = b->hD[G.i0 + i].levels;
+                if (Li >= l + 2 || (opt->all_levels && Li >= l + 1)) {
+                    h.push_back(i);
+                    G.nnet[l]++;
+                }
+            }
+            if (G.nnet[l]) {
+                const long long Pl = (long long)G.nnet[l] * grid_n(D0.nx0, l) * grid_n(D0.ny0, l);
+                P = Pl > P ? Pl : P;
+            }
+        }
+        if (P > (1LL << 28)) return fail(ART_EINVAL, "network grid of %lld positions too large", P);
+        if (P > 0) {
+            int rc = cnn_work_reserve(&G.ws, P);
             if (rc) return rc;
+        }
+        if (G.imap) (void)hipFree(G.imap);
+        G.imap = nullptr;
+        if (!h.empty()) {
+            if (hipMalloc((void**)&G.imap, sizeof(int) * h.size()) != hipSuccess)
+                return fail(ART_ENOMEM, "hipMalloc(network image map) failed");
+            HIP_TRY(hipMemcpy(G.imap, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
         }
     }
     b->net = net;

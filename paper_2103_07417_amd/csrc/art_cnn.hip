@@ -1,6 +1,7 @@
 // art_cnn.hip -- learned refinement proposal: a 4-layer 3x3 convolutional
 // network (channels 3 -> 32 -> 32 -> 32 -> 15) run and trained with BF16 MFMA
-// (v_mfma_f32_32x32x8_bf16) and FP32 accumulation on gfx950.
+// (gfx950's v_mfma_f32_32x32x16_bf16: 32 x 32 outputs, depth 16 per
+// instruction) and FP32 accumulation.
 //
 // The network sees the level-l vertex grid of an adaptive render (log
 // intensity, minimum radius, equatorial crossings) and predicts, for every
@@ -10,9 +11,10 @@
 //
 // Layouts.  Activations are NHWC in BF16 with the channel count padded to a
 // multiple of 8 (input 3 -> 8, hidden 32, output gradient 15 -> 16), so a
-// lane's 4 consecutive reduction elements are one 8-byte load.  The GEMM
-// depth is ordered tap-major, k = (dy * 3 + dx) * C_pad + c, so one 8-wide
-// MFMA step reads 8 channels of one shifted position.  Logits are FP32 NCHW
+// lane's 8 consecutive reduction elements are one 16-byte load.  The GEMM
+// depth is ordered tap-major, k = (dy * 3 + dx) * C_pad + c, and cut into
+// 8-channel chunks; one 16-deep MFMA step takes two consecutive chunks, one
+// per half-wave (for 8 channels: two taps; a ninth tap is paired with zeros).  Logits are FP32 NCHW
 // ([b][15][H][W]) like labels.  Master weights stay FP32 in the order
 // W[c_out][c_in][3][3] and are packed into BF16 GEMM matrices after each
 // update.
@@ -32,7 +34,22 @@
 namespace art {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// D += A B on a 32 x 32 tile, depth 16: lane l supplies A[l % 32][8 (l / 32)
+// .. + 7] and B[8 (l / 32) .. + 7][l % 32]; D[8 (j / 4) + 4 (l / 32) + j % 4]
+// [l % 32] is element j of its accumulator.
+__device__ __forceinline__ floatx16 mfma16(shortx8 a, shortx8 b, floatx16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                   c, 0, 0, 0);
+}
+__device__ __forceinline__ shortx8 join8(bf16x4 lo, bf16x4 hi)
+{
+    return shortx8{ lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3] };
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -65,32 +82,27 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
     floatx16 acc;
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-    // operands of one tap (up to 32 channels = 4 MFMA steps) are loaded
-    // together, and the next tap's loads are issued before this tap's MFMAs,
-    // so a wave waits for one memory round trip per tap, not one per step
-    bf16x4 A[2][4], Bw[2][4];
-    auto load_tap = [&](int r, bf16x4* Ar, bf16x4* Br) {
-        const int yy = y + r / 3 - 1, xx = x + (r % 3) - 1;
-        const bool inside = x < W && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const long long so = inside ? ((long long)yy * W + xx) * cin_pad : 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            Ar[q] = bf16x4{ 0, 0, 0, 0 };
-            Br[q] = bf16x4{ 0, 0, 0, 0 };
-            if (8 * q < cin_pad) {
-                if (inside) Ar[q] = *(const bf16x4*)(inb + so + 8 * q + 4 * kb);
-                Br[q] = *(const bf16x4*)(Wm + (long long)m * Kp + r * cin_pad + 8 * q + 4 * kb);
-            }
+    // depth in 8-channel chunks, two per 16-deep step (one per half-wave);
+    // the next step's operands are loaded before this step's MFMA
+    const int nch = (9 * cin_pad) >> 3;
+    const int nst = (nch + 1) >> 1;
+    auto load = [&](int st, shortx8& a, shortx8& bw) {
+        const int ch = 2 * st + kb;
+        a = shortx8{ 0, 0, 0, 0, 0, 0, 0, 0 };
+        bw = a;
+        if (ch < nch) {
+            const int k0 = ch << 3, tap = k0 / cin_pad, c8 = k0 - tap * cin_pad;
+            const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+            if (x < W && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                a = *(const shortx8*)(inb + ((long long)yy * W + xx) * cin_pad + c8);
+            bw = *(const shortx8*)(Wm + (long long)m * Kp + k0);
         }
     };
-    load_tap(0, A[0], Bw[0]);
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-        if (r + 1 < 9) load_tap(r + 1, A[(r + 1) & 1], Bw[(r + 1) & 1]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (8 * q < cin_pad)
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[r & 1][q], Bw[r & 1][q], acc, 0, 0, 0);
+    shortx8 A[2], Bw[2];
+    load(0, A[0], Bw[0]);
+    for (int st = 0; st < nst; ++st) {
+        if (st + 1 < nst) load(st + 1, A[(st + 1) & 1], Bw[(st + 1) & 1]);
+        acc = mfma16(A[st & 1], Bw[st & 1], acc);
     }
     // D[row][col]: col = lane % 32 (output channel), row = 8 (j/4) + 4 (lane/32) + j%4
     const int oc = m;
@@ -193,15 +205,22 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict
     floatx16 acc;
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+    // 8-channel chunks of the tap-major depth, two per 16-deep step: this
+    // half-wave takes chunk 2 st + kb (a chunk past the depth is zero)
+    constexpr int NCH = KP / 8;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-        const int dy = r / 3, dx = r % 3;
-#pragma unroll
-        for (int c8 = 0; c8 < CIN; c8 += 8) {
-            const bf16x4 a = *(const bf16x4*)&a_s[(dy * 34 + m + dx) * CS + c8 + 4 * kb];
-            const bf16x4 bw = *(const bf16x4*)&sW[m * WS + r * CIN + c8 + 4 * kb];
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bw, acc, 0, 0, 0);
+    for (int st = 0; st < (NCH + 1) / 2; ++st) {
+        const int ch = 2 * st + kb;
+        const int tap = (8 * ch) / CIN, c8 = 8 * ch - tap * CIN;
+        const int dy = tap / 3, dx = tap - 3 * dy;
+        shortx8 a = shortx8{ 0, 0, 0, 0, 0, 0, 0, 0 }, bw = a;
+        if (ch < NCH) {
+            const uint16_t* pa = &a_s[(dy * 34 + m + dx) * CS + c8];
+            const uint16_t* pb = &sW[m * WS + 8 * ch];
+            a = join8(*(const bf16x4*)pa, *(const bf16x4*)(pa + 4));
+            bw = join8(*(const bf16x4*)pb, *(const bf16x4*)(pb + 4));
         }
+        acc = mfma16(a, bw, acc);
     }
     const int oc = m;
     if (mode == 1 && oc >= co) return;
@@ -227,12 +246,15 @@ hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, co
                         const float* bias, int co, int mode, void* out, const uint16_t* mask,
                         hipStream_t s)
 {
+    // the kernels read the depth in 8-channel chunks of at most 32 channels
+    if (cin_pad < 8 || cin_pad > 32 || (cin_pad & 7) || Kp != 9 * cin_pad || co < 1 || co > 32)
+        return hipErrorInvalidValue;
     const long long waves = (long long)B * H * ((W + 31) / 32);
     const long long blocks = (waves + 3) / 4;
-    if (cin_pad == 32 && Kp == 9 * 32)
+    if (cin_pad == 32)
         hipLaunchKernelGGL(k_conv_fwd_lds<32>, dim3((unsigned)blocks), dim3(256), 0, s, in, B, H, W, Wm, bias, co,
                            mode, out, mask);
-    else if (cin_pad == 8 && Kp == 9 * 8)
+    else if (cin_pad == 8)
         hipLaunchKernelGGL(k_conv_fwd_lds<8>, dim3((unsigned)blocks), dim3(256), 0, s, in, B, H, W, Wm, bias, co,
                            mode, out, mask);
     else
@@ -242,7 +264,7 @@ hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, co
 }
 
 // ------------------------------------------------------- weight gradients
-// Positions are split into nchunks chunks of clen (a multiple of 8); one wave
+// Positions are split into nchunks chunks of clen (a multiple of 16); one wave
 // per (chunk, 32-wide tile of the tap-major depth k = tap * cin_pad + c)
 // writes part[chunk][ktile][32 c_out][32 k].  A operand = dZ (rows = output
 // channel), B operand = im2col(in) (columns = k, 32 consecutive channels of
@@ -272,16 +294,16 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
     const int tap = k / cin_pad, c = k - tap * cin_pad;
     const bool kval = tap < 9 && c < ci;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    // (image, row, column) of the first position of each 8-position step
+    // (image, row, column) of the first position of each 16-position step
     int pb = (int)(p0 / HW);
     const long long q0 = p0 - (long long)pb * HW;
     int py = (int)(q0 / W), px = (int)(q0 - (long long)py * W);
     float sdb = 0.0f;                                // bias gradient partial (k tile 0 only)
-    for (long long ps = p0; ps < p1; ps += 8) {
-        bf16x4 a, bv;
+    for (long long ps = p0; ps < p1; ps += 16) {
+        shortx8 a, bv;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int o = 4 * kb + t;
+        for (int t = 0; t < 8; ++t) {
+            const int o = 8 * kb + t;
             const long long p = ps + o;
             short av = 0, bw = 0;
             if (p < p1) {
@@ -301,8 +323,8 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t* __restrict__ in
             a[t] = av;
             bv[t] = bw;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
-        px += 8;
+        acc = mfma16(a, bv, acc);
+        px += 16;
         while (px >= W) { px -= W; ++py; }
         while (py >= H) { py -= H; ++pb; }
     }
@@ -372,7 +394,7 @@ void dw_split(long long P, int& nchunks, long long& clen)
 {
     clen = 1024;
     if (P < 64LL * 1024) clen = (P + 63) / 64;
-    clen = (clen + 7) / 8 * 8;
+    clen = (clen + 15) / 16 * 16;
     if (clen < 64) clen = 64;
     nchunks = (int)((P + clen - 1) / clen);
 }
@@ -632,13 +654,14 @@ hipError_t cnn_features(const double* img, const RayFeat* feat, long long nx, in
 
 // Batched form: grid.y = image; N_abs = the image's level-0 normalisation.
 __global__ void k_cnn_features_batch(const ImageDesc* __restrict__ desc, const Counters* __restrict__ ctr,
-                                     int l, int H, int W, float* __restrict__ x)
+                                     int l, int H, int W, float* __restrict__ x, const int* __restrict__ imap)
 {
     const int b = blockIdx.y;
+    const int img = imap ? imap[b] : b;
     const long long HW = (long long)H * W;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= HW) return;
-    const ImageDesc& D = desc[b];
+    const ImageDesc& D = desc[img];
     float* xb = x + (long long)b * kCnnIn * HW;
     if (D.levels < l) {
         // an image of the batch with fewer levels: it has no level-l grid and
@@ -651,18 +674,18 @@ __global__ void k_cnn_features_batch(const ImageDesc* __restrict__ desc, const C
     const int s = 1 << (D.levels - l);
     const int j = (int)(t / W), i = (int)(t - (long long)j * W);
     float c0, c1, c2;
-    feature_at(D.img, D.feat, (long long)j * s * D.nx + (long long)i * s, ctr->scal[b][2], c0, c1, c2);
+    feature_at(D.img, D.feat, (long long)j * s * D.nx + (long long)i * s, ctr->scal[img][2], c0, c1, c2);
     xb[t] = c0;
     xb[HW + t] = c1;
     xb[2 * HW + t] = c2;
 }
 
 hipError_t cnn_features_batch(const ImageDesc* desc, const Counters* ctr, int nimg, int l, int H, int W,
-                              float* x, hipStream_t st)
+                              float* x, hipStream_t st, const int* imap)
 {
     const long long HW = (long long)H * W;
     hipLaunchKernelGGL(k_cnn_features_batch, dim3((unsigned)((HW + 255) / 256), nimg), dim3(256), 0, st, desc, ctr,
-                       l, H, W, x);
+                       l, H, W, x, imap);
     return hipGetLastError();
 }
 
@@ -721,10 +744,11 @@ __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ l
                                                      const ImageDesc* __restrict__ desc, int l, int H, int W,
                                                      float z_hi, float z_lo, int all_levels,
                                                      unsigned long long* __restrict__ list,
-                                                     Counters* __restrict__ ctr)
+                                                     Counters* __restrict__ ctr, const int* __restrict__ imap)
 {
-    const int b = blockIdx.y;
-    const ImageDesc& D = desc[b];
+    const int b = blockIdx.y;                 // slot of the logits
+    const int img = imap ? imap[b] : b;       // image of the batch
+    const ImageDesc& D = desc[img];
     const long long HW = (long long)H * W;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     // the network decides for this image only where it can look ahead (its
@@ -764,24 +788,25 @@ __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ l
         unsigned base = 0;
         if (lane == leader) {
             base = atomicAdd(&ctr->count[l + 1], n);
-            atomicAdd(&ctr->img_traced[b][l + 1], n);
-            atomicAdd(&ctr->judge[b][4], (unsigned long long)n);
+            atomicAdd(&ctr->img_traced[img][l + 1], n);
+            atomicAdd(&ctr->judge[img][4], (unsigned long long)n);
         }
         base = __shfl(base, leader);
         if (app) {
             const unsigned off = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-            list[base + off] = make_item((uint32_t)b, (uint32_t)pix);
+            list[base + off] = make_item((uint32_t)img, (uint32_t)pix);
         }
     }
 }
 
 hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int l, int H, int W, float z_hi,
-                       float z_lo, int all_levels, unsigned long long* list, Counters* ctr, hipStream_t s)
+                       float z_lo, int all_levels, unsigned long long* list, Counters* ctr, hipStream_t s,
+                       const int* imap)
 {
     const long long n = (long long)H * W * kCnnOut;
     hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((n + 255) / 256), nimg), dim3(256), 0, s, logits, desc, l, H,
-                       W, z_hi, z_lo, all_levels, list, ctr);
+                       W, z_hi, z_lo, all_levels, list, ctr, imap);
     return hipGetLastError();
 }
 

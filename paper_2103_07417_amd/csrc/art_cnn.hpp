@@ -21,7 +21,8 @@ constexpr int8_t kMarkUnset = -2;       // level map before a learned render dec
 // [B][H][W][cin_pad] BF16, Wm = packed forward matrix [32][9 * cin_pad].
 // mode 0: out bf16 NHWC32 = relu(conv + b); mode 1: out f32 NCHW [B][co][H][W]
 // = conv + b; mode 2: out bf16 NHWC32 = conv * (mask > 0), no bias (input
-// gradient through a ReLU).
+// gradient through a ReLU).  Returns hipErrorInvalidValue unless cin_pad is
+// 8, 16, 24 or 32, Kp == 9 * cin_pad and 1 <= co <= 32.
 hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, const uint16_t* Wm, int Kp,
                         const float* bias, int co, int mode, void* out, const uint16_t* mask,
                         hipStream_t s);
@@ -50,9 +51,10 @@ hipError_t cnn_input_bf16(const float* x, long long B, long long HW, uint16_t* y
 // grid of width nx) into x[3][H][W] (FP32).
 hipError_t cnn_features(const double* img, const RayFeat* feat, long long nx, int s, int H, int W,
                         double nabs, float* x, hipStream_t st);
-// Same for every image of a batch: x[b][3][H][W], N_abs from the counters.
+// Same for images of a batch: x[b][3][H][W] for image imap[b] (b < nimg; all
+// images in order if imap is null), N_abs from the counters.
 hipError_t cnn_features_batch(const ImageDesc* desc, const Counters* ctr, int nimg, int l, int H, int W,
-                              float* x, hipStream_t st);
+                              float* x, hipStream_t st, const int* imap = nullptr);
 // Labels of one plain render's level map at level l: lab/val[15][H][W].
 hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N, int l, uint8_t* lab,
                       uint8_t* val, hipStream_t s);
@@ -62,9 +64,10 @@ hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N
 // kMarkSuppress, all others kMarkUnset (every owned point is written).  An
 // image whose level count is l + 1 gets kMarkUnset everywhere unless
 // all_levels (the plain criterion decides its last level).
+// logits[b] belongs to image imap[b] (all images in order if imap is null).
 hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int l, int H, int W,
                        float z_hi, float z_lo, int all_levels, unsigned long long* list, Counters* ctr,
-                       hipStream_t s);
+                       hipStream_t s, const int* imap = nullptr);
 
 // Activation workspace of one forward pass over P = B * H * W positions.
 struct CnnWork {

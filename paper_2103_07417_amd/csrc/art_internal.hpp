@@ -114,7 +114,8 @@ hipError_t launch_spectral_base(const ImageDesc* desc, int img_off, int nimg, in
 // flags takes the spectral value where the rule along ln nu accepts it and is
 // traced otherwise.  mode 1: learned, level l -> l+1 (points marked
 // proposed are traced, points marked suppressed are interpolated, the
-// criterion decides the rest).  mode 2: learned, after a look-ahead pass
+// criterion decides the rest; `fallback` here means all_levels: without it
+// images with one level left carry no marks and take the criterion).  mode 2: learned, after a look-ahead pass
 // (points already traced are kept, suppressed points are interpolated, the
 // criterion decides the rest and its points are traced only if `fallback`).
 // Points whose neighbours needed at least `long_steps` geodesic steps are

@@ -375,7 +375,11 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
             spec = crit && spectral_ok(desc, D, pix, ctr);
             trace = crit && !spec;
         } else {
-            const int8_t mk = D.level[pix];
+            // mode 1: the network marked the images that can look ahead
+            // (levels >= l + 2), with all_levels (fallback = 1 here) also those
+            // with one level left; the others take the plain criterion
+            const bool marked = mode != 1 || D.levels >= l + 2 || fallback;
+            const int8_t mk = marked ? D.level[pix] : kMarkUnset;
             const bool sup = mk == kMarkSuppress;
             if (mode == 1) {
                 const bool prop = mk == kMarkPropose;

@@ -1,6 +1,7 @@
 """Host logic of the benchmark script (no GPU): the report is strict JSON,
 the measured HBM traffic is reported only for the kernel sources and the
-headline form it was counted on, and the FLOP count of one step adds up."""
+headline form it was counted on, the operation count of a render adds up,
+and the operating points and timed forms follow the held-out protocol."""
 import json
 import math
 
@@ -16,6 +17,9 @@ def test_report_is_strict_json():
 
 def test_traffic_only_for_profiled_sources_and_form():
     t = bench.TRAFFIC
+    if t is None:
+        assert bench.measured_traffic(8, "learned_batched") is None
+        return
     launches = 8
     got = bench.measured_traffic(launches, t["form"])
     if t["kernel_hash"] == bench.kernel_hash():
@@ -27,17 +31,20 @@ def test_traffic_only_for_profiled_sources_and_form():
     assert bench.measured_traffic(0, t["form"]) is None
 
 
-def test_flop_count_of_a_step():
+def test_flop_count_of_a_render():
     cfg = {"model": "thermal", "nstokes": 4}
     st = {"steps": 10, "steps_emit": 4}
-    want = 10 * bench.FLOP_GEO_STEP + 4 * (bench.FLOP_PLASMA_THERMAL + bench.FLOP_TRANSFER_IQUV)
+    want = 10 * bench.FLOP_GEO_STEP + 4 * (bench.FLOP_PLASMA_THERMAL + bench.FLOP_TRANSFER_IQUV) + \
+        6 * bench.FLOP_PLASMA_NOEMIT
     assert bench.flops(st, cfg) == want
+    s = bench.FLOP_STRUCTURED
+    assert bench.flops(st, cfg, dict(s, noemit=0)) == 10 * s["geo"] + 4 * (s["plasma"] + s["transfer_iquv"])
     assert bench.flops(st, {"model": "toy_disk", "nstokes": 1}) == 10 * bench.FLOP_GEO_STEP + 4 * (
         bench.FLOP_PLASMA_TOY + bench.FLOP_TRANSFER_I)
 
 
 def test_search_grids():
-    assert list(bench.OP_RREL) == sorted(bench.OP_RREL) and bench.OP_RREL[0] == 0.01
+    assert list(bench.OP_RREL) == sorted(bench.OP_RREL) and bench.OP_RREL[0] == 0.001
     assert all(1 <= d <= 4 for d in bench.IN_FLIGHT_DEPTHS)
 
 
@@ -53,10 +60,30 @@ def test_operating_points_pick_the_loosest_passing_tolerance():
     op = bench.operating_points(search, forms)
     assert op["plain"]["r_rel"] == 0.01 and op["lookahead_z4"]["r_rel"] == 0.015
     assert op["lookahead_z4"]["options"] == {"z_propose": 4.0}
-    extra = bench.forms_to_time(op, 0.01)
-    assert [n for n, _ in extra] == ["learned_batched_op"] and extra[0][1]["rays"] == 97
-    # a plain operating point looser than the workload's tolerance is timed too
-    op2 = bench.operating_points(search + [dict(form="plain", r_rel=0.0125, rays=98, ok=True)], forms)
-    assert [n for n, _ in bench.forms_to_time(op2, 0.01)] == ["plain_batched_op", "learned_batched_op"]
     # a form that never passes has no operating point
     assert "x" not in bench.operating_points([dict(form="x", r_rel=0.01, rays=1, ok=False)], [("x", None)])
+
+
+def test_forms_timed_follow_the_held_out_choice():
+    grid = (0.001, 0.005, 0.01)
+    op_h = {"lookahead_z0": dict(r_rel=0.005, rays=120), "lookahead_z4": dict(r_rel=0.005, rays=100),
+            "plain": dict(r_rel=0.001, rays=130)}
+    op_t = {"plain": dict(r_rel=0.01, rays=90)}
+    got = bench.choose_forms(op_h, op_t, grid)
+    assert [(n, f, r) for n, f, r, _ in got] == [("learned_batched", "lookahead_z4", 0.005),
+                                                 ("plain_batched", "plain", 0.001),
+                                                 ("plain_batched_own_op", "plain", 0.01)]
+    # no held-out operating point for plain: its tightest grid tolerance
+    got = bench.choose_forms({"lookahead_z4": dict(r_rel=0.005, rays=100)}, {"plain": dict(r_rel=0.001)}, grid)
+    assert [(n, r) for n, _, r, _ in got] == [("learned_batched", 0.005), ("plain_batched", 0.001)]
+    assert "tightest" in got[1][3]
+
+
+def test_one_gpu_only(monkeypatch, capsys):
+    import sys
+    import pytest
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
+    with pytest.raises(SystemExit) as e:
+        bench.main()
+    assert e.value.code == 2
+    assert "one GPU" in capsys.readouterr().err
