@@ -276,46 +276,48 @@ def test_uneven_batch_image_error(art, uneven):
 
 
 # --------------------------------------------------------------------------
-# What the trained network gains at the 0.1 % bar on the 64-image batch: the
-# plain criterion passes only at R_rel = 0.01 of the grid {0.01, 0.0125,
-# 0.015}; the look-ahead form (proposal threshold z = 4, criterion as
-# fallback) passes at R_rel = 0.015 with fewer traced rays than the plain
-# criterion at 0.01.
+# What the trained network gains at the 0.1 % bar, with the benchmark's
+# held-out protocol: on the held-out batch (other spins, inclinations and
+# field phases, the same structure as the uneven batch) the plain criterion
+# misses the bar even at the grid's tightest R_rel (one image keeps an error
+# floor: features the base grid does not see), while the look-ahead form
+# (proposal threshold z = 4, criterion as fallback) passes at R_rel = 0.005;
+# applied unchanged to the uneven batch it passes there too.
 
 def test_learned_operating_point_gain(art):
     from paper_2103_07417_amd import learn
     import bench
-    print("CASE learned operating point", flush=True)
+    print("CASE learned operating point (held-out protocol)", flush=True)
     S = art.Stream()
     s = S.torch
     net, _ = learn.train(art_inputs.training_workload(precision="mixed"), steps=300, lr=3e-3, seed=4, stream=s)
-    cfgs = art_inputs.batch_workload_1025(precision="mixed")
-    truths = []
-    for c in cfgs:
-        t, _, _ = art.render_uniform(c, stream=s)
-        truths.append(t[0].clone())
-    s.synchronize()
     res = {}
-    for rr in (0.01, 0.0125, 0.015):
-        c_rr = [dict(c, r_rel=rr) for c in cfgs]
-        B = art.Batch(c_rr, feat=True)
-        for form in ("plain", "lookahead"):
+    for name, cfgs in (("heldout", art_inputs.batch_workload_heldout(precision=UNEVEN_PRECISION)),
+                       ("timed", art_inputs.batch_workload(precision=UNEVEN_PRECISION))):
+        truths = []
+        for c in cfgs:
+            t, _, _ = art.render_uniform(c, stream=s)
+            truths.append(t.clone())
+            del t
+        s.synchronize()
+        for form, rr in (("plain", min(bench.OP_RREL)), ("lookahead", 0.005)):
+            B = art.Batch([dict(c, r_rel=rr) for c in cfgs], feat=True)
             if form == "plain":
                 B.set_learned(None)
             else:
                 B.set_learned(net, z_propose=4.0, z_suppress=-float("inf"), fallback=True)
             B.render(s)
             st = B.stats(stream=s)
-            chk = bench.mse_check(art, c_rr, B.images, truths)
-            res[(form, rr)] = (st["rays"], chk["mse_max"], chk["mse_ok"])
-            print(form, rr, res[(form, rr)], flush=True)
-        B.close()
+            chk = bench.mse_check(art, cfgs, B.images, truths)
+            res[(name, form)] = (st["rays"], chk["mse_max"], chk["mse_ok"], chk["worst"])
+            print(name, form, rr, res[(name, form)], flush=True)
+            B.close()
+        del truths
     net.close()
     S.close()
-    assert res[("plain", 0.01)][2]
-    assert not res[("plain", 0.0125)][2] and not res[("plain", 0.015)][2]
-    assert res[("lookahead", 0.015)][2]
-    assert res[("lookahead", 0.015)][0] < res[("plain", 0.01)][0]
+    assert not res[("heldout", "plain")][2]
+    assert res[("heldout", "lookahead")][2]
+    assert res[("timed", "lookahead")][2] and res[("timed", "plain")][2]
 
 
 # --------------------------------------------------------------------------
