@@ -210,6 +210,25 @@ int art_render(const art_spacetime* sp, const art_camera* cam, const art_emissio
                const art_refine* rf, const art_transfer* tr, art_image* out,
                art_stats* st, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * adaptive render as art_render, with the trace list, cost map, counters,
+ * parameter block, descriptor and theta table in a static device array of
+ * the library (about 42 MB, held by each device the library runs on until
+ * the process ends) instead of library allocations.  Images of at most
+ * 2049 x 2049 pixels (any base grid and level count reaching at most that);
+ * larger ones return ART_EINVAL before any device work.  Calls no hipMalloc,
+ * hipFree, stream or event creation; the first call on a device looks up its
+ * array's address.  The caller still owns and passes the image, level-map
+ * and feature buffers.  Every call on one device shares that device's array
+ * and leaves its contents behind (the counters are cleared at the start of
+ * each render): calls that overlap on one device, on any streams, race.
+ * Statistics as art_render, except that t_trace_ms, t_render_ms and
+ * trace-launch timing are not recorded (0). */
+int art_render_noalloc(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                       const art_refine* rf, const art_transfer* tr, art_image* out,
+                       art_stats* st, void* stream);
+
 /* Uniform render: one ray per vertex of the camera's final grid (the "truth"
  * image of Sec. 4.1).  The level map, if given, is set to 0 everywhere. */
 int art_render_uniform(const art_spacetime* sp, const art_camera* cam, const art_emission* em,

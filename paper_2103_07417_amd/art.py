@@ -120,6 +120,8 @@ def lib():
                                      P(ctypes.c_int32), P(ctypes.c_size_t)]
         L.art_render.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine), P(Transfer),
                                  P(Image), P(Stats), vp]
+        L.art_render_noalloc.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine), P(Transfer),
+                                         P(Image), P(Stats), vp]
         L.art_render_uniform.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Transfer),
                                          P(Image), P(Stats), vp]
         L.art_trace_points.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Transfer), i64,
@@ -265,6 +267,22 @@ def render(cfg, out=None, feat=False, stats=True, stream=None):
     rc = lib().art_render(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em), ctypes.byref(rf),
                           ctypes.byref(tr), ctypes.byref(im),
                           ctypes.byref(st) if stats else None, _stream(torch, stream))
+    _check(rc)
+    return img, lev, ft, (stats_dict(st) if stats else None)
+
+
+def render_noalloc(cfg, out, stats=True, stream=None):
+    """Adaptive render through the entry point that allocates nothing (the
+    library's static scratch; images up to 2049^2).  `out` = (image, level,
+    feat or None), caller-allocated.  Returns (image, level, feat, stats)."""
+    torch = _torch()
+    sp, cam, em, rf, tr = blocks(cfg)
+    img, lev, ft = out
+    im = _image(img, lev, ft)
+    st = Stats()
+    rc = lib().art_render_noalloc(ctypes.byref(sp), ctypes.byref(cam), ctypes.byref(em), ctypes.byref(rf),
+                                  ctypes.byref(tr), ctypes.byref(im),
+                                  ctypes.byref(st) if stats else None, _stream(torch, stream))
     _check(rc)
     return img, lev, ft, (stats_dict(st) if stats else None)
 

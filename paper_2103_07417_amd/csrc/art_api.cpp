@@ -136,6 +136,8 @@ struct art_batch {
     int cus = 0;
     art_cnn* net = nullptr;        // learned renders when set
     art_learned lopt{};
+    bool fixed_mem = false;        // buffers live in the library's static scratch: never (re)allocated
+    Counters* hstat = nullptr;     // host buffer for statistics (no per-call allocation), or null
     int cube_n0 = 0;               // axis-sampled cube (cube_levels >= 0): base images
     int cube_levels = -1;          // refinements along the axis (-1: not a cube)
     std::vector<int> cube_perm;    // internal index -> axis index
@@ -374,6 +376,10 @@ void free_batch_mem(art_batch* b)
 // Grow-only device buffers of a batch.
 int ensure_mem(art_batch* b, size_t list_need)
 {
+    if (b->fixed_mem)
+        return list_need > b->list_cap ? fail(ART_EINVAL, "%zu pixels exceed the static scratch (%zu pixels)",
+                                              list_need, b->list_cap)
+                                       : ART_OK;
     if (!b->ctr) {
         if (hipMalloc(&b->ctr, sizeof(Counters) * kMaxGroups) != hipSuccess)
             return fail(ART_ENOMEM, "hipMalloc(counters) failed");
@@ -418,7 +424,8 @@ int default_groups(int n)
 // group's slice of the trace list and upload the descriptors.
 int layout(art_batch* b, hipStream_t s)
 {
-    int G = (b->uniform || b->spectral) ? 1 : (b->req_groups > 0 ? b->req_groups : default_groups(b->n));
+    int G = (b->uniform || b->spectral || b->fixed_mem) ? 1
+                                                        : (b->req_groups > 0 ? b->req_groups : default_groups(b->n));
     if (G > b->n) G = b->n;
     if (G > kMaxGroups) G = kMaxGroups;
     b->ngroups = G;
@@ -835,8 +842,13 @@ int enqueue_uniform(art_batch* b, hipStream_t s)
 // Step counts and the status histogram are batch-wide.
 int batch_stats(art_batch* b, int i, art_stats* st, hipStream_t s)
 {
-    std::vector<Counters> h(b->ngroups);
-    HIP_TRY(hipMemcpyAsync(h.data(), b->ctr, sizeof(Counters) * b->ngroups, hipMemcpyDeviceToHost, s));
+    std::vector<Counters> hv;
+    Counters* h = b->hstat;
+    if (!h) {
+        hv.resize(b->ngroups);
+        h = hv.data();
+    }
+    HIP_TRY(hipMemcpyAsync(h, b->ctr, sizeof(Counters) * b->ngroups, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::memset(st, 0, sizeof(*st));
     long long npix = 0, traced = 0;
@@ -900,6 +912,59 @@ int batch_stats(art_batch* b, int i, art_stats* st, hipStream_t s)
 art_batch g_single[64];
 std::mutex g_single_mu;
 
+// ---------------------------------------------------------------- scratch
+// Static device scratch of art_render_noalloc: counters, parameter block,
+// image descriptor and theta table of one image group, then the trace list
+// (8 B per pixel) and the cost map (2 B per pixel) of an image of at most
+// kNoAllocPixels pixels (2049^2: the largest image of the batched workload).
+// Each device holds its own copy from module load to process exit.
+constexpr size_t kNoAllocPixels = 2049ull * 2049ull;
+constexpr size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaCtr = 0;
+constexpr size_t kNaPar = kNaCtr + round256(sizeof(Counters));
+constexpr size_t kNaDesc = kNaPar + round256(sizeof(Params));
+constexpr size_t kNaTheta = kNaDesc + round256(sizeof(ImageDesc));
+constexpr size_t kNaList = kNaTheta + round256(sizeof(double) * kMaxThetaCells);
+constexpr size_t kNaCost = kNaList + round256(sizeof(unsigned long long) * kNoAllocPixels);
+constexpr size_t kNoAllocBytes = kNaCost + round256(sizeof(uint16_t) * kNoAllocPixels);
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocState {
+    bool ready = false;
+    unsigned char* ptr = nullptr;  // device address of this device's scratch
+    art_batch b;
+    Counters hstat;
+};
+NoAllocState g_noalloc[64];
+std::mutex g_noalloc_mu;
+
+// Set-up on the first call on a device (that device current): the scratch's
+// device address, the batch's fixed buffers, host vectors reserved.
+int noalloc_setup(NoAllocState& N, int dev)
+{
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(ART_EDEVICE, "no address for the static scratch on device %d", dev);
+    N.ptr = (unsigned char*)ptr;
+    art_batch& b = N.b;
+    b.dev = dev;
+    HIP_TRY(hipDeviceGetAttribute(&b.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b.ctr = (Counters*)(N.ptr + kNaCtr);
+    b.dP = (Params*)(N.ptr + kNaPar);
+    b.dD = (ImageDesc*)(N.ptr + kNaDesc);
+    b.dTh = (double*)(N.ptr + kNaTheta);
+    b.list = (unsigned long long*)(N.ptr + kNaList);
+    b.cost = (uint16_t*)(N.ptr + kNaCost);
+    b.list_cap = kNoAllocPixels;
+    b.fixed_mem = true;
+    b.hstat = &N.hstat;
+    b.hP.reserve(1);
+    b.hD.reserve(1);
+    N.ready = true;
+    return ART_OK;
+}
+
 art_batch* single_batch()
 {
     int dev = 0;
@@ -955,6 +1020,37 @@ int art_render(const art_spacetime* sp, const art_camera* cam, const art_emissio
     rc = enqueue_render(b, s);
     if (rc) return rc;
     if (st) return batch_stats(b, 0, st, s);
+    return ART_OK;
+}
+
+int art_render_noalloc(const art_spacetime* sp, const art_camera* cam, const art_emission* em,
+                       const art_refine* rf, const art_transfer* tr, art_image* out, art_stats* st,
+                       void* stream)
+{
+    if (!sp || !cam || !em || !rf || !tr || !out) return fail(ART_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(ART_EDEVICE, "no current device");
+    NoAllocState& N = g_noalloc[dev];
+    if (!N.ready) {
+        int rc = noalloc_setup(N, dev);
+        if (rc) return rc;
+    }
+    int32_t nx, ny;
+    int rc = grid_size(cam, tr->nstokes, &nx, &ny);
+    if (rc) return rc;
+    if ((size_t)nx * (size_t)ny > kNoAllocPixels)
+        return fail(ART_EINVAL, "%d x %d image exceeds the no-allocation limit of %zu pixels", nx, ny,
+                    kNoAllocPixels);
+    hipStream_t s = (hipStream_t)stream;
+    const art_job j = make_job(sp, cam, em, rf, tr);
+    rc = prepare(&N.b, 1, &j, out, false, s);
+    if (rc) return rc;
+    N.b.timing = false;
+    N.b.net = nullptr;
+    rc = enqueue_render(&N.b, s);
+    if (rc) return rc;
+    if (st) return batch_stats(&N.b, 0, st, s);
     return ART_OK;
 }
 
