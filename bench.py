@@ -67,6 +67,7 @@ FLOP_PLASMA_TOY = 176
 # GPU actually executes, reported beside the algorithmic figure.
 FLOP_STRUCTURED = dict(geo=381, plasma=390, transfer_iquv=639)
 PEAK_VECTOR = 78.6e12        # MI355X FP64 vector peak = its unpacked FP32 rate (no packed FP32 here)
+PEAK_FP64_MATRIX = 78.6e12   # MI355X FP64 matrix (MFMA) peak: the visibility stages
 COPY_BYTES = 256 << 20       # read and written once by the calibration copy
 ROOF_RENDERS = 2             # eager renders of the headline form timed for the roofline
 # Algorithmic HBM bytes per traced ray of the thermal model: the list item
@@ -609,7 +610,7 @@ def deploy_visibility(art, torch, art_inputs, cfg, img, truth):
         pr = img[pl].sum(dim=0).cpu().numpy()
         d_img.append(float(xg[np.argmax(np.where(xg > 0, pr, -1.0))] - xg[np.argmax(np.where(xg < 0, pr, -1.0))]))
     res = dict(window_glambda=1000.0, nu=nu, nv=nv, planes=P, taper_fwhm=fov / 4, ms=ms,
-               tflops=flops / ms / 1e9, frac_fp64_peak=flops / ms / 1e9 / (PEAK_FP64_VECTOR / 1e12),
+               tflops=flops / ms / 1e9, frac_fp64_peak=flops / ms / 1e9 / (PEAK_FP64_MATRIX / 1e12),
                residual_ratio_median=q[0], residual_ratio_p99=q[1],
                residual_ratio_u_axis_max=float((Vr.abs()[k] / Vt.abs()[k]).max()),
                u_axis_samples_glambda=[0, 100, 250, 500, 1000],

@@ -44,7 +44,7 @@ extern "C" {
 
 #define ART_OK        0
 #define ART_EINVAL   -1   /* invalid argument (|a| >= 1, n0 < 2, fov <= 0, ...) */
-#define ART_ENOMEM   -2   /* device allocation failed */
+#define ART_ENOMEM   -2   /* device allocation failed, or above the allocation limit */
 #define ART_EDEVICE  -3   /* HIP runtime error */
 #define ART_ENUMERIC -4   /* a NaN reached the image (rays flagged in features) */
 
@@ -285,6 +285,13 @@ int art_batch_stats(art_batch* b, int32_t i, art_stats* st, void* stream);
 
 /* Free the batch (after synchronising the device). */
 int art_batch_destroy(art_batch* b);
+
+/* Upper bound on the device memory one render or batch may allocate for its
+ * trace list and cost map (10 bytes per pixel of the batch; 0 = no bound, the
+ * default).  A render or batch set-up that would need more returns ART_ENOMEM
+ * and leaves earlier buffers in place; buffers already allocated are kept.
+ * Process-wide, applies to later calls. */
+int art_set_alloc_limit(size_t bytes);
 
 /* ------------------------------------------------------- launch configuration
  * Persistent-tracer launch shape: grid size, threads per block (64, 128 or

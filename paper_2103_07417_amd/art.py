@@ -122,6 +122,7 @@ def lib():
                                  P(Image), P(Stats), vp]
         L.art_render_noalloc.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Refine), P(Transfer),
                                          P(Image), P(Stats), vp]
+        L.art_set_alloc_limit.argtypes = [ctypes.c_size_t]
         L.art_render_uniform.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Transfer),
                                          P(Image), P(Stats), vp]
         L.art_trace_points.argtypes = [P(Spacetime), P(Camera), P(Emission), P(Transfer), i64,
@@ -269,6 +270,12 @@ def render(cfg, out=None, feat=False, stats=True, stream=None):
                           ctypes.byref(st) if stats else None, _stream(torch, stream))
     _check(rc)
     return img, lev, ft, (stats_dict(st) if stats else None)
+
+
+def set_alloc_limit(nbytes):
+    """Bound the trace-list + cost-map allocation of later renders and batch
+    set-ups (bytes; 0 = no bound)."""
+    _check(lib().art_set_alloc_limit(int(nbytes)))
 
 
 def render_noalloc(cfg, out, stats=True, stream=None):

@@ -75,6 +75,7 @@ int env_int(const char* name, int dflt)
 }
 
 art_launch g_launch = { 0, 0, 0, 0 };   // user override (0 = default)
+size_t g_list_limit = 0;                // bytes a trace list + cost map may take (0: no limit)
 std::mutex g_mu;
 
 constexpr int kMaxEv = 64;   // timed tracing launches per group and render
@@ -396,6 +397,15 @@ int ensure_mem(art_batch* b, size_t list_need)
         HIP_TRY(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev));
     }
     if (list_need > b->list_cap) {
+        size_t limit;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            limit = g_list_limit;
+        }
+        const size_t bytes = list_need * (sizeof(unsigned long long) + sizeof(uint16_t));
+        if (limit && bytes > limit)
+            return fail(ART_ENOMEM, "trace list and cost map of %zu pixels need %zu bytes (allocation limit %zu)",
+                        list_need, bytes, limit);
         if (b->list || b->cost) {
             HIP_TRY(hipDeviceSynchronize());
             if (b->list) HIP_TRY(hipFree(b->list));
@@ -1362,6 +1372,13 @@ int art_batch_destroy(art_batch* b)
     (void)hipDeviceSynchronize();
     free_batch_mem(b);
     delete b;
+    return ART_OK;
+}
+
+int art_set_alloc_limit(size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_list_limit = bytes;
     return ART_OK;
 }
 
