@@ -103,6 +103,8 @@ struct BatchGroup {
     int* imap = nullptr;
     int imap_off[kMaxLevels + 1] = {};
     int nnet[kMaxLevels + 1] = {};
+    // the group-local images that have a level l+1 are emap(g, l)[0 .. nest[l])
+    int nest[kMaxLevels + 1] = {};
 };
 
 struct art_batch {
@@ -137,6 +139,8 @@ struct art_batch {
     int cus = 0;
     art_cnn* net = nullptr;        // learned renders when set
     art_learned lopt{};
+    int* emap = nullptr;           // device [group][level][image]: images an estimator pass concerns
+    int hemap[kMaxGroups][kMaxLevels + 1][kMaxBatch] = {};
     bool fixed_mem = false;        // buffers live in the library's static scratch: never (re)allocated
     Counters* hstat = nullptr;     // host buffer for statistics (no per-call allocation), or null
     int cube_n0 = 0;               // axis-sampled cube (cube_levels >= 0): base images
@@ -362,6 +366,8 @@ void free_batch_mem(art_batch* b)
         if (b->ev_render[k]) (void)hipEventDestroy(b->ev_render[k]);
         b->ev_render[k] = nullptr;
     }
+    if (b->emap) (void)hipFree(b->emap);
+    b->emap = nullptr;
     if (b->list) (void)hipFree(b->list);
     if (b->cost) (void)hipFree(b->cost);
     b->cost = nullptr;
@@ -387,6 +393,7 @@ int ensure_mem(art_batch* b, size_t list_need)
         if (hipMalloc(&b->dP, sizeof(Params) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(params) failed");
         if (hipMalloc(&b->dD, sizeof(ImageDesc) * kMaxBatch) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(descs) failed");
         if (hipMalloc(&b->dTh, sizeof(double) * kMaxThetaCells) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(theta table) failed");
+        if (hipMalloc(&b->emap, sizeof(b->hemap)) != hipSuccess) return fail(ART_ENOMEM, "hipMalloc(image maps) failed");
         for (int g = 0; g < kMaxGroups; ++g)
             for (int k = 0; k < 2 * kMaxEv; ++k) HIP_TRY(hipEventCreate(&b->grp[g].ev[k]));
         HIP_TRY(hipEventCreate(&b->ev_render[0]));
@@ -462,7 +469,15 @@ int layout(art_batch* b, hipStream_t s)
             off += (size_t)D.plane;
         }
         Gr.list_len = off - off0;
+        for (int l = 0; l <= kMaxLevels; ++l) {
+            Gr.nest[l] = 0;
+            for (int k = 0; k < Gr.n; ++k)
+                if (b->hD[Gr.i0 + k].levels > l) b->hemap[g][l][Gr.nest[l]++] = k;
+        }
     }
+    if (b->emap)
+        HIP_TRY(hipMemcpyAsync(b->emap, b->hemap, sizeof(int) * kMaxBatch * (kMaxLevels + 1) * G,
+                               hipMemcpyHostToDevice, s));
     for (int g = 1; g < G; ++g)
         if (!b->gs[g]) HIP_TRY(hipStreamCreateWithFlags(&b->gs[g], hipStreamNonBlocking));
     HIP_TRY(hipMemcpyAsync(b->dD, b->hD.data(), sizeof(ImageDesc) * b->n, hipMemcpyHostToDevice, s));
@@ -549,6 +564,19 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
     return layout(b, s);
 }
 
+// Images of group g that have level l+1 (device map) and their number; a
+// batch without maps (static scratch) launches over all its images.
+const int* est_map(const art_batch* b, int g, int l, int& n)
+{
+    const BatchGroup& G = b->grp[g];
+    if (!b->emap) {
+        n = G.n;
+        return nullptr;
+    }
+    n = G.nest[l];
+    return b->emap + ((size_t)g * (kMaxLevels + 1) + l) * kMaxBatch;
+}
+
 TraceJob base_job(const art_batch* b, int g, int level)
 {
     const BatchGroup& G = b->grp[g];
@@ -616,8 +644,10 @@ int enqueue_adaptive(art_batch* b, int g, hipStream_t s)
     if (rc) return rc;
     for (int l = 0; l < G.lmax; ++l) {
         const int nxl = (int)grid_n(G.nx0m, l + 1), nyl = (int)grid_n(G.ny0m, l + 1);
-        HIP_TRY(launch_estimate(b->dD + G.i0, G.n, nxl, nyl, l, b->ctr + g, b->list + G.list_off,
-                                (long long)G.list_len, b->L.long_steps, s));
+        int ne;
+        const int* em = est_map(b, g, l, ne);
+        HIP_TRY(launch_estimate(b->dD + G.i0, ne, nxl, nyl, l, b->ctr + g, b->list + G.list_off,
+                                (long long)G.list_len, b->L.long_steps, s, 0, 1, 0, -1, em));
         rc = trace_pass(b, g, l + 1, s);
         if (rc) return rc;
     }
@@ -656,7 +686,9 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         const bool net_here = G.nnet[l] > 0;
         const int nxl = (int)grid_n(D0.nx0, l + 1), nyl = (int)grid_n(D0.ny0, l + 1);
         if (!net_here) {
-            HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s));
+            int ne;
+            const int* em = est_map(b, g, l, ne);
+            HIP_TRY(launch_estimate(dD, ne, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 0, 1, 0, -1, em));
             rc = trace_pass(b, g, l + 1, s);
             if (rc) return rc;
             l += 1;
@@ -671,13 +703,18 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
                             ctr, s, im));
         // mode 1: images the network decided for read its marks; the others
         // (one level left, no all_levels) take the plain criterion
-        HIP_TRY(launch_estimate(dD, G.n, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 1, o.all_levels ? 1 : 0));
+        int ne;
+        const int* em = est_map(b, g, l, ne);
+        HIP_TRY(launch_estimate(dD, ne, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 1, o.all_levels ? 1 : 0, 0,
+                                -1, em));
         rc = trace_pass(b, g, l + 1, s);
         if (rc) return rc;
         if (ahead) {
             const int nx2 = (int)grid_n(D0.nx0, l + 2), ny2 = (int)grid_n(D0.ny0, l + 2);
-            HIP_TRY(launch_estimate(dD, G.n, nx2, ny2, l + 1, ctr, list, cap, b->L.long_steps, s, 2,
-                                    o.fallback ? 1 : 0));
+            int ne2;
+            const int* em2 = est_map(b, g, l + 1, ne2);
+            HIP_TRY(launch_estimate(dD, ne2, nx2, ny2, l + 1, ctr, list, cap, b->L.long_steps, s, 2,
+                                    o.fallback ? 1 : 0, 0, -1, em2));
             if (o.fallback) {
                 rc = trace_pass(b, g, l + 2, s);
                 if (rc) return rc;

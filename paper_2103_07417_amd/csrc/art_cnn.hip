@@ -125,14 +125,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
     }
 }
 
-// The same convolution with its operands staged in LDS (CIN = 8 or 32): the
-// block's four waves copy the weight matrix once ([32][9 CIN], rows padded by
-// 4) and each wave its 3 x 34 input halo (rows y-1..y+1, zero outside the
-// image, positions padded by 4 channels), every staging load issued before
-// the first LDS store; the nine taps then read LDS.  Scattered 8-byte global
-// reads of one cache line per lane (the plain kernel's A and B operands) are
-// what limits the plain kernel.  Halo lanes of the last tile beyond the image
-// width produce output rows that are discarded.
+// The same convolution with its operands staged in LDS (CIN = 8 or 32).  A
+// block of four waves copies the weight matrix once ([32][9 CIN], rows padded
+// by 4) and then walks kConvTiles rounds of four consecutive 32-position
+// tiles, one per wave: each wave stages its tile's 3 x 34 input halo (rows
+// y-1..y+1, zero outside the image, positions padded by 4 channels) and runs
+// the nine taps from LDS.  The next round's halo is loaded into registers
+// before this round's MFMAs, so its global reads overlap them; reusing the
+// staged weights over the rounds removes the per-tile weight copy that
+// bounded a one-tile block.  Halo lanes of a tile beyond the image width
+// produce output rows that are discarded.
+constexpr int kConvTiles = 8;
+
 template <int CIN>
 __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict__ in, int B, int H, int W,
                                                       const uint16_t* __restrict__ Wm,
@@ -147,97 +151,119 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict
     constexpr int NAL = (NA + 63) / 64;  // per lane
     constexpr int NW = 32 * (KP / 4);    // 8-byte chunks of the weights
     constexpr int NWT = (NW + 255) / 256;
+    constexpr int NCH = KP / 8;          // 8-channel chunks of the depth
     __shared__ __align__(16) uint16_t sW[32 * WS];
     __shared__ __align__(16) uint16_t sA[4][NPOS * CS];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const long long wave = (long long)blockIdx.x * 4 + wv;
     const int tiles_x = (W + 31) >> 5;
-    const long long row = wave / tiles_x;                 // b * H + y
-    const bool valid = row < (long long)B * H;            // uniform per wave
-    const int b = valid ? (int)(row / H) : 0;
-    const int y = valid ? (int)(row - (long long)b * H) : 0;
-    const int x0 = valid ? (int)(wave - row * tiles_x) << 5 : 0;
+    const long long ntiles = (long long)B * H * tiles_x;
     const long long HW = (long long)H * W;
-    const uint16_t* inb = in + (long long)b * HW * CIN;
-    bf16x4 wv_[NWT], av_[NAL];
-#pragma unroll
-    for (int t = 0; t < NWT; ++t) {
-        const int q = threadIdx.x + 256 * t;
-        wv_[t] = bf16x4{ 0, 0, 0, 0 };
-        if (q < NW) {
-            const int r = q / (KP / 4), c4 = q - r * (KP / 4);
-            wv_[t] = *(const bf16x4*)(Wm + (long long)r * KP + 4 * c4);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < NAL; ++t) {
-        const int q = lane + 64 * t;
-        av_[t] = bf16x4{ 0, 0, 0, 0 };
-        if (q < NA) {
-            const int pos = q / (CIN / 4), c4 = q - pos * (CIN / 4);
-            const int pr = pos / 34, pc = pos - pr * 34;
-            const int yy = y - 1 + pr, xx = x0 - 1 + pc;
-            if (valid && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                av_[t] = *(const bf16x4*)(inb + ((long long)yy * W + xx) * CIN + 4 * c4);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < NWT; ++t) {
-        const int q = threadIdx.x + 256 * t;
-        if (q < NW) {
-            const int r = q / (KP / 4), c4 = q - r * (KP / 4);
-            *(bf16x4*)&sW[r * WS + 4 * c4] = wv_[t];
-        }
-    }
-    uint16_t* a_s = sA[wv];
-#pragma unroll
-    for (int t = 0; t < NAL; ++t) {
-        const int q = lane + 64 * t;
-        if (q < NA) {
-            const int pos = q / (CIN / 4), c4 = q - pos * (CIN / 4);
-            *(bf16x4*)&a_s[pos * CS + 4 * c4] = av_[t];
-        }
-    }
-    __syncthreads();
-    if (!valid) return;
     const int m = lane & 31, kb = lane >> 5;
-    floatx16 acc;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-    // 8-channel chunks of the tap-major depth, two per 16-deep step: this
-    // half-wave takes chunk 2 st + kb (a chunk past the depth is zero)
-    constexpr int NCH = KP / 8;
-#pragma unroll
-    for (int st = 0; st < (NCH + 1) / 2; ++st) {
-        const int ch = 2 * st + kb;
-        const int tap = (8 * ch) / CIN, c8 = 8 * ch - tap * CIN;
-        const int dy = tap / 3, dx = tap - 3 * dy;
-        shortx8 a = shortx8{ 0, 0, 0, 0, 0, 0, 0, 0 }, bw = a;
-        if (ch < NCH) {
-            const uint16_t* pa = &a_s[(dy * 34 + m + dx) * CS + c8];
-            const uint16_t* pb = &sW[m * WS + 8 * ch];
-            a = join8(*(const bf16x4*)pa, *(const bf16x4*)(pa + 4));
-            bw = join8(*(const bf16x4*)pb, *(const bf16x4*)(pb + 4));
-        }
-        acc = mfma16(a, bw, acc);
-    }
     const int oc = m;
-    if (mode == 1 && oc >= co) return;
-    const float bb = (mode == 2 || oc >= co) ? 0.0f : bias[oc];
+    const float bb = (mode == 2 || oc >= co) ? 0.0f : bias[oc < co ? oc : 0];
+    uint16_t* a_s = sA[wv];
+
+    // tile of round r: (image b, row y, first column x0), or invalid
+    auto tile_of = [&](int r, int& b, int& y, int& x0) {
+        const long long t = ((long long)blockIdx.x * kConvTiles + r) * 4 + wv;
+        if (t >= ntiles) return false;
+        const long long row = t / tiles_x;
+        b = (int)(row / H);
+        y = (int)(row - (long long)b * H);
+        x0 = (int)(t - row * tiles_x) << 5;
+        return true;
+    };
+    bf16x4 av_[NAL];
+    auto load_halo = [&](int r) {
+        int b, y, x0;
+        const bool ok = tile_of(r, b, y, x0);
+        const uint16_t* inb = in + (long long)(ok ? b : 0) * HW * CIN;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int xo = x0 + 8 * (j >> 2) + 4 * kb + (j & 3);
-        if (xo >= W) continue;
-        const long long pos = (long long)y * W + xo;
-        const float v = acc[j] + bb;
-        if (mode == 0) {
-            ((uint16_t*)out)[((long long)b * HW + pos) * 32 + oc] = f2bf(v > 0.0f ? v : 0.0f);
-        } else if (mode == 1) {
-            ((float*)out)[((long long)b * co + oc) * HW + pos] = v;
-        } else {
-            const long long o = ((long long)b * HW + pos) * 32 + oc;
-            ((uint16_t*)out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? v : 0.0f);
+        for (int t = 0; t < NAL; ++t) {
+            const int q = lane + 64 * t;
+            av_[t] = bf16x4{ 0, 0, 0, 0 };
+            if (ok && q < NA) {
+                const int pos = q / (CIN / 4), c4 = q - pos * (CIN / 4);
+                const int pr = pos / 34, pc = pos - pr * 34;
+                const int yy = y - 1 + pr, xx = x0 - 1 + pc;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    av_[t] = *(const bf16x4*)(inb + ((long long)yy * W + xx) * CIN + 4 * c4);
+            }
+        }
+    };
+    {
+        bf16x4 wv_[NWT];
+#pragma unroll
+        for (int t = 0; t < NWT; ++t) {
+            const int q = threadIdx.x + 256 * t;
+            wv_[t] = bf16x4{ 0, 0, 0, 0 };
+            if (q < NW) {
+                const int r = q / (KP / 4), c4 = q - r * (KP / 4);
+                wv_[t] = *(const bf16x4*)(Wm + (long long)r * KP + 4 * c4);
+            }
+        }
+        load_halo(0);
+#pragma unroll
+        for (int t = 0; t < NWT; ++t) {
+            const int q = threadIdx.x + 256 * t;
+            if (q < NW) {
+                const int r = q / (KP / 4), c4 = q - r * (KP / 4);
+                *(bf16x4*)&sW[r * WS + 4 * c4] = wv_[t];
+            }
+        }
+    }
+    for (int r = 0; r < kConvTiles; ++r) {
+        if (r > 0) __syncthreads();           // every wave is done reading its halo slot
+#pragma unroll
+        for (int t = 0; t < NAL; ++t) {
+            const int q = lane + 64 * t;
+            if (q < NA) {
+                const int pos = q / (CIN / 4), c4 = q - pos * (CIN / 4);
+                *(bf16x4*)&a_s[pos * CS + 4 * c4] = av_[t];
+            }
+        }
+        __syncthreads();                      // halos (and, in round 0, weights) staged
+        int b, y, x0;
+        const bool ok = tile_of(r, b, y, x0);
+        if (r + 1 < kConvTiles) load_halo(r + 1);
+        if (ok) {
+            floatx16 acc;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+            // two 8-channel chunks per 16-deep step: this half-wave takes
+            // chunk 2 st + kb (a chunk past the depth is zero)
+#pragma unroll
+            for (int st = 0; st < (NCH + 1) / 2; ++st) {
+                const int ch = 2 * st + kb;
+                const int tap = (8 * ch) / CIN, c8 = 8 * ch - tap * CIN;
+                const int dy = tap / 3, dx = tap - 3 * dy;
+                shortx8 a = shortx8{ 0, 0, 0, 0, 0, 0, 0, 0 }, bw = a;
+                if (ch < NCH) {
+                    const uint16_t* pa = &a_s[(dy * 34 + m + dx) * CS + c8];
+                    const uint16_t* pb = &sW[m * WS + 8 * ch];
+                    a = join8(*(const bf16x4*)pa, *(const bf16x4*)(pa + 4));
+                    bw = join8(*(const bf16x4*)pb, *(const bf16x4*)(pb + 4));
+                }
+                acc = mfma16(a, bw, acc);
+            }
+            if (!(mode == 1 && oc >= co)) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int xo = x0 + 8 * (j >> 2) + 4 * kb + (j & 3);
+                    if (xo >= W) continue;
+                    const long long pos = (long long)y * W + xo;
+                    const float v = acc[j] + bb;
+                    if (mode == 0) {
+                        ((uint16_t*)out)[((long long)b * HW + pos) * 32 + oc] = f2bf(v > 0.0f ? v : 0.0f);
+                    } else if (mode == 1) {
+                        ((float*)out)[((long long)b * co + oc) * HW + pos] = v;
+                    } else {
+                        const long long o = ((long long)b * HW + pos) * 32 + oc;
+                        ((uint16_t*)out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? v : 0.0f);
+                    }
+                }
+            }
         }
     }
 }
@@ -251,12 +277,13 @@ hipError_t cnn_conv_fwd(const uint16_t* in, int cin_pad, int B, int H, int W, co
         return hipErrorInvalidValue;
     const long long waves = (long long)B * H * ((W + 31) / 32);
     const long long blocks = (waves + 3) / 4;
+    const long long lds_blocks = (waves + 4 * kConvTiles - 1) / (4 * kConvTiles);
     if (cin_pad == 32)
-        hipLaunchKernelGGL(k_conv_fwd_lds<32>, dim3((unsigned)blocks), dim3(256), 0, s, in, B, H, W, Wm, bias, co,
-                           mode, out, mask);
+        hipLaunchKernelGGL(k_conv_fwd_lds<32>, dim3((unsigned)lds_blocks), dim3(256), 0, s, in, B, H, W, Wm, bias,
+                           co, mode, out, mask);
     else if (cin_pad == 8)
-        hipLaunchKernelGGL(k_conv_fwd_lds<8>, dim3((unsigned)blocks), dim3(256), 0, s, in, B, H, W, Wm, bias, co,
-                           mode, out, mask);
+        hipLaunchKernelGGL(k_conv_fwd_lds<8>, dim3((unsigned)lds_blocks), dim3(256), 0, s, in, B, H, W, Wm, bias,
+                           co, mode, out, mask);
     else
         hipLaunchKernelGGL(k_conv_fwd, dim3((unsigned)blocks), dim3(256), 0, s, in, cin_pad, B, H, W, Wm, Kp,
                            bias, co, mode, out, mask);

@@ -84,17 +84,19 @@ hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsig
 
 // ------------------------------------------------------ level-0 reduction
 // One block per image: trapezoid-weighted mean and maximum of the base grid.
-__global__ __launch_bounds__(1024) void k_reduce_base(const ImageDesc* desc, Counters* ctr, int img_off)
+// Four waves per block (not sixteen), so that a batch's reduction fits into
+// the wave slots the tracing launches of other batches in flight leave free.
+__global__ __launch_bounds__(256) void k_reduce_base(const ImageDesc* desc, Counters* ctr, int img_off)
 {
-    __shared__ double ssum[1024];
-    __shared__ double smax[1024];
+    __shared__ double ssum[256];
+    __shared__ double smax[256];
     const int img = img_off + blockIdx.x;
     const ImageDesc D = desc[img];
     const int t = threadIdx.x;
     const int st0 = 1 << D.levels;
     double sum = 0.0, mx = -HUGE_VAL;
     const int n = D.nx0 * D.ny0;
-    for (int k = t; k < n; k += 1024) {
+    for (int k = t; k < n; k += 256) {
         const int i = k % D.nx0, j = k / D.nx0;
         const double v = D.img[(long long)(j * st0) * D.nx + (long long)(i * st0)];
         const double wx = (i == 0 || i == D.nx0 - 1) ? 0.5 : 1.0;
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_reduce_base(const ImageDesc* desc, Cou
     ssum[t] = sum;
     smax[t] = mx;
     __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if (t < off) {
             ssum[t] += ssum[t + off];
             smax[t] = smax[t + off] > smax[t] ? smax[t + off] : smax[t];
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_reduce_base(const ImageDesc* desc, Cou
 
 hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s, int img_off)
 {
-    hipLaunchKernelGGL(k_reduce_base, dim3(nimg), dim3(1024), 0, s, desc, ctr, img_off);
+    hipLaunchKernelGGL(k_reduce_base, dim3(nimg), dim3(256), 0, s, desc, ctr, img_off);
     return hipGetLastError();
 }
 
@@ -265,20 +267,38 @@ __device__ __forceinline__ bool axis_D(const double* I, long long nx, int s, int
     return false;
 }
 
-// grid (x: 256-wide strips of p, y: q, z: image).  One thread per point of the
-// level-(l+1) grid; new points are classified by index parity (categories 2-4).
+// Blocks of a launch are placed on the eight XCDs round robin (block b on
+// XCD b mod 8).  The estimator maps hardware block b to a logical block so
+// that each XCD gets one contiguous range of logical blocks, i.e. runs of
+// consecutive rows of an image: the neighbour and continuation rows a block
+// reads (q -+ 1, q -+ 3) were fetched into that XCD's L2 by its neighbours.
+// A bijection on [0, nb) for any nb.
+__device__ __forceinline__ unsigned long long xcd_contiguous(unsigned long long b, unsigned long long nb)
+{
+    const unsigned long long q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
+// grid (x: 256-wide strips of p, y: q, z: image), remapped per XCD as above.
+// One thread per point of the level-(l+1) grid; new points are classified by
+// index parity (categories 2-4).
 __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
                                                   unsigned long long* list, long long cap, int long_steps,
-                                                  int mode, int fallback, int img_off, int slot)
+                                                  int mode, int fallback, int img_off, int slot,
+                                                  const int* __restrict__ imap)
 {
-    const int img = img_off + blockIdx.z;
+    const unsigned long long gx = gridDim.x, gy = gridDim.y;
+    const unsigned long long lb = xcd_contiguous(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z),
+                                                 gx * gy * gridDim.z);
+    const int bx = (int)(lb % gx), by = (int)((lb / gx) % gy), bz = (int)(lb / (gx * gy));
+    const int img = imap ? imap[bz] : img_off + bz;
     const ImageDesc D = desc[img];
     if (l >= D.levels) return;                     // uniform over the block
     const int nxl = (1 << (l + 1)) * (D.nx0 - 1) + 1;
     const int nyl = (1 << (l + 1)) * (D.ny0 - 1) + 1;
     const int s = 1 << (D.levels - l - 1);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int q = blockIdx.y;
+    const int p = bx * blockDim.x + threadIdx.x;
+    const int q = by;
     const bool isnew = p < nxl && q < nyl && ((p & 1) | (q & 1));
     bool trace = false;
     bool longr = false;                      // expected to be a long ray: queue at the front
@@ -474,11 +494,12 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
 
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
                            Counters* ctr, unsigned long long* list, long long cap, int long_steps,
-                           hipStream_t s, int mode, int fallback, int img_off, int slot)
+                           hipStream_t s, int mode, int fallback, int img_off, int slot, const int* imap)
 {
+    if (nimg <= 0) return hipSuccess;
     dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
     hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, cap, long_steps, mode, fallback,
-                       img_off, slot < 0 ? l + 1 : slot);
+                       img_off, slot < 0 ? l + 1 : slot, imap);
     return hipGetLastError();
 }
 
