@@ -197,7 +197,9 @@ def mse_check(art, cfgs, images, truths, planes=1):
     for k, c in enumerate(cfgs):
         m = []
         for q in range(planes):
-            fe, mse = art.metrics(truths[k][q], images[k][q])
+            # a truth given as one 2D plane is Stokes I
+            t = truths[k] if truths[k].dim() == 2 else truths[k][q]
+            fe, mse = art.metrics(t, images[k][q])
             m.append(mse)
             if q == 0:
                 fe0 = fe

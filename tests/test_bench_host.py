@@ -87,3 +87,25 @@ def test_one_gpu_only(monkeypatch, capsys):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_mse_check_reads_whole_planes():
+    """A truth given as one 2D plane is Stokes I; a 3D truth is compared plane
+    by plane (a 2D truth must not be indexed by row)."""
+    import torch
+
+    class FakeArt:
+        @staticmethod
+        def metrics(t, a):
+            t, a = t.double(), a.double()
+            return float(abs(t.sum() - a.sum()) / t.sum()), float(((t - a) ** 2).sum() / (t * t).sum())
+    truth = torch.ones(4, 3, 5, dtype=torch.float64)
+    img = truth.clone()
+    img[0, 2, 4] = 1.5                       # one pixel of plane 0, last row
+    img[1] *= 2.0
+    cfgs = [{"name": "a"}]
+    whole = bench.mse_check(FakeArt, cfgs, [img], [truth[0]])
+    assert math.isclose(whole["mse_max"], 0.25 / 15)
+    per = bench.mse_check(FakeArt, cfgs, [img], [truth], planes=2)
+    assert math.isclose(per["mse_max_planes"][0], 0.25 / 15) and math.isclose(per["mse_max_planes"][1], 1.0)
+    assert per["mse_ok"] is False and per["n_over_bar"] == 1
