@@ -78,7 +78,7 @@ BYTES_PER_RAY = 58
 # HBM traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE counter runs
 # of this benchmark, per render of the headline form; valid only for the
 # kernel sources it was measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=377575119, kernel_hash="7e97b7bd5e7e51a7", form="learned_batched",
+TRAFFIC = dict(bytes_per_render=376705222, kernel_hash="7e97b7bd5e7e51a7", form="learned_batched",
                source="profiles/k_trace_learned_batched_uneven_64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
 TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
