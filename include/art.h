@@ -403,8 +403,11 @@ typedef struct {
 } art_learned;
 
 /* Switch a batch to learned renders with `net` (NULL: back to plain).  All
- * images need the same base grid and level count, and feature buffers
- * (art_image.feat_dev).  Allocates the batch's own network workspace; later
+ * images need the same base grid and feature buffers (art_image.feat_dev);
+ * their level counts may differ.  In a learned render the feature records of
+ * interpolated points are written only on the levels up to the last one the
+ * network reads (traced points always get theirs); elsewhere the buffer keeps
+ * what it held.  Allocates the batch's own network workspace; later
  * art_batch_render / art_batch_capture use the network (a captured graph
  * reads the parameters at replay, so training in between is seen).  `net`
  * must outlive the batch's use of it. */

@@ -663,6 +663,8 @@ int enqueue_adaptive(art_batch* b, int g, hipStream_t s)
 // with levels >= l+2 takes the look-ahead, one with l+1 levels its last level
 // by the criterion alone (the network too with all_levels), and one with fewer
 // is finished; every kernel skips the images a level does not concern.
+// Interpolated points get feature records only up to the last level the
+// network reads (traced points always get theirs).
 int enqueue_learned(art_batch* b, int g, hipStream_t s)
 {
     BatchGroup& G = b->grp[g];
@@ -680,6 +682,17 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
             if (b->hD[i].levels >= lo) return true;
         return false;
     };
+    // the last level the network reads: interpolated points of deeper levels
+    // need no feature records (the same walk over the levels as below)
+    int last_net = -1;
+    for (int l = 0; l < N;) {
+        if (G.nnet[l] > 0) {
+            last_net = l;
+            l += any_with(l + 2) ? 2 : 1;
+        } else {
+            l += 1;
+        }
+    }
     int l = 0;
     while (l < N) {
         const bool ahead = any_with(l + 2);
@@ -688,7 +701,8 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         if (!net_here) {
             int ne;
             const int* em = est_map(b, g, l, ne);
-            HIP_TRY(launch_estimate(dD, ne, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 0, 1, 0, -1, em));
+            HIP_TRY(launch_estimate(dD, ne, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 0, 1, 0, -1, em,
+                                    l + 1 <= last_net));
             rc = trace_pass(b, g, l + 1, s);
             if (rc) return rc;
             l += 1;
@@ -706,7 +720,7 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         int ne;
         const int* em = est_map(b, g, l, ne);
         HIP_TRY(launch_estimate(dD, ne, nxl, nyl, l, ctr, list, cap, b->L.long_steps, s, 1, o.all_levels ? 1 : 0, 0,
-                                -1, em));
+                                -1, em, l + 1 <= last_net));
         rc = trace_pass(b, g, l + 1, s);
         if (rc) return rc;
         if (ahead) {
@@ -714,7 +728,7 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
             int ne2;
             const int* em2 = est_map(b, g, l + 1, ne2);
             HIP_TRY(launch_estimate(dD, ne2, nx2, ny2, l + 1, ctr, list, cap, b->L.long_steps, s, 2,
-                                    o.fallback ? 1 : 0, 0, -1, em2));
+                                    o.fallback ? 1 : 0, 0, -1, em2, l + 2 <= last_net));
             if (o.fallback) {
                 rc = trace_pass(b, g, l + 2, s);
                 if (rc) return rc;

@@ -122,11 +122,13 @@ hipError_t launch_spectral_base(const ImageDesc* desc, int img_off, int nimg, in
 // queued at the front of the list (traced first), the others from the back
 // (list capacity `cap`).
 // imap: if given, block z of the launch takes image imap[z] (nimg of them),
-// else image img_off + z.
+// else image img_off + z.  feat: interpolated points inherit feature records
+// (images with a feature buffer); 0 where no later network run reads this
+// level.
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
                            Counters* ctr, unsigned long long* list, long long cap, int long_steps,
                            hipStream_t s, int mode = 0, int fallback = 1, int img_off = 0, int slot = -1,
-                           const int* imap = nullptr);
+                           const int* imap = nullptr, int feat = 1);
 hipError_t launch_metrics(const double* t, const double* a, long long n, double* partial,
                           int nblocks, hipStream_t s);
 int trace_occupancy_blocks(int precision, int model, int nstokes, bool subrings, int threads);

@@ -285,7 +285,7 @@ __device__ __forceinline__ unsigned long long xcd_contiguous(unsigned long long 
 __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
                                                   unsigned long long* list, long long cap, int long_steps,
                                                   int mode, int fallback, int img_off, int slot,
-                                                  const int* __restrict__ imap)
+                                                  const int* __restrict__ imap, int feat)
 {
     const unsigned long long gx = gridDim.x, gy = gridDim.y;
     const unsigned long long lb = xcd_contiguous(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z),
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
                     D.img[st * D.plane + pix] = S * w;
                 }
             }
-            if (D.feat) {
+            if (D.feat && feat) {
                 // interpolated points inherit the smallest radius and the largest
                 // crossing count of their neighbours
                 RayFeat f = D.feat[o[0]];
@@ -494,12 +494,13 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
 
 hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl_max, int l,
                            Counters* ctr, unsigned long long* list, long long cap, int long_steps,
-                           hipStream_t s, int mode, int fallback, int img_off, int slot, const int* imap)
+                           hipStream_t s, int mode, int fallback, int img_off, int slot, const int* imap,
+                           int feat)
 {
     if (nimg <= 0) return hipSuccess;
     dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
     hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, cap, long_steps, mode, fallback,
-                       img_off, slot < 0 ? l + 1 : slot, imap);
+                       img_off, slot < 0 ? l + 1 : slot, imap, feat);
     return hipGetLastError();
 }
 

@@ -151,6 +151,51 @@ def test_learned_uneven_batch(art, fallback):
     net.close()
 
 
+def test_learned_feature_records_up_to_the_last_network_level(art):
+    """A learned render writes the feature records of interpolated points
+    only on the levels the network reads (0..2 of a 4-level image: it runs at
+    levels 0 and 2); deeper interpolated points keep what the buffer held,
+    traced points always carry theirs.  A plain render writes every record."""
+    case("learned feature records")
+    params = net_params(5)
+    net = art.Cnn()
+    net.set_params(ocnn.flatten(params).astype(np.float32))
+    c = small_cfg(levels=4)
+    N = c["levels"]
+
+    def level_of(x):
+        tz = np.zeros_like(x)
+        y = x.copy()
+        for _ in range(N):
+            odd = (y % 2 == 1) | (y == 0)
+            tz += np.where(odd, 0, 1)
+            y = np.where(odd, y, y // 2)
+        return np.where(x == 0, 0, np.maximum(0, N - tz))
+
+    for learned in (True, False):
+        out = art.alloc(c, feat=True)
+        out[2].fill_(-7)
+        if learned:
+            _, lev, ft, st = art.render_learned(c, net, out=out, z_propose=0.3, z_suppress=-2.0, fallback=True)
+        else:
+            _, lev, ft, st = art.render(c, out=out)
+        torch.cuda.synchronize()
+        f = art.feat_numpy(ft)
+        L = lev.cpu().numpy()
+        jj, ii = np.mgrid[0:L.shape[0], 0:L.shape[1]]
+        pl = np.maximum(level_of(ii), level_of(jj))
+        assert pl.max() == N and (pl == 0).sum() == c["nx0"] * c["ny0"]
+        unset = f["status"] == -7
+        traced = L >= 0
+        assert not unset[traced].any()
+        if learned:
+            assert not unset[~traced & (pl <= 2)].any()
+            assert unset[~traced & (pl > 2)].all() and (~traced & (pl > 2)).sum() > 0
+        else:
+            assert not unset.any()
+    net.close()
+
+
 def test_learned_batch_equals_single_and_graph(art):
     case("learned batch")
     params = net_params(3)
