@@ -165,6 +165,28 @@ def training_workload(precision="mixed", nx0=129, levels=3):
     return cfgs
 
 
+BATCH_TRAIN_SPINS = (0.3, -0.3, 0.8, -0.8)
+BATCH_TRAIN_INCS = (25.0, 75.0, 105.0, 140.0)
+
+
+def training_workload_batch(precision="mixed", r_rel=0.005, base=129, levels=4):
+    """Training images of the learned proposal for the batched workload: 16
+    thermal images on its base grid with four levels (so the network sees the
+    grids of both levels it runs at, 129^2 and 513^2), spins, inclinations and
+    field phases (seeds 401..416) disjoint from batch_workload and
+    batch_workload_heldout, each of the four frequencies at every spin;
+    labels come from the criterion at r_rel."""
+    cfgs = []
+    k = 0
+    for a in BATCH_TRAIN_SPINS:
+        for inc in BATCH_TRAIN_INCS:
+            cfgs.append(dict(workload("thermal_1025"), name="btrain_%02d" % k, a=a, inc_deg=inc,
+                             freq_hz=BATCH_FREQS[(k + k // 4) % 4], mp=thermal_params(seed=401 + k),
+                             precision=precision, nx0=base, ny0=base, levels=levels, r_rel=r_rel))
+            k += 1
+    return cfgs
+
+
 GRID_TRAIN_VIEWS = ((0.94, 17.0), (0.94, 60.0), (0.94, 120.0), (0.5, 163.0))
 
 

@@ -5,21 +5,26 @@ thermal plasma, spins a in {0, 0.5, 0.94, -0.94} x inclinations {17, 60, 90,
 163} deg x frequencies {86, 230, 345, 690} GHz, polarised I, Q, U, V, base
 129^2 vertices with image k refined 1 + (k mod 4) levels (257^2 ... 2049^2,
 89.3 M effective pixels), R_abs = 1e-3 x (max of the level-0 image), FP32
-transfer with FP64 geodesic right-hand sides only near the photon shell, the
-horizon and the theta turning points.  One step = one render of the batch,
+plasma and transfer with the FP64 geodesic (the selective-FP64 policy, FP32
+right-hand sides away from the photon shell, the horizon and the theta
+turning points, and the all-FP64 path are timed beside it: on this chip an
+FP64 FMA issues at the unpacked FP32 rate, so the selective policy saves no
+time).  One step = one render of the batch,
 the whole level loop one hipGraph replay; steps are timed with several
 batches in flight (depth and persistent-grid shape autotuned per form).
 
 Forms compared at the 0.1 % MSE bar (normalised MSE of Stokes I against the
 uniform render of the same view, Sec. 4.1 Eq. 9):
   - learned + batched: the proposal network (trained first, untimed, on
-    plain renders of 16 other images) looks two levels ahead, the criterion
-    of Sec. 3.2 judges and traces what it missed;
+    plain renders of 16 other images of the batch's structure) looks two
+    levels ahead, the criterion of Sec. 3.2 judges and traces what it missed
+    (or only counts it: judge-only forms);
   - plain batched: the criterion alone.
 Each form's tolerance is chosen on a held-out batch of the same structure
 (other spins, inclinations and field phases): the loosest R_rel of a fixed
 grid at which all 64 held-out images pass the bar, then applied unchanged to
-the timed batch.  A form with no passing R_rel on the held-out batch is timed
+the timed batch; among the learned forms the one fastest on the held-out
+batch at its operating point is timed.  A form with no passing R_rel on the held-out batch is timed
 at the grid's tightest R_rel and reported as such; the plain criterion is
 also timed at the loosest R_rel that passes on the timed batch itself (a
 choice made on the measured images, favourable to it).  Timings are repeated
@@ -79,6 +84,7 @@ BYTES_PER_RAY = 58
 # of this benchmark, per render of the headline form; valid only for the
 # kernel sources it was measured on (hash below), else reported as null.
 TRAFFIC = dict(bytes_per_render=376705222, kernel_hash="7e97b7bd5e7e51a7", form="learned_batched",
+               precision="mixed_geo",
                source="profiles/k_trace_learned_batched_uneven_64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
 TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
@@ -86,6 +92,12 @@ TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_
 # operating-point grid (R_rel) and the look-ahead proposal thresholds tried
 OP_RREL = (0.001, 0.002, 0.003, 0.005, 0.0075, 0.01, 0.0125, 0.015)
 OP_Z = (0.0, 2.0, 4.0)
+OP_Z_JUDGE = (0.0, 2.0)      # judge-only forms (no fallback pass)
+HELDOUT_LAUNCH = dict(trace_blocks=256, trace_threads=256, refill=1, groups=1)
+TRAIN_RREL = 0.005           # tolerance of the plain renders the network learns from
+PRECISION_NAMES = dict(fp64="FP64 throughout", mixed="FP64 geodesic, FP32 plasma and transfer",
+                       mixed_geo="FP64 geodesic with FP32 right-hand sides outside the sensitive zones, "
+                                 "FP32 plasma and transfer")
 # depths searched for the batches in flight (the box gives a process four
 # hardware queues)
 IN_FLIGHT_DEPTHS = (2, 3, 4)
@@ -101,11 +113,13 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launches, form):
+def measured_traffic(launches, form, precision):
     """HBM bytes per tracing launch of the roofline renders (per-render counter
-    total over this run's launches per render), or None for other kernels or
-    another headline form."""
-    if not TRAFFIC or TRAFFIC["kernel_hash"] != kernel_hash() or TRAFFIC["form"] != form or launches <= 0:
+    total over this run's launches per render), or None for other kernels,
+    another headline form or another precision policy (another kernel
+    instantiation)."""
+    if not TRAFFIC or TRAFFIC["kernel_hash"] != kernel_hash() or TRAFFIC["form"] != form or \
+            TRAFFIC["precision"] != precision or launches <= 0:
         return None
     return dict(bytes_per_launch=TRAFFIC["bytes_per_render"] * ROOF_RENDERS / launches,
                 source=TRAFFIC["source"])
@@ -244,17 +258,24 @@ def operating_points(search, op_forms):
     return op
 
 
-def choose_forms(op_heldout, op_timed, grid):
+def choose_forms(op_heldout, op_timed, grid, heldout_ms=None):
     """The forms timed on the headline batch, as (name, form, R_rel, how):
-    the learned form with the fewest held-out rays at its held-out operating
-    point; the plain criterion at its held-out operating point, or at the
-    grid's tightest R_rel if it has none; and the plain criterion at the
-    loosest R_rel passing on the timed batch itself, if that differs."""
+    the learned form fastest on the held-out batch at its held-out operating
+    point (heldout_ms: form -> ms per batch; without it the one with the
+    fewest held-out rays); the plain criterion at its held-out operating
+    point, or at the grid's tightest R_rel if it has none; and the plain
+    criterion at the loosest R_rel passing on the timed batch itself, if that
+    differs."""
     out = []
     lop = {k: v for k, v in op_heldout.items() if k != "plain"}
     if lop:
-        k = min(lop, key=lambda n: lop[n]["rays"])
-        out.append(("learned_batched", k, lop[k]["r_rel"], "held-out operating point"))
+        if heldout_ms:
+            k = min((n for n in lop if n in heldout_ms), key=lambda n: heldout_ms[n])
+            how = "held-out operating point, fastest learned form on the held-out batch"
+        else:
+            k = min(lop, key=lambda n: lop[n]["rays"])
+            how = "held-out operating point"
+        out.append(("learned_batched", k, lop[k]["r_rel"], how))
     if "plain" in op_heldout:
         out.append(("plain_batched", "plain", op_heldout["plain"]["r_rel"], "held-out operating point"))
     else:
@@ -294,14 +315,15 @@ def c4_forms(art, torch, art_inputs, args):
     ss = [S.torch for S in Ss]
     s = ss[0]
     t0 = time.perf_counter()
-    net, tinfo = learn.train(art_inputs.training_workload(precision="mixed"), steps=args.train_steps, lr=3e-3,
-                             seed=4, stream=s)
+    net, tinfo = learn.train(art_inputs.training_workload_batch(precision="mixed", r_rel=TRAIN_RREL),
+                             steps=args.train_steps, lr=3e-3, seed=4, stream=s)
     s.synchronize()
     t_train = time.perf_counter() - t0
     log("trained proposal network in %.1f s: loss %s -> %s" % (t_train, tinfo["loss_first"], tinfo["loss_last"]))
     inf = float("inf")
     op_forms = [("plain", None)] + [("lookahead_z%g" % z, dict(z_propose=z, z_suppress=-inf, fallback=True))
-                                    for z in OP_Z]
+                                    for z in OP_Z] + \
+        [("judge_z%g" % z, dict(z_propose=z, z_suppress=-inf, fallback=False)) for z in OP_Z_JUDGE]
     opts_of = dict(op_forms)
 
     def truths_of(cfgs):
@@ -319,13 +341,29 @@ def c4_forms(art, torch, art_inputs, args):
     op_h = operating_points(search_h, op_forms)
     log("held-out operating points: %s" % {k: (v["r_rel"], v["rays"], "%.2e" % v["mse_max"])
                                            for k, v in op_h.items()})
+    # the learned forms timed on the held-out batch at their operating points
+    # (a fixed launch shape, three batches in flight): the fastest is timed
+    # on the headline batch
+    ms_h = {}
+    dh = min(3, nmax)
+    for name, row in op_h.items():
+        if name == "plain":
+            continue
+        bs = [art.Batch([dict(c, r_rel=row["r_rel"]) for c in held], feat=True) for _ in range(dh)]
+        for X in bs:
+            X.set_learned(net, **opts_of[name])
+            X.set_launch(**HELDOUT_LAUNCH)
+        ms_h[name] = min(time_pipelined(bs, torch, ss[:dh], args.steps) for _ in range(2)) * 1e3
+        for X in bs:
+            X.close()
+    log("learned forms on the held-out batch (ms per batch): %s" % {k: round(v, 2) for k, v in ms_h.items()})
     cfgs = art_inputs.batch_workload(precision=args.precision)
     truths = truths_of(cfgs)
     search_c = search_batch(art, torch, cfgs, truths, net, op_forms, s, 4)
     op_c = operating_points(search_c, op_forms)
     log("operating points on the timed batch itself: %s" % {k: (v["r_rel"], v["rays"], "%.2e" % v["mse_max"])
                                                             for k, v in op_c.items()})
-    chosen = choose_forms(op_h, op_c, OP_RREL)
+    chosen = choose_forms(op_h, op_c, OP_RREL, ms_h)
     npix = sum(c_img.shape[1] * c_img.shape[2] for c_img in truths)
     forms, sets = {}, {}
     for name, form, rr, how in chosen:
@@ -380,6 +418,33 @@ def c4_forms(art, torch, art_inputs, args):
         f["effective_px_per_s"] = npix / (f["ms_per_batch"] * 1e-3)
         log("%s: %.2f ms/batch median of %d rounds [%.2f, %.2f], %d in flight; alone %.1f ms" % (
             name, f["ms_per_batch"], len(ms), ms[0], ms[-1], f["in_flight"], f["latency_ms"]))
+    # the other precision policies: the same forms, tolerances, depth and
+    # launch shape, timed the same way (two rounds), with the MSE check
+    policies = {}
+    for prec in ("mixed", "mixed_geo", "fp64"):
+        if prec == args.precision:
+            continue
+        for name in ("learned_batched", "plain_batched"):
+            if name not in forms:
+                continue
+            f = forms[name]
+            opts = opts_of[f["form"]]
+            c_rr = [dict(c, r_rel=f["r_rel"], precision=prec) for c in cfgs]
+            bs = [art.Batch(c_rr, feat=opts is not None) for _ in range(f["in_flight"])]
+            for X in bs:
+                X.set_learned(None) if opts is None else X.set_learned(net, **opts)
+                X.set_launch(**f["launch"])
+            ms = sorted(time_pipelined(bs, torch, ss[:len(bs)], args.steps) * 1e3 for _ in range(2))
+            bs[0].render(s)
+            st = bs[0].stats(stream=s)
+            chk = mse_check(art, c_rr, bs[0].images, truths, 1)
+            policies.setdefault(prec, {})[name] = dict(
+                ms_per_batch=ms[0], ms_range=[ms[0], ms[-1]], rays=st["rays"], steps=st["steps"],
+                rays_per_s=st["rays"] / (ms[0] * 1e-3), effective_px_per_s=npix / (ms[0] * 1e-3),
+                mse_max=chk["mse_max"], mse_ok=chk["mse_ok"])
+            log("%s in %s: %.2f ms/batch, %d rays, mse max %.2e" % (name, prec, ms[0], st["rays"], chk["mse_max"]))
+            for X in bs:
+                X.close()
     # eager renders of the headline form with HIP events around each tracing
     # launch (on the group stream): the roofline figures
     head = "learned_batched" if "learned_batched" in forms else "plain_batched"
@@ -409,9 +474,9 @@ def c4_forms(art, torch, art_inputs, args):
     torch.cuda.empty_cache()
     roof_src = dict(tr_ms=tr_ms, launches=launches, flops=fl, flops_structured=fls, render_ms=render_ms,
                     rays=rays)
-    search = dict(heldout=search_h, timed=search_c,
-                  operating_points_heldout=op_h, operating_points_timed=op_c)
-    return forms, head, training, npix, roof_src, search
+    search = dict(heldout=search_h, timed=search_c, operating_points_heldout=op_h,
+                  operating_points_timed=op_c, learned_heldout_ms=ms_h)
+    return forms, head, training, npix, roof_src, search, policies
 
 
 def grid_forms(art, torch, art_inputs, args):
@@ -822,7 +887,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="mixed_geo", choices=["fp64", "mixed", "mixed_geo"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed_geo"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-1core-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -850,15 +915,14 @@ def main():
     plain, uniform = plain_single(art, torch, cfg, args)
     log("thermal view, plain one image at a time: %.1f ms/image, %d rays, mse %.2e; uniform %.1f ms" % (
         plain["ms_per_image"], plain["rays"], plain["mse"], uniform["ms"]))
-    forms, head, training, npix, rs, search = c4_forms(art, torch, art_inputs, args)
+    forms, head, training, npix, rs, search, policies = c4_forms(art, torch, art_inputs, args)
     L = forms[head]
     P = forms["plain_batched"]
     achieved = (rs["flops"] / rs["launches"]) / (rs["tr_ms"] / rs["launches"] * 1e-3)
-    traffic = measured_traffic(rs["launches"], head)
+    traffic = measured_traffic(rs["launches"], head, args.precision)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_VECTOR / 1e12, unit="TFLOP/s",
                 frac=achieved / PEAK_VECTOR, traffic=traffic and traffic["bytes_per_launch"],
-                kernel="k_trace (FP64 geodesic, FP32 right-hand sides outside the sensitive zones, FP32 "
-                       "transfer), %s render" % head,
+                kernel="k_trace (%s), %s render" % (PRECISION_NAMES[args.precision], head),
                 launches=rs["launches"], renders=ROOF_RENDERS,
                 avg_launch_ms=rs["tr_ms"] / rs["launches"],
                 flops_per_launch=rs["flops"] / rs["launches"],
@@ -907,6 +971,7 @@ def main():
         "uniform": uniform,
         "training": training,
         "roofline": roof,
+        "precision_policies": policies,
     }
     if "plain_batched_own_op" in forms:
         O = forms["plain_batched_own_op"]

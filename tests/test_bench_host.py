@@ -18,17 +18,19 @@ def test_report_is_strict_json():
 def test_traffic_only_for_profiled_sources_and_form():
     t = bench.TRAFFIC
     if t is None:
-        assert bench.measured_traffic(8, "learned_batched") is None
+        assert bench.measured_traffic(8, "learned_batched", "mixed") is None
         return
     launches = 8
-    got = bench.measured_traffic(launches, t["form"])
+    got = bench.measured_traffic(launches, t["form"], t["precision"])
     if t["kernel_hash"] == bench.kernel_hash():
         assert got is not None
         assert math.isclose(got["bytes_per_launch"], t["bytes_per_render"] * bench.ROOF_RENDERS / launches)
     else:
         assert got is None
-    assert bench.measured_traffic(launches, "some_other_form") is None
-    assert bench.measured_traffic(0, t["form"]) is None
+    assert bench.measured_traffic(launches, "some_other_form", t["precision"]) is None
+    other = next(p for p in ("mixed", "mixed_geo", "fp64") if p != t["precision"])
+    assert bench.measured_traffic(launches, t["form"], other) is None
+    assert bench.measured_traffic(0, t["form"], t["precision"]) is None
 
 
 def test_flop_count_of_a_render():
@@ -77,6 +79,27 @@ def test_forms_timed_follow_the_held_out_choice():
     got = bench.choose_forms({"lookahead_z4": dict(r_rel=0.005, rays=100)}, {"plain": dict(r_rel=0.001)}, grid)
     assert [(n, r) for n, _, r, _ in got] == [("learned_batched", 0.005), ("plain_batched", 0.001)]
     assert "tightest" in got[1][3]
+    # with held-out timings the fastest learned form is taken, not the one with the fewest rays
+    op_h["judge_z2"] = dict(r_rel=0.005, rays=110)
+    got = bench.choose_forms(op_h, op_t, grid, {"lookahead_z0": 40.0, "lookahead_z4": 38.0, "judge_z2": 36.5})
+    assert got[0][:3] == ("learned_batched", "judge_z2", 0.005) and "fastest" in got[0][3]
+
+
+def test_training_heldout_and_timed_batches_are_disjoint():
+    """The network's training images, the held-out batch (operating points)
+    and the timed batch share no spin, no inclination and no field phase;
+    the training set has the batch's frequencies and both network levels."""
+    import art_inputs
+    tr = art_inputs.training_workload_batch()
+    ho = art_inputs.batch_workload_heldout()
+    tb = art_inputs.batch_workload()
+    key = lambda cs, f: {c[f] for c in cs}
+    for f in ("a", "inc_deg"):
+        assert not (key(tr, f) & key(ho, f)) and not (key(tr, f) & key(tb, f)) and not (key(ho, f) & key(tb, f))
+    phase = lambda cs: {tuple(c["mp"]) for c in cs}
+    assert not (phase(tr) & phase(ho)) and not (phase(tr) & phase(tb)) and not (phase(ho) & phase(tb))
+    assert key(tr, "freq_hz") == key(tb, "freq_hz") and {c["levels"] for c in tr} == {4}
+    assert all(c["nx0"] == tb[0]["nx0"] for c in tr)
 
 
 def test_one_gpu_only(monkeypatch, capsys):

@@ -256,23 +256,27 @@ def test_uneven_batch_equals_single_and_oracle(art, uneven):
             assert rel_l2(got[:, s], want[:, s]) <= 1e-4, (k, s, rel_l2(got[:, s], want[:, s]))
 
 
-def test_uneven_batch_image_error(art, uneven):
-    """Image MSE (Eq. 9) against the uniform full-resolution render of the
-    same view, one image of every level count and the view a = -0.94,
-    i = 163 deg, 690 GHz at 2049^2.  Measured: 3.6e-5 (1 level) to 1.5e-4
-    (4 levels), 1.08e-3 for that view, just above the 0.1 % bar: at
-    R_rel = 0.01 its fourth level's interpolation error is of the bar's size
-    (the 3-level batch of the benchmark stays below the bar).
-    The bound, twice the bar, fails on any error of the size a broken
-    interpolation or decision produces (1e-2 and up)."""
-    cfgs, imgs, _, _, _ = uneven
-    for k in (0, 1, 2, 3, 39, 63):
-        truth, _, _ = art.render_uniform(cfgs[k])
-        mse = art.metrics(truth[0], imgs[k][0])[1]
-        print("image", k, "levels", cfgs[k]["levels"], "mse", mse, flush=True)
-        assert mse <= 2e-3, (k, mse)
-        if k != 63:
-            assert mse <= 1e-3, (k, mse)
+@pytest.mark.parametrize("precision", ["mixed", "mixed_geo"])
+def test_uneven_batch_image_error(art, precision):
+    """Every image of the uneven batch within the 0.1 % bar (Eq. 9) of its
+    uniform full-resolution render, plain criterion at R_rel = 0.005 (on this
+    batch the plain criterion reaches the bar from R_rel = 0.0075 down; at
+    0.01 its worst image sits at 1.08e-3).  Measured with MIXED_GEO: largest
+    5.0e-4."""
+    import bench
+    print("CASE uneven batch image error", precision, flush=True)
+    cfgs = [dict(c, r_rel=0.005) for c in art_inputs.batch_workload(precision=precision)]
+    B = art.Batch(cfgs)
+    B.render()
+    truths = []
+    for c in cfgs:
+        t, _, _ = art.render_uniform(c)
+        truths.append(t[0].clone())
+        del t
+    chk = bench.mse_check(art, cfgs, B.images, truths)
+    print("mse max", chk["mse_max"], "worst", chk["worst"], "mean", chk["mse_mean"], flush=True)
+    assert chk["mse_ok"] and chk["n_over_bar"] == 0, chk
+    B.close()
 
 
 # --------------------------------------------------------------------------
@@ -280,9 +284,11 @@ def test_uneven_batch_image_error(art, uneven):
 # held-out protocol: on the held-out batch (other spins, inclinations and
 # field phases, the same structure as the uneven batch) the plain criterion
 # misses the bar even at the grid's tightest R_rel (one image keeps an error
-# floor: features the base grid does not see), while the look-ahead form
-# (proposal threshold z = 4, criterion as fallback) passes at R_rel = 0.005;
-# applied unchanged to the uneven batch it passes there too.
+# floor: features the base grid does not see), while the look-ahead forms
+# (proposal threshold z = 4 with the criterion as fallback, and z = 2 with
+# the criterion as judge only) pass at R_rel = 0.005; applied unchanged to
+# the uneven batch they pass there too.  The network is trained on the
+# batch-structured training set (four frequencies, both network levels).
 
 def test_learned_operating_point_gain(art):
     from paper_2103_07417_amd import learn
@@ -290,7 +296,8 @@ def test_learned_operating_point_gain(art):
     print("CASE learned operating point (held-out protocol)", flush=True)
     S = art.Stream()
     s = S.torch
-    net, _ = learn.train(art_inputs.training_workload(precision="mixed"), steps=300, lr=3e-3, seed=4, stream=s)
+    net, _ = learn.train(art_inputs.training_workload_batch(precision="mixed", r_rel=bench.TRAIN_RREL),
+                         steps=300, lr=3e-3, seed=4, stream=s)
     res = {}
     for name, cfgs in (("heldout", art_inputs.batch_workload_heldout(precision=UNEVEN_PRECISION)),
                        ("timed", art_inputs.batch_workload(precision=UNEVEN_PRECISION))):
@@ -300,12 +307,14 @@ def test_learned_operating_point_gain(art):
             truths.append(t.clone())
             del t
         s.synchronize()
-        for form, rr in (("plain", min(bench.OP_RREL)), ("lookahead", 0.005)):
+        for form, rr in (("plain", min(bench.OP_RREL)), ("lookahead", 0.005), ("judge", 0.005)):
             B = art.Batch([dict(c, r_rel=rr) for c in cfgs], feat=True)
             if form == "plain":
                 B.set_learned(None)
-            else:
+            elif form == "lookahead":
                 B.set_learned(net, z_propose=4.0, z_suppress=-float("inf"), fallback=True)
+            else:
+                B.set_learned(net, z_propose=2.0, z_suppress=-float("inf"), fallback=False)
             B.render(s)
             st = B.stats(stream=s)
             chk = bench.mse_check(art, cfgs, B.images, truths)
@@ -316,8 +325,8 @@ def test_learned_operating_point_gain(art):
     net.close()
     S.close()
     assert not res[("heldout", "plain")][2]
-    assert res[("heldout", "lookahead")][2]
-    assert res[("timed", "lookahead")][2] and res[("timed", "plain")][2]
+    assert res[("heldout", "lookahead")][2] and res[("heldout", "judge")][2]
+    assert res[("timed", "lookahead")][2] and res[("timed", "judge")][2] and res[("timed", "plain")][2]
 
 
 # --------------------------------------------------------------------------
