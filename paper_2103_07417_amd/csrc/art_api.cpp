@@ -711,8 +711,8 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         // the network only on the images it decides for at this level
         const int W = (int)grid_n(D0.nx0, l), H = (int)grid_n(D0.ny0, l);
         const int* im = G.imap + G.imap_off[l];
-        HIP_TRY(cnn_features_batch(dD, ctr, G.nnet[l], l, H, W, G.ws.xf, s, im));
-        HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, G.ws.xf, G.nnet[l], H, W, G.ws.logits, s));
+        HIP_TRY(cnn_features_batch(dD, ctr, G.nnet[l], l, H, W, nullptr, G.ws.x, s, im));
+        HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, nullptr, G.nnet[l], H, W, G.ws.logits, s));
         HIP_TRY(cnn_propose(G.ws.logits, dD, G.nnet[l], l, H, W, o.z_propose, o.z_suppress, o.all_levels, list,
                             ctr, s, im));
         // mode 1: images the network decided for read its marks; the others

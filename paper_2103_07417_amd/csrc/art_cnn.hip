@@ -680,39 +680,46 @@ hipError_t cnn_features(const double* img, const RayFeat* feat, long long nx, in
 }
 
 // Batched form: grid.y = image; N_abs = the image's level-0 normalisation.
+// Output either FP32 NCHW x[b][3][H][W] or, if x is null, the network's BF16
+// NHWC input xb[b][H][W][8] (channels 3..7 zero; the rounding of
+// k_input_bf16, so both routes give the same network input).
 __global__ void k_cnn_features_batch(const ImageDesc* __restrict__ desc, const Counters* __restrict__ ctr,
-                                     int l, int H, int W, float* __restrict__ x, const int* __restrict__ imap)
+                                     int l, int H, int W, float* __restrict__ x, uint16_t* __restrict__ xb,
+                                     const int* __restrict__ imap)
 {
     const int b = blockIdx.y;
     const int img = imap ? imap[b] : b;
-    const long long HW = (long long)H * W;
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int HW = H * W;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= HW) return;
     const ImageDesc& D = desc[img];
-    float* xb = x + (long long)b * kCnnIn * HW;
-    if (D.levels < l) {
-        // an image of the batch with fewer levels: it has no level-l grid and
-        // the network's output for it is not read; its input is zero
-        xb[t] = 0.0f;
-        xb[HW + t] = 0.0f;
-        xb[2 * HW + t] = 0.0f;
-        return;
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    // an image of the batch with fewer levels has no level-l grid and the
+    // network's output for it is not read; its input is zero
+    if (D.levels >= l) {
+        const int s = 1 << (D.levels - l);
+        const int j = t / W, i = t - j * W;
+        feature_at(D.img, D.feat, (long long)j * s * D.nx + (long long)i * s, ctr->scal[img][2], c0, c1, c2);
     }
-    const int s = 1 << (D.levels - l);
-    const int j = (int)(t / W), i = (int)(t - (long long)j * W);
-    float c0, c1, c2;
-    feature_at(D.img, D.feat, (long long)j * s * D.nx + (long long)i * s, ctr->scal[img][2], c0, c1, c2);
-    xb[t] = c0;
-    xb[HW + t] = c1;
-    xb[2 * HW + t] = c2;
+    if (x) {
+        float* xo = x + (long long)b * kCnnIn * HW;
+        xo[t] = c0;
+        xo[HW + t] = c1;
+        xo[2 * HW + t] = c2;
+    } else {
+        const uint32_t w0 = (uint32_t)f2bf(c0) | ((uint32_t)f2bf(c1) << 16);
+        const uint32_t w1 = (uint32_t)f2bf(c2);
+        *(uint4*)(xb + ((long long)b * HW + t) * 8) = make_uint4(w0, w1, 0u, 0u);
+    }
 }
 
 hipError_t cnn_features_batch(const ImageDesc* desc, const Counters* ctr, int nimg, int l, int H, int W,
-                              float* x, hipStream_t st, const int* imap)
+                              float* x, uint16_t* xb, hipStream_t st, const int* imap)
 {
     const long long HW = (long long)H * W;
+    if (HW >= (1LL << 31) || (!x && !xb)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cnn_features_batch, dim3((unsigned)((HW + 255) / 256), nimg), dim3(256), 0, st, desc, ctr,
-                       l, H, W, x, imap);
+                       l, H, W, x, xb, imap);
     return hipGetLastError();
 }
 
@@ -765,8 +772,9 @@ hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N
     return hipGetLastError();
 }
 
-// Proposals: one thread per (vertex, output) of image blockIdx.y.  Level-(l+2)
-// proposals are compacted with a wave ballot into the trace list of pass l+1.
+// Proposals: one thread per vertex of image blockIdx.y and output blockIdx.z.
+// Level-(l+2) proposals are compacted with a wave ballot into the trace list
+// of pass l+1.
 __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ logits,
                                                      const ImageDesc* __restrict__ desc, int l, int H, int W,
                                                      float z_hi, float z_lo, int all_levels,
@@ -774,23 +782,22 @@ __global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ l
                                                      Counters* __restrict__ ctr, const int* __restrict__ imap)
 {
     const int b = blockIdx.y;                 // slot of the logits
+    const int k = blockIdx.z;                 // output (owned point)
     const int img = imap ? imap[b] : b;       // image of the batch
     const ImageDesc& D = desc[img];
-    const long long HW = (long long)H * W;
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int HW = H * W;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
     // the network decides for this image only where it can look ahead (its
     // level count reaches l + 2) or everywhere with all_levels; an image with
     // one level left keeps the plain criterion (marks left undecided)
     const bool decides = D.levels >= l + 2 || all_levels;
     bool app = false;
     long long pix = 0;
-    if (t < HW * kCnnOut) {
-        const int k = (int)(t / HW);
-        const long long v = t - (long long)k * HW;
-        const int j = (int)(v / W), i = (int)(v - (long long)j * W);
+    if (v < HW) {
+        const int j = v / W, i = v - j * W;
         int lev;
         if (owned_point(k, i, j, l, D.levels, D.nx0, D.ny0, D.nx, pix, lev)) {
-            const float z = logits[(long long)b * kCnnOut * HW + t];
+            const float z = logits[((long long)b * kCnnOut + k) * HW + v];
             if (!decides) {
                 D.level[pix] = kMarkUnset;
             } else if (z > z_hi) {
@@ -831,9 +838,10 @@ hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int
                        float z_lo, int all_levels, unsigned long long* list, Counters* ctr, hipStream_t s,
                        const int* imap)
 {
-    const long long n = (long long)H * W * kCnnOut;
-    hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((n + 255) / 256), nimg), dim3(256), 0, s, logits, desc, l, H,
-                       W, z_hi, z_lo, all_levels, list, ctr, imap);
+    const long long HW = (long long)H * W;
+    if (HW >= (1LL << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((HW + 255) / 256), nimg, kCnnOut), dim3(256), 0, s, logits,
+                       desc, l, H, W, z_hi, z_lo, all_levels, list, ctr, imap);
     return hipGetLastError();
 }
 

@@ -52,9 +52,10 @@ hipError_t cnn_input_bf16(const float* x, long long B, long long HW, uint16_t* y
 hipError_t cnn_features(const double* img, const RayFeat* feat, long long nx, int s, int H, int W,
                         double nabs, float* x, hipStream_t st);
 // Same for images of a batch: x[b][3][H][W] for image imap[b] (b < nimg; all
-// images in order if imap is null), N_abs from the counters.
+// images in order if imap is null), N_abs from the counters; with x null the
+// network's BF16 input xb[b][H][W][8] instead (cnn_input_bf16's rounding).
 hipError_t cnn_features_batch(const ImageDesc* desc, const Counters* ctr, int nimg, int l, int H, int W,
-                              float* x, hipStream_t st, const int* imap = nullptr);
+                              float* x, uint16_t* xb, hipStream_t st, const int* imap = nullptr);
 // Labels of one plain render's level map at level l: lab/val[15][H][W].
 hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N, int l, uint8_t* lab,
                       uint8_t* val, hipStream_t s);
@@ -75,7 +76,6 @@ struct CnnWork {
     uint16_t* x = nullptr;     // input [B][H][W][8] bf16
     uint16_t* act[3] = {};     // post-ReLU activations [B][H][W][32]
     float* logits = nullptr;   // [B][15][H][W]
-    float* xf = nullptr;       // FP32 features [B][3][H][W]
 };
 
 // Network state (device): FP32 master parameters in the flat order
@@ -108,7 +108,8 @@ struct CnnNet {
 // Grow a workspace to P positions (synchronises the device when it grows).
 int cnn_work_reserve(CnnWork* w, long long P);
 void cnn_work_free(CnnWork* w);
-// Logits of B feature grids x_dev [B][3][H][W] into logits [B][15][H][W].
+// Logits of B feature grids x_dev [B][3][H][W] into logits [B][15][H][W]
+// (x_dev null: the BF16 input is already in w->x).
 hipError_t cnn_net_forward(const CnnNet* n, CnnWork* w, const float* x_dev, int B, int H, int W, float* logits,
                            hipStream_t s);
 

@@ -83,7 +83,7 @@ namespace art {
 
 void cnn_work_free(CnnWork* w)
 {
-    void* ptrs[] = { w->x, w->act[0], w->act[1], w->act[2], w->logits, w->xf };
+    void* ptrs[] = { w->x, w->act[0], w->act[1], w->act[2], w->logits };
     for (void* q : ptrs) free_ptr(q);
     *w = CnnWork();
 }
@@ -94,10 +94,10 @@ int cnn_work_reserve(CnnWork* w, long long P)
     (void)hipDeviceSynchronize();
     cnn_work_free(w);
     void** bufs[] = { (void**)&w->x, (void**)&w->act[0], (void**)&w->act[1], (void**)&w->act[2],
-                      (void**)&w->logits, (void**)&w->xf };
+                      (void**)&w->logits };
     const size_t per[] = { 8 * sizeof(uint16_t), 32 * sizeof(uint16_t), 32 * sizeof(uint16_t),
-                           32 * sizeof(uint16_t), kCnnOut * sizeof(float), kCnnIn * sizeof(float) };
-    for (int i = 0; i < 6; ++i)
+                           32 * sizeof(uint16_t), kCnnOut * sizeof(float) };
+    for (int i = 0; i < 5; ++i)
         if (hipMalloc(bufs[i], per[i] * (size_t)P) != hipSuccess) {
             cnn_work_free(w);
             return api_fail(ART_ENOMEM, "hipMalloc(network workspace, %lld positions) failed", P);
@@ -110,7 +110,7 @@ hipError_t cnn_net_forward(const CnnNet* n, CnnWork* w, const float* x_dev, int 
                            hipStream_t s)
 {
     const long long HW = (long long)H * W;
-    hipError_t e = cnn_input_bf16(x_dev, B, HW, w->x, s);
+    hipError_t e = x_dev ? cnn_input_bf16(x_dev, B, HW, w->x, s) : hipSuccess;
     if (e != hipSuccess) return e;
     const uint16_t* in = w->x;
     for (int l = 0; l < 3; ++l) {
