@@ -288,7 +288,7 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
         const double th_ref = Th0 * std::pow(rref, -em->params[7]);
         const double me = 9.1093837015e-28;
         P.Bref = std::sqrt(8.0 * M_PI * ne_ref * me * C * C * th_ref / beta);
-        P.r_ref = rref;
+        P.lnr_ref = std::log(rref);
         P.psi_c = std::cos(em->params[4]);
         P.psi_s = std::sin(em->params[4]);
     }

@@ -46,7 +46,7 @@ struct Params {
     int32_t model, nstokes, max_steps, nsub;   // nsub: subring planes of I (0..8)
     double freq, L_cm;
     double mp[16];
-    double Bref, r_ref, psi_c, psi_s;   // thermal: |B| at r_ref, field phase
+    double Bref, lnr_ref, psi_c, psi_s;   // thermal: |B| at r_ref, ln r_ref, field phase
     const float* grid;             // gridded model: [n3][n2][n1][8] cell-centre fields
     const double* theta_tab;       // gridded model: theta of the n2 cell centres
     double B_unit;                 // gridded model: Gauss per code field unit
@@ -118,20 +118,25 @@ __device__ __forceinline__ float flog1p(float x)
     const float u = 1.0f + x;
     return u == 1.0f ? x : flog(u) * (x * frcp(u - 1.0f));
 }
-__device__ __forceinline__ float fexpm1(float x)
+// e^x - 1 given u = fexp(x) (the compensation above; FP64: the library).
+__device__ __forceinline__ float fexpm1_u(float x, float u)
 {
-    const float u = fexp(x);
     if (u == 1.0f) return x;
     const float um = u - 1.0f;
     if (um == -1.0f || __builtin_isinf(u)) return um;
     return um * (x * frcp(flog(u)));
 }
+__device__ __forceinline__ double fexpm1_u(double x, double) { return ::expm1(x); }
+__device__ __forceinline__ float fexpm1(float x) { return fexpm1_u(x, fexp(x)); }
 
 // sin and cos of theta + d from sin, cos of theta for a small increment d
-// (|d| <= 0.25: Taylor series to d^13, then the angle-addition formulas).
+// (|d| <= 1/8: Taylor series of sin d to d^9 and of 1 - cos d to d^10, whose
+// first omitted terms are below 2.5e-17 relative; then the angle-addition
+// formulas).  The step rule keeps |h dtheta/dlambda| <= eps * 4, so the
+// library branch is the exception.
 __device__ __forceinline__ void rotate_sc(double s0, double c0, double d, double& s, double& c)
 {
-    if (::fabs(d) > 0.25) {
+    if (::fabs(d) > 0.125) {
         double sd, cd;
         ::sincos(d, &sd, &cd);
         s = s0 * cd + c0 * sd;
@@ -139,8 +144,8 @@ __device__ __forceinline__ void rotate_sc(double s0, double c0, double d, double
         return;
     }
     const double d2 = d * d;
-    const double sd = d * (1.0 - d2 * (1.0 / 6.0) * (1.0 - d2 * (1.0 / 20.0) * (1.0 - d2 * (1.0 / 42.0) * (1.0 - d2 * (1.0 / 72.0) * (1.0 - d2 * (1.0 / 110.0) * (1.0 - d2 * (1.0 / 156.0)))))));
-    const double cm = d2 * (1.0 / 2.0) * (1.0 - d2 * (1.0 / 12.0) * (1.0 - d2 * (1.0 / 30.0) * (1.0 - d2 * (1.0 / 56.0) * (1.0 - d2 * (1.0 / 90.0) * (1.0 - d2 * (1.0 / 132.0))))));
+    const double sd = d * (1.0 - d2 * (1.0 / 6.0) * (1.0 - d2 * (1.0 / 20.0) * (1.0 - d2 * (1.0 / 42.0) * (1.0 - d2 * (1.0 / 72.0)))));
+    const double cm = d2 * (1.0 / 2.0) * (1.0 - d2 * (1.0 / 12.0) * (1.0 - d2 * (1.0 / 30.0) * (1.0 - d2 * (1.0 / 56.0) * (1.0 - d2 * (1.0 / 90.0)))));
     // cos d = 1 - cm; keep the small correction separate for accuracy
     s = s0 + (c0 * sd - s0 * cm);
     c = c0 - (s0 * sd + c0 * cm);
@@ -328,9 +333,11 @@ __device__ __forceinline__ void thermal_coefs(R ne, R Th, R B, R nu, R cth,
     }
     // 1/B_nu = expm1(q) c^2 / (2 h nu^3) with q = h nu / (Theta m c^2), written as
     // (expm1(q)/q) / (2 Theta m nu^2) so that no factor leaves the FP32 range
+    // (1/q and 1/(2 Theta m nu^2) from the reciprocals of Theta and nu:
+    // nu^-2 >= 1e-26 and 1/m ~ 1e27 for the frequencies of the method)
     const R q = R(kH / (kMe * kC * kC)) * nu * iTh;
-    const R phq = q < R(1e-6) ? R(1) + R(0.5) * q : fexpm1(q) * frcp(q);
-    const R iBnu = phq * frcp(R(2) * Th * (R(kMe) * nu) * nu);
+    const R phq = q < R(1e-6) ? R(1) + R(0.5) * q : fexpm1(q) * (Th * inu * R(kMe * kC * kC / kH));
+    const R iBnu = phq * ((R(0.5 / kMe) * iTh) * (inu * inu));
     jI = jI_; jQ = -jQ_; jV = jV_;
     aI = jI_ * iBnu; aQ = -jQ_ * iBnu; aV = jV_ * iBnu;
 }
@@ -443,7 +450,7 @@ __device__ __forceinline__ bool plasma_point(const Params& P, const double* tht,
             const R lr = flog(R(r));
             ne = R(P.mp[0]) * fexp(-R(P.mp[6]) * lr);
             Th = R(P.mp[1]) * fexp(-R(P.mp[7]) * lr);
-            Bm = R(P.Bref) * fexp(-R(P.mp[8]) * (lr - flog(R(P.r_ref))));
+            Bm = R(P.Bref) * fexp(-R(P.mp[8]) * (lr - R(P.lnr_ref)));
             G vr, vp;
             flow_v3<G>(P, r, dr, vr, vp);
             v3[0] = vr; v3[1] = G(0); v3[2] = vp;
@@ -552,30 +559,45 @@ __device__ __forceinline__ R h_poly(R v2)
 __device__ __forceinline__ void fsincos(double x, double* s, double* c) { ::sincos(x, s, c); }
 __device__ __forceinline__ void fsincos(float x, float* s, float* c) { ::sincosf(x, s, c); }
 
-// Coefficients c0..c3 with exp(-aI x) exp(-A x) = c0 + c1 A + c2 A^2 + c3 A^3.
-// The eigenvalues of A are +-L1, +-i L2 (L1^2 - L2^2 = |a|^2 - |r|^2,
-// L1 L2 = a.r); with u = x L1, v = x L2, w = x aI (u <= w for physical
-// coefficients):
+// Invariants of A = [[0, a^T], [a, K]] (a = (aQ, aU, aV), K x = x × rho)
+// shared by every exponential of one step: |a|^2, |rho|^2, a.rho and the
+// eigenvalue parameters (the eigenvalues of A are +-L1, +-i L2 with
+// L1^2 - L2^2 = |a|^2 - |rho|^2, L1 L2 = a.rho, D = L1^2 + L2^2).
+template <typename R>
+struct LorentzInv {
+    R a2, r2, ad, D, iD, L1s, L2s, L1, L2;
+};
+template <typename R>
+__device__ __forceinline__ LorentzInv<R> lorentz_inv(const R av[3], const R rv[3])
+{
+    LorentzInv<R> L;
+    L.a2 = av[0] * av[0] + av[1] * av[1] + av[2] * av[2];
+    L.r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+    L.ad = av[0] * rv[0] + av[1] * rv[1] + av[2] * rv[2];
+    const R dl = L.a2 - L.r2;
+    L.D = fsqrt(dl * dl + R(4) * L.ad * L.ad);
+    L.iD = L.D > R(0) ? frcp(L.D) : R(0);
+    L.L1s = R(0.5) * (L.D + dl); L.L1s = L.L1s < R(0) ? R(0) : L.L1s;
+    L.L2s = R(0.5) * (L.D - dl); L.L2s = L.L2s < R(0) ? R(0) : L.L2s;
+    L.L1 = fsqrt(L.L1s);
+    L.L2 = fsqrt(L.L2s);
+    return L;
+}
+
+// Coefficients c0..c3 with exp(-aI x) exp(-A x) = c0 + c1 A + c2 A^2 + c3 A^3;
+// with u = x L1, v = x L2, w = x aI (u <= w for physical coefficients):
 //   c2 = x^2/2 (L1^2 e^-w shc(u/2)^2 + L2^2 e^-w sinc(v/2)^2) / D
 //   c1 = -x (L2^2 e^-w shc(u) + L1^2 e^-w sinc(v)) / D
-//   c3 = -x^3 (L1^2 e^-w g(u) + L2^2 e^-w h(v)) / D,   c0 = e^-w cosh u - L1^2 c2,
-// D = L1^2 + L2^2.  Exponentials: e^-w and e^u (square roots give the half
-// arguments); sin/cos of v/2 give sin v and the half-argument sinc.
+//   c3 = -x^3 (L1^2 e^-w g(u) + L2^2 e^-w h(v)) / D,   c0 = e^-w cosh u - L1^2 c2.
+// The caller supplies w, ew = e^-w and ew2 = e^-w/2 (1, 1 for an undamped
+// exponential, folded at compile time); e^u and square roots give the half
+// arguments, sin/cos of v/2 give sin v and the half-argument sinc.
 template <typename R>
-__device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3], R x,
+__device__ __forceinline__ void lorentz_coeffs(const LorentzInv<R>& L, R x, R w, R ew, R ew2,
                                                R& c0, R& c1, R& c2, R& c3)
 {
-    const R a2 = av[0] * av[0] + av[1] * av[1] + av[2] * av[2];
-    const R r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
-    const R ad = av[0] * rv[0] + av[1] * rv[1] + av[2] * rv[2];
-    const R dl = a2 - r2;
-    const R D = fsqrt(dl * dl + R(4) * ad * ad);
-    R L1s = R(0.5) * (D + dl); L1s = L1s < R(0) ? R(0) : L1s;
-    R L2s = R(0.5) * (D - dl); L2s = L2s < R(0) ? R(0) : L2s;
-    const R L1 = fsqrt(L1s), L2 = fsqrt(L2s);
-    const R u = x * L1, v = x * L2, w = x * aI;
-    const R ew = fexp(-w);
-    const R ew2 = fsqrt(ew);                 // e^-w/2
+    const R L1s = L.L1s, L2s = L.L2s;
+    const R u = x * L.L1, v = x * L.L2;
     // hyperbolic parts, damped by e^-w
     R ch, shc, sh2, gu;
     const R u2 = u * u;
@@ -617,8 +639,8 @@ __device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3
         sn2 = R(2) * sh * iv;
         hv = (R(1) - snc) * (iv * iv);
     }
-    if (D > R(0)) {
-        const R iD = frcp(D);
+    if (L.D > R(0)) {
+        const R iD = L.iD;
         c2 = R(0.5) * x * x * (L1s * sh2 * sh2 + L2s * ew * sn2 * sn2) * iD;
         c1 = -x * (L2s * shc + L1s * ew * snc) * iD;
         c3 = -x * x * x * (L1s * gu + L2s * ew * hv) * iD;
@@ -630,17 +652,29 @@ __device__ __forceinline__ void lorentz_coeffs(R aI, const R av[3], const R rv[3
     c0 = ch - L1s * c2;
 }
 
+// Step functions of the optical depth w = aI h, from ew = e^-w (computed
+// once per step): phi1(w) = (1 - e^-w)/w, the weight of the step's emission,
+// and the mean depth m(w) = 1/w - 1/(e^w - 1) = 1/w + 1 + 1/(e^-w - 1) at
+// which the emission integral's exponential is evaluated (series below the
+// cancellation thresholds).
 template <typename R>
-__device__ __forceinline__ R phi1_(R w)
+__device__ __forceinline__ void depth_fns(R w, R ew, R& phi1, R& mdepth)
 {
-    if (w < R(1e-4)) return R(1) + w * (R(-1.0 / 2.0) + w * (R(1.0 / 6.0) + w * R(-1.0 / 24.0)));
-    return -fexpm1(-w) * frcp(w);
+    const R em1 = w < R(1e-4) ? R(0) : fexpm1_u(-w, ew);
+    const R iw = w < R(1e-4) ? R(0) : frcp(w);
+    phi1 = w < R(1e-4) ? R(1) + w * (R(-1.0 / 2.0) + w * (R(1.0 / 6.0) + w * R(-1.0 / 24.0))) : -em1 * iw;
+    if (w < R(0.1)) {
+        const R w2 = w * w;
+        mdepth = R(0.5) + w * (R(-1.0 / 12.0) + w2 * (R(1.0 / 720.0) + w2 * R(-1.0 / 30240.0)));
+    } else {
+        mdepth = (iw + R(1)) + frcp(em1);
+    }
 }
 template <typename R>
-__device__ __forceinline__ R mean_depth_(R w)
+__device__ __forceinline__ R phi1_(R w, R ew)
 {
-    if (w < R(0.1)) { const R w2 = w * w; return R(0.5) + w * (R(-1.0 / 12.0) + w2 * (R(1.0 / 720.0) + w2 * R(-1.0 / 30240.0))); }
-    return frcp(w) - frcp(fexpm1(w));
+    if (w < R(1e-4)) return R(1) + w * (R(-1.0 / 2.0) + w * (R(1.0 / 6.0) + w * R(-1.0 / 24.0)));
+    return -fexpm1_u(-w, ew) * frcp(w);
 }
 
 // y = A x for A = [[0,aQ,aU,aV],[aQ,0,rV,-rU],[aU,-rV,0,rQ],[aV,rU,-rQ,0]]
@@ -661,14 +695,13 @@ __device__ __forceinline__ void applyA(const Coef<R>& K, const R x[4], R y[4])
 // 60-odd operations, then O M in 64 against 208 for three row products per
 // row of O.
 template <typename R>
-__device__ __forceinline__ void lorentz_matrix(const Coef<R>& K, R c0, R c1, R c2, R c3, R M[16])
+__device__ __forceinline__ void lorentz_matrix(const Coef<R>& K, const LorentzInv<R>& L, R c0, R c1, R c2, R c3,
+                                               R M[16])
 {
     const R a[3] = { K.aQ, K.aU, K.aV };
     const R q[3] = { K.rQ, K.rU, K.rV };
     const R w[3] = { a[1] * q[2] - a[2] * q[1], a[2] * q[0] - a[0] * q[2], a[0] * q[1] - a[1] * q[0] };
-    const R sa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-    const R sr = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-    const R p = a[0] * q[0] + a[1] * q[1] + a[2] * q[2];
+    const R sa = L.a2, sr = L.r2, p = L.ad;
     const R e = c1 + c3 * (sa - sr), f = c3 * p;      // c1 a + c3 u = e a + f rho
     M[0] = c0 + c2 * sa;
 #pragma unroll
@@ -695,22 +728,27 @@ __device__ __forceinline__ void lorentz_matrix(const Coef<R>& K, R c0, R c1, R c
 }
 
 // One constant-coefficient polarised step of affine length h:
-//   S += O * h phi1(aI h) exp(-A sbar) J,   O <- O exp(-aI h) exp(-A h).
+//   S += O * h phi1(aI h) exp(-A sbar) J,   O <- O exp(-aI h) exp(-A h),
+// sbar = h m(aI h); both exponentials share the invariants of A and e^-aI h.
 template <typename R, typename RS>
 __device__ __forceinline__ void transfer_step4(RS S[4], R O[16], const Coef<R>& K, R h)
 {
     const R av[3] = { K.aQ, K.aU, K.aV };
     const R rv[3] = { K.rQ, K.rU, K.rV };
+    const LorentzInv<R> L = lorentz_inv<R>(av, rv);
     const R w = K.aI * h;
-    const R sbar = h * mean_depth_(w);
+    const R ew = fexp(-w);
+    R ph1, md;
+    depth_fns<R>(w, ew, ph1, md);
+    const R sbar = h * md;
     R g0, g1, g2, g3;
-    lorentz_coeffs<R>(R(0), av, rv, sbar, g0, g1, g2, g3);
+    lorentz_coeffs<R>(L, sbar, R(0), R(1), R(1), g0, g1, g2, g3);
     const R J[4] = { K.jI, K.jQ, K.jU, K.jV };
     R AJ[4], A2J[4], A3J[4];
     applyA(K, J, AJ);
     applyA(K, AJ, A2J);
     applyA(K, A2J, A3J);
-    const R sc = h * phi1_(w);
+    const R sc = h * ph1;
     R d[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = sc * (g0 * J[i] + g1 * AJ[i] + g2 * A2J[i] + g3 * A3J[i]);
@@ -718,9 +756,9 @@ __device__ __forceinline__ void transfer_step4(RS S[4], R O[16], const Coef<R>& 
     for (int i = 0; i < 4; ++i)
         S[i] += RS(O[i * 4 + 0] * d[0] + O[i * 4 + 1] * d[1] + O[i * 4 + 2] * d[2] + O[i * 4 + 3] * d[3]);
     R c0, c1, c2, c3;
-    lorentz_coeffs<R>(K.aI, av, rv, h, c0, c1, c2, c3);
+    lorentz_coeffs<R>(L, h, w, ew, fsqrt(ew), c0, c1, c2, c3);
     R M[16];
-    lorentz_matrix<R>(K, c0, c1, c2, c3, M);
+    lorentz_matrix<R>(K, L, c0, c1, c2, c3, M);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const R x[4] = { O[i * 4 + 0], O[i * 4 + 1], O[i * 4 + 2], O[i * 4 + 3] };

@@ -138,8 +138,9 @@ __device__ __forceinline__ int ray_step(const Params& P, const double* tht, RayS
             transfer_step4<R, R>(st.S, st.O, C, R(h));
         } else {
             const R w = C.aI * R(h);
-            st.S[0] += st.O[0] * R(h) * phi1_(w) * C.jI;
-            st.O[0] *= fexp(-w);
+            const R ew = fexp(-w);
+            st.S[0] += st.O[0] * R(h) * phi1_(w, ew) * C.jI;
+            st.O[0] *= ew;
         }
         if constexpr (SUB > 0) {
             // subring decomposition (Sec. 5.1): the step's increment of I goes
