@@ -271,6 +271,11 @@ void make_params(const art_spacetime* sp, const art_camera* cam, const art_emiss
     P.c_ghh = Sig;
     P.c_gpp = (r * r + a * a + 2.0 * a * a * r * s * s / Sig) * s * s;
     P.c_del = Del;
+    P.s_cam = s;
+    P.c_cam = c;
+    P.ic_al = 1.0 / P.c_al;
+    P.ic_del = 1.0 / Del;
+    P.ic_ep = std::sqrt(A / Sig) * s;
     P.risco = r_isco(a);
     circ_EL(a, P.risco, &P.Eis, &P.Lis);
     P.model = em->kind;

@@ -41,6 +41,9 @@ struct Params {
     // ZAMO frame and BL metric at the camera
     double c_al, c_om, c_er, c_eh, c_ep;
     double c_gtt, c_gtp, c_grr, c_ghh, c_gpp, c_del;
+    // per-image constants of the ray start: sin, cos of th_cam, 1/c_al,
+    // 1/c_del, 1/c_ep (computed on the host once, not per ray)
+    double s_cam, c_cam, ic_al, ic_del, ic_ep;
     // equatorial flow: ISCO radius, energy, angular momentum
     double risco, Eis, Lis;
     int32_t model, nstokes, max_steps, nsub;   // nsub: subring planes of I (0..8)
@@ -225,7 +228,7 @@ __device__ __forceinline__ void camera_start(const Params& P, double al, double 
     const double r = P.r_cam;
     const double inrm = 1.0 / ::sqrt(r * r + al * al + be * be);
     const double dr = -r * inrm, dh = -be * inrm, dp = al * inrm;
-    const double iual = 1.0 / P.c_al;
+    const double iual = P.ic_al;
     const double ku_t = -iual;
     const double ku_r = dr * P.c_er;
     const double ku_h = dh * P.c_eh;
@@ -235,9 +238,9 @@ __device__ __forceinline__ void camera_start(const Params& P, double al, double 
     const double kth = P.c_ghh * ku_h;
     // k_phi = sqrt(g_phiphi) (k . e_(phi)) = dp / e_phi: the ZAMO observer has no
     // angular momentum, so alpha = 0 gives k_phi = 0 exactly
-    const double kph = dp * frcp(P.c_ep);
+    const double kph = dp * P.ic_ep;
     (void)ku_p;
-    const double iD = 1.0 / P.c_del;
+    const double iD = P.ic_del;
     R.y[0] = r;
     R.y[1] = P.th_cam;
     R.y[2] = P.phi_cam;
@@ -251,9 +254,7 @@ __device__ __forceinline__ void camera_start(const Params& P, double al, double 
     fr *= ifn; fh *= ifn; fp *= ifn;
     const double kup[4] = { ku_t, ku_r, ku_h, ku_p };
     const double fup[4] = { 0.0, fr * P.c_er, fh * P.c_eh, fp * P.c_ep };
-    double s, c;
-    ::sincos(P.th_cam, &s, &c);
-    walker_penrose(P.a, r, s, c, kup, fup, R.k0r, R.k0i);
+    walker_penrose(P.a, r, P.s_cam, P.c_cam, kup, fup, R.k0r, R.k0i);
 }
 
 // ------------------------------------------------------------- fluid model

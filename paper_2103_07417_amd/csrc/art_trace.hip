@@ -34,7 +34,8 @@ __device__ __forceinline__ void ray_init(const Params& P, RayState<R, MODEL, NS,
 #pragma unroll
     for (int i = 0; i < 5; ++i) st.y[i] = rs.y[i];
     st.kt = rs.kt; st.kph = rs.kph; st.k0r = rs.k0r; st.k0i = rs.k0i;
-    ::sincos(rs.y[1], &st.sth, &st.cth);
+    st.sth = P.s_cam;                  // the ray starts at the camera's theta
+    st.cth = P.c_cam;
     st.cprev = st.cth;
     st.rmin = rs.y[0];
 #pragma unroll
