@@ -83,8 +83,8 @@ BYTES_PER_RAY = 58
 # HBM traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE counter runs
 # of this benchmark, per render of the headline form; valid only for the
 # kernel sources it was measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=376705222, kernel_hash="7e97b7bd5e7e51a7", form="learned_batched",
-               precision="mixed_geo",
+TRAFFIC = dict(bytes_per_render=429407745, kernel_hash="1013ae1ac963895c", form="learned_batched",
+               precision="mixed",
                source="profiles/k_trace_learned_batched_uneven_64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
 TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
@@ -373,7 +373,13 @@ def c4_forms(art, torch, art_inputs, args):
         for X in bset:
             X.set_learned(None) if opts is None else X.set_learned(net, **opts)
         depth, launch, tune = nmax, dict(trace_blocks=512, trace_threads=256, refill=1, groups=1), None
-        if not args.no_autotune:
+        if args.launch:
+            # a fixed shape (counter runs serialise dispatches, which would
+            # steer the in-flight search to other shapes than the timed run's)
+            tb, tt = (int(v) for v in args.launch.lower().split("x"))
+            launch = dict(trace_blocks=tb, trace_threads=tt, refill=1, groups=1)
+            depth = args.in_flight or 3
+        elif not args.no_autotune:
             depths = (args.in_flight,) if args.in_flight else IN_FLIGHT_DEPTHS
             tune = autotune.autotune_in_flight(bset, ss, depths=depths, log=None)
             depth = tune["in_flight"]
@@ -877,8 +883,8 @@ def plain_single(art, torch, cfg, args):
     plain = dict(ms_per_image=dt * 1e3, rays=rays // args.steps, passes=st["trace_launches"],
                  rays_per_s=rays / args.steps / dt, effective_px_per_s=nx * ny / dt,
                  interp_frac=st["interp_frac"], mse=mse, flux_error=fe)
-    uniform = dict(ms=t_uniform * 1e3, rays=ust["rays"], rays_per_s=ust["rays"] / t_uniform,
-                   effective_px_per_s=nx * ny / t_uniform)
+    uniform = dict(ms=t_uniform * 1e3, rays=ust["rays"], steps=ust["steps"], steps_emit=ust["steps_emit"],
+                   rays_per_s=ust["rays"] / t_uniform, effective_px_per_s=nx * ny / t_uniform)
     return plain, uniform
 
 
@@ -894,6 +900,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--in-flight", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="batches in flight in the timed step (0: autotuned over 2-4)")
+    ap.add_argument("--launch", default="",
+                    help="persistent-tracer shape BLOCKSxTHREADS of the timed forms instead of the in-flight "
+                         "autotuner (with --in-flight, else three batches in flight)")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-deploy", action="store_true")
     ap.add_argument("--no-spectral", action="store_true")
