@@ -83,7 +83,7 @@ BYTES_PER_RAY = 58
 # HBM traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE counter runs
 # of this benchmark, per render of the headline form; valid only for the
 # kernel sources it was measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=429407745, kernel_hash="1013ae1ac963895c", form="learned_batched",
+TRAFFIC = dict(bytes_per_render=435287709, kernel_hash="1013ae1ac963895c", form="learned_batched",
                precision="mixed",
                source="profiles/k_trace_learned_batched_uneven_64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
