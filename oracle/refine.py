@@ -118,7 +118,7 @@ def linear_margin(D, S, magD, magS, thrA, crel):
                       [magD + thrA, magD + crel * magS])
 
 
-def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False, with_mag=False):
+def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False, with_mag=False, mag_all=False):
     """Stencil sums for every new point of level l+1 (Sec. 3.2 categories 2-4).
 
     img holds the level-l values at multiples of 2s (final-grid units).
@@ -126,7 +126,8 @@ def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False, with_mag=False
     S per Stokes plane, the second-difference sum D of Stokes I (of every
     plane, shape (nstokes, n), with all_planes), the no-available-axis flag
     and the neighbour count m.  with_mag adds the magnitude sums of D's terms
-    (same shape as D) and of Stokes I's neighbours (for tie margins).
+    (same shape as D) and of Stokes I's neighbours (for tie margins; of every
+    plane's neighbours, shape (nstokes, n), with mag_all).
     """
     nxl, nyl = grid_size(nx0, l + 1), grid_size(ny0, l + 1)
     q, p = np.meshgrid(np.arange(nyl), np.arange(nxl), indexing="ij")
@@ -147,7 +148,7 @@ def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False, with_mag=False
     nd = nstokes if all_planes else 1
     D = np.zeros((nd, npt))
     magD = np.zeros((nd, npt))
-    magS = np.zeros(npt)
+    magS = np.zeros((nstokes, npt))
     inf = np.zeros(npt, dtype=bool)
     m = np.where(cat4, 4.0, 2.0)
     # categories 2 and 3: one axis (dx, dy) = (0, 1) or (1, 0)
@@ -157,8 +158,7 @@ def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False, with_mag=False
             lo_in, _ = val(pc - dx, qc - dy, st)
             hi_in, _ = val(pc + dx, qc + dy, st)
             S_all[st, cat] = lo_in + hi_in
-            if st == 0:
-                magS[cat] = np.abs(lo_in) + np.abs(hi_in)
+            magS[st, cat] = np.abs(lo_in) + np.abs(hi_in)
         for st in range(nd):
             lo_in, _ = val(pc - dx, qc - dy, st)
             hi_in, _ = val(pc + dx, qc + dy, st)
@@ -176,8 +176,7 @@ def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False, with_mag=False
         i2, _ = val(pc + 1, qc - 1, st)
         i3, _ = val(pc - 1, qc + 1, st)
         S_all[st, cat4] = (i1 + i4) + (i2 + i3)
-        if st == 0:
-            magS[cat4] = np.abs(i1) + np.abs(i4) + np.abs(i2) + np.abs(i3)
+        magS[st, cat4] = np.abs(i1) + np.abs(i4) + np.abs(i2) + np.abs(i3)
     for st in range(nd):
         i1, _ = val(pc - 1, qc - 1, st)
         i4, _ = val(pc + 1, qc + 1, st)
@@ -194,7 +193,7 @@ def level_stencil(img, nx0, ny0, l, s, nstokes, all_planes=False, with_mag=False
         inf[cat4] = infx & infy
     out = (p, q, S_all, (D if all_planes else D[0]), inf, m)
     if with_mag:
-        out = out + ((magD if all_planes else magD[0]), magS)
+        out = out + ((magD if all_planes else magD[0]), (magS if mag_all else magS[0]))
     return out
 
 
@@ -245,7 +244,12 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
     interp: "linear" (Eqs. 5-6 linear branch, interpolation by the neighbour
     mean) or "nearest" (Eqs. 5-6 nearest branch, the nearest neighbour's
     value).  all_planes: the decision is the OR of the criterion over every
-    plane, each plane's estimate measured against N_abs and |Stokes I|.
+    plane, each plane's estimate measured against N_abs and |Stokes I|;
+    all_planes="own": each plane measured against its own normalisation (the
+    trapezoid mean, or with abs_norm="max" the maximum, of |plane| over the
+    base grid) and its own neighbour sum |S_plane| (linear branch), so a
+    faint plane (a high-order subring, polarisation) is refined where it has
+    structure of its own.
     alt: optional cheaper source of values, alt(i, j) -> (ok, values) for
     final-grid points (i, j); it is consulted for every base point and for
     every point the criterion flags, and points where ok holds take its
@@ -305,6 +309,12 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
     ibar = trapezoid_mean(I0)
     imax0 = float(I0.max())
     n_abs = ibar if abs_norm == "mean" else imax0
+    own_norm = all_planes == "own"
+    if own_norm and interp != "linear":
+        raise ValueError("own-normalisation planes are defined for the linear branch")
+    # every plane's normalisation (plane 0: Stokes I's, the usual one)
+    n_abs_p = [n_abs] + [trapezoid_mean(np.abs(img[st, jj, ii])) if abs_norm == "mean"
+                         else float(np.abs(img[st, jj, ii]).max()) for st in range(1, nstokes)]
     cand, traced = [nx0 * ny0], [ntr0]
     for l in range(levels):
         s = 1 << (levels - l - 1)          # spacing of the level-(l+1) grid
@@ -328,18 +338,19 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
                 margin = np.where(nan0, np.inf, margin)
             interp_vals = Inn
         else:
-            p, q, S_all, D, inf, m, magD, magS = level_stencil(img, nx0, ny0, l, s, nstokes,
-                                                               all_planes, with_mag=True)
+            p, q, S_all, D, inf, m, magD, magSa = level_stencil(img, nx0, ny0, l, s, nstokes,
+                                                                bool(all_planes), with_mag=True, mag_all=True)
             npt = p.size
             S = S_all[0]
-            thrA = (4.0 * m * r_abs) * n_abs
             crel = 4.0 * r_rel
             Ds = D if all_planes else D[None, :]
             Ms = magD if all_planes else magD[None, :]
             with np.errstate(invalid="ignore"):
                 decs, margins = [], []
-                for Dp, Mp in zip(Ds, Ms):
-                    d, mg = linear_margin(Dp, S, Mp, magS, thrA, crel)
+                for st, (Dp, Mp) in enumerate(zip(Ds, Ms)):
+                    pl = st if own_norm else 0
+                    thrA = (4.0 * m * r_abs) * n_abs_p[pl]
+                    d, mg = linear_margin(Dp, S_all[pl], Mp, magSa[pl], thrA, crel)
                     bad = np.isnan(Dp)
                     decs.append(d | bad)
                     margins.append(np.where(bad, np.inf, mg))
@@ -384,7 +395,7 @@ def refine(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm="mean",
         cand.append(int(npt))
         traced.append(int(dec.sum()))
     n_interp = int((lev < 0).sum())
-    return dict(img=img, level=lev, n_abs=n_abs, ibar=ibar, imax0=imax0,
+    return dict(img=img, level=lev, n_abs=n_abs, n_abs_planes=n_abs_p, ibar=ibar, imax0=imax0,
                 candidates=cand, traced=traced, rays=int(sum(traced)), spectral=nspec,
                 interp_frac=n_interp / float(nx * ny), nx=nx, ny=ny, audit=audit)
 

@@ -57,7 +57,7 @@ def run(fn, nplanes=1, **kw):
                          interp=kw.get("interp", "linear"), all_planes=kw.get("all_planes", False))
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(interp="nearest"), dict(all_planes=True)])
+@pytest.mark.parametrize("opts", [dict(), dict(interp="nearest"), dict(all_planes=True), dict(all_planes="own")])
 def test_unforced_audit_equals_own_map(opts):
     nplanes = 4 if opts.get("all_planes") else 1
     out = run(ray_fn_for(1, nplanes=nplanes), nplanes, **opts)
@@ -67,7 +67,7 @@ def test_unforced_audit_equals_own_map(opts):
     assert np.all(m >= 0) and np.isfinite(m).sum() > 100
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(interp="nearest"), dict(all_planes=True)])
+@pytest.mark.parametrize("opts", [dict(), dict(interp="nearest"), dict(all_planes=True), dict(all_planes="own")])
 @pytest.mark.parametrize("delta", [1e-9, 1e-6, 1e-3])
 def test_decisions_changed_by_a_perturbation_have_smaller_margins(opts, delta):
     nplanes = 4 if opts.get("all_planes") else 1

@@ -359,3 +359,35 @@ def test_all_planes_criterion(interp):
     b = refine.refine(_planes(sharp), 20.0, 9, 9, 1, 0.02, 0.01, "mean", 2, interp=interp, all_planes=True)
     ta, tb = a["level"] == 1, b["level"] == 1
     assert np.all(tb[ta]) and tb.sum() > ta.sum()
+
+
+def test_own_norm_planes_criterion():
+    """all_planes="own": every plane against its own normalisation and its own
+    neighbour sum.  A copy of I (or its negative) as second plane changes
+    nothing (the same test on the same magnitudes); scaling the second plane by
+    a power of two changes no decision (both thresholds scale with the plane,
+    exactly in binary); so a faint copy of a sharp feature is refined as fully
+    as the feature itself, while the shared normalisation (all_planes=True)
+    ignores it; a constant plane c has N_abs = |c| (trapezoid mean of |c|)."""
+    args = (20.0, 9, 9, 2, 0.02, 0.01, "mean", 2)
+    base = refine.refine(_planes(lambda x, y: ring(x, y)), *args)
+    for fn2 in (lambda x, y: ring(x, y), lambda x, y: -ring(x, y)):
+        o = refine.refine(_planes(fn2), *args, all_planes="own")
+        assert np.array_equal(o["level"], base["level"])
+    sharp = lambda x, y: np.stack([np.tanh((x - 1.3) / 0.2) + 1.5 * np.exp(-(x * x + (y - 2.0) ** 2))], -1)
+    faint = lambda x, y: sharp(x, y) * 2.0 ** -12
+    full = refine.refine(_planes(sharp), *args, all_planes="own")
+    own = refine.refine(_planes(faint), *args, all_planes="own")
+    assert np.array_equal(own["level"], full["level"])
+    assert np.isclose(own["n_abs_planes"][1], full["n_abs_planes"][1] * 2.0 ** -12, rtol=0, atol=0)
+    # one level (the same history for both): the shared normalisation's traced
+    # points are a strict subset of the own normalisation's
+    args1 = (20.0, 9, 9, 1, 0.02, 0.01, "mean", 2)
+    own1 = refine.refine(_planes(faint), *args1, all_planes="own")
+    shared1 = refine.refine(_planes(faint), *args1, all_planes=True)
+    t_own, t_sh = own1["level"] > 0, shared1["level"] > 0
+    assert np.all(t_own[t_sh]) and t_own.sum() >= t_sh.sum() + 5
+    const = refine.refine(_planes(lambda x, y: np.full((np.size(x), 1), -0.75)), *args, all_planes="own")
+    assert const["n_abs_planes"][1] == 0.75 and const["n_abs_planes"][0] == const["n_abs"]
+    with pytest.raises(ValueError):
+        refine.refine(_planes(sharp), *args, interp="nearest", all_planes="own")
