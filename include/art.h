@@ -131,7 +131,12 @@ typedef struct {
     int32_t interp;                /* ART_INTERP_* */
     int32_t all_planes;            /* 0: the criterion on Stokes I; 1: traced if the criterion
                                       holds on any image plane (Q, U, V, subrings), each
-                                      plane's estimate compared with N_abs and |Stokes I| */
+                                      plane's estimate compared with N_abs and |Stokes I|;
+                                      2 (linear branch only): the same OR with every plane
+                                      compared with its own normalisation (abs_norm applied
+                                      to |plane| on the base grid) and its own neighbour
+                                      sum, so faint planes are refined on their own
+                                      structure (Sec. 6's per-Stokes rule, Sec. 5.1) */
     int32_t pad;
 } art_refine;
 
@@ -433,7 +438,7 @@ int art_render_learned(const art_spacetime* sp, const art_camera* cam, const art
  *   |D| > 8 r_abs N_abs  and  |D| > 4 r_rel |b + c|,   D = (a + d) - (b + c)
  * (twice the one-sided second difference if a or d is outside the cube, never
  * accepted if both are; N_abs the mean of b's and c's own N_abs; every plane
- * with rf->all_planes); points it rejects are traced.  Level map: l = traced at
+ * with rf->all_planes, which must be 0 or 1 here); points it rejects are traced.  Level map: l = traced at
  * spatial level l, -1 spatially interpolated, -3 spectral value.  Eager (for
  * capture and replay see art_cube_create); camera levels + spectral levels
  * <= 21.  The decisions of

@@ -204,7 +204,7 @@ def blocks(cfg):
         em.grid_len = g.numel()
     rf = Refine(float(cfg.get("r_rel", -1.0)), float(cfg.get("r_abs", -1.0)),
                 NORM[cfg.get("abs_norm", "mean")], INTERP[cfg.get("interp", "linear")],
-                1 if cfg.get("all_planes", False) else 0, 0)
+                2 if cfg.get("all_planes", False) == "own" else (1 if cfg.get("all_planes", False) else 0), 0)
     tr = Transfer(int(cfg.get("nstokes", 1)), PREC[cfg.get("precision", "fp64")],
                   int(cfg.get("max_steps", 100000)), int(cfg.get("subrings", 0)), float(cfg.get("eps", 0.03)),
                   float(cfg.get("fp64_radius", 0.0)), float(cfg.get("fp64_ktheta", -1.0)))

@@ -516,6 +516,10 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
                 return fail(ART_EINVAL, "image %d: NaN tolerance", i);
             if (J.rf.interp != ART_INTERP_LINEAR && J.rf.interp != ART_INTERP_NEAREST)
                 return fail(ART_EINVAL, "image %d: unknown interpolation %d", i, J.rf.interp);
+            if (J.rf.all_planes < 0 || J.rf.all_planes > 2)
+                return fail(ART_EINVAL, "image %d: all_planes must be 0, 1 or 2", i);
+            if (J.rf.all_planes == 2 && J.rf.interp != ART_INTERP_LINEAR)
+                return fail(ART_EINVAL, "image %d: per-plane normalisation needs the linear branch", i);
         }
         if (i == 0) {
             b->model = J.em.kind;
@@ -546,7 +550,8 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
         D.nstokes = J.tr.nstokes;
         D.nplanes = J.tr.nstokes + J.tr.subrings;
         D.flags = uniform ? 0 : ((J.rf.interp == ART_INTERP_NEAREST ? kRefineNearest : 0) |
-                                 (J.rf.all_planes ? kRefineAllPlanes : 0));
+                                 (J.rf.all_planes ? kRefineAllPlanes : 0) |
+                                 (J.rf.all_planes == 2 ? kRefineOwnNorm : 0));
         D.abs_norm = J.rf.abs_norm;
         D.r_rel = J.rf.r_rel;
         D.r_abs = J.rf.r_abs;
@@ -1172,6 +1177,9 @@ int setup_cube(art_batch* b, int32_t n, const art_job* jobs, int32_t n0, int32_t
 {
     int rc = check_cube(n, jobs, n0, L, r_rel, r_abs, out);
     if (rc) return rc;
+    for (int i = 0; i < n; ++i)
+        if (jobs[i].rf.all_planes == 2)
+            return fail(ART_EINVAL, "image %d: axis-sampled cubes take all_planes 0 or 1", i);
     std::vector<int> perm, inv(n, -1);
     for (int k = 0; k < n0; ++k) perm.push_back(k << L);
     for (int sl = 1; sl <= L; ++sl) {

@@ -21,6 +21,7 @@ struct Counters {
     unsigned long long status[8];
     uint32_t img_traced[kMaxBatch][kMaxLevels + 1];   // per image and level
     double scal[kMaxBatch][4];            // per image: ibar_int, imax0, n_abs, spare
+    double nabs_plane[kMaxBatch][12];     // per image and plane (kRefineOwnNorm): the plane's own N_abs
     // learned proposals, per image: [0] proposed points the criterion would
     // not trace, [1] criterion-flagged points the network rejected, [2] points
     // traced by the criterion as fallback after a look-ahead pass, [3]
@@ -50,8 +51,10 @@ struct ImageDesc {
 
 constexpr int32_t kRefineNearest = 1;     // nearest branch of Eqs. 5-6 and nearest interpolation
 constexpr int32_t kRefineAllPlanes = 2;   // criterion ORed over every image plane
+constexpr int32_t kRefineOwnNorm = 4;     // ... each plane against its own N_abs and neighbour sum
 
 constexpr int kMaxSub = 8;        // subring planes a ray accumulates
+static_assert(4 + kMaxSub <= 12, "Counters::nabs_plane holds every image plane");
 constexpr int8_t kMarkSpectral = -3;   // level map: value taken from the spectral neighbours
 
 enum TraceSrc : int { SRC_LIST = 0, SRC_POINTS = 1 };

@@ -83,9 +83,11 @@ hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsig
 }
 
 // ------------------------------------------------------ level-0 reduction
-// One block per image: trapezoid-weighted mean and maximum of the base grid.
-// Four waves per block (not sixteen), so that a batch's reduction fits into
-// the wave slots the tracing launches of other batches in flight leave free.
+// One block per image: trapezoid-weighted mean and maximum of the base grid
+// (Stokes I; with kRefineOwnNorm also of |plane| for every further plane, each
+// plane's own N_abs).  Four waves per block (not sixteen), so that a batch's
+// reduction fits into the wave slots the tracing launches of other batches in
+// flight leave free.
 __global__ __launch_bounds__(256) void k_reduce_base(const ImageDesc* desc, Counters* ctr, int img_off)
 {
     __shared__ double ssum[256];
@@ -94,31 +96,41 @@ __global__ __launch_bounds__(256) void k_reduce_base(const ImageDesc* desc, Coun
     const ImageDesc D = desc[img];
     const int t = threadIdx.x;
     const int st0 = 1 << D.levels;
-    double sum = 0.0, mx = -HUGE_VAL;
     const int n = D.nx0 * D.ny0;
-    for (int k = t; k < n; k += 256) {
-        const int i = k % D.nx0, j = k / D.nx0;
-        const double v = D.img[(long long)(j * st0) * D.nx + (long long)(i * st0)];
-        const double wx = (i == 0 || i == D.nx0 - 1) ? 0.5 : 1.0;
-        const double wy = (j == 0 || j == D.ny0 - 1) ? 0.5 : 1.0;
-        sum += (wy * wx) * v;
-        mx = v > mx ? v : mx;
-    }
-    ssum[t] = sum;
-    smax[t] = mx;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
-            ssum[t] += ssum[t + off];
-            smax[t] = smax[t + off] > smax[t] ? smax[t + off] : smax[t];
+    const int nplanes = (D.flags & kRefineOwnNorm) ? D.nplanes : 1;      // uniform over the block
+    for (int pl = 0; pl < nplanes; ++pl) {
+        const double* P = D.img + (long long)pl * D.plane;
+        double sum = 0.0, mx = -HUGE_VAL;
+        for (int k = t; k < n; k += 256) {
+            const int i = k % D.nx0, j = k / D.nx0;
+            const double v0 = P[(long long)(j * st0) * D.nx + (long long)(i * st0)];
+            const double v = pl == 0 ? v0 : ::fabs(v0);
+            const double wx = (i == 0 || i == D.nx0 - 1) ? 0.5 : 1.0;
+            const double wy = (j == 0 || j == D.ny0 - 1) ? 0.5 : 1.0;
+            sum += (wy * wx) * v;
+            mx = v > mx ? v : mx;
         }
+        ssum[t] = sum;
+        smax[t] = mx;
         __syncthreads();
-    }
-    if (t == 0) {
-        const double ibar = ssum[0] / ((double)(D.nx0 - 1) * (double)(D.ny0 - 1));
-        ctr->scal[img][0] = ibar;
-        ctr->scal[img][1] = smax[0];
-        ctr->scal[img][2] = D.abs_norm == 0 ? ibar : smax[0];
+        for (int off = 128; off > 0; off >>= 1) {
+            if (t < off) {
+                ssum[t] += ssum[t + off];
+                smax[t] = smax[t + off] > smax[t] ? smax[t + off] : smax[t];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            const double mean = ssum[0] / ((double)(D.nx0 - 1) * (double)(D.ny0 - 1));
+            const double na = D.abs_norm == 0 ? mean : smax[0];
+            if (pl == 0) {
+                ctr->scal[img][0] = mean;
+                ctr->scal[img][1] = smax[0];
+                ctr->scal[img][2] = na;
+            }
+            ctr->nabs_plane[img][pl] = na;
+        }
+        __syncthreads();                      // the shared sums are reused by the next plane
     }
 }
 
@@ -370,7 +382,10 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
             const double aD = ::fabs(D2);
             crit = !avail || !(D2 == D2) || !(Ssum == Ssum) || (aD > thrA && aD > crel * aS);
             if (allp) {
-                // the same estimate on every further plane (Q, U, V, subrings)
+                // the same estimate on every further plane (Q, U, V, subrings),
+                // against Stokes I's N_abs and |S|, or (kRefineOwnNorm) against
+                // the plane's own N_abs and neighbour sum
+                const bool own = (D.flags & kRefineOwnNorm) != 0;
                 for (int st = 1; st < D.nplanes; ++st) {
                     const double* Is = I + st * D.plane;
                     double Dp;
@@ -383,8 +398,13 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
                         const int dx = (p & 1) ? 1 : 0, dy = (p & 1) ? 0 : 1;
                         axis_D(Is, NX, s, nxl, nyl, p, q, dx, dy, Is[o[0]], Is[o[1]], Dp);
                     }
+                    double thrP = thrA, aSp = aS;
+                    if (own) {
+                        thrP = (4.0 * m * D.r_abs) * ctr->nabs_plane[img][st];
+                        aSp = ::fabs(nnb == 4 ? (Is[o[0]] + Is[o[1]]) + (Is[o[2]] + Is[o[3]]) : Is[o[0]] + Is[o[1]]);
+                    }
                     const double aDp = ::fabs(Dp);
-                    crit = crit || !(Dp == Dp) || (aDp > thrA && aDp > crel * aS);
+                    crit = crit || !(Dp == Dp) || (aDp > thrP && aDp > crel * aSp);
                 }
             }
         }

@@ -168,7 +168,8 @@ def test_invalid_arguments(art):
 
 @pytest.mark.parametrize("interp,all_planes,subrings", [("nearest", False, 0), ("nearest", True, 0),
                                                        ("linear", True, 0), ("linear", True, 3),
-                                                       ("nearest", True, 3)])
+                                                       ("nearest", True, 3), ("linear", "own", 0),
+                                                       ("linear", "own", 3)])
 def test_refinement_variants(art, interp, all_planes, subrings):
     """Nearest branch of Eqs. 5-6 and the per-plane criterion (Stokes and
     subring planes) against the oracle: decisions up to floating-point ties,
@@ -182,3 +183,17 @@ def test_refinement_variants(art, interp, all_planes, subrings):
     if all_planes:
         one = art.render(dict(cfg, all_planes=False))[3]
         assert st["rays"] >= one["rays"]
+    if all_planes == "own":
+        shared = art.render(dict(cfg, all_planes=True))[3]
+        assert st["rays"] > shared["rays"]
+
+
+def test_own_normalisation_rejected_where_undefined(art):
+    """The per-plane normalisation is defined for the linear branch of
+    spatial refinement only: the nearest branch and axis-sampled cubes refuse it."""
+    base = dict(art_inputs.reduced(art_inputs.workload("thermal_1025"), 9, 2), all_planes="own")
+    with pytest.raises(art.ArtError):
+        art.render(dict(base, interp="nearest"))
+    cfgs = [dict(base, freq_hz=f) for f in (86e9, 150e9, 230e9)]
+    with pytest.raises(art.ArtError):
+        art.render_cube(cfgs, 2, 1)
