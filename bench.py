@@ -784,7 +784,7 @@ def spectral_1025(art, torch, art_inputs, args):
     return out
 
 
-MOVIE_AXIS_RABS = (1.0, 0.5, 0.25)   # the time axis's R_abs as fractions of the spatial one
+MOVIE_RABS = (1.0, 0.5, 0.25)   # R_abs of both axes as fractions of the paper's 0.025 Ibar_int
 
 
 def movie_1025(art, torch, art_inputs, args):
@@ -792,16 +792,16 @@ def movie_1025(art, torch, art_inputs, args):
     evolving synthetic flow at the paper's 5 M cadence (t = 0..40 M), gridded
     model, 1025^2 (base 129^2, 3 levels), Stokes I, as a cube along t (3 base
     frames, 2 levels) against plain adaptive renders of the 9 frames (one
-    batch, hipGraph replay) and uniform truths.  The time axis's R_abs is
-    chosen on a held-out movie (the turbulence of another seed) as the
-    loosest of MOVIE_AXIS_RABS x the spatial R_abs at which its 9 frames pass
-    the bar, then applied unchanged."""
+    batch, hipGraph replay) and uniform truths.  R_abs (both axes) is chosen
+    on a held-out movie (the turbulence of another seed) as the loosest of
+    MOVIE_RABS x 0.025 Ibar_int at which its 9 cube frames pass the bar, then
+    applied unchanged to the cube and the plain renders of the timed movie."""
     from art_inputs import mks
     times = [5.0 * k for k in range(9)]
-    base = dict(art_inputs.workload("grid_4097"), nx0=129, ny0=129, levels=3, nstokes=1,
-                precision=args.precision)
+    base0 = dict(art_inputs.workload("grid_4097"), nx0=129, ny0=129, levels=3, nstokes=1,
+                 precision=args.precision)
 
-    def movie(seed):
+    def movie(seed, base):
         grids, _ = mks.mks_movie(times, seed=seed)
         gd = [torch.from_numpy(g).cuda() for g in grids]
         del grids
@@ -811,26 +811,27 @@ def movie_1025(art, torch, art_inputs, args):
             t, _, _ = art.render_uniform(c)
             tr.append(t[0].clone())
         return gd, cf, tr
-    gh, cfh, trh = movie(5)
+    gh, cfh, trh = movie(5, base0)
     held = []
-    ra_axis = base["r_abs"] * MOVIE_AXIS_RABS[-1]
-    for f in MOVIE_AXIS_RABS:
-        ra = base["r_abs"] * f
-        im, _, _, sth = art.render_cube(cfh, 3, 2, r_abs=ra)
-        m = max(art.metrics(trh[i], im[i][0])[1] for i in range(len(cfh)))
-        held.append(dict(axis_r_abs=ra, mse_max=m, rays=sum(x["rays"] for x in sth)))
+    ra = base0["r_abs"] * MOVIE_RABS[-1]
+    for f in MOVIE_RABS:
+        ra_f = base0["r_abs"] * f
+        cf = [dict(c, r_abs=ra_f) for c in cfh]
+        im, _, _, sth = art.render_cube(cf, 3, 2)
+        m = max(art.metrics(trh[i], im[i][0])[1] for i in range(len(cf)))
+        held.append(dict(r_abs=ra_f, mse_max=m, rays=sum(x["rays"] for x in sth)))
         del im
         if m <= 1e-3:
-            ra_axis = ra
+            ra = ra_f
             break
     del gh, cfh, trh
-    log("movie: time-axis R_abs chosen on the held-out movie: %g (%s)" % (
-        ra_axis, ["%.2e" % h["mse_max"] for h in held]))
-    gdev, cfgs, truths = movie(2)
-    art.render_cube(cfgs, 3, 2, r_abs=ra_axis)          # warm
+    log("movie: R_abs chosen on the held-out movie: %g (%s)" % (ra, ["%.2e" % h["mse_max"] for h in held]))
+    base = dict(base0, r_abs=ra)
+    gdev, cfgs, truths = movie(2, base)
+    art.render_cube(cfgs, 3, 2)                          # warm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    imgs, levs, _, sts = art.render_cube(cfgs, 3, 2, r_abs=ra_axis)
+    imgs, levs, _, sts = art.render_cube(cfgs, 3, 2)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     rays = sum(st["rays"] for st in sts)
@@ -850,8 +851,8 @@ def movie_1025(art, torch, art_inputs, args):
     plain = dict(ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse_max=chk["mse_max"],
                  mse_mean=chk["mse_mean"], mse_ok=chk["mse_ok"])
     B.close()
-    cube["ms_in_flight"] = in_flight_ms(art, torch, lambda: art.Batch(cfgs, cube=(3, 2, base["r_rel"],
-                                                                                    ra_axis)), args.steps)
+    cube["ms_in_flight"] = in_flight_ms(art, torch, lambda: art.Batch(cfgs, cube=(3, 2, base["r_rel"], ra)),
+                                        args.steps)
     plain["ms_in_flight"] = in_flight_ms(art, torch, lambda: art.Batch(cfgs), args.steps)
     log("movie cube in flight: %.1f ms per cube, plain %.1f ms per batch (3 in flight)" % (
         cube["ms_in_flight"], plain["ms_in_flight"]))
@@ -862,9 +863,9 @@ def movie_1025(art, torch, art_inputs, args):
     torch.cuda.empty_cache()
     return dict(workload="gridded snapshot movie a=0.94 i=163 deg 230 GHz, 9 frames at 5 M cadence "
                          "(Keplerian-sheared turbulence renewed over 200 M), 1025^2, Stokes I, R_rel=1e-3, "
-                         "R_abs=0.025 Ibar_int in space and %g Ibar_int in time (chosen on a held-out movie), "
-                         "3 base frames + 2 levels in time" % ra_axis,
-                cube=cube, plain_batched=plain, rays_ratio=rays / max(plain["rays"], 1), axis_r_abs_heldout=held)
+                         "R_abs=%g Ibar_int on both axes (chosen on a held-out movie), 3 base frames + 2 levels "
+                         "in time" % ra,
+                cube=cube, plain_batched=plain, rays_ratio=rays / max(plain["rays"], 1), r_abs_heldout=held)
 
 
 def refine_variants(art, torch, cfg, args):
