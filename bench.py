@@ -18,7 +18,9 @@ uniform render of the same view, Sec. 4.1 Eq. 9):
   - learned + batched: the proposal network (trained first, untimed, on
     plain renders of 16 other images of the batch's structure) looks two
     levels ahead, the criterion of Sec. 3.2 judges and traces what it missed
-    (or only counts it: judge-only forms);
+    (or only counts it: judge-only forms); the network runs at every level it
+    can look ahead from, or (forms *_l0) at level 0 only, the deeper levels
+    taking the criterion alone;
   - plain batched: the criterion alone.
 Each form's tolerance is chosen on a held-out batch of the same structure
 (other spins, inclinations and field phases): the loosest R_rel of a fixed
@@ -83,7 +85,7 @@ BYTES_PER_RAY = 58
 # HBM traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE counter runs
 # of this benchmark, per render of the headline form; valid only for the
 # kernel sources it was measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=435287709, kernel_hash="1013ae1ac963895c", form="learned_batched",
+TRAFFIC = dict(bytes_per_render=435287709, kernel_hash="1013ae1ac963895c", form="judge_z2",
                precision="mixed",
                source="profiles/k_trace_learned_batched_uneven_64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
@@ -323,7 +325,9 @@ def c4_forms(art, torch, art_inputs, args):
     inf = float("inf")
     op_forms = [("plain", None)] + [("lookahead_z%g" % z, dict(z_propose=z, z_suppress=-inf, fallback=True))
                                     for z in OP_Z] + \
-        [("judge_z%g" % z, dict(z_propose=z, z_suppress=-inf, fallback=False)) for z in OP_Z_JUDGE]
+        [("judge_z%g" % z, dict(z_propose=z, z_suppress=-inf, fallback=False)) for z in OP_Z_JUDGE] + \
+        [("lookahead_z4_l0", dict(z_propose=4.0, z_suppress=-inf, fallback=True, level_cap=1))] + \
+        [("judge_z%g_l0" % z, dict(z_propose=z, z_suppress=-inf, fallback=False, level_cap=1)) for z in OP_Z_JUDGE]
     opts_of = dict(op_forms)
 
     def truths_of(cfgs):
@@ -965,7 +969,7 @@ def main():
     L = forms[head]
     P = forms["plain_batched"]
     achieved = (rs["flops"] / rs["launches"]) / (rs["tr_ms"] / rs["launches"] * 1e-3)
-    traffic = measured_traffic(rs["launches"], head, args.precision)
+    traffic = measured_traffic(rs["launches"], L["form"], args.precision)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_VECTOR / 1e12, unit="TFLOP/s",
                 frac=achieved / PEAK_VECTOR, traffic=traffic and traffic["bytes_per_launch"],
                 kernel="k_trace (%s), %s render" % (PRECISION_NAMES[args.precision], head),

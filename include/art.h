@@ -405,6 +405,9 @@ typedef struct {
                                       counts them (art_stats.learned[3]) */
     int32_t all_levels;            /* 0: the network runs only at levels l with l + 2 <= N
                                       (look-ahead); 1: also at l = N - 1 */
+    int32_t level_cap;             /* 0: the network runs at every such level; k > 0: only at
+                                      levels l < k, deeper levels take the criterion alone */
+    int32_t pad;
 } art_learned;
 
 /* Switch a batch to learned renders with `net` (NULL: back to plain).  All

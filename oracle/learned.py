@@ -49,8 +49,10 @@ def _neighbours(p, q):
 
 
 def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstokes, logits_fn,
-                   z_hi, z_lo, fallback=True, all_levels=False, forced_level=None):
+                   z_hi, z_lo, fallback=True, all_levels=False, forced_level=None, level_cap=0):
     """ray_fn(x, y) -> (S (n, nstokes), rmin (n,), ncross (n,)).
+    level_cap > 0: the network runs only at levels l < level_cap; deeper
+    levels take the criterion alone (as a plain render does).
     logits_fn(x) -> (15, H, W) for the features x (3, H, W) of a level.
     forced_level: optional final-grid level map to replay (a point new at
     level l+1 or l+2 of a network pass is traced iff the map says so).
@@ -128,7 +130,7 @@ def refine_learned(ray_fn, fov, nx0, ny0, levels, r_rel, r_abs, abs_norm, nstoke
 
     l = 0
     while l < levels:
-        net_here = l + 2 <= levels or (all_levels and l + 1 <= levels)
+        net_here = (level_cap <= 0 or l < level_cap) and (l + 2 <= levels or (all_levels and l + 1 <= levels))
         if not net_here:
             p, q, s, S_all, m, crit, cm = criterion(l)
             record(p, q, s, crit, l + 1, cm, np.full(p.shape, np.inf))

@@ -82,7 +82,8 @@ class Spectral(ctypes.Structure):
 
 class Learned(ctypes.Structure):
     _fields_ = [("z_propose", ctypes.c_float), ("z_suppress", ctypes.c_float),
-                ("fallback", ctypes.c_int32), ("all_levels", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("all_levels", ctypes.c_int32),
+                ("level_cap", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -357,8 +358,9 @@ def render_cube(cfgs, n0, levels, r_rel=None, r_abs=None, feat=False, stream=Non
         [stats_dict(sts[i]) for i in range(n)]
 
 
-def learned_opts(z_propose=2.0, z_suppress=float("-inf"), fallback=True, all_levels=False):
-    return Learned(float(z_propose), float(z_suppress), 1 if fallback else 0, 1 if all_levels else 0)
+def learned_opts(z_propose=2.0, z_suppress=float("-inf"), fallback=True, all_levels=False, level_cap=0):
+    return Learned(float(z_propose), float(z_suppress), 1 if fallback else 0, 1 if all_levels else 0,
+                   int(level_cap), 0)
 
 
 def render_learned(cfg, net, out=None, stats=True, stream=None, **opts):

@@ -840,6 +840,7 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
     if (!opt) return fail(ART_EINVAL, "NULL learned-render options");
     if (std::isnan(opt->z_propose) || std::isnan(opt->z_suppress) || !(opt->z_suppress <= opt->z_propose))
         return fail(ART_EINVAL, "need z_suppress <= z_propose (no NaN)");
+    if (opt->level_cap < 0) return fail(ART_EINVAL, "level_cap must be >= 0");
     if (b->uniform) return fail(ART_EINVAL, "uniform renders have no refinement");
     const ImageDesc& D0 = b->hD[0];
     int nmax = 0;
@@ -852,7 +853,8 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
     }
     // per group and level, the images the network decides for: those that
     // can look two levels ahead (levels >= l + 2), with all_levels also those
-    // with one level left; the workspace holds the largest such set's grids
+    // with one level left, at levels below level_cap if it is set; the
+    // workspace holds the largest such set's grids
     for (int g = 0; g < b->ngroups; ++g) {
         BatchGroup& G = b->grp[g];
         std::vector<int> h;
@@ -862,7 +864,8 @@ int setup_learned(art_batch* b, art_cnn* net, const art_learned* opt)
             G.nnet[l] = 0;
             for (int i = 0; i < G.n; ++i) {
                 const int Li = b->hD[G.i0 + i].levels;
-                if (Li >= l + 2 || (opt->all_levels && Li >= l + 1)) {
+                const bool capped = opt->level_cap > 0 && l >= opt->level_cap;
+                if (!capped && (Li >= l + 2 || (opt->all_levels && Li >= l + 1))) {
                     h.push_back(i);
                     G.nnet[l]++;
                 }

@@ -18,7 +18,7 @@ def test_report_is_strict_json():
 def test_traffic_only_for_profiled_sources_and_form():
     t = bench.TRAFFIC
     if t is None:
-        assert bench.measured_traffic(8, "learned_batched", "mixed") is None
+        assert bench.measured_traffic(8, "judge_z2", "mixed") is None
         return
     launches = 8
     got = bench.measured_traffic(launches, t["form"], t["precision"])

@@ -72,15 +72,17 @@ def thresholds(art, cfg, params):
     return float(np.percentile(zz, 85)), float(np.percentile(zz, 10))
 
 
-@pytest.mark.parametrize("fallback", [True, False])
-def test_learned_render_parity(art, fallback):
+@pytest.mark.parametrize("fallback,cap", [(True, 0), (False, 0), (False, 1)])
+def test_learned_render_parity(art, fallback, cap):
+    """cap = 1: the network only at level 0, levels 3 and 4 by the criterion."""
     cfg = small_cfg()
-    case("learned parity", fallback=fallback)
+    case("learned parity", fallback=fallback, level_cap=cap)
     params = net_params(7)
     net = art.Cnn()
     net.set_params(ocnn.flatten(params).astype(np.float32))
     zh, zl = thresholds(art, cfg, params)
-    img, lev, ft, st = art.render_learned(cfg, net, z_propose=zh, z_suppress=zl, fallback=fallback)
+    img, lev, ft, st = art.render_learned(cfg, net, z_propose=zh, z_suppress=zl, fallback=fallback,
+                                          level_cap=cap)
     g = img.cpu().numpy()[0]
     gl = lev.cpu().numpy()
     assert gl.min() >= -1 and gl.max() <= cfg["levels"]
@@ -98,9 +100,9 @@ def test_learned_render_parity(art, fallback):
     # every decision of the GPU's level map that the oracle's own learned rule
     # (given the same history) takes differently sits at a tie: a criterion
     # margin below 1e-9 or a logit within TAU_Z of a threshold
-    rep = olearned.refine_learned(*args, fallback=fallback, forced_level=gl)
+    rep = olearned.refine_learned(*args, fallback=fallback, forced_level=gl, level_cap=cap)
     check_ties(rep, gl, ETA_FP64, tau_z=TAU_Z)
-    ol = olearned.refine_learned(*args, fallback=fallback)
+    ol = olearned.refine_learned(*args, fallback=fallback, level_cap=cap)
     flips = int((gl != ol["level"]).sum())
     print("level-map differences from the unforced oracle", flips, "judge gpu", st["learned"],
           "oracle", ol["judge"], flush=True)

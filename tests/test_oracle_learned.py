@@ -108,3 +108,27 @@ def test_interpolated_points_inherit_neighbour_features():
     p, q = 1, 1
     corners = [rm[0, 0], rm[0, 2 * s], rm[2 * s, 0], rm[2 * s, 2 * s]]
     assert rm[q * s, p * s] == min(corners)
+
+
+def test_level_cap_hands_deeper_levels_to_the_criterion():
+    """With level_cap = 1 a network that proposes everything traces the
+    level-2 grid completely (one look-ahead pass) and the criterion alone
+    refines levels 3 and 4: the plain method started from the level-2 grid
+    (with R_abs = 0 the normalisation, which differs between the two, plays
+    no part).  A cap at or above the deepest network level changes nothing."""
+    levels = 4
+    a = dict(ARGS, r_abs=0.0)
+    out = learned.refine_learned(ray_fn, levels=levels, logits_fn=const_logits(10.0), z_hi=1.0, z_lo=-1.0,
+                                 level_cap=1, **a)
+    nx0b, ny0b = refine.grid_size(9, 2), refine.grid_size(7, 2)
+    plain = refine.refine(lambda x, y: ring(x, y), a["fov"], nx0b, ny0b, 2, a["r_rel"], 0.0, "mean", 1)
+    assert np.array_equal(out["img"], plain["img"])
+    deeper = plain["level"] >= 1
+    assert np.array_equal(out["level"][deeper], plain["level"][deeper] + 2)
+    assert np.all((out["level"][~deeper] >= 0) & (out["level"][~deeper] <= 2) | (plain["level"][~deeper] < 0))
+    assert out["passes"] == 5 and plain["rays"] > plain["traced"][0]
+    assert all(np.all(np.isinf(x["zmargin"])) for x in out["audit"][-2:])
+    full = learned.refine_learned(ray_fn, levels=levels, logits_fn=const_logits(3.0), z_hi=1.0, z_lo=-1.0, **ARGS)
+    capped = learned.refine_learned(ray_fn, levels=levels, logits_fn=const_logits(3.0), z_hi=1.0, z_lo=-1.0,
+                                    level_cap=3, **ARGS)
+    assert np.array_equal(full["level"], capped["level"]) and np.array_equal(full["img"], capped["img"])
