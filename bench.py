@@ -85,7 +85,7 @@ BYTES_PER_RAY = 58
 # HBM traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE counter runs
 # of this benchmark, per render of the headline form; valid only for the
 # kernel sources it was measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=435287709, kernel_hash="1013ae1ac963895c", form="judge_z2",
+TRAFFIC = dict(bytes_per_render=401859027, kernel_hash="1013ae1ac963895c", form="judge_z2_l0",
                precision="mixed",
                source="profiles/k_trace_learned_batched_uneven_64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
                       "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
@@ -350,8 +350,11 @@ def c4_forms(art, torch, art_inputs, args):
     # on the headline batch
     ms_h = {}
     dh = min(3, nmax)
+    if args.learned_form and args.learned_form not in op_h:
+        raise SystemExit("--learned-form %s: no held-out operating point for that form (have %s)"
+                         % (args.learned_form, sorted(op_h)))
     for name, row in op_h.items():
-        if name == "plain":
+        if name == "plain" or (args.learned_form and name != args.learned_form):
             continue
         bs = [art.Batch([dict(c, r_rel=row["r_rel"]) for c in held], feat=True) for _ in range(dh)]
         for X in bs:
@@ -944,6 +947,9 @@ def main():
     ap.add_argument("--launch", default="",
                     help="persistent-tracer shape BLOCKSxTHREADS of the timed forms instead of the in-flight "
                          "autotuner (with --in-flight, else three batches in flight)")
+    ap.add_argument("--learned-form", default="",
+                    help="learned form timed on the headline batch instead of the fastest on the held-out "
+                         "batch (for counter runs, whose serialised dispatches change the held-out timings)")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-deploy", action="store_true")
     ap.add_argument("--no-spectral", action="store_true")
