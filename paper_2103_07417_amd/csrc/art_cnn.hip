@@ -772,65 +772,84 @@ hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N
     return hipGetLastError();
 }
 
-// Proposals: one thread per vertex of image blockIdx.y and output blockIdx.z.
-// Level-(l+2) proposals are compacted with a wave ballot into the trace list
-// of pass l+1.
-__global__ __launch_bounds__(256) void k_cnn_propose(const float* __restrict__ logits,
-                                                     const ImageDesc* __restrict__ desc, int l, int H, int W,
-                                                     float z_hi, float z_lo, int all_levels,
-                                                     unsigned long long* __restrict__ list,
-                                                     Counters* __restrict__ ctr, const int* __restrict__ imap)
+// Proposals: one thread per vertex of image blockIdx.y, every output of the
+// vertex.  The block's level-(l+2) proposals are counted first and reserved in
+// the trace list of pass l+1 with one atomic per block (per wave and output,
+// the shared list counter serialised the kernel).
+constexpr int kProposeThreads = 256;
+
+__global__ __launch_bounds__(kProposeThreads) void k_cnn_propose(const float* __restrict__ logits,
+                                                                 const ImageDesc* __restrict__ desc, int l, int H,
+                                                                 int W, float z_hi, float z_lo, int all_levels,
+                                                                 unsigned long long* __restrict__ list,
+                                                                 Counters* __restrict__ ctr,
+                                                                 const int* __restrict__ imap)
 {
+    constexpr int kWaves = kProposeThreads / 64;
+    __shared__ unsigned s_cnt[kWaves];
+    __shared__ unsigned s_base;
     const int b = blockIdx.y;                 // slot of the logits
-    const int k = blockIdx.z;                 // output (owned point)
     const int img = imap ? imap[b] : b;       // image of the batch
     const ImageDesc& D = desc[img];
     const int HW = H * W;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.x * kProposeThreads + threadIdx.x;
     // the network decides for this image only where it can look ahead (its
     // level count reaches l + 2) or everywhere with all_levels; an image with
     // one level left keeps the plain criterion (marks left undecided)
     const bool decides = D.levels >= l + 2 || all_levels;
-    bool app = false;
-    long long pix = 0;
+    const int j = v < HW ? v / W : 0, i = v < HW ? v - j * W : 0;
+    unsigned app = 0;                         // bit k: level-(l+2) output k proposed
     if (v < HW) {
-        const int j = v / W, i = v - j * W;
-        int lev;
-        if (owned_point(k, i, j, l, D.levels, D.nx0, D.ny0, D.nx, pix, lev)) {
+        for (int k = 0; k < kCnnOut; ++k) {
+            long long pix = 0;
+            int lev;
+            if (!owned_point(k, i, j, l, D.levels, D.nx0, D.ny0, D.nx, pix, lev)) continue;
             const float z = logits[((long long)b * kCnnOut + k) * HW + v];
-            if (!decides) {
-                D.level[pix] = kMarkUnset;
-            } else if (z > z_hi) {
+            int8_t m = kMarkUnset;            // undecided: the criterion decides
+            if (decides && z > z_hi) {
                 if (k < 3) {
-                    D.level[pix] = kMarkPropose;
+                    m = kMarkPropose;
                 } else {
-                    D.level[pix] = (int8_t)lev;
-                    app = true;
+                    m = (int8_t)lev;
+                    app |= 1u << k;
                 }
-            } else if (z < z_lo) {
-                D.level[pix] = kMarkSuppress;
-            } else {
-                D.level[pix] = kMarkUnset;      // undecided: the criterion decides
+            } else if (decides && z < z_lo) {
+                m = kMarkSuppress;
             }
+            D.level[pix] = m;
         }
     }
-    const unsigned long long mask = __ballot(app);
-    if (mask) {
-        const int lane = __lane_id();
-        const int leader = __ffsll((long long)mask) - 1;
-        const unsigned n = (unsigned)__popcll(mask);
+    const int wave = threadIdx.x >> 6;
+    unsigned wtot = 0;
+    for (int k = 3; k < kCnnOut; ++k) wtot += (unsigned)__popcll(__ballot((app >> k) & 1u));
+    if (__lane_id() == 0) s_cnt[wave] = wtot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned n = 0;
+        for (int w = 0; w < kWaves; ++w) n += s_cnt[w];
         unsigned base = 0;
-        if (lane == leader) {
+        if (n) {
             base = atomicAdd(&ctr->count[l + 1], n);
             atomicAdd(&ctr->img_traced[img][l + 1], n);
             atomicAdd(&ctr->judge[img][4], (unsigned long long)n);
         }
-        base = __shfl(base, leader);
-        if (app) {
-            const unsigned off = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-            list[base + off] = make_item((uint32_t)img, (uint32_t)pix);
+        s_base = base;
+    }
+    __syncthreads();
+    if (wtot == 0) return;                    // wave-uniform
+    unsigned off = s_base;
+    for (int w = 0; w < wave; ++w) off += s_cnt[w];
+    for (int k = 3; k < kCnnOut; ++k) {
+        const unsigned long long mask = __ballot((app >> k) & 1u);
+        if ((app >> k) & 1u) {
+            long long pix = 0;
+            int lev;
+            owned_point(k, i, j, l, D.levels, D.nx0, D.ny0, D.nx, pix, lev);
+            const unsigned r = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            list[off + r] = make_item((uint32_t)img, (uint32_t)pix);
         }
+        off += (unsigned)__popcll(mask);
     }
 }
 
@@ -840,8 +859,8 @@ hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int
 {
     const long long HW = (long long)H * W;
     if (HW >= (1LL << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((HW + 255) / 256), nimg, kCnnOut), dim3(256), 0, s, logits,
-                       desc, l, H, W, z_hi, z_lo, all_levels, list, ctr, imap);
+    hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((HW + kProposeThreads - 1) / kProposeThreads), nimg),
+                       dim3(kProposeThreads), 0, s, logits, desc, l, H, W, z_hi, z_lo, all_levels, list, ctr, imap);
     return hipGetLastError();
 }
 
