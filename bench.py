@@ -260,6 +260,14 @@ def operating_points(search, op_forms):
     return op
 
 
+def parse_launch(text):
+    """BLOCKSxTHREADS[:REFINE_BLOCKS] -> launch dict (refine_blocks 0: the
+    refinement passes use BLOCKS)."""
+    shape, _, rb = text.lower().partition(":")
+    tb, tt = (int(v) for v in shape.split("x"))
+    return dict(trace_blocks=tb, trace_threads=tt, refill=1, groups=1, refine_blocks=int(rb) if rb else 0)
+
+
 def choose_forms(op_heldout, op_timed, grid, heldout_ms=None):
     """The forms timed on the headline batch, as (name, form, R_rel, how):
     the learned form fastest on the held-out batch at its held-out operating
@@ -379,25 +387,28 @@ def c4_forms(art, torch, art_inputs, args):
         bset = [art.Batch(c_rr, feat=opts is not None) for _ in range(nmax)]
         for X in bset:
             X.set_learned(None) if opts is None else X.set_learned(net, **opts)
-        depth, launch, tune = nmax, dict(trace_blocks=512, trace_threads=256, refill=1, groups=1), None
+        depth, tune = nmax, None
+        launch = dict(trace_blocks=512, trace_threads=256, refill=1, groups=1, refine_blocks=0)
         if args.launch:
             # a fixed shape (counter runs serialise dispatches, which would
             # steer the in-flight search to other shapes than the timed run's)
-            tb, tt = (int(v) for v in args.launch.lower().split("x"))
-            launch = dict(trace_blocks=tb, trace_threads=tt, refill=1, groups=1)
+            launch = parse_launch(args.launch)
             depth = args.in_flight or 3
         elif not args.no_autotune:
             depths = (args.in_flight,) if args.in_flight else IN_FLIGHT_DEPTHS
             tune = autotune.autotune_in_flight(bset, ss, depths=depths, log=None)
             depth = tune["in_flight"]
-            launch = {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "groups")}
+            launch = {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "groups", "refine_blocks")}
         for X in bset:
             X.set_launch(**launch)
         for X in bset[depth:]:
             X.close()
         bset = bset[:depth]
-        # latency of one batch alone (at the in-flight launch shape)
+        # latency of one batch alone (at the in-flight shape with the base
+        # grid's size for every pass: a smaller refinement grid only pays
+        # when other batches take the freed slots)
         B0 = bset[0]
+        B0.set_launch(**dict(launch, refine_blocks=0))
         lat = time_graph(B0, torch, s, max(3, args.steps // 3))
         for X in bset:
             X.set_launch(**launch)
@@ -945,8 +956,8 @@ def main():
     ap.add_argument("--in-flight", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="batches in flight in the timed step (0: autotuned over 2-4)")
     ap.add_argument("--launch", default="",
-                    help="persistent-tracer shape BLOCKSxTHREADS of the timed forms instead of the in-flight "
-                         "autotuner (with --in-flight, else three batches in flight)")
+                    help="persistent-tracer shape BLOCKSxTHREADS[:REFINE_BLOCKS] of the timed forms instead of the "
+                         "in-flight autotuner (with --in-flight, else three batches in flight)")
     ap.add_argument("--learned-form", default="",
                     help="learned form timed on the headline batch instead of the fastest on the held-out "
                          "batch (for counter runs, whose serialised dispatches change the held-out timings)")

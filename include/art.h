@@ -314,6 +314,9 @@ typedef struct {
                                       caller's stream) so that one group's long-ray tail
                                       overlaps the others' work; 0 = two groups from 16
                                       images on, else one; at most 8 */
+    int32_t refine_blocks;         /* grid size of the refinement passes (every pass after a
+                                      batch's base grid, and a cube's passes after its first);
+                                      0 = trace_blocks */
 } art_launch;
 
 int art_set_launch(const art_launch* launch);

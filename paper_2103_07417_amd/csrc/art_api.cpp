@@ -74,7 +74,7 @@ int env_int(const char* name, int dflt)
     return atoi(v);
 }
 
-art_launch g_launch = { 0, 0, 0, 0 };   // user override (0 = default)
+art_launch g_launch = { 0, 0, 0, 0, 0 };   // user override (0 = default)
 size_t g_list_limit = 0;                // bytes a trace list + cost map may take (0: no limit)
 std::mutex g_mu;
 
@@ -329,6 +329,7 @@ LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes, bool sub = 
     const int occ = trace_occupancy_blocks(precision, model, nstokes, sub, L.trace_threads);
     L.trace_blocks = u.trace_blocks > 0 ? u.trace_blocks : env_int("ART_TRACE_BLOCKS", cus * occ);
     if (L.trace_blocks < 1) L.trace_blocks = 1;
+    L.refine_blocks = u.refine_blocks > 0 ? u.refine_blocks : L.trace_blocks;
     L.refill = u.refill > 0 ? u.refill : env_int("ART_REFILL", 1);
     if (L.refill < 1) L.refill = 1;
     if (L.refill > 64) L.refill = 64;
@@ -626,8 +627,10 @@ hipError_t ev_end(art_batch* b, int g, hipStream_t s)
 int trace_pass(art_batch* b, int g, int level, hipStream_t s)
 {
     TraceJob J = base_job(b, g, level);
+    LaunchCfg L = b->L;
+    if (level > 0) L.trace_blocks = b->L.refine_blocks;
     HIP_TRY(ev_begin(b, g, s));
-    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, b->nsub > 0, J, b->L, s));
+    HIP_TRY(launch_trace(b->precision, b->model, b->nstokes, b->nsub > 0, J, L, s));
     HIP_TRY(ev_end(b, g, s));
     return ART_OK;
 }
@@ -1454,8 +1457,8 @@ int art_set_launch(const art_launch* L)
     if (!L) return fail(ART_EINVAL, "NULL launch configuration");
     if (L->trace_threads != 0 && L->trace_threads != 64 && L->trace_threads != 128 && L->trace_threads != 256)
         return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
-    if (L->trace_blocks < 0 || L->refill < 0 || L->refill > 64)
-        return fail(ART_EINVAL, "trace_blocks >= 0 and 0 <= refill <= 64 required");
+    if (L->trace_blocks < 0 || L->refine_blocks < 0 || L->refill < 0 || L->refill > 64)
+        return fail(ART_EINVAL, "trace_blocks >= 0, refine_blocks >= 0 and 0 <= refill <= 64 required");
     if (L->groups < 0 || L->groups > kMaxGroups) return fail(ART_EINVAL, "groups must be in 0..%d", kMaxGroups);
     std::lock_guard<std::mutex> lk(g_mu);
     g_launch = *L;
@@ -1467,12 +1470,13 @@ int art_batch_set_launch(art_batch* b, const art_launch* L)
     if (!b || !L) return fail(ART_EINVAL, "NULL argument");
     if (L->trace_threads != 0 && L->trace_threads != 64 && L->trace_threads != 128 && L->trace_threads != 256)
         return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
-    if (L->trace_blocks < 0 || L->refill < 0 || L->refill > 64)
-        return fail(ART_EINVAL, "trace_blocks >= 0 and 0 <= refill <= 64 required");
+    if (L->trace_blocks < 0 || L->refine_blocks < 0 || L->refill < 0 || L->refill > 64)
+        return fail(ART_EINVAL, "trace_blocks >= 0, refine_blocks >= 0 and 0 <= refill <= 64 required");
     if (L->groups < 0 || L->groups > kMaxGroups) return fail(ART_EINVAL, "groups must be in 0..%d", kMaxGroups);
     const LaunchCfg d = launch_cfg(b->cus, b->precision, b->model, b->nstokes, b->nsub > 0);
     b->L.trace_threads = L->trace_threads ? L->trace_threads : d.trace_threads;
     b->L.trace_blocks = L->trace_blocks ? L->trace_blocks : d.trace_blocks;
+    b->L.refine_blocks = L->refine_blocks ? L->refine_blocks : b->L.trace_blocks;
     b->L.refill = L->refill ? L->refill : d.refill;
     b->L.long_steps = d.long_steps;
     if (L->groups != b->req_groups) {
@@ -1497,6 +1501,7 @@ int art_batch_get_launch(const art_batch* b, art_launch* L)
 {
     if (!b || !L) return fail(ART_EINVAL, "NULL argument");
     L->trace_blocks = b->L.trace_blocks;
+    L->refine_blocks = b->L.refine_blocks;
     L->trace_threads = b->L.trace_threads;
     L->refill = b->L.refill;
     L->groups = b->ngroups;
@@ -1511,6 +1516,7 @@ int art_get_launch(int32_t precision, int32_t kind, int32_t nstokes, art_launch*
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const LaunchCfg c = launch_cfg(cus, precision, kind, nstokes);
     L->trace_blocks = c.trace_blocks;
+    L->refine_blocks = c.refine_blocks;
     L->trace_threads = c.trace_threads;
     L->refill = c.refill;
     L->groups = 0;

@@ -92,7 +92,8 @@ struct TraceJob {
 };
 
 struct LaunchCfg {
-    int trace_blocks;             // persistent grid size
+    int trace_blocks;             // persistent grid size of the base pass
+    int refine_blocks;            // persistent grid size of the refinement passes
     int trace_threads;            // 64, 128 or 256
     int refill;                   // refill threshold (1..64)
     int long_steps;               // expected steps from which a point is queued first

@@ -107,3 +107,14 @@ def test_cube_batch_validation_host_only():
     assert L.art_cube_create(5, jobs, 3, 1, 0.01, float("nan"), ims, ctypes.byref(h)) == -1
     assert L.art_cube_create(5, jobs, 3, 1, 0.01, 1e-3, ims, None) == -1
     assert not h.value
+
+
+def test_launch_configuration_validation_host_only():
+    """art_set_launch checks its fields on the host (no device call)."""
+    for bad in (dict(trace_threads=96), dict(trace_blocks=-1), dict(refine_blocks=-1), dict(refill=65),
+                dict(groups=9)):
+        with pytest.raises(art.ArtError):
+            art.set_launch(**bad)
+    art.set_launch(256, 256, 1, refine_blocks=192)
+    art.set_launch(0, 0, 0)
+    assert ctypes.sizeof(art.Launch) == 20

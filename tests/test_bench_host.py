@@ -132,3 +132,10 @@ def test_mse_check_reads_whole_planes():
     per = bench.mse_check(FakeArt, cfgs, [img], [truth], planes=2)
     assert math.isclose(per["mse_max_planes"][0], 0.25 / 15) and math.isclose(per["mse_max_planes"][1], 1.0)
     assert per["mse_ok"] is False and per["n_over_bar"] == 1
+
+
+def test_parse_launch():
+    assert bench.parse_launch("256x256") == dict(trace_blocks=256, trace_threads=256, refill=1, groups=1,
+                                                  refine_blocks=0)
+    assert bench.parse_launch("256X128:192")["refine_blocks"] == 192
+    assert bench.parse_launch("256X128:192")["trace_threads"] == 128

@@ -79,10 +79,11 @@ def test_launch_shape_does_not_change_results(art):
     cfg = art_inputs.reduced(art_inputs.workload("thermal_1025"), 17, 2)
     ref, rlev, _, _ = art.render(cfg)
     try:
-        for blocks, threads, refill in ((7, 64, 1), (300, 128, 8), (64, 256, 64)):
-            art.set_launch(blocks, threads, refill)
+        for blocks, threads, refill, rb in ((7, 64, 1, 0), (300, 128, 8, 0), (64, 256, 64, 0), (256, 256, 1, 3),
+                                            (5, 128, 1, 192)):
+            art.set_launch(blocks, threads, refill, refine_blocks=rb)
             img, lev, _, _ = art.render(cfg)
-            assert torch.equal(img, ref) and torch.equal(lev, rlev), (blocks, threads, refill)
+            assert torch.equal(img, ref) and torch.equal(lev, rlev), (blocks, threads, refill, rb)
     finally:
         art.set_launch(0, 0, 0)
 
