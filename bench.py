@@ -392,7 +392,7 @@ def c4_forms(art, torch, art_inputs, args):
         if args.launch:
             # a fixed shape (counter runs serialise dispatches, which would
             # steer the in-flight search to other shapes than the timed run's)
-            launch = parse_launch(args.launch)
+            launch = dict(parse_launch(args.launch), refill=args.refill)
             depth = args.in_flight or 3
         elif not args.no_autotune:
             depths = (args.in_flight,) if args.in_flight else IN_FLIGHT_DEPTHS
@@ -958,6 +958,8 @@ def main():
     ap.add_argument("--launch", default="",
                     help="persistent-tracer shape BLOCKSxTHREADS[:REFINE_BLOCKS] of the timed forms instead of the "
                          "in-flight autotuner (with --in-flight, else three batches in flight)")
+    ap.add_argument("--refill", type=int, default=1,
+                    help="refill threshold of the timed forms with --launch (lanes idle before a wave claims rays)")
     ap.add_argument("--learned-form", default="",
                     help="learned form timed on the headline batch instead of the fastest on the held-out "
                          "batch (for counter runs, whose serialised dispatches change the held-out timings)")

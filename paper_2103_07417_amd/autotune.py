@@ -130,10 +130,13 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
     co-reside.  For every depth d in `depths` (default: all the batches)
     the first d batches are replayed round robin on the first d streams,
     searching blocks per CU and threads per block; then, at the fastest
-    (depth, shape), smaller grids for the refinement passes (7/8, 3/4 and 5/8
-    of the base grid: fewer waves left with idle lanes once a pass's queue has
-    drained, while the other batches take the freed slots).  The fastest
-    choice is applied to every batch.  Returns the choice and the table."""
+    (depth, shape), smaller grids for the refinement passes (7/8 and 3/4 of
+    the base grid: fewer waves left with idle lanes once a pass's queue has
+    drained, while the other batches take the freed slots) crossed with
+    refill thresholds 1, 2, 4, 8 (a wave that waits for a few idle lanes
+    starts their rays with one pass through the ray set-up instead of one
+    per termination).  The fastest choice is applied to every batch.  Returns
+    the choice and the table."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     depths = tuple(depths or (len(batches),))
@@ -156,18 +159,26 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
                         % (d, blocks, threads, ms))
     best = dict(min(table, key=lambda r: r["ms"]), refine_blocks=0)
     d = best["in_flight"]
-    n = reps or max(4, 2 * d)
-    for frac in (0.875, 0.75, 0.625):
+    # the second stage's differences are a few percent: longer timings, the
+    # better of two, and the first stage's row timed again the same way
+    n = reps or max(12, 4 * d)
+    for b in batches[:d]:
+        b.set_launch(best["trace_blocks"], best["trace_threads"], 1, 1)
+    best = dict(best, ms=min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2)))
+    table.append(best)
+    for frac in (1.0, 0.875, 0.75):
         rb = max(1, int(round(best["trace_blocks"] * frac)))
-        for b in batches[:d]:
-            b.set_launch(best["trace_blocks"], best["trace_threads"], 1, 1, refine_blocks=rb)
-        ms = time_in_flight(batches[:d], torch, streams[:d], n)
-        table.append(dict(best, refine_blocks=rb, ms=ms))
-        if log:
-            log("autotune in flight depth=%d blocks=%d threads=%d refine_blocks=%d: %.2f ms/batch"
-                % (d, best["trace_blocks"], best["trace_threads"], rb, ms))
-    best = min((r for r in table if r["in_flight"] == d and r["trace_blocks"] == best["trace_blocks"]
-                and r["trace_threads"] == best["trace_threads"]), key=lambda r: r["ms"])
+        for refill in (1, 2, 4, 8):
+            if frac == 1.0 and refill == 1:
+                continue                      # the first stage's row
+            for b in batches[:d]:
+                b.set_launch(best["trace_blocks"], best["trace_threads"], refill, 1, refine_blocks=rb)
+            ms = min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2))
+            table.append(dict(best, refine_blocks=rb, refill=refill, ms=ms))
+            if log:
+                log("autotune in flight depth=%d blocks=%d threads=%d refine_blocks=%d refill=%d: %.2f ms/batch"
+                    % (d, best["trace_blocks"], best["trace_threads"], rb, refill, ms))
+    best = min(table[-12:], key=lambda r: r["ms"])
     best = dict(best, refine_blocks=best.get("refine_blocks", 0))
     for b in batches:
         b.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], 1,

@@ -1,0 +1,41 @@
+"""Selection logic of the in-flight autotuner with a synthetic cost model
+(no device: the timer and the device query are replaced)."""
+import types
+
+import torch
+
+from paper_2103_07417_amd import autotune
+
+
+class FakeBatch:
+    def __init__(self):
+        self.launch = None
+
+    def set_launch(self, blocks, threads, refill, groups, refine_blocks=0):
+        self.launch = dict(trace_blocks=blocks, trace_threads=threads, refill=refill, groups=groups,
+                           refine_blocks=refine_blocks)
+
+
+def cost(launch, d):
+    # fastest at 256 x 256 with 3 in flight, then refill 4 and a 224-block refinement grid
+    ms = 30.0 + abs(launch["trace_blocks"] - 256) / 64 + (0 if launch["trace_threads"] == 256 else 1)
+    ms += {1: 0.0, 2: -0.3, 4: -0.6, 8: -0.2}[launch["refill"]]
+    rb = launch["refine_blocks"] or launch["trace_blocks"]
+    ms += {256: 0.0, 224: -0.4, 192: -0.1}.get(rb, 5.0)
+    return ms + (0 if d == 3 else 2)
+
+
+def test_in_flight_autotuner_picks_the_cheapest_second_stage(monkeypatch):
+    monkeypatch.setattr(torch.cuda, "get_device_properties",
+                        lambda i: types.SimpleNamespace(multi_processor_count=256))
+    monkeypatch.setattr(autotune, "time_in_flight",
+                        lambda bs, t, ss, n: cost(bs[0].launch, len(bs)))
+    bs = [FakeBatch() for _ in range(3)]
+    out = autotune.autotune_in_flight(bs, [None] * 3, depths=(2, 3))
+    assert (out["in_flight"], out["trace_blocks"], out["trace_threads"]) == (3, 256, 256)
+    assert (out["refill"], out["refine_blocks"]) == (4, 224)
+    assert out["ms"] == min(r["ms"] for r in out["table"])
+    for b in bs:
+        assert b.launch == dict(trace_blocks=256, trace_threads=256, refill=4, groups=1, refine_blocks=224)
+    # first stage: 2 depths x 2 thread counts x 4 grid sizes; second: the best row again + 11 candidates
+    assert len(out["table"]) == 16 + 12
