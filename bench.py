@@ -91,6 +91,11 @@ TRAFFIC = dict(bytes_per_render=401859027, kernel_hash="1013ae1ac963895c", form=
                       "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
 TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
 
+# proposal thresholds of the judge-only render at 16385^2, chosen on a held-out
+# snapshot (other turbulence seed, same view)
+DEPLOY_Z = (0.0, 1.0, 2.0, 3.0, 4.0, 6.0)
+DEPLOY_HELDOUT_SEED = 5
+
 # operating-point grid (R_rel) and the look-ahead proposal thresholds tried
 OP_RREL = (0.001, 0.002, 0.003, 0.005, 0.0075, 0.01, 0.0125, 0.015)
 OP_Z = (0.0, 2.0, 4.0)
@@ -633,6 +638,36 @@ def deploy_16385(art, torch, art_inputs, args):
                          options=opts, subrings=sub_flux(img), subring_mse=sub_mse(img))
         log("16385^2 %s: %.0f ms, %d rays, %d passes, mse %.2e, judge %s" % (
             name, dt * 1e3, st["rays"], st["trace_launches"], mse, st["learned"]))
+    # the judge-only form at the proposal threshold chosen on a held-out
+    # snapshot (turbulence of another seed, the same view): the largest z of
+    # the grid whose render of it keeps Stokes I within the bar
+    img_keep = img.clone()
+    held, _ = mks.mks_snapshot(seed=DEPLOY_HELDOUT_SEED)
+    gh = torch.from_numpy(held).cuda()
+    del held
+    cfg_h = dict(cfg, grid_dev=gh)
+    truth_h, _, _ = art.render_uniform(cfg_h)
+    search = []
+    for z in DEPLOY_Z:
+        img_h, _, _, st_h = art.render_learned(cfg_h, net, out=bufs, z_propose=z, fallback=False)
+        search.append(dict(z_propose=z, mse=art.metrics(truth_h[0], img_h[0])[1], rays=st_h["rays"]))
+    del truth_h, gh, cfg_h
+    torch.cuda.empty_cache()
+    passing = [r["z_propose"] for r in search if r["mse"] <= 1e-3]
+    z_h = max(passing) if passing else min(DEPLOY_Z)
+    opts = dict(z_propose=z_h, fallback=False)
+    (img, lev, ft, st), dt = timed(lambda: art.render_learned(cfg, net, out=bufs, **opts))
+    fe, mse = art.metrics(truth[0], img[0])
+    out["learned_judge_heldout_z"] = dict(
+        ms=dt * 1e3, rays=st["rays"], passes=st["trace_launches"], mse=mse, flux_error=fe,
+        effective_px_per_s=nx * ny / dt, rays_per_s=st["rays"] / dt, judge=st["learned"], options=opts,
+        subrings=sub_flux(img), subring_mse=sub_mse(img), heldout_seed=DEPLOY_HELDOUT_SEED, heldout_search=search,
+        vs_plain=dict(ms=dt * 1e3 / out["plain"]["ms"], rays=st["rays"] / out["plain"]["rays"]))
+    log("16385^2 learned_judge at z = %g (held-out snapshot %s): %.0f ms, %d rays, %d passes, mse %.2e, "
+        "subring mse %s" % (z_h, ["%g: %.2e" % (r["z_propose"], r["mse"]) for r in search], dt * 1e3,
+                            st["rays"], st["trace_launches"], mse,
+                            ["%.2e" % x for x in out["learned_judge_heldout_z"]["subring_mse"]]))
+    img = img_keep
     net.close()
     out["visibility"] = deploy_visibility(art, torch, art_inputs, cfg, img, truth)
     del bufs, truth, img, lev, ft, g
