@@ -100,6 +100,7 @@ DEPLOY_HELDOUT_SEED = 5
 OP_RREL = (0.001, 0.002, 0.003, 0.005, 0.0075, 0.01, 0.0125, 0.015)
 OP_Z = (0.0, 2.0, 4.0)
 OP_Z_JUDGE = (0.0, 2.0)      # judge-only forms (no fallback pass)
+OP_Z_JUDGE_L0 = (0.0, 2.0, 4.0, 6.0)    # judge-only forms with the network at level 0 only
 HELDOUT_LAUNCH = dict(trace_blocks=256, trace_threads=256, refill=1, groups=1)
 TRAIN_RREL = 0.005           # tolerance of the plain renders the network learns from
 PRECISION_NAMES = dict(fp64="FP64 throughout", mixed="FP64 geodesic, FP32 plasma and transfer",
@@ -340,7 +341,8 @@ def c4_forms(art, torch, art_inputs, args):
                                     for z in OP_Z] + \
         [("judge_z%g" % z, dict(z_propose=z, z_suppress=-inf, fallback=False)) for z in OP_Z_JUDGE] + \
         [("lookahead_z4_l0", dict(z_propose=4.0, z_suppress=-inf, fallback=True, level_cap=1))] + \
-        [("judge_z%g_l0" % z, dict(z_propose=z, z_suppress=-inf, fallback=False, level_cap=1)) for z in OP_Z_JUDGE]
+        [("judge_z%g_l0" % z, dict(z_propose=z, z_suppress=-inf, fallback=False, level_cap=1))
+         for z in OP_Z_JUDGE_L0]
     opts_of = dict(op_forms)
 
     def truths_of(cfgs):
