@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const uint16_t* __restrict
                 *(bf16x4*)&a_s[pos * CS + 4 * c4] = av_[t];
             }
         }
-        __syncthreads();                      // halos (and, in round 0, weights) staged
+        __syncthreads();                      // halos (and, in the first tile round, weights) staged
         int b, y, x0;
         const bool ok = tile_of(r, b, y, x0);
         if (r + 1 < kConvTiles) load_halo(r + 1);
