@@ -555,6 +555,14 @@ def grid_forms(art, torch, art_inputs, args):
     return out
 
 
+def deploy_threshold(search, bar=1e-3):
+    """Proposal threshold of the 16385^2 judge-only render from the held-out
+    search rows (z_propose, mse): the largest z whose render kept Stokes I
+    within the bar, else the smallest z tried."""
+    passing = [r["z_propose"] for r in search if r["mse"] <= bar]
+    return max(passing) if passing else min(r["z_propose"] for r in search)
+
+
 def deploy_16385(art, torch, art_inputs, args):
     """Learned proposal deployed on the snapshot at 16385^2 (base 257^2, 6
     levels, Stokes I): plain and learned adaptive renders against the uniform
@@ -655,8 +663,7 @@ def deploy_16385(art, torch, art_inputs, args):
         search.append(dict(z_propose=z, mse=art.metrics(truth_h[0], img_h[0])[1], rays=st_h["rays"]))
     del truth_h, gh, cfg_h
     torch.cuda.empty_cache()
-    passing = [r["z_propose"] for r in search if r["mse"] <= 1e-3]
-    z_h = max(passing) if passing else min(DEPLOY_Z)
+    z_h = deploy_threshold(search)
     opts = dict(z_propose=z_h, fallback=False)
     (img, lev, ft, st), dt = timed(lambda: art.render_learned(cfg, net, out=bufs, **opts))
     fe, mse = art.metrics(truth[0], img[0])

@@ -139,3 +139,10 @@ def test_parse_launch():
                                                   refine_blocks=0)
     assert bench.parse_launch("256X128:192")["refine_blocks"] == 192
     assert bench.parse_launch("256X128:192")["trace_threads"] == 128
+
+
+def test_deploy_threshold():
+    rows = [dict(z_propose=z, mse=m) for z, m in ((0.0, 6e-5), (2.0, 2e-4), (4.0, 5e-4), (6.0, 1.2e-3))]
+    assert bench.deploy_threshold(rows) == 4.0
+    assert bench.deploy_threshold([dict(r, mse=2e-3) for r in rows]) == 0.0
+    assert bench.deploy_threshold([dict(r, mse=1e-4) for r in rows]) == 6.0
