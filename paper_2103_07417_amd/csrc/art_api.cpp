@@ -461,12 +461,9 @@ int layout(art_batch* b, hipStream_t s)
         Gr.max_base = 0;
         Gr.nx0m = Gr.ny0m = 0;
         Gr.list_off = off;
-        int base = 0;
         const size_t off0 = off;
         for (int k = 0; k < Gr.n; ++k) {
             ImageDesc& D = b->hD[Gr.i0 + k];
-            D.base_off = base;                 // base items of an image are contiguous in its group's slice
-            base += D.nx0 * D.ny0;
             Gr.lmax = D.levels > Gr.lmax ? D.levels : Gr.lmax;
             Gr.max_base = D.nx0 * D.ny0 > Gr.max_base ? D.nx0 * D.ny0 : Gr.max_base;
             Gr.nx0m = D.nx0 > Gr.nx0m ? D.nx0 : Gr.nx0m;
@@ -554,9 +551,9 @@ int prepare(art_batch* b, int n, const art_job* jobs, const art_image* images, b
                                  (J.rf.all_planes ? kRefineAllPlanes : 0) |
                                  (J.rf.all_planes == 2 ? kRefineOwnNorm : 0));
         D.abs_norm = J.rf.abs_norm;
+        D.pad0 = 0;
         D.r_rel = J.rf.r_rel;
         D.r_abs = J.rf.r_abs;
-        D.base_off = 0;
         D.sa = D.sb = D.sc = D.sd = -1;
         D.sr_rel = D.sr_abs = 0.0;
         total += (size_t)D.plane;
@@ -642,7 +639,8 @@ int enqueue_base(art_batch* b, int g, hipStream_t s)
     const BatchGroup& G = b->grp[g];
     Counters* ctr = b->ctr + g;
     HIP_TRY(launch_fill_u32((uint32_t*)ctr, sizeof(Counters) / 4, 0u, s));
-    HIP_TRY(launch_base_list(b->dD + G.i0, G.n, G.max_base, b->list + G.list_off, ctr, 0, s));
+    HIP_TRY(launch_base_list(b->dD + G.i0, b->dP + G.i0, G.n, G.max_base, b->list + G.list_off,
+                             (long long)G.list_len, ctr, 0, s));
     int rc = trace_pass(b, g, 0, s);
     if (rc) return rc;
     HIP_TRY(launch_reduce_base(b->dD + G.i0, G.n, ctr, s));
@@ -816,7 +814,7 @@ int enqueue_spectral(art_batch* b, int n0, int slevels, hipStream_t s)
             if (l < 0 || l > N) continue;
             if (l == 0) {
                 if (sl == 0)
-                    HIP_TRY(launch_base_list(b->dD, n0, nb, list, ctr, t, s));
+                    HIP_TRY(launch_base_list(b->dD, b->dP, n0, nb, list, cap, ctr, t, s));
                 else
                     HIP_TRY(launch_spectral_base(b->dD, off[sl], m[sl], nb, ctr, list, cap, b->L.long_steps, t, s));
             } else {

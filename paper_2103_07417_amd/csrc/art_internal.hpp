@@ -37,7 +37,7 @@ struct ImageDesc {
     RayFeat* feat;        // optional
     uint16_t* cost;       // steps of each traced ray, neighbours' maximum for interpolated points
     long long plane;      // nx * ny
-    int32_t nx, ny, nx0, ny0, levels, nstokes, abs_norm, base_off;
+    int32_t nx, ny, nx0, ny0, levels, nstokes, abs_norm, pad0;
     int32_t nplanes;       // image planes: nstokes + subring planes
     int32_t flags;         // kRefine* bits
     double r_rel, r_abs;
@@ -101,8 +101,8 @@ struct LaunchCfg {
 
 hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_i8(int8_t* p, long long n, int8_t v, hipStream_t s);
-hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsigned long long* list,
-                            Counters* ctr, int level_slot, hipStream_t s);
+hipError_t launch_base_list(const ImageDesc* desc, const Params* params, int nimg, int max_base,
+                            unsigned long long* list, long long cap, Counters* ctr, int level_slot, hipStream_t s);
 hipError_t launch_trace(int precision, int model, int nstokes, bool subrings, const TraceJob& J,
                         const LaunchCfg& L, hipStream_t s);
 hipError_t launch_reduce_base(const ImageDesc* desc, int nimg, Counters* ctr, hipStream_t s, int img_off = 0);

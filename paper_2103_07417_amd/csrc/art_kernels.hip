@@ -53,32 +53,72 @@ hipError_t launch_fill_i8(int8_t* p, long long n, int8_t v, hipStream_t s)
 }
 
 // ------------------------------------------------------------ base-grid list
-// grid (x: base points, y: image).  Items of image i occupy
-// list[base_off_i, base_off_i + nx0_i ny0_i).
-__global__ void k_base_list(const ImageDesc* desc, unsigned long long* list, Counters* ctr, int slot)
+// grid (x: base points, y: image).  Base points within kFrontRadius (in M) of
+// the screen centre, where the critical curve of every Kerr spin and view
+// lies, are queued at the front of the list, the others from its back: the
+// photon-ring rays, the longest of the pass, start first instead of wherever
+// their image falls in the batch, so the pass does not end on a late one.
+// The order changes no result.  List slots are reserved once per block.
+constexpr double kFrontRadius = 8.0;
+constexpr int kBaseThreads = 256;
+
+__global__ __launch_bounds__(kBaseThreads) void k_base_list(const ImageDesc* desc, const Params* params,
+                                                            unsigned long long* list, long long cap,
+                                                            Counters* ctr, int slot)
 {
+    constexpr int kWaves = kBaseThreads / 64;
+    __shared__ unsigned s_cnt[2][kWaves];
+    __shared__ unsigned s_base[2];
     const int img = blockIdx.y;
     const ImageDesc D = desc[img];
+    const double x0 = params[img].x0, y0 = params[img].y0, dx = params[img].dx;
     const int n = D.nx0 * D.ny0;
     const int st0 = 1 << D.levels;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        const int i = t % D.nx0, j = t / D.nx0;
-        const uint32_t pix = (uint32_t)(j * st0) * (uint32_t)D.nx + (uint32_t)(i * st0);
-        list[D.base_off + t] = make_item((uint32_t)img, pix);
-        if (D.level) D.level[pix] = 0;
+    const int wave = threadIdx.x >> 6;
+    // block-uniform trip count: every lane takes part in the ballots and barriers
+    for (int t0 = blockIdx.x * kBaseThreads; t0 < n; t0 += gridDim.x * kBaseThreads) {
+        const int t = t0 + threadIdx.x;
+        const bool valid = t < n;
+        bool front = false;
+        uint32_t pix = 0;
+        if (valid) {
+            const int i = t % D.nx0, j = t / D.nx0;
+            pix = (uint32_t)(j * st0) * (uint32_t)D.nx + (uint32_t)(i * st0);
+            const double al = x0 + (double)(i * st0) * dx, be = y0 + (double)(j * st0) * dx;
+            front = al * al + be * be <= kFrontRadius * kFrontRadius;
+            if (D.level) D.level[pix] = 0;
+        }
+        const unsigned long long mf = __ballot(valid && front), mb = __ballot(valid && !front);
+        if (__lane_id() == 0) {
+            s_cnt[0][wave] = (unsigned)__popcll(mf);
+            s_cnt[1][wave] = (unsigned)__popcll(mb);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned nf = 0, nb = 0;
+            for (int w = 0; w < kWaves; ++w) { nf += s_cnt[0][w]; nb += s_cnt[1][w]; }
+            s_base[0] = nf ? atomicAdd(&ctr->count[slot], nf) : 0u;
+            s_base[1] = nb ? atomicAdd(&ctr->count_back[slot], nb) : 0u;
+        }
+        __syncthreads();
+        unsigned of = s_base[0], ob = s_base[1];
+        for (int w = 0; w < wave; ++w) { of += s_cnt[0][w]; ob += s_cnt[1][w]; }
+        const unsigned long long item = make_item((uint32_t)img, pix);
+        if (valid && front) list[of + lane_prefix(mf)] = item;
+        if (valid && !front) list[cap - 1 - (long long)(ob + lane_prefix(mb))] = item;
+        __syncthreads();                       // s_cnt and s_base are reused
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        atomicAdd(&ctr->count[slot], (uint32_t)n);
-        ctr->img_traced[img][0] = (uint32_t)n;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->img_traced[img][0] = (uint32_t)n;
 }
 
-hipError_t launch_base_list(const ImageDesc* desc, int nimg, int max_base, unsigned long long* list,
-                            Counters* ctr, int slot, hipStream_t s)
+hipError_t launch_base_list(const ImageDesc* desc, const Params* params, int nimg, int max_base,
+                            unsigned long long* list, long long cap, Counters* ctr, int slot, hipStream_t s)
 {
-    int bx = (max_base + 255) / 256;
+    if (nimg <= 0) return hipSuccess;
+    int bx = (max_base + kBaseThreads - 1) / kBaseThreads;
     if (bx > 1024) bx = 1024;
-    hipLaunchKernelGGL(k_base_list, dim3(bx, nimg), dim3(256), 0, s, desc, list, ctr, slot);
+    hipLaunchKernelGGL(k_base_list, dim3(bx, nimg), dim3(kBaseThreads), 0, s, desc, params, list, cap, ctr,
+                       slot);
     return hipGetLastError();
 }
 
