@@ -395,17 +395,18 @@ def c4_forms(art, torch, art_inputs, args):
         for X in bset:
             X.set_learned(None) if opts is None else X.set_learned(net, **opts)
         depth, tune = nmax, None
-        launch = dict(trace_blocks=512, trace_threads=256, refill=1, groups=1, refine_blocks=0)
+        launch = dict(trace_blocks=512, trace_threads=256, refill=1, groups=1, refine_blocks=0, long_steps=0)
         if args.launch:
             # a fixed shape (counter runs serialise dispatches, which would
             # steer the in-flight search to other shapes than the timed run's)
-            launch = dict(parse_launch(args.launch), refill=args.refill)
+            launch = dict(parse_launch(args.launch), refill=args.refill, long_steps=args.long_steps)
             depth = args.in_flight or 3
         elif not args.no_autotune:
             depths = (args.in_flight,) if args.in_flight else IN_FLIGHT_DEPTHS
             tune = autotune.autotune_in_flight(bset, ss, depths=depths, log=None)
             depth = tune["in_flight"]
-            launch = {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "groups", "refine_blocks")}
+            launch = {k: tune[k] for k in ("trace_blocks", "trace_threads", "refill", "groups", "refine_blocks",
+                                           "long_steps")}
         for X in bset:
             X.set_launch(**launch)
         for X in bset[depth:]:
@@ -1004,6 +1005,8 @@ def main():
                          "in-flight autotuner (with --in-flight, else three batches in flight)")
     ap.add_argument("--refill", type=int, default=1,
                     help="refill threshold of the timed forms with --launch (lanes idle before a wave claims rays)")
+    ap.add_argument("--long-steps", type=int, default=0,
+                    help="long-ray threshold of the refinement queues of the timed forms with --launch (0: 800)")
     ap.add_argument("--learned-form", default="",
                     help="learned form timed on the headline batch instead of the fastest on the held-out "
                          "batch (for counter runs, whose serialised dispatches change the held-out timings)")

@@ -317,6 +317,10 @@ typedef struct {
     int32_t refine_blocks;         /* grid size of the refinement passes (every pass after a
                                       batch's base grid, and a cube's passes after its first);
                                       0 = trace_blocks */
+    int32_t long_steps;            /* refinement queues: a new point whose neighbours' largest
+                                      step count reaches this is queued at the front of its pass
+                                      (started first), the others at the back; 0 = 800; at most
+                                      65535 */
 } art_launch;
 
 int art_set_launch(const art_launch* launch);

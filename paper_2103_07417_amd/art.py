@@ -94,7 +94,7 @@ class Job(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("trace_blocks", ctypes.c_int32), ("trace_threads", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("groups", ctypes.c_int32),
-                ("refine_blocks", ctypes.c_int32)]
+                ("refine_blocks", ctypes.c_int32), ("long_steps", ctypes.c_int32)]
 
 
 FEAT_DTYPE = np.dtype([("rmin", np.float32), ("ncross", np.int32),
@@ -473,10 +473,10 @@ def feat_numpy(ft):
     return a.view(FEAT_DTYPE).reshape(a.shape[:-1])
 
 
-def set_launch(trace_blocks=0, trace_threads=0, refill=0, groups=0, refine_blocks=0):
+def set_launch(trace_blocks=0, trace_threads=0, refill=0, groups=0, refine_blocks=0, long_steps=0):
     """Persistent-tracer launch shape for later renders (0 = default)."""
     _check(lib().art_set_launch(ctypes.byref(Launch(trace_blocks, trace_threads, refill, groups,
-                                                    refine_blocks))))
+                                                    refine_blocks, long_steps))))
 
 
 def get_launch(cfg):
@@ -484,7 +484,7 @@ def get_launch(cfg):
     L = Launch()
     _check(lib().art_get_launch(tr.precision, em.kind, tr.nstokes, ctypes.byref(L)))
     return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill,
-                groups=L.groups, refine_blocks=L.refine_blocks)
+                groups=L.groups, refine_blocks=L.refine_blocks, long_steps=L.long_steps)
 
 
 class Batch:
@@ -536,15 +536,16 @@ class Batch:
         _check(lib().art_batch_stats(self._h, int(i), ctypes.byref(st), _stream(self._torch, stream)))
         return stats_dict(st)
 
-    def set_launch(self, trace_blocks=0, trace_threads=0, refill=0, groups=0, refine_blocks=0):
+    def set_launch(self, trace_blocks=0, trace_threads=0, refill=0, groups=0, refine_blocks=0, long_steps=0):
         _check(lib().art_batch_set_launch(self._h, ctypes.byref(Launch(trace_blocks, trace_threads,
-                                                                         refill, groups, refine_blocks))))
+                                                                         refill, groups, refine_blocks,
+                                                                         long_steps))))
 
     def get_launch(self):
         L = Launch()
         _check(lib().art_batch_get_launch(self._h, ctypes.byref(L)))
         return dict(trace_blocks=L.trace_blocks, trace_threads=L.trace_threads, refill=L.refill,
-                    groups=L.groups, refine_blocks=L.refine_blocks)
+                    groups=L.groups, refine_blocks=L.refine_blocks, long_steps=L.long_steps)
 
     def set_learned(self, net, **opts):
         """Use the network `net` (a Cnn, or None for plain renders) in later

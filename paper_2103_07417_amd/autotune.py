@@ -135,8 +135,11 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
     drained, while the other batches take the freed slots) crossed with
     refill thresholds 1, 2, 4, 8 (a wave that waits for a few idle lanes
     starts their rays with one pass through the ray set-up instead of one
-    per termination).  The fastest choice is applied to every batch.  Returns
-    the choice and the table."""
+    per termination); then, at that choice, the long-ray threshold of the
+    refinement queues (600, 700, 900 besides the default 800: the points
+    queued at the front should be about as many as the lanes that start
+    them).  The fastest choice is applied to every batch.  Returns the choice
+    and the table."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     depths = tuple(depths or (len(batches),))
@@ -179,8 +182,19 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
                 log("autotune in flight depth=%d blocks=%d threads=%d refine_blocks=%d refill=%d: %.2f ms/batch"
                     % (d, best["trace_blocks"], best["trace_threads"], rb, refill, ms))
     best = min(table[-12:], key=lambda r: r["ms"])
-    best = dict(best, refine_blocks=best.get("refine_blocks", 0))
+    best = dict(best, refine_blocks=best.get("refine_blocks", 0), long_steps=0)
+    for ls in (600, 700, 900):
+        for b in batches[:d]:
+            b.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], 1,
+                         refine_blocks=best["refine_blocks"], long_steps=ls)
+        ms = min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2))
+        table.append(dict(best, long_steps=ls, ms=ms))
+        if log:
+            log("autotune in flight depth=%d blocks=%d threads=%d refine_blocks=%d refill=%d long_steps=%d: "
+                "%.2f ms/batch" % (d, best["trace_blocks"], best["trace_threads"], best["refine_blocks"],
+                                   best["refill"], ls, ms))
+    best = min([best] + table[-3:], key=lambda r: r["ms"])
     for b in batches:
         b.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], 1,
-                     refine_blocks=best["refine_blocks"])
+                     refine_blocks=best["refine_blocks"], long_steps=best["long_steps"])
     return dict(best, search_s=time.perf_counter() - t0, table=table)

@@ -74,7 +74,7 @@ int env_int(const char* name, int dflt)
     return atoi(v);
 }
 
-art_launch g_launch = { 0, 0, 0, 0, 0 };   // user override (0 = default)
+art_launch g_launch = { 0, 0, 0, 0, 0, 0 };   // user override (0 = default)
 size_t g_list_limit = 0;                // bytes a trace list + cost map may take (0: no limit)
 std::mutex g_mu;
 
@@ -333,7 +333,7 @@ LaunchCfg launch_cfg(int cus, int precision, int model, int nstokes, bool sub = 
     L.refill = u.refill > 0 ? u.refill : env_int("ART_REFILL", 1);
     if (L.refill < 1) L.refill = 1;
     if (L.refill > 64) L.refill = 64;
-    L.long_steps = env_int("ART_LONG_STEPS", 800);
+    L.long_steps = u.long_steps > 0 ? u.long_steps : env_int("ART_LONG_STEPS", 800);
     return L;
 }
 
@@ -1457,6 +1457,7 @@ int art_set_launch(const art_launch* L)
         return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
     if (L->trace_blocks < 0 || L->refine_blocks < 0 || L->refill < 0 || L->refill > 64)
         return fail(ART_EINVAL, "trace_blocks >= 0, refine_blocks >= 0 and 0 <= refill <= 64 required");
+    if (L->long_steps < 0 || L->long_steps > 65535) return fail(ART_EINVAL, "long_steps must be in 0..65535");
     if (L->groups < 0 || L->groups > kMaxGroups) return fail(ART_EINVAL, "groups must be in 0..%d", kMaxGroups);
     std::lock_guard<std::mutex> lk(g_mu);
     g_launch = *L;
@@ -1470,13 +1471,14 @@ int art_batch_set_launch(art_batch* b, const art_launch* L)
         return fail(ART_EINVAL, "trace_threads must be 0, 64, 128 or 256");
     if (L->trace_blocks < 0 || L->refine_blocks < 0 || L->refill < 0 || L->refill > 64)
         return fail(ART_EINVAL, "trace_blocks >= 0, refine_blocks >= 0 and 0 <= refill <= 64 required");
+    if (L->long_steps < 0 || L->long_steps > 65535) return fail(ART_EINVAL, "long_steps must be in 0..65535");
     if (L->groups < 0 || L->groups > kMaxGroups) return fail(ART_EINVAL, "groups must be in 0..%d", kMaxGroups);
     const LaunchCfg d = launch_cfg(b->cus, b->precision, b->model, b->nstokes, b->nsub > 0);
     b->L.trace_threads = L->trace_threads ? L->trace_threads : d.trace_threads;
     b->L.trace_blocks = L->trace_blocks ? L->trace_blocks : d.trace_blocks;
     b->L.refine_blocks = L->refine_blocks ? L->refine_blocks : b->L.trace_blocks;
     b->L.refill = L->refill ? L->refill : d.refill;
-    b->L.long_steps = d.long_steps;
+    b->L.long_steps = L->long_steps ? L->long_steps : d.long_steps;
     if (L->groups != b->req_groups) {
         // a new split of the images: new descriptors, and a captured graph is stale
         HIP_TRY(hipDeviceSynchronize());
@@ -1500,6 +1502,7 @@ int art_batch_get_launch(const art_batch* b, art_launch* L)
     if (!b || !L) return fail(ART_EINVAL, "NULL argument");
     L->trace_blocks = b->L.trace_blocks;
     L->refine_blocks = b->L.refine_blocks;
+    L->long_steps = b->L.long_steps;
     L->trace_threads = b->L.trace_threads;
     L->refill = b->L.refill;
     L->groups = b->ngroups;
@@ -1515,6 +1518,7 @@ int art_get_launch(int32_t precision, int32_t kind, int32_t nstokes, art_launch*
     const LaunchCfg c = launch_cfg(cus, precision, kind, nstokes);
     L->trace_blocks = c.trace_blocks;
     L->refine_blocks = c.refine_blocks;
+    L->long_steps = c.long_steps;
     L->trace_threads = c.trace_threads;
     L->refill = c.refill;
     L->groups = 0;

@@ -112,9 +112,9 @@ def test_cube_batch_validation_host_only():
 def test_launch_configuration_validation_host_only():
     """art_set_launch checks its fields on the host (no device call)."""
     for bad in (dict(trace_threads=96), dict(trace_blocks=-1), dict(refine_blocks=-1), dict(refill=65),
-                dict(groups=9)):
+                dict(groups=9), dict(long_steps=-1), dict(long_steps=65536)):
         with pytest.raises(art.ArtError):
             art.set_launch(**bad)
-    art.set_launch(256, 256, 1, refine_blocks=192)
+    art.set_launch(256, 256, 1, refine_blocks=192, long_steps=700)
     art.set_launch(0, 0, 0)
-    assert ctypes.sizeof(art.Launch) == 20
+    assert ctypes.sizeof(art.Launch) == 24

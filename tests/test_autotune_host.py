@@ -11,9 +11,9 @@ class FakeBatch:
     def __init__(self):
         self.launch = None
 
-    def set_launch(self, blocks, threads, refill, groups, refine_blocks=0):
+    def set_launch(self, blocks, threads, refill, groups, refine_blocks=0, long_steps=0):
         self.launch = dict(trace_blocks=blocks, trace_threads=threads, refill=refill, groups=groups,
-                           refine_blocks=refine_blocks)
+                           refine_blocks=refine_blocks, long_steps=long_steps)
 
 
 def cost(launch, d):
@@ -22,6 +22,7 @@ def cost(launch, d):
     ms += {1: 0.0, 2: -0.3, 4: -0.6, 8: -0.2}[launch["refill"]]
     rb = launch["refine_blocks"] or launch["trace_blocks"]
     ms += {256: 0.0, 224: -0.4, 192: -0.1}.get(rb, 5.0)
+    ms += {0: 0.0, 600: -0.1, 700: -0.3, 900: 0.4}[launch["long_steps"]]
     return ms + (0 if d == 3 else 2)
 
 
@@ -33,9 +34,11 @@ def test_in_flight_autotuner_picks_the_cheapest_second_stage(monkeypatch):
     bs = [FakeBatch() for _ in range(3)]
     out = autotune.autotune_in_flight(bs, [None] * 3, depths=(2, 3))
     assert (out["in_flight"], out["trace_blocks"], out["trace_threads"]) == (3, 256, 256)
-    assert (out["refill"], out["refine_blocks"]) == (4, 224)
+    assert (out["refill"], out["refine_blocks"], out["long_steps"]) == (4, 224, 700)
     assert out["ms"] == min(r["ms"] for r in out["table"])
     for b in bs:
-        assert b.launch == dict(trace_blocks=256, trace_threads=256, refill=4, groups=1, refine_blocks=224)
-    # first stage: 2 depths x 2 thread counts x 4 grid sizes; second: the best row again + 11 candidates
-    assert len(out["table"]) == 16 + 12
+        assert b.launch == dict(trace_blocks=256, trace_threads=256, refill=4, groups=1, refine_blocks=224,
+                                long_steps=700)
+    # first stage: 2 depths x 2 thread counts x 4 grid sizes; second: the best row again + 11 candidates;
+    # third: 3 thresholds
+    assert len(out["table"]) == 16 + 12 + 3

@@ -79,11 +79,11 @@ def test_launch_shape_does_not_change_results(art):
     cfg = art_inputs.reduced(art_inputs.workload("thermal_1025"), 17, 2)
     ref, rlev, _, _ = art.render(cfg)
     try:
-        for blocks, threads, refill, rb in ((7, 64, 1, 0), (300, 128, 8, 0), (64, 256, 64, 0), (256, 256, 1, 3),
-                                            (5, 128, 1, 192)):
-            art.set_launch(blocks, threads, refill, refine_blocks=rb)
+        for blocks, threads, refill, rb, ls in ((7, 64, 1, 0, 0), (300, 128, 8, 0, 0), (64, 256, 64, 0, 0),
+                                                (256, 256, 1, 3, 1), (5, 128, 1, 192, 65535), (96, 256, 4, 64, 300)):
+            art.set_launch(blocks, threads, refill, refine_blocks=rb, long_steps=ls)
             img, lev, _, _ = art.render(cfg)
-            assert torch.equal(img, ref) and torch.equal(lev, rlev), (blocks, threads, refill, rb)
+            assert torch.equal(img, ref) and torch.equal(lev, rlev), (blocks, threads, refill, rb, ls)
     finally:
         art.set_launch(0, 0, 0)
 
