@@ -725,7 +725,7 @@ int enqueue_learned(art_batch* b, int g, hipStream_t s)
         HIP_TRY(cnn_features_batch(dD, ctr, G.nnet[l], l, H, W, nullptr, G.ws.x, s, im));
         HIP_TRY(cnn_net_forward(&b->net->net, &G.ws, nullptr, G.nnet[l], H, W, G.ws.logits, s));
         HIP_TRY(cnn_propose(G.ws.logits, dD, G.nnet[l], l, H, W, o.z_propose, o.z_suppress, o.all_levels, list,
-                            ctr, s, im));
+                            cap, b->L.long_steps, ctr, s, im));
         // mode 1: images the network decided for read its marks; the others
         // (one level left, no all_levels) take the plain criterion
         int ne;

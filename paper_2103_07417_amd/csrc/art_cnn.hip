@@ -774,20 +774,25 @@ hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N
 
 // Proposals: one thread per vertex of image blockIdx.y, every output of the
 // vertex.  The block's level-(l+2) proposals are counted first and reserved in
-// the trace list of pass l+1 with one atomic per block (per wave and output,
-// the shared list counter serialised the kernel).
+// the trace list of pass l+1 with one atomic per block and list end (per wave
+// and output, the shared list counter serialised the kernel).  A proposal is
+// queued at the front of the list when the largest step count of its cell's
+// four level-l corners reaches long_steps, else from the back, as the
+// estimator queues the points it flags: the long rays of the look-ahead pass
+// start first.
 constexpr int kProposeThreads = 256;
 
 __global__ __launch_bounds__(kProposeThreads) void k_cnn_propose(const float* __restrict__ logits,
                                                                  const ImageDesc* __restrict__ desc, int l, int H,
                                                                  int W, float z_hi, float z_lo, int all_levels,
                                                                  unsigned long long* __restrict__ list,
+                                                                 long long cap, int long_steps,
                                                                  Counters* __restrict__ ctr,
                                                                  const int* __restrict__ imap)
 {
     constexpr int kWaves = kProposeThreads / 64;
-    __shared__ unsigned s_cnt[kWaves];
-    __shared__ unsigned s_base;
+    __shared__ unsigned s_cnt[2][kWaves];
+    __shared__ unsigned s_base[2];
     const int b = blockIdx.y;                 // slot of the logits
     const int img = imap ? imap[b] : b;       // image of the batch
     const ImageDesc& D = desc[img];
@@ -819,48 +824,74 @@ __global__ __launch_bounds__(kProposeThreads) void k_cnn_propose(const float* __
             D.level[pix] = m;
         }
     }
+    // expected cost of the cell's proposals: its most expensive corner
+    bool front = false;
+    if (app && D.cost) {
+        const int nxl = (1 << l) * (D.nx0 - 1) + 1, nyl = (1 << l) * (D.ny0 - 1) + 1;
+        const long long sL = 1LL << (D.levels - l);
+        const int i1 = i + 1 < nxl ? i + 1 : i, j1 = j + 1 < nyl ? j + 1 : j;
+        const uint16_t c00 = D.cost[(long long)j * sL * D.nx + (long long)i * sL];
+        const uint16_t c10 = D.cost[(long long)j * sL * D.nx + (long long)i1 * sL];
+        const uint16_t c01 = D.cost[(long long)j1 * sL * D.nx + (long long)i * sL];
+        const uint16_t c11 = D.cost[(long long)j1 * sL * D.nx + (long long)i1 * sL];
+        const uint16_t ca = c00 > c10 ? c00 : c10, cb = c01 > c11 ? c01 : c11;
+        front = (int)(ca > cb ? ca : cb) >= long_steps;
+    }
+    const unsigned fb = front ? app : 0u, bb = front ? 0u : app;
     const int wave = threadIdx.x >> 6;
-    unsigned wtot = 0;
-    for (int k = 3; k < kCnnOut; ++k) wtot += (unsigned)__popcll(__ballot((app >> k) & 1u));
-    if (__lane_id() == 0) s_cnt[wave] = wtot;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned n = 0;
-        for (int w = 0; w < kWaves; ++w) n += s_cnt[w];
-        unsigned base = 0;
-        if (n) {
-            base = atomicAdd(&ctr->count[l + 1], n);
-            atomicAdd(&ctr->img_traced[img][l + 1], n);
-            atomicAdd(&ctr->judge[img][4], (unsigned long long)n);
-        }
-        s_base = base;
+    unsigned wf = 0, wb = 0;
+    for (int k = 3; k < kCnnOut; ++k) {
+        wf += (unsigned)__popcll(__ballot((fb >> k) & 1u));
+        wb += (unsigned)__popcll(__ballot((bb >> k) & 1u));
+    }
+    if (__lane_id() == 0) {
+        s_cnt[0][wave] = wf;
+        s_cnt[1][wave] = wb;
     }
     __syncthreads();
-    if (wtot == 0) return;                    // wave-uniform
-    unsigned off = s_base;
-    for (int w = 0; w < wave; ++w) off += s_cnt[w];
+    if (threadIdx.x == 0) {
+        unsigned nf = 0, nb = 0;
+        for (int w = 0; w < kWaves; ++w) { nf += s_cnt[0][w]; nb += s_cnt[1][w]; }
+        s_base[0] = nf ? atomicAdd(&ctr->count[l + 1], nf) : 0u;
+        s_base[1] = nb ? atomicAdd(&ctr->count_back[l + 1], nb) : 0u;
+        if (nf + nb) {
+            atomicAdd(&ctr->img_traced[img][l + 1], nf + nb);
+            atomicAdd(&ctr->judge[img][4], (unsigned long long)(nf + nb));
+        }
+    }
+    __syncthreads();
+    if (wf + wb == 0) return;                 // wave-uniform
+    unsigned of = s_base[0], ob = s_base[1];
+    for (int w = 0; w < wave; ++w) { of += s_cnt[0][w]; ob += s_cnt[1][w]; }
     for (int k = 3; k < kCnnOut; ++k) {
-        const unsigned long long mask = __ballot((app >> k) & 1u);
+        const unsigned long long mf = __ballot((fb >> k) & 1u), mb = __ballot((bb >> k) & 1u);
         if ((app >> k) & 1u) {
             long long pix = 0;
             int lev;
             owned_point(k, i, j, l, D.levels, D.nx0, D.ny0, D.nx, pix, lev);
-            const unsigned r = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-            list[off + r] = make_item((uint32_t)img, (uint32_t)pix);
+            const unsigned long long item = make_item((uint32_t)img, (uint32_t)pix);
+            if (front)
+                list[of + __builtin_amdgcn_mbcnt_hi((unsigned)(mf >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mf, 0u))]
+                    = item;
+            else
+                list[cap - 1 - (long long)(ob + __builtin_amdgcn_mbcnt_hi((unsigned)(mb >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((unsigned)mb, 0u)))]
+                    = item;
         }
-        off += (unsigned)__popcll(mask);
+        of += (unsigned)__popcll(mf);
+        ob += (unsigned)__popcll(mb);
     }
 }
 
 hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int l, int H, int W, float z_hi,
-                       float z_lo, int all_levels, unsigned long long* list, Counters* ctr, hipStream_t s,
-                       const int* imap)
+                       float z_lo, int all_levels, unsigned long long* list, long long cap, int long_steps,
+                       Counters* ctr, hipStream_t s, const int* imap)
 {
     const long long HW = (long long)H * W;
     if (HW >= (1LL << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cnn_propose, dim3((unsigned)((HW + kProposeThreads - 1) / kProposeThreads), nimg),
-                       dim3(kProposeThreads), 0, s, logits, desc, l, H, W, z_hi, z_lo, all_levels, list, ctr, imap);
+                       dim3(kProposeThreads), 0, s, logits, desc, l, H, W, z_hi, z_lo, all_levels, list, cap,
+                       long_steps, ctr, imap);
     return hipGetLastError();
 }
 

@@ -61,14 +61,16 @@ hipError_t cnn_labels(const int8_t* level, long long nx, int nx0, int ny0, int N
                       uint8_t* val, hipStream_t s);
 // Proposals of every image from logits[b][15][H][W]: level-(l+1) points above
 // z_hi are marked kMarkPropose, level-(l+2) points above z_hi are marked l+2
-// and appended to the trace list of pass l+1; points below z_lo are marked
+// and appended to the trace list of pass l+1 (of capacity cap: at the front
+// when the largest step count of their cell's level-l corners reaches
+// long_steps, else from the back); points below z_lo are marked
 // kMarkSuppress, all others kMarkUnset (every owned point is written).  An
 // image whose level count is l + 1 gets kMarkUnset everywhere unless
 // all_levels (the plain criterion decides its last level).
 // logits[b] belongs to image imap[b] (all images in order if imap is null).
 hipError_t cnn_propose(const float* logits, const ImageDesc* desc, int nimg, int l, int H, int W,
-                       float z_hi, float z_lo, int all_levels, unsigned long long* list, Counters* ctr,
-                       hipStream_t s, const int* imap = nullptr);
+                       float z_hi, float z_lo, int all_levels, unsigned long long* list, long long cap,
+                       int long_steps, Counters* ctr, hipStream_t s, const int* imap = nullptr);
 
 // Activation workspace of one forward pass over P = B * H * W positions.
 struct CnnWork {
