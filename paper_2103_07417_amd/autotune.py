@@ -138,8 +138,9 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
     per termination); then, at that choice, the long-ray threshold of the
     refinement queues (600, 700, 900 besides the default 800: the points
     queued at the front should be about as many as the lanes that start
-    them).  The fastest choice is applied to every batch.  Returns the choice
-    and the table."""
+    them); last, a larger grid for the base pass alone (5/4, 3/2, 2 of it,
+    the refinement grid kept).  The fastest choice is applied to every batch.
+    Returns the choice and the table."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     depths = tuple(depths or (len(batches),))
@@ -193,6 +194,19 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
             log("autotune in flight depth=%d blocks=%d threads=%d refine_blocks=%d refill=%d long_steps=%d: "
                 "%.2f ms/batch" % (d, best["trace_blocks"], best["trace_threads"], best["refine_blocks"],
                                    best["refill"], ls, ms))
+    best = min([best] + table[-3:], key=lambda r: r["ms"])
+    rb = best["refine_blocks"] or best["trace_blocks"]
+    for mult in (1.25, 1.5, 2.0):
+        tb = int(round(best["trace_blocks"] * mult))
+        for b in batches[:d]:
+            b.set_launch(tb, best["trace_threads"], best["refill"], 1, refine_blocks=rb,
+                         long_steps=best["long_steps"])
+        ms = min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2))
+        table.append(dict(best, trace_blocks=tb, refine_blocks=rb, ms=ms))
+        if log:
+            log("autotune in flight depth=%d base blocks=%d threads=%d refine_blocks=%d refill=%d "
+                "long_steps=%d: %.2f ms/batch" % (d, tb, best["trace_threads"], rb, best["refill"],
+                                                  best["long_steps"], ms))
     best = min([best] + table[-3:], key=lambda r: r["ms"])
     for b in batches:
         b.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], 1,
