@@ -123,13 +123,20 @@ def time_in_flight(batches, torch, streams, reps):
     return (time.perf_counter() - t0) / reps * 1e3
 
 
+def median_in_flight(batches, torch, streams, reps, k=3):
+    """Median of k in-flight timings: a shape whose time scatters between
+    replays is judged by its typical time, not its best."""
+    return sorted(time_in_flight(batches, torch, streams, reps) for _ in range(k))[k // 2]
+
+
 def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
     """Launch shape and depth for batches in flight (one image group each, the
     streams take the groups' role): with d batches in flight each batch's
     persistent grid should fill only its share of the chip so the batches
     co-reside.  For every depth d in `depths` (default: all the batches)
     the first d batches are replayed round robin on the first d streams,
-    searching blocks per CU and threads per block; then, at the fastest
+    searching blocks per CU and threads per block (every candidate timed as
+    the median of three replays of the batches); then, at the fastest
     (depth, shape), smaller grids for the refinement passes (7/8 and 3/4 of
     the base grid: fewer waves left with idle lanes once a pass's queue has
     drained, while the other batches take the freed slots) crossed with
@@ -155,7 +162,7 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
                 blocks = max(1, cus * waves_per_cu * 64 // threads)
                 for b in batches[:d]:
                     b.set_launch(blocks, threads, 1, 1)
-                ms = time_in_flight(batches[:d], torch, streams[:d], n)
+                ms = median_in_flight(batches[:d], torch, streams[:d], n)
                 table.append(dict(in_flight=d, trace_blocks=blocks, trace_threads=threads, refill=1, groups=1,
                                   ms=ms))
                 if log:
@@ -163,12 +170,12 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
                         % (d, blocks, threads, ms))
     best = dict(min(table, key=lambda r: r["ms"]), refine_blocks=0)
     d = best["in_flight"]
-    # the second stage's differences are a few percent: longer timings, the
-    # better of two, and the first stage's row timed again the same way
+    # the later stages' differences are a few percent: longer timings, and
+    # the first stage's row timed again the same way
     n = reps or max(12, 4 * d)
     for b in batches[:d]:
         b.set_launch(best["trace_blocks"], best["trace_threads"], 1, 1)
-    best = dict(best, ms=min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2)))
+    best = dict(best, ms=median_in_flight(batches[:d], torch, streams[:d], n))
     table.append(best)
     for frac in (1.0, 0.875, 0.75):
         rb = max(1, int(round(best["trace_blocks"] * frac)))
@@ -177,7 +184,7 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
                 continue                      # the first stage's row
             for b in batches[:d]:
                 b.set_launch(best["trace_blocks"], best["trace_threads"], refill, 1, refine_blocks=rb)
-            ms = min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2))
+            ms = median_in_flight(batches[:d], torch, streams[:d], n)
             table.append(dict(best, refine_blocks=rb, refill=refill, ms=ms))
             if log:
                 log("autotune in flight depth=%d blocks=%d threads=%d refine_blocks=%d refill=%d: %.2f ms/batch"
@@ -188,7 +195,7 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
         for b in batches[:d]:
             b.set_launch(best["trace_blocks"], best["trace_threads"], best["refill"], 1,
                          refine_blocks=best["refine_blocks"], long_steps=ls)
-        ms = min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2))
+        ms = median_in_flight(batches[:d], torch, streams[:d], n)
         table.append(dict(best, long_steps=ls, ms=ms))
         if log:
             log("autotune in flight depth=%d blocks=%d threads=%d refine_blocks=%d refill=%d long_steps=%d: "
@@ -201,7 +208,7 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
         for b in batches[:d]:
             b.set_launch(tb, best["trace_threads"], best["refill"], 1, refine_blocks=rb,
                          long_steps=best["long_steps"])
-        ms = min(time_in_flight(batches[:d], torch, streams[:d], n) for _ in range(2))
+        ms = median_in_flight(batches[:d], torch, streams[:d], n)
         table.append(dict(best, trace_blocks=tb, refine_blocks=rb, ms=ms))
         if log:
             log("autotune in flight depth=%d base blocks=%d threads=%d refine_blocks=%d refill=%d "
