@@ -331,9 +331,16 @@ __device__ __forceinline__ unsigned long long xcd_contiguous(unsigned long long 
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
-// grid (x: 256-wide strips of p, y: q, z: image), remapped per XCD as above.
-// One thread per point of the level-(l+1) grid; new points are classified by
-// index parity (categories 2-4).
+// grid (x: 256-wide strips of the new points of an image, z: image), remapped
+// per XCD as above.  One thread per new point of the level-(l+1) grid, taken
+// row pair by row pair: the (nxl - 1) / 2 odd columns of an even row, then
+// all nxl columns of the next odd row (the old points, even row and column,
+// get no thread); new points are classified by index parity (categories 2-4).
+__host__ __device__ __forceinline__ long long estimate_points(int nxl, int nyl)
+{
+    return (long long)((nyl - 1) >> 1) * (((nxl - 1) >> 1) + nxl) + ((nxl - 1) >> 1);
+}
+
 __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, Counters* ctr,
                                                   unsigned long long* list, long long cap, int long_steps,
                                                   int mode, int fallback, int img_off, int slot,
@@ -349,9 +356,17 @@ __global__ __launch_bounds__(256) void k_estimate(const ImageDesc* desc, int l, 
     const int nxl = (1 << (l + 1)) * (D.nx0 - 1) + 1;
     const int nyl = (1 << (l + 1)) * (D.ny0 - 1) + 1;
     const int s = 1 << (D.levels - l - 1);
-    const int p = bx * blockDim.x + threadIdx.x;
-    const int q = by;
-    const bool isnew = p < nxl && q < nyl && ((p & 1) | (q & 1));
+    (void)by;
+    const int m0 = (nxl - 1) >> 1;                 // new points of an even row
+    const long long t = (long long)bx * blockDim.x + threadIdx.x;
+    const bool isnew = t < estimate_points(nxl, nyl);
+    int p = 0, q = 0;
+    if (isnew) {
+        const long long k = t / (m0 + nxl);
+        const int r = (int)(t - k * (m0 + nxl));
+        q = (int)(2 * k) + (r < m0 ? 0 : 1);
+        p = r < m0 ? 2 * r + 1 : r - m0;
+    }
     bool trace = false;
     bool longr = false;                      // expected to be a long ray: queue at the front
     bool spec = false;                       // value taken from the spectral neighbours
@@ -558,7 +573,9 @@ hipError_t launch_estimate(const ImageDesc* desc, int nimg, int nxl_max, int nyl
                            int feat)
 {
     if (nimg <= 0) return hipSuccess;
-    dim3 grid((nxl_max + 255) / 256, nyl_max, nimg);
+    const long long pts = estimate_points(nxl_max, nyl_max);
+    if ((pts + 255) / 256 >= (1LL << 31)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((pts + 255) / 256), 1, nimg);
     hipLaunchKernelGGL(k_estimate, grid, dim3(256), 0, s, desc, l, ctr, list, cap, long_steps, mode, fallback,
                        img_off, slot < 0 ? l + 1 : slot, imap, feat);
     return hipGetLastError();
