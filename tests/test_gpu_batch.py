@@ -52,6 +52,30 @@ def test_batch_equals_single(art):
     B.close()
 
 
+def test_batch_of_mixed_base_grids_equals_single(art):
+    """Images with different (and non-square) base grids in one batch: the
+    base-list and estimator launches are sized for the largest image, every
+    other image uses its own grid; each image equals its single render."""
+    print("CASE mixed base grids", flush=True)
+    cfgs = []
+    for k, (nx0, ny0, lv) in enumerate([(17, 17, 2), (9, 13, 3), (13, 5, 1), (5, 9, 2), (2, 3, 3)]):
+        c = art_inputs.reduced(art_inputs.workload("thermal_1025"), nx0, lv)
+        c.update(ny0=ny0, a=(0.94, 0.0, -0.5, 0.5, 0.9)[k], inc_deg=(163.0, 60.0, 90.0, 17.0, 120.0)[k],
+                 precision="fp64")
+        cfgs.append(c)
+    for groups in (1, 2):
+        B = art.Batch(cfgs)
+        B.set_launch(groups=groups)
+        B.render()
+        torch.cuda.synchronize()
+        for i, c in enumerate(cfgs):
+            img, lev, _, s1 = art.render(c)
+            assert torch.equal(img, B.images[i]), (groups, i)
+            assert torch.equal(lev, B.levels[i]), (groups, i)
+            assert B.stats(i)["rays"] == s1["rays"]
+        B.close()
+
+
 def test_batch_graph_replays(art):
     print("CASE batch graph replays", flush=True)
     cfgs = small_batch("mixed")
