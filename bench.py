@@ -414,16 +414,20 @@ def c4_forms(art, torch, art_inputs, args):
         bset = bset[:depth]
         # latency of one batch alone: the in-flight shape with the base grid's
         # size for every pass (a smaller refinement grid only pays when other
-        # batches take the freed slots), and with twice that grid (alone, a
-        # batch has every wave slot of the chip); the faster is reported
+        # batches take the freed slots) and with twice that grid (alone, a
+        # batch has every wave slot of the chip), each with one and with two
+        # image groups (one group's pass tail overlaps the other's work); the
+        # fastest is reported
         B0 = bset[0]
         lat, lat_launch = None, None
-        for mult in (1, 2):
-            shape = dict(launch, trace_blocks=launch["trace_blocks"] * mult, refine_blocks=0)
-            B0.set_launch(**shape)
-            t = time_graph(B0, torch, s, max(3, args.steps // 3))
-            if lat is None or t < lat:
-                lat, lat_launch = t, shape
+        for groups in (1, 2):
+            for mult in (1, 2):
+                shape = dict(launch, trace_blocks=launch["trace_blocks"] * mult, refine_blocks=0, groups=groups)
+                B0.set_launch(**shape)
+                t = time_graph(B0, torch, s, max(3, args.steps // 3))
+                if lat is None or t < lat:
+                    lat, lat_launch = t, shape
+        B0.set_launch(**launch)
         for X in bset:
             X.set_launch(**launch)
         for _ in range(args.warmup):
