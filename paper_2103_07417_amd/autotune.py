@@ -135,8 +135,8 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
     persistent grid should fill only its share of the chip so the batches
     co-reside.  For every depth d in `depths` (default: all the batches)
     the first d batches are replayed round robin on the first d streams,
-    searching blocks per CU and threads per block (every candidate timed as
-    the median of three replays of the batches); then, at the fastest
+    searching blocks per CU (256-thread blocks; every candidate timed as the
+    median of three replays of the batches); then, at the fastest
     (depth, shape), smaller grids for the refinement passes (7/8 and 3/4 of
     the base grid: fewer waves left with idle lanes once a pass's queue has
     drained, while the other batches take the freed slots) crossed with
@@ -157,7 +157,10 @@ def autotune_in_flight(batches, streams, depths=None, reps=None, log=None):
     t0 = time.perf_counter()
     for d in depths:
         n = reps or max(4, 2 * d)
-        for threads in (128, 256):
+        # 256-thread blocks only: with batches in flight, 128-thread shapes
+        # timed well here and then ran 10-15 % slower and unevenly in the
+        # longer timed replays
+        for threads in (256,):
             for waves_per_cu in (4, 8, 12, 16):
                 blocks = max(1, cus * waves_per_cu * 64 // threads)
                 for b in batches[:d]:

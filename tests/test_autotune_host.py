@@ -42,6 +42,6 @@ def test_in_flight_autotuner_picks_the_cheapest_second_stage(monkeypatch):
     for b in bs:
         assert b.launch == dict(trace_blocks=320, trace_threads=256, refill=4, groups=1, refine_blocks=224,
                                 long_steps=700)
-    # first stage: 2 depths x 2 thread counts x 4 grid sizes; second: the best row again + 11 candidates;
+    # first stage: 2 depths x 4 grid sizes; second: the best row again + 11 candidates;
     # third: 3 thresholds; fourth: 3 base grids
-    assert len(out["table"]) == 16 + 12 + 3 + 3
+    assert len(out["table"]) == 8 + 12 + 3 + 3
