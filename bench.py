@@ -85,11 +85,17 @@ BYTES_PER_RAY = 58
 # HBM traffic of the tracing kernel from FETCH_SIZE / WRITE_SIZE counter runs
 # of this benchmark, per render of the headline form; valid only for the
 # kernel sources it was measured on (hash below), else reported as null.
-TRAFFIC = dict(bytes_per_render=401859027, kernel_hash="1013ae1ac963895c", form="judge_z2_l0",
+TRAFFIC = dict(bytes_per_render=313801608, kernel_hash="d340999eb37e1e55", form="judge_z2_l0",
                precision="mixed",
                source="profiles/k_trace_learned_batched_uneven_64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
-                      "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders")
-TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp")
+                      "(scales from a 256 MiB device copy), k_trace launches of the two roofline renders, "
+                      "counter runs at 256 x 256 threads, 224 refinement blocks, refill 4, long-ray "
+                      "threshold 700")
+# the tracer and the kernels that build its queues (the queue order sets which
+# rays finish together, and so how many of their scattered result stores share
+# a sector)
+TRAFFIC_SOURCES = ("paper_2103_07417_amd/csrc/art_trace.hip", "paper_2103_07417_amd/csrc/art_device.hpp",
+                   "paper_2103_07417_amd/csrc/art_kernels.hip", "paper_2103_07417_amd/csrc/art_cnn.hip")
 
 # proposal thresholds of the judge-only render at 16385^2, chosen on a held-out
 # snapshot (other turbulence seed, same view)
